@@ -1,0 +1,174 @@
+/*
+ * rbsog.h -- C ABI of librbsog, the MI355X (gfx950) implementation of the
+ * IRBSOG force evaluation for Born-Mayer-Huggins melts: random batch list
+ * (RBL) short range plus random batch sum-of-Gaussians (RBSOG) long range,
+ * and velocity-Verlet steps (Chen, Liang, Xu, Zhang, arXiv:2512.24970,
+ * Section 2).
+ *
+ * Conventions
+ *  - Units: eV, Angstrom, ps, amu, elementary charge, K.
+ *  - Every call returns an rbsog_status (0 = OK, < 0 = error).  Nothing throws
+ *    or aborts across the ABI; rbsog_last_error() holds the message of the
+ *    last failed call of a context.
+ *  - One context owns one HIP stream (the caller's, or the default stream)
+ *    and the device memory of one system.  A context is not thread safe.
+ *  - Per-atom arrays passed in or out are in the caller's atom order ("user
+ *    order", atom index = id) and row-major [N][3] for vectors.  Inside, the
+ *    library keeps atoms sorted by cell; that order never leaks out.
+ *  - Pointer arguments are owned by the caller and only read or written
+ *    during the call (device outputs are written by work enqueued on the
+ *    context's stream; the call returns once that work is enqueued unless it
+ *    says it synchronises).
+ *  - Invalid parameters are rejected before any device allocation.
+ */
+#ifndef RBSOG_H
+#define RBSOG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBSOG_MAX_SPECIES 8
+#define RBSOG_MAX_SOG 512  /* capacity of the SOG weight array returned by rbsog_sog_params */
+
+typedef struct rbsog_ctx rbsog_ctx;
+
+typedef enum {
+    RBSOG_OK = 0,
+    RBSOG_E_ARG = -1,        /* invalid argument or parameter */
+    RBSOG_E_STATE = -2,      /* call out of order (e.g. no system set) */
+    RBSOG_E_HIP = -3,        /* a HIP runtime call failed */
+    RBSOG_E_OOM = -4,        /* device allocation failed */
+    RBSOG_E_LIST_STALE = -5, /* an atom moved more than skin/2 since the list build */
+    RBSOG_E_NONNEUTRAL = -6, /* total charge is not zero */
+    RBSOG_E_BOX = -7,        /* box shorter than 2 (r_shell + skin) along some axis */
+    RBSOG_E_NONFINITE = -8,  /* a non-finite force or position was produced */
+    RBSOG_E_CAPACITY = -9    /* a per-cell or per-atom capacity was exceeded */
+} rbsog_status;
+
+typedef enum { RBSOG_FP64 = 0, RBSOG_MIXED = 1 } rbsog_precision;
+
+typedef struct {
+    double q;    /* charge, e */
+    double mass; /* amu */
+} rbsog_species;
+
+/* Born-Mayer-Huggins pair parameters of eq. (1):
+ * U_B(r) = A exp((sigma - r)/rho) - C/r^6 - D/r^8. */
+typedef struct {
+    double A, sigma, rho, C, D;
+} rbsog_pair;
+
+typedef struct {
+    int32_t n_atoms;
+    int32_t n_species;                          /* 1..RBSOG_MAX_SPECIES */
+    double box[3];                              /* orthorhombic, origin 0 */
+    rbsog_species species[RBSOG_MAX_SPECIES];
+    rbsog_pair pair[RBSOG_MAX_SPECIES * RBSOG_MAX_SPECIES]; /* [i*MAX + j], symmetric */
+    double r_core;     /* RBL core radius (eq. 24) */
+    double r_shell;    /* RBL shell radius (eq. 25); also the SOG cutoff r_c (eqs. 8-10) */
+    double skin;       /* list skin; lists hold r < r_core+skin and
+                          r_core-skin <= r < r_shell+skin */
+    int32_t p_r;       /* shell batch size P_R; <= 0: every candidate, weight 1 */
+    int32_t p_f;       /* Fourier batch size P_F; <= 0: full k-sum of eq. (23) */
+    double sog_eps;    /* target of the eq. (5) bound; <= 0 means 1e-5 */
+    double dt;         /* ps */
+    int32_t rebuild_every; /* list rebuild period in steps (>= 1) */
+    int32_t precision;     /* rbsog_precision */
+    uint64_t seed;         /* Philox key */
+    uint32_t replica;      /* Philox stream id of this system */
+    uint32_t flags;        /* reserved, 0 */
+    double coulomb_k;      /* e^2/(4 pi eps0) in eV*Angstrom; <= 0 means 14.399645478 */
+} rbsog_params;
+
+typedef struct {
+    double u_core;    /* core-list energy, sum over r < r_core of N + B_BMH (eqs. 13-14, 24) */
+    double u_shell;   /* shell estimate, (N_shell/P_R) times the batch sum (eq. 25) */
+    double u_kspace;  /* U*_F of eq. (18), estimated with the sampled modes */
+    double u_self;    /* U_self of eq. (18) */
+    double u_total;   /* u_core + u_shell + u_kspace - u_self */
+    double kinetic;
+    double p_corr[3]; /* momentum correction F_corr of eq. (26) that was subtracted */
+    double max_disp;  /* largest displacement since the last list build */
+} rbsog_energy;
+
+/* Library version string. */
+const char* rbsog_version(void);
+
+/* SOG split of eqs. (4)-(10) for a target eps (eq. 5 bound) and cutoff
+ * r_c = r_shell, computed on the host: base b, bandwidth s, x_c = r_c/s,
+ * series length M (m = 0..M) and weights w[0..M] (w[0] adjusted for C1
+ * continuity).  w may be NULL; otherwise it must hold w_cap >= M+1 values.
+ * Needs no GPU. */
+rbsog_status rbsog_sog_params(double eps, double r_shell, double* b, double* s, double* x_c,
+                              int32_t* M, double* w, int32_t w_cap);
+
+/* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+rbsog_status rbsog_create(rbsog_ctx** out, int hip_device, void* hip_stream);
+rbsog_status rbsog_destroy(rbsog_ctx* ctx);
+const char* rbsog_last_error(const rbsog_ctx* ctx);
+
+/* Validate parameters (neutrality, box >= 2(r_shell+skin), species count),
+ * set up the SOG split and the k-space sampling tables (eq. 28) and copy
+ * type[N], pos[N][3] and vel[N][3] (vel may be NULL = zero) into device
+ * memory.  Pointers are device pointers if ptrs_on_device != 0, else host.
+ * Builds the lists.  Synchronises. */
+rbsog_status rbsog_set_system(rbsog_ctx* ctx, const rbsog_params* p, const int32_t* type,
+                              const double* pos, const double* vel, int ptrs_on_device);
+
+/* Rebuild the cell order and the core/shell-candidate lists at the current
+ * positions (Section 2.2 core-shell lists). */
+rbsog_status rbsog_build_lists(rbsog_ctx* ctx);
+
+/* One IRBSOG force evaluation at the current positions with Philox counter
+ * `eval` (shell batches of eq. 25, modes of eq. 28): F = F_core + F*_shell -
+ * F_corr + F*_F (eqs. 24-27, 29).  Writes the force in user order to the
+ * device array force_out[N][3] if non-NULL.  Energies are returned in e_out
+ * if non-NULL (the call then synchronises).  Does not move atoms.  Returns
+ * RBSOG_E_LIST_STALE if an atom moved more than skin/2 since the build. */
+rbsog_status rbsog_compute_forces(rbsog_ctx* ctx, uint64_t eval, double* force_out, rbsog_energy* e_out);
+
+/* Force parts of the last evaluation in user order into device arrays
+ * [N][3] (any may be NULL): short range before the momentum correction
+ * (eqs. 24-25), and the k-space part (eq. 29). */
+rbsog_status rbsog_get_force_parts(rbsog_ctx* ctx, double* f_short, double* f_kspace);
+
+/* n_steps velocity-Verlet steps: kick, drift (wrap), rebuild when the step
+ * number is a multiple of rebuild_every, force with eval = step number,
+ * kick.  The per-step work is captured once in a HIP graph and replayed.
+ * e_last (may be NULL) receives the energies of the last step; the call
+ * synchronises at the end. */
+rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last);
+
+/* Current positions, velocities, forces (user order, [N][3]) and the eval
+ * index of the last force evaluation.  Pointers are device pointers if
+ * ptrs_on_device != 0, else host (then the call synchronises).  Any may be
+ * NULL. */
+rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* force, uint64_t* eval,
+                             int ptrs_on_device);
+
+/* ---- parity exports (host outputs, synchronise) ----------------------- */
+
+/* Core and candidate list sizes n_core[N], n_cand[N]. */
+rbsog_status rbsog_get_list_counts(rbsog_ctx* ctx, int32_t* n_core, int32_t* n_cand);
+/* Lists of atom i: core neighbour ids ascending, candidate ids ascending. */
+rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_t* cand);
+/* Shell batch ranks (indices into the id-ascending candidate list, ascending)
+ * of every atom for evaluation `eval`: ranks[N][P_R]; unused slots are -1.
+ * n_ranks[N] gets min(P_R, n_cand). */
+rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ranks, int32_t* ranks);
+/* The P_F modes m[P_F][3] drawn for evaluation `eval` and S of eq. (28). */
+rbsog_status rbsog_get_kmodes(rbsog_ctx* ctx, uint64_t eval, int32_t* m, double* S);
+/* Structure factors rho[P_F][2] (eq. 22) of the last force evaluation. */
+rbsog_status rbsog_get_rho(rbsog_ctx* ctx, double* rho);
+/* SOG split in use (see rbsog_sog_params). */
+rbsog_status rbsog_get_sog(rbsog_ctx* ctx, double* b, double* s, double* x_c, int32_t* M, double* w,
+                           int32_t w_cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1026 @@
+// HIP kernels of the IRBSOG evaluation for gfx950 (CDNA4, wave64).
+//
+// Layout: atoms in cell order as structure-of-arrays FP64; the core list is
+// stored in 64-atom tiles (entry k of the 64 atoms of a tile contiguous) so a
+// wavefront reads it coalesced; shell candidates are stored row-major per atom
+// in ascending atom id, so the shell batch of eq. (25) maps ranks to atoms the
+// same way on any device.  Every reduction runs in a fixed order, so FP64
+// results are bit-reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace rbsog {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kCellCap = 2048;  // atoms per cell the in-cell sort can hold
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of v over a 256-thread block in a fixed order; valid in thread 0.
+__device__ inline double block_sum(double v, double* red /*[4]*/)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) t = ((red[0] + red[1]) + red[2]) + red[3];
+    __syncthreads();
+    return t;
+}
+
+// Minimum image with the operations in a fixed order (no contraction):
+// d -= L * rint(d / L), d / L evaluated as d * (1/L).
+__device__ inline double min_image(double d, double L, double invL)
+{
+    const double k = rint(d * invL);
+    const double Lk = L * k;
+    return d - Lk;
+}
+
+__device__ inline double wrap_coord(double x, double L, double invL)
+{
+    const double f = floor(x * invL);
+    double v = x - L * f;
+    if (v >= L) v -= L;
+    if (v < 0.0) v += L;
+    return v;
+}
+
+__device__ inline int cell_coord(double v, double scale, int nc)
+{
+    int c = (int)(v * scale);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+// ---------------------------------------------------------------- scalars
+__global__ void k_set_eval(DeviceScalars* sc, uint64_t eval) { sc->eval = eval; }
+__global__ void k_bump_eval(DeviceScalars* sc) { sc->eval += 1; }
+__global__ void k_reset_disp(DeviceScalars* sc) { sc->max_disp2 = 0.0; }
+__global__ void k_clear_flags(DeviceScalars* sc)
+{
+    sc->overflow = 0;
+    sc->stale = 0;
+    sc->nonfinite = 0;
+    sc->max_disp2 = 0.0;
+}
+
+// ---------------------------------------------------------------- cell sort
+__global__ void k_bin(DevSys s)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const double x = wrap_coord(s.x[i], s.L[0], s.invL[0]);
+    const double y = wrap_coord(s.y[i], s.L[1], s.invL[1]);
+    const double z = wrap_coord(s.z[i], s.L[2], s.invL[2]);
+    s.x[i] = x;
+    s.y[i] = y;
+    s.z[i] = z;
+    const int cx = cell_coord(x, s.cell_scale[0], s.nc[0]);
+    const int cy = cell_coord(y, s.cell_scale[1], s.nc[1]);
+    const int cz = cell_coord(z, s.cell_scale[2], s.nc[2]);
+    const int c = (cz * s.nc[1] + cy) * s.nc[0] + cx;
+    s.cell_of[i] = c;
+    s.slot_of[i] = atomicAdd(&s.cell_count[c], 1);
+}
+
+// Exclusive scan of count[0..n) into start[0..n], one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan(int32_t* count, int32_t* start, int n)
+{
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int b = t * per, e = min(n, b + per);
+    int32_t sum = 0;
+    for (int i = b; i < e; ++i) sum += count[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int32_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+    for (int i = b; i < e; ++i) {
+        start[i] = run;
+        run += count[i];
+        count[i] = 0;  // ready for the next build
+    }
+    if (t == 1023) start[n] = part[1023];
+}
+
+__global__ void k_scatter(DevSys s)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const int d = s.cell_start[s.cell_of[i]] + s.slot_of[i];
+    s.tx[d] = s.x[i];
+    s.ty[d] = s.y[i];
+    s.tz[d] = s.z[i];
+    s.tvx[d] = s.vx[i];
+    s.tvy[d] = s.vy[i];
+    s.tvz[d] = s.vz[i];
+    s.ttype[d] = s.type[i];
+    s.tid[d] = s.id[i];
+}
+
+// Within each cell, order atoms by id so the cell order is deterministic.
+__global__ __launch_bounds__(kBlock) void k_cell_sort(DevSys s)
+{
+    __shared__ int32_t key[kCellCap];
+    __shared__ int32_t val[kCellCap];
+    const int c = blockIdx.x;
+    const int beg = s.cell_start[c];
+    const int cnt = s.cell_start[c + 1] - beg;
+    if (cnt > kCellCap) {
+        // keep a valid (unsorted) permutation; the host reports the overflow
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) s.order[beg + t] = beg + t;
+        if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 2);
+        return;
+    }
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        key[t] = t < cnt ? s.tid[beg + t] : INT_MAX;
+        val[t] = t < cnt ? beg + t : -1;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < P; t += blockDim.x) {
+                const int u = t ^ j;
+                if (u > t) {
+                    const bool up = (t & k) == 0;
+                    const int32_t a = key[t], b = key[u];
+                    if ((a > b) == up) {
+                        key[t] = b;
+                        key[u] = a;
+                        const int32_t va = val[t];
+                        val[t] = val[u];
+                        val[u] = va;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) s.order[beg + t] = val[t];
+}
+
+__global__ void k_gather(DevSys s)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.n) return;
+    const int o = s.order[t];
+    const double x = s.tx[o], y = s.ty[o], z = s.tz[o];
+    s.x[t] = x;
+    s.y[t] = y;
+    s.z[t] = z;
+    s.xr[t] = x;
+    s.yr[t] = y;
+    s.zr[t] = z;
+    s.vx[t] = s.tvx[o];
+    s.vy[t] = s.tvy[o];
+    s.vz[t] = s.tvz[o];
+    s.type[t] = s.ttype[o];
+    const int id = s.tid[o];
+    s.id[t] = id;
+    s.inv[id] = t;
+}
+
+// ---------------------------------------------------------------- lists
+// One 64-thread block per atom: the lanes sweep the neighbouring cells,
+// compact core and candidate entries with ballots, then sort the candidates
+// by atom id (bitonic network in LDS).
+__global__ __launch_bounds__(64) void k_lists(DevSys s)
+{
+    extern __shared__ int32_t lsm[];
+    const int capP2 = [&] {
+        int p = 1;
+        while (p < s.cap_cand) p <<= 1;
+        return p;
+    }();
+    int32_t* ckey = lsm;
+    int32_t* cval = lsm + capP2;
+    int32_t* core = lsm + 2 * capP2;
+
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double xi = s.x[i], yi = s.y[i], zi = s.z[i];
+    const int ci[3] = {cell_coord(xi, s.cell_scale[0], s.nc[0]), cell_coord(yi, s.cell_scale[1], s.nc[1]),
+                       cell_coord(zi, s.cell_scale[2], s.nc[2])};
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int ncore = 0, ncand = 0;
+    const int lo0 = s.nc[0] >= 3 ? -1 : 0, hi0 = s.nc[0] >= 3 ? 1 : 0;
+    const int lo1 = s.nc[1] >= 3 ? -1 : 0, hi1 = s.nc[1] >= 3 ? 1 : 0;
+    const int lo2 = s.nc[2] >= 3 ? -1 : 0, hi2 = s.nc[2] >= 3 ? 1 : 0;
+    for (int oz = lo2; oz <= hi2; ++oz) {
+        const int cz = (ci[2] + oz + s.nc[2]) % s.nc[2];
+        for (int oy = lo1; oy <= hi1; ++oy) {
+            const int cy = (ci[1] + oy + s.nc[1]) % s.nc[1];
+            for (int ox = lo0; ox <= hi0; ++ox) {
+                const int cx = (ci[0] + ox + s.nc[0]) % s.nc[0];
+                const int c = (cz * s.nc[1] + cy) * s.nc[0] + cx;
+                const int beg = s.cell_start[c], end = s.cell_start[c + 1];
+                for (int base = beg; base < end; base += 64) {
+                    const int j = base + lane;
+                    bool is_core = false, is_cand = false;
+                    if (j < end && j != i) {
+                        const double dx = min_image(xi - s.x[j], s.L[0], s.invL[0]);
+                        const double dy = min_image(yi - s.y[j], s.L[1], s.invL[1]);
+                        const double dz = min_image(zi - s.z[j], s.L[2], s.invL[2]);
+                        const double r2 = (dx * dx + dy * dy) + dz * dz;
+                        is_core = r2 < s.rc2_list;
+                        is_cand = r2 >= s.lo2_list && r2 < s.hi2_list;
+                    }
+                    const uint64_t mc = __ballot(is_core);
+                    const uint64_t mk = __ballot(is_cand);
+                    if (is_core) {
+                        const int slot = ncore + __popcll(mc & below);
+                        if (slot < s.cap_core) core[slot] = j;
+                    }
+                    if (is_cand) {
+                        const int slot = ncand + __popcll(mk & below);
+                        if (slot < s.cap_cand) {
+                            ckey[slot] = s.id[j];
+                            cval[slot] = j;
+                        }
+                    }
+                    ncore += __popcll(mc);
+                    ncand += __popcll(mk);
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        s.core_cnt[i] = ncore;
+        s.cand_cnt[i] = ncand;
+        if (ncore > s.cap_core || ncand > s.cap_cand) atomicOr(&s.sc->overflow, 1);
+    }
+    const int nk = min(ncand, s.cap_cand);
+    const int nc = min(ncore, s.cap_core);
+    int P = 1;
+    while (P < nk) P <<= 1;
+    for (int t = nk + lane; t < P; t += 64) {
+        ckey[t] = INT_MAX;
+        cval[t] = -1;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < P; t += 64) {
+                const int u = t ^ j;
+                if (u > t) {
+                    const bool up = (t & k) == 0;
+                    const int32_t a = ckey[t], b = ckey[u];
+                    if ((a > b) == up) {
+                        ckey[t] = b;
+                        ckey[u] = a;
+                        const int32_t va = cval[t];
+                        cval[t] = cval[u];
+                        cval[u] = va;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
+    for (int t = lane; t < nk; t += 64) crow[t] = cval[t];
+    int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
+    for (int t = lane; t < nc; t += 64) ctile[(size_t)t * 64] = core[t];
+}
+
+// ---------------------------------------------------------------- pair forces
+struct PairCoefF {
+    float qq, A, sig, irho, C, D;
+};
+
+struct SogCoefF {
+    int n_exp, chain, n_poly, pad;
+    float a[kMaxExplicit];
+    float fw[kMaxExplicit];
+    float ew[kMaxExplicit];
+    float pc[kMaxPoly];
+    float pd[kMaxPoly];
+};
+
+// Pair force scalar f (F_i += f * r_ij) of eq. (15) with k_e on the Coulomb
+// part, and the pair energy k_e q_i q_j N(r) + B_BMH(r), in FP64.
+template <int J, bool ENERGY>
+__device__ inline double pair_scalar_f64(const PairCoef& c, const SogCoef& g, double r2, double& u)
+{
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    const double ir2 = ir * ir;
+    const int n = g.n_exp;
+    double fsum = 0.0, esum = 0.0;
+    if (J == 1) {
+        double gm = exp(-r2 * g.a[n - 1]);
+        fsum = g.fw[n - 1] * gm;
+        if (ENERGY) esum = g.ew[n - 1] * gm;
+        for (int m = n - 2; m >= 0; --m) {
+            gm = gm * gm;
+            fsum = fma(g.fw[m], gm, fsum);
+            if (ENERGY) esum = fma(g.ew[m], gm, esum);
+        }
+    } else {
+        double ga = exp(-r2 * g.a[n - 1]);  // g_{m+2}
+        double gb = exp(-r2 * g.a[n - 2]);  // g_{m+1}
+        fsum = fma(g.fw[n - 2], gb, g.fw[n - 1] * ga);
+        if (ENERGY) esum = fma(g.ew[n - 2], gb, g.ew[n - 1] * ga);
+        for (int m = n - 3; m >= 0; --m) {
+            const double gm = ga * ga;
+            ga = gb;
+            gb = gm;
+            fsum = fma(g.fw[m], gm, fsum);
+            if (ENERGY) esum = fma(g.ew[m], gm, esum);
+        }
+    }
+    if (g.n_poly > 0) {
+        double pf = g.pc[g.n_poly - 1];
+        double pe = g.pd[g.n_poly - 1];
+        for (int k = g.n_poly - 2; k >= 0; --k) {
+            pf = fma(pf, r2, g.pc[k]);
+            if (ENERGY) pe = fma(pe, r2, g.pd[k]);
+        }
+        fsum += pf;
+        if (ENERGY) esum += pe;
+    }
+    const double rep = c.A * exp((c.sig - r) * c.irho);
+    const double ir6 = ir2 * ir2 * ir2;
+    const double ir8 = ir6 * ir2;
+    const double f = c.qq * (ir2 * ir - fsum) + rep * c.irho * ir - 6.0 * c.C * ir8 - 8.0 * c.D * ir8 * ir2;
+    if (ENERGY) u = c.qq * (ir - esum) + rep - c.C * ir6 - c.D * ir8;
+    return f;
+}
+
+// FP32 form: every narrow Gaussian by its own exponential.
+template <bool ENERGY>
+__device__ inline float pair_scalar_f32(const PairCoefF& c, const SogCoefF& g, float r2, float& u)
+{
+    const float ir = __frsqrt_rn(r2);
+    const float r = r2 * ir;
+    const float ir2 = ir * ir;
+    float fsum = 0.f, esum = 0.f;
+    for (int m = 0; m < g.n_exp; ++m) {
+        const float gm = __expf(-r2 * g.a[m]);
+        fsum = fmaf(g.fw[m], gm, fsum);
+        if (ENERGY) esum = fmaf(g.ew[m], gm, esum);
+    }
+    if (g.n_poly > 0) {
+        float pf = g.pc[g.n_poly - 1];
+        float pe = g.pd[g.n_poly - 1];
+        for (int k = g.n_poly - 2; k >= 0; --k) {
+            pf = fmaf(pf, r2, g.pc[k]);
+            if (ENERGY) pe = fmaf(pe, r2, g.pd[k]);
+        }
+        fsum += pf;
+        if (ENERGY) esum += pe;
+    }
+    const float rep = c.A * __expf((c.sig - r) * c.irho);
+    const float ir6 = ir2 * ir2 * ir2;
+    const float ir8 = ir6 * ir2;
+    const float f = c.qq * (ir2 * ir - fsum) + rep * c.irho * ir - 6.f * c.C * ir8 - 8.f * c.D * ir8 * ir2;
+    if (ENERGY) u = c.qq * (ir - esum) + rep - c.C * ir6 - c.D * ir8;
+    return f;
+}
+
+// Floyd's selection of P_R distinct ranks out of n (Bentley & Floyd 1987) with
+// a per-lane bitmask in LDS: step k draws t uniform in [0, n-P_R+k] and takes
+// t, or n-P_R+k if t was already taken.
+struct FloydMask {
+    uint32_t* m;
+    int stride;
+    __device__ void clear(int n)
+    {
+        const int words = (n + 31) >> 5;
+        for (int w = 0; w < words; ++w) m[w * stride] = 0u;
+    }
+    __device__ int step(PhiloxStream& st, int jj)
+    {
+        const uint32_t t = st.bounded((uint32_t)jj + 1u);
+        const uint32_t wt = m[(t >> 5) * stride];
+        int e = (int)t;
+        if ((wt >> (t & 31)) & 1u) e = jj;
+        m[(e >> 5) * stride] |= 1u << (e & 31);
+        return e;
+    }
+};
+
+template <bool MIXED, bool ENERGY, int J>
+__global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF gf, double* part)
+{
+    extern __shared__ uint32_t mask_sm[];
+    __shared__ PairCoef pc[kMaxSpecies * kMaxSpecies];
+    __shared__ PairCoefF pcf[kMaxSpecies * kMaxSpecies];
+    __shared__ double red[4];
+    const int S = s.n_species;
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
+        const PairCoef c = s.pair[t];
+        pc[t] = c;
+        pcf[t] = PairCoefF{(float)c.qq, (float)c.A, (float)c.sig, (float)c.irho, (float)c.C, (float)c.D};
+    }
+    __syncthreads();
+
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, Uc = 0.0, Us = 0.0;
+    if (i < s.n) {
+        const double xi = s.x[i], yi = s.y[i], zi = s.z[i];
+        const int ti = s.type[i];
+        // core sum, eq. (24)
+        const int nc = min(s.core_cnt[i], s.cap_core);
+        const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
+        for (int k = 0; k < nc; ++k) {
+            const int j = ctile[(size_t)k * 64];
+            const double dx = min_image(xi - s.x[j], s.L[0], s.invL[0]);
+            const double dy = min_image(yi - s.y[j], s.L[1], s.invL[1]);
+            const double dz = min_image(zi - s.z[j], s.L[2], s.invL[2]);
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            if (r2 < s.rc2) {
+                const int t = ti * S + s.type[j];
+                double f, u = 0.0;
+                if (MIXED) {
+                    float uf = 0.f;
+                    f = (double)pair_scalar_f32<ENERGY>(pcf[t], gf, (float)r2, uf);
+                    u = uf;
+                } else {
+                    f = pair_scalar_f64<J, ENERGY>(pc[t], g, r2, u);
+                }
+                Fx = fma(f, dx, Fx);
+                Fy = fma(f, dy, Fy);
+                Fz = fma(f, dz, Fz);
+                if (ENERGY) Uc += 0.5 * u;
+            }
+        }
+        // shell batch, eq. (25)
+        const int n = min(s.cand_cnt[i], s.cap_cand);
+        const int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
+        const bool take_all = s.p_r <= 0 || n <= s.p_r;
+        const int cnt = take_all ? n : s.p_r;
+        const double wgt = take_all ? 1.0 : (double)n / (double)s.p_r;
+        FloydMask fm{mask_sm + threadIdx.x, (int)blockDim.x};
+        PhiloxStream st(s.seed, (uint32_t)s.id[i], (uint32_t)s.sc->eval, kTagShell, s.replica);
+        if (!take_all) fm.clear(n);
+        double Sx = 0.0, Sy = 0.0, Sz = 0.0, Su = 0.0;
+        for (int k = 0; k < cnt; ++k) {
+            const int e = take_all ? k : fm.step(st, n - s.p_r + k);
+            const int j = crow[e];
+            const double dx = min_image(xi - s.x[j], s.L[0], s.invL[0]);
+            const double dy = min_image(yi - s.y[j], s.L[1], s.invL[1]);
+            const double dz = min_image(zi - s.z[j], s.L[2], s.invL[2]);
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            if (r2 >= s.rc2 && r2 < s.rs2) {
+                const int t = ti * S + s.type[j];
+                double f, u = 0.0;
+                if (MIXED) {
+                    float uf = 0.f;
+                    f = (double)pair_scalar_f32<ENERGY>(pcf[t], gf, (float)r2, uf);
+                    u = uf;
+                } else {
+                    f = pair_scalar_f64<J, ENERGY>(pc[t], g, r2, u);
+                }
+                Sx = fma(f, dx, Sx);
+                Sy = fma(f, dy, Sy);
+                Sz = fma(f, dz, Sz);
+                if (ENERGY) Su += 0.5 * u;
+            }
+        }
+        Fx = fma(wgt, Sx, Fx);
+        Fy = fma(wgt, Sy, Fy);
+        Fz = fma(wgt, Sz, Fz);
+        if (ENERGY) Us = wgt * Su;
+        s.fsx[i] = Fx;
+        s.fsy[i] = Fy;
+        s.fsz[i] = Fz;
+    }
+    const double bx = block_sum(Fx, red);
+    const double by = block_sum(Fy, red);
+    const double bz = block_sum(Fz, red);
+    double bu = 0.0, bs = 0.0;
+    if (ENERGY) {
+        bu = block_sum(Uc, red);
+        bs = block_sum(Us, red);
+    }
+    if (threadIdx.x == 0) {
+        double* p = part + (size_t)blockIdx.x * kPairPart;
+        p[0] = bx;
+        p[1] = by;
+        p[2] = bz;
+        p[3] = bu;
+        p[4] = bs;
+    }
+}
+
+// Export of the shell ranks drawn by the pair kernel (same selection code).
+__global__ __launch_bounds__(kBlock) void k_shell_ranks(DevSys s, int32_t* out, int32_t* n_out)
+{
+    extern __shared__ uint32_t mask_sm[];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const int n = min(s.cand_cnt[i], s.cap_cand);
+    const int P = s.p_r;
+    const int uid = s.id[i];
+    int32_t* o = out + (size_t)uid * (P > 0 ? P : 1);
+    if (P <= 0 || n <= P) {
+        n_out[uid] = n;
+        for (int k = 0; k < (P > 0 ? P : 0); ++k) o[k] = k < n ? k : -1;
+        return;
+    }
+    FloydMask fm{mask_sm + threadIdx.x, (int)blockDim.x};
+    PhiloxStream st(s.seed, (uint32_t)uid, (uint32_t)s.sc->eval, kTagShell, s.replica);
+    fm.clear(n);
+    for (int k = 0; k < P; ++k) o[k] = fm.step(st, n - P + k);
+    n_out[uid] = P;
+}
+
+// ---------------------------------------------------------------- k-space
+__device__ inline int first_above(const double* cdf, int len, double u)
+{
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u < cdf[mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo < len ? lo : len - 1;
+}
+
+// Draw the P_F modes of eq. (28): component (m, d) by its mass, then the
+// three axis indices from their 1D lattice distributions, then signs.
+__global__ void k_ksample(DevSys s, KDev k)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= k.n_modes) return;
+    PhiloxStream st(s.seed, (uint32_t)p, (uint32_t)s.sc->eval, kTagKmode, s.replica);
+    const double uc = st.uniform();
+    double ua[3];
+    for (int a = 0; a < 3; ++a) ua[a] = st.uniform();
+    const uint32_t signs = st.next();
+    const int c = first_above(k.comp_cdf, k.nm * 3, uc);
+    const int m = c / 3, d = c % 3;
+    int mi[3];
+    for (int a = 0; a < 3; ++a) {
+        const int o = k.off[m * 3 + a], L = k.len[m * 3 + a];
+        const double* cdf = (a == d) ? k.g2cdf + o : k.g0cdf + o;
+        int nn = first_above(cdf, L, ua[a]);
+        if (nn > 0 && ((signs >> a) & 1u)) nn = -nn;
+        mi[a] = nn;
+    }
+    k.m[3 * p] = mi[0];
+    k.m[3 * p + 1] = mi[1];
+    k.m[3 * p + 2] = mi[2];
+    double k2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double kk = s.two_pi_L[a] * (double)mi[a];
+        k2 += kk * kk;
+    }
+    ModeRec r;
+    r.mx = mi[0];
+    r.my = mi[1];
+    r.mz = mi[2];
+    r.A = 0.0;
+    r.B = 0.0;
+    r.coef = k.coef_scale / k2;
+    r.e = 0.0;
+    r.pad = 0.0;
+    k.modes[p] = r;
+}
+
+// e^{2 pi i t / 1024} for a phase t in units of 2 pi / 1024: table entry
+// rint(t) mod 1024 rotated by the remainder, whose sine and cosine come from
+// short Taylor series (|x| <= pi/1024, truncation below 1e-18).
+__device__ inline void sincos1024(double t, const double2* tab, double& c, double& s)
+{
+    const double j = rint(t);
+    const double x = (t - j) * (2.0 * kPi / kTableSize);
+    const double x2 = x * x;
+    const double cd = fma(x2, fma(x2, 1.0 / 24.0, -0.5), 1.0);
+    const double sd = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
+    const double2 T = tab[((int)j) & (kTableSize - 1)];
+    c = fma(T.x, cd, -(T.y * sd));
+    s = fma(T.y, cd, T.x * sd);
+}
+
+// rho(k) of eq. (22) over one atom chunk for 64 modes: one mode per lane,
+// the four waves of the block take every fourth atom, atoms read through the
+// scalar unit.  Partial sums per chunk, reduced later in a fixed order.
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_rho(DevSys s, KDev k)
+{
+    __shared__ double2 tab[kTableSize];
+    __shared__ double red[4][64][2];
+    for (int t = threadIdx.x; t < kTableSize; t += blockDim.x)
+        tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int p = blockIdx.y * 64 + lane;
+    const bool ok = p < k.n_modes;
+    const ModeRec mr = ok ? k.modes[p] : ModeRec{0, 0, 0, 0, 0, 0, 0, 0};
+    const double mx = mr.mx, my = mr.my, mz = mr.mz;
+    const int a0 = blockIdx.x * k.chunk;
+    const int a1 = min(s.n, a0 + k.chunk);
+    double re = 0.0, im = 0.0;
+    for (int a = a0 + wave; a < a1; a += 4) {
+        const double ux = s.x[a] * s.u1024[0];
+        const double uy = s.y[a] * s.u1024[1];
+        const double uz = s.z[a] * s.u1024[2];
+        const double q = s.q[s.type[a]];
+        const double t = fma(mz, uz, fma(my, uy, mx * ux));
+        double c, sn;
+        if (MIXED) {
+            const double f = t * (1.0 / kTableSize);
+            const float fr = (float)(f - rint(f));
+            c = (double)__builtin_amdgcn_cosf(fr);
+            sn = (double)__builtin_amdgcn_sinf(fr);
+        } else {
+            sincos1024(t, tab, c, sn);
+        }
+        re = fma(q, c, re);
+        im = fma(q, sn, im);
+    }
+    red[wave][lane][0] = re;
+    red[wave][lane][1] = im;
+    __syncthreads();
+    if (wave == 0 && ok) {
+        const double r = ((red[0][lane][0] + red[1][lane][0]) + red[2][lane][0]) + red[3][lane][0];
+        const double i = ((red[0][lane][1] + red[1][lane][1]) + red[2][lane][1]) + red[3][lane][1];
+        double* o = k.rho_part + ((size_t)blockIdx.x * k.n_modes_pad + p) * 2;
+        o[0] = r;
+        o[1] = i;
+    }
+}
+
+// rho_p = sum over chunks (fixed tree), then the per-mode force coefficients.
+__global__ __launch_bounds__(64) void k_rho_finalize(KDev k)
+{
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int c = lane; c < k.n_chunks; c += 64) {
+        const double* o = k.rho_part + ((size_t)c * k.n_modes_pad + p) * 2;
+        re += o[0];
+        im += o[1];
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+        k.rho[2 * p] = re;
+        k.rho[2 * p + 1] = im;
+        ModeRec& r = k.modes[p];
+        const double cf = r.coef;
+        r.A = cf * im;
+        r.B = cf * re;
+        r.e = cf * (re * re + im * im);
+    }
+}
+
+// Momentum correction (eq. 26) and energy sums; one block.
+__global__ __launch_bounds__(kBlock) void k_finalize(DevSys s, KDev k, const double* part, int nb)
+{
+    __shared__ double red[4];
+    double v[kPairPart] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+        for (int c = 0; c < kPairPart; ++c) v[c] += part[(size_t)b * kPairPart + c];
+    double ue = 0.0;
+    for (int p = threadIdx.x; p < k.n_modes; p += blockDim.x) ue += k.modes[p].e;
+    double tot[kPairPart];
+    for (int c = 0; c < kPairPart; ++c) tot[c] = block_sum(v[c], red);
+    const double ut = block_sum(ue, red);
+    if (threadIdx.x == 0) {
+        DeviceScalars* sc = s.sc;
+        const double inv_n = s.n > 0 ? 1.0 / (double)s.n : 0.0;
+        sc->p_corr[0] = tot[0] * inv_n;
+        sc->p_corr[1] = tot[1] * inv_n;
+        sc->p_corr[2] = tot[2] * inv_n;
+        sc->u_core = tot[3];
+        sc->u_shell = tot[4];
+        sc->u_kspace = 0.5 * s.coulomb_k * ut;
+    }
+}
+
+// k-space force of eq. (29) (or eq. 23) on one atom per lane, looping over all
+// modes; adds the short-range force minus the momentum correction, optionally
+// the closing half kick of velocity Verlet.
+template <bool MIXED, bool KICK, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_kforce(DevSys s, KDev k, double* kin_part)
+{
+    __shared__ double2 tab[kTableSize];
+    __shared__ double red[4];
+    for (int t = threadIdx.x; t < kTableSize; t += blockDim.x)
+        tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double ke = 0.0;
+    if (i < s.n) {
+        const double ux = s.x[i] * s.u1024[0];
+        const double uy = s.y[i] * s.u1024[1];
+        const double uz = s.z[i] * s.u1024[2];
+        double Gx = 0.0, Gy = 0.0, Gz = 0.0;
+        for (int p = 0; p < k.n_modes; ++p) {
+            const ModeRec mr = k.modes[p];
+            const double t = fma(mr.mz, uz, fma(mr.my, uy, mr.mx * ux));
+            double c, sn;
+            if (MIXED) {
+                const double f = t * (1.0 / kTableSize);
+                const float fr = (float)(f - rint(f));
+                c = (double)__builtin_amdgcn_cosf(fr);
+                sn = (double)__builtin_amdgcn_sinf(fr);
+            } else {
+                sincos1024(t, tab, c, sn);
+            }
+            // Im(e^{-i theta} rho) * coef = c * A - s * B
+            const double w = fma(c, mr.A, -(sn * mr.B));
+            Gx = fma(w, mr.mx, Gx);
+            Gy = fma(w, mr.my, Gy);
+            Gz = fma(w, mr.mz, Gz);
+        }
+        const int ti = s.type[i];
+        const double qk = -s.coulomb_k * s.q[ti];
+        const DeviceScalars* sc = s.sc;
+        const double fx = s.fsx[i] - sc->p_corr[0] + qk * s.two_pi_L[0] * Gx;
+        const double fy = s.fsy[i] - sc->p_corr[1] + qk * s.two_pi_L[1] * Gy;
+        const double fz = s.fsz[i] - sc->p_corr[2] + qk * s.two_pi_L[2] * Gz;
+        s.fx[i] = fx;
+        s.fy[i] = fy;
+        s.fz[i] = fz;
+        if (KICK) {
+            const double a = 0.5 * s.dt * s.inv_mass_acc[ti];
+            const double vx = s.vx[i] + a * fx, vy = s.vy[i] + a * fy, vz = s.vz[i] + a * fz;
+            s.vx[i] = vx;
+            s.vy[i] = vy;
+            s.vz[i] = vz;
+            if (ENERGY) ke = 0.5 * s.mass[ti] * (vx * vx + vy * vy + vz * vz);
+        } else if (ENERGY) {
+            const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+            ke = 0.5 * s.mass[ti] * (vx * vx + vy * vy + vz * vz);
+        }
+    }
+    if (ENERGY) {
+        const double b = block_sum(ke, red);
+        if (threadIdx.x == 0) kin_part[blockIdx.x] = b;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_kinetic_finalize(DevSys s, const double* part, int nb)
+{
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[b];
+    const double t = block_sum(v, red);
+    if (threadIdx.x == 0) s.sc->kinetic = t / kAccUnit;
+}
+
+// ---------------------------------------------------------------- integrator
+// v += dt/2 F/m; r += dt v (wrapped); displacement since the build checked
+// against skin/2.
+template <bool CHECK>
+__global__ __launch_bounds__(kBlock) void k_kick_drift(DevSys s)
+{
+    __shared__ double red[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0;
+    if (i < s.n) {
+        const int ti = s.type[i];
+        const double a = 0.5 * s.dt * s.inv_mass_acc[ti];
+        const double vx = s.vx[i] + a * s.fx[i];
+        const double vy = s.vy[i] + a * s.fy[i];
+        const double vz = s.vz[i] + a * s.fz[i];
+        s.vx[i] = vx;
+        s.vy[i] = vy;
+        s.vz[i] = vz;
+        const double x = wrap_coord(s.x[i] + s.dt * vx, s.L[0], s.invL[0]);
+        const double y = wrap_coord(s.y[i] + s.dt * vy, s.L[1], s.invL[1]);
+        const double z = wrap_coord(s.z[i] + s.dt * vz, s.L[2], s.invL[2]);
+        s.x[i] = x;
+        s.y[i] = y;
+        s.z[i] = z;
+        if (CHECK) {
+            const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
+            const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
+            const double dz = min_image(z - s.zr[i], s.L[2], s.invL[2]);
+            d2 = (dx * dx + dy * dy) + dz * dz;
+            if (!(d2 <= s.half_skin2)) atomicOr(&s.sc->stale, 1);
+        }
+    }
+    if (!CHECK) return;
+    // block maximum, then a device-wide max on the bit pattern (d2 >= 0)
+    double m = d2;
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double b = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        atomicMax((unsigned long long*)&s.sc->max_disp2, (unsigned long long)__double_as_longlong(b));
+    }
+}
+
+// ---------------------------------------------------------------- exports
+__global__ void k_to_user3(DevSys s, const double* ax, const double* ay, const double* az, double* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const size_t u = (size_t)s.id[i] * 3;
+    out[u] = ax[i];
+    out[u + 1] = ay[i];
+    out[u + 2] = az[i];
+}
+
+__global__ void k_kspace_part(DevSys s, double* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const size_t u = (size_t)s.id[i] * 3;
+    const DeviceScalars* sc = s.sc;
+    out[u] = s.fx[i] - (s.fsx[i] - sc->p_corr[0]);
+    out[u + 1] = s.fy[i] - (s.fsy[i] - sc->p_corr[1]);
+    out[u + 2] = s.fz[i] - (s.fsz[i] - sc->p_corr[2]);
+}
+
+// Initial load: user order in, identity cell order (sorted at the first build).
+__global__ void k_from_user(DevSys s, const int32_t* type, const double* pos, const double* vel)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    s.x[i] = pos[3 * (size_t)i];
+    s.y[i] = pos[3 * (size_t)i + 1];
+    s.z[i] = pos[3 * (size_t)i + 2];
+    s.vx[i] = vel ? vel[3 * (size_t)i] : 0.0;
+    s.vy[i] = vel ? vel[3 * (size_t)i + 1] : 0.0;
+    s.vz[i] = vel ? vel[3 * (size_t)i + 2] : 0.0;
+    s.fx[i] = 0.0;
+    s.fy[i] = 0.0;
+    s.fz[i] = 0.0;
+    s.type[i] = type[i];
+    s.id[i] = i;
+    s.inv[i] = i;
+}
+
+inline int blocks_for(int n, int b) { return (n + b - 1) / b; }
+
+SogCoefF to_f32(const SogCoef& g)
+{
+    SogCoefF f{};
+    f.n_exp = g.n_exp;
+    f.chain = g.chain;
+    f.n_poly = g.n_poly;
+    for (int m = 0; m < kMaxExplicit; ++m) {
+        f.a[m] = (float)g.a[m];
+        f.fw[m] = (float)g.fw[m];
+        f.ew[m] = (float)g.ew[m];
+    }
+    for (int n = 0; n < kMaxPoly; ++n) {
+        f.pc[n] = (float)g.pc[n];
+        f.pd[n] = (float)g.pd[n];
+    }
+    return f;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+void launch_set_eval(DeviceScalars* sc, uint64_t eval, hipStream_t st) { k_set_eval<<<1, 1, 0, st>>>(sc, eval); }
+void launch_bump_eval(DeviceScalars* sc, hipStream_t st) { k_bump_eval<<<1, 1, 0, st>>>(sc); }
+void launch_clear_flags(DeviceScalars* sc, hipStream_t st) { k_clear_flags<<<1, 1, 0, st>>>(sc); }
+
+void launch_bin(const DevSys& s, hipStream_t st) { k_bin<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s); }
+void launch_scan(int32_t* count, int32_t* start, int n, hipStream_t st) { k_scan<<<1, 1024, 0, st>>>(count, start, n); }
+void launch_scatter(const DevSys& s, hipStream_t st) { k_scatter<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s); }
+void launch_cell_sort(const DevSys& s, hipStream_t st) { k_cell_sort<<<s.ncell, kBlock, 0, st>>>(s); }
+void launch_gather(const DevSys& s, hipStream_t st) { k_gather<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s); }
+
+void launch_lists(const DevSys& s, hipStream_t st)
+{
+    int capP2 = 1;
+    while (capP2 < s.cap_cand) capP2 <<= 1;
+    const size_t sm = sizeof(int32_t) * (2 * (size_t)capP2 + s.cap_core);
+    if (s.n > 0) k_lists<<<s.n, 64, sm, st>>>(s);
+}
+
+void launch_ksample(const DevSys& s, const KDev& k, hipStream_t st)
+{
+    if (k.n_modes > 0) k_ksample<<<blocks_for(k.n_modes, 64), 64, 0, st>>>(s, k);
+}
+
+void launch_pair(const DevSys& s, const SogCoef& g, bool mixed, bool energy, double* part, int n_blocks,
+                 hipStream_t st)
+{
+    const size_t sm = sizeof(uint32_t) * (size_t)((s.cap_cand + 31) / 32) * kBlock;
+    const SogCoefF gf = to_f32(g);
+    if (n_blocks <= 0) return;
+#define RB_PAIR(M, E, J) k_pair<M, E, J><<<n_blocks, kBlock, sm, st>>>(s, g, gf, part)
+    if (mixed) {
+        if (energy)
+            RB_PAIR(true, true, 1);
+        else
+            RB_PAIR(true, false, 1);
+    } else if (g.chain == 1) {
+        if (energy)
+            RB_PAIR(false, true, 1);
+        else
+            RB_PAIR(false, false, 1);
+    } else {
+        if (energy)
+            RB_PAIR(false, true, 2);
+        else
+            RB_PAIR(false, false, 2);
+    }
+#undef RB_PAIR
+}
+
+void launch_rho(const DevSys& s, const KDev& k, bool mixed, hipStream_t st)
+{
+    if (k.n_modes <= 0 || s.n <= 0) return;
+    dim3 grid(k.n_chunks, (k.n_modes + 63) / 64);
+    if (mixed)
+        k_rho<true><<<grid, kBlock, 0, st>>>(s, k);
+    else
+        k_rho<false><<<grid, kBlock, 0, st>>>(s, k);
+}
+
+void launch_rho_finalize(const DevSys&, const KDev& k, hipStream_t st)
+{
+    if (k.n_modes > 0) k_rho_finalize<<<k.n_modes, 64, 0, st>>>(k);
+}
+
+void launch_finalize(const DevSys& s, const KDev& k, const double* part, int nb, hipStream_t st)
+{
+    k_finalize<<<1, kBlock, 0, st>>>(s, k, part, nb);
+}
+
+void launch_kforce(const DevSys& s, const KDev& k, bool mixed, bool kick, bool energy, double* kin_part,
+                   hipStream_t st)
+{
+    if (s.n <= 0) return;
+    const int nb = blocks_for(s.n, kBlock);
+#define RB_KF(M, K, E) k_kforce<M, K, E><<<nb, kBlock, 0, st>>>(s, k, kin_part)
+    if (mixed) {
+        if (kick) {
+            if (energy) RB_KF(true, true, true); else RB_KF(true, true, false);
+        } else {
+            if (energy) RB_KF(true, false, true); else RB_KF(true, false, false);
+        }
+    } else {
+        if (kick) {
+            if (energy) RB_KF(false, true, true); else RB_KF(false, true, false);
+        } else {
+            if (energy) RB_KF(false, false, true); else RB_KF(false, false, false);
+        }
+    }
+#undef RB_KF
+}
+
+void launch_kinetic_finalize(const DevSys& s, const double* part, int nb, hipStream_t st)
+{
+    k_kinetic_finalize<<<1, kBlock, 0, st>>>(s, part, nb);
+}
+
+void launch_kick_drift(const DevSys& s, bool check, hipStream_t st)
+{
+    if (s.n <= 0) return;
+    if (check)
+        k_kick_drift<true><<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s);
+    else
+        k_kick_drift<false><<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s);
+}
+
+void launch_reset_disp(DeviceScalars* sc, hipStream_t st) { k_reset_disp<<<1, 1, 0, st>>>(sc); }
+
+void launch_to_user3(const DevSys& s, const double* ax, const double* ay, const double* az, double* out,
+                     hipStream_t st)
+{
+    if (s.n > 0) k_to_user3<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, ax, ay, az, out);
+}
+
+void launch_kspace_part(const DevSys& s, double* out, hipStream_t st)
+{
+    if (s.n > 0) k_kspace_part<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, out);
+}
+
+void launch_shell_ranks(const DevSys& s, int32_t* out, int32_t* n_out, hipStream_t st)
+{
+    const size_t sm = sizeof(uint32_t) * (size_t)((s.cap_cand + 31) / 32) * kBlock;
+    if (s.n > 0) k_shell_ranks<<<blocks_for(s.n, kBlock), kBlock, sm, st>>>(s, out, n_out);
+}
+
+void launch_from_user(const DevSys& s, const int32_t* type, const double* pos, const double* vel, hipStream_t st)
+{
+    if (s.n > 0) k_from_user<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, type, pos, vel);
+}
+
+}  // namespace rbsog

@@ -1,0 +1,116 @@
+// Device data of one system and the kernel launchers (defined in kernels.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace rbsog {
+
+// Mode record read with one 64-byte scalar load in the k-space force kernel.
+struct ModeRec {
+    double mx, my, mz;  // integer mode vector as doubles
+    double A, B;        // coef * Im rho, coef * Re rho
+    double coef;        // S/(P_F V k^2), or F^(k)/V for the full sum
+    double e;           // coef * |rho|^2
+    double pad;
+};
+
+// Everything the kernels read or write.  Per-atom arrays are in cell order.
+struct DevSys {
+    int n;
+    int n_species;
+    double L[3], invL[3];
+    double cell_scale[3];  // n_c / L
+    int nc[3];
+    int ncell;
+    double u1024[3];       // 1024 / L: phase in units of 2 pi / 1024
+    double two_pi_L[3];
+    double rc2_list, lo2_list, hi2_list;  // (r_core+skin)^2, (r_core-skin)^2, (r_shell+skin)^2
+    double rc2, rs2;                      // r_core^2, r_shell^2
+    double half_skin2;
+    double dt, coulomb_k;
+    int p_r;
+    int cap_core, cap_cand;
+    uint32_t replica;
+    uint64_t seed;
+    double q[kMaxSpecies];
+    double inv_mass_acc[kMaxSpecies];  // kAccUnit / m
+    double mass[kMaxSpecies];
+
+    // atoms (cell order)
+    double *x, *y, *z, *vx, *vy, *vz;
+    double *fx, *fy, *fz;     // total force of the last evaluation
+    double *fsx, *fsy, *fsz;  // short-range force before the momentum correction
+    double *xr, *yr, *zr;     // positions at the last list build
+    int32_t *type, *id, *inv;
+    // sort scratch
+    double *tx, *ty, *tz, *tvx, *tvy, *tvz;
+    int32_t *ttype, *tid, *cell_of, *slot_of, *order;
+    int32_t *cell_count, *cell_start;
+    // lists
+    int32_t *core_cnt, *core_idx, *cand_cnt, *cand_idx;
+    // pair coefficients [S*S]
+    const PairCoef* pair;
+    DeviceScalars* sc;
+};
+
+struct KDev {
+    int n_modes;          // P_F, or the enumerated count
+    int sampled;          // 1: modes drawn each evaluation from the tables
+    int n_chunks;         // atom chunks of the rho kernel
+    int chunk;            // atoms per chunk
+    int nm;               // Gaussians in the sampling tables
+    double S;
+    double coef_scale;    // S / (P_F V)
+    const double* table;  // sincos table [1024][2]
+    const int32_t* off;
+    const int32_t* len;
+    const double* g0cdf;
+    const double* g2cdf;
+    const double* comp_cdf;
+    int32_t* m;           // [n_modes][3]
+    ModeRec* modes;       // [n_modes]
+    double* rho_part;     // [n_chunks][n_modes_pad][2]
+    int n_modes_pad;
+    double* rho;          // [n_modes][2]
+};
+
+// Block partial sums written by the pair kernel: F (3), u_core, u_shell.
+constexpr int kPairPart = 5;
+
+void launch_set_eval(DeviceScalars* sc, uint64_t eval, hipStream_t st);
+void launch_bump_eval(DeviceScalars* sc, hipStream_t st);
+void launch_clear_flags(DeviceScalars* sc, hipStream_t st);
+
+// cell sort + lists
+void launch_bin(const DevSys& s, hipStream_t st);
+void launch_scan(int32_t* count, int32_t* start, int n, hipStream_t st);
+void launch_scatter(const DevSys& s, hipStream_t st);
+void launch_cell_sort(const DevSys& s, hipStream_t st);
+void launch_gather(const DevSys& s, hipStream_t st);
+void launch_lists(const DevSys& s, hipStream_t st);
+
+// forces
+void launch_ksample(const DevSys& s, const KDev& k, hipStream_t st);
+void launch_pair(const DevSys& s, const SogCoef& sog, bool mixed, bool energy, double* part, int n_blocks,
+                 hipStream_t st);
+void launch_rho(const DevSys& s, const KDev& k, bool mixed, hipStream_t st);
+void launch_rho_finalize(const DevSys& s, const KDev& k, hipStream_t st);
+void launch_finalize(const DevSys& s, const KDev& k, const double* pair_part, int n_pair_blocks, hipStream_t st);
+void launch_kforce(const DevSys& s, const KDev& k, bool mixed, bool kick, bool energy, double* kin_part,
+                   hipStream_t st);
+void launch_kinetic_finalize(const DevSys& s, const double* kin_part, int n_blocks, hipStream_t st);
+
+// integrator
+// check: track the displacement since the build and flag a stale list (skip
+// when a rebuild follows in the same step)
+void launch_kick_drift(const DevSys& s, bool check, hipStream_t st);
+void launch_reset_disp(DeviceScalars* sc, hipStream_t st);
+
+// exports
+void launch_to_user3(const DevSys& s, const double* ax, const double* ay, const double* az, double* out,
+                     hipStream_t st);
+void launch_kspace_part(const DevSys& s, double* out, hipStream_t st);
+void launch_shell_ranks(const DevSys& s, int32_t* out, int32_t* n_out, hipStream_t st);
+void launch_from_user(const DevSys& s, const int32_t* type, const double* pos, const double* vel, hipStream_t st);
+
+}  // namespace rbsog

@@ -1,0 +1,46 @@
+// Host-side planning of the IRBSOG evaluation: SOG split (Section 2.1),
+// k-space sampling tables (eq. 28), kernel coefficient blocks.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace rbsog {
+
+struct SogSplit {
+    double b = 0, s = 0, x_c = 0;
+    int M = 0;
+    std::vector<double> w;  // w[0..M], w[0] adjusted
+};
+
+// b = 2^(1/(2J)) for the smallest J whose eq. (5) bound is <= eps.
+double sog_base(double eps, int* J);
+// Smallest positive x with value and slope continuity (eqs. 8-10), s = 1.
+double sog_root(double b, int M);
+// Full split for the cutoff r_c = r_shell.
+bool sog_split(double eps, double r_shell, SogSplit* out, std::string* err);
+// Kernel coefficients: explicit narrow Gaussians + Taylor block for the wide ones.
+bool sog_kernel_coef(const SogSplit& sp, int J, double r_shell, bool mixed, SogCoef* c, std::string* err);
+
+// Importance-sampling tables of P(k) = k^2 F^(k) / S (eq. 28) as a mixture
+// over (m, d) of products of 1D lattice distributions.
+struct KTables {
+    int nm = 0;
+    std::vector<int32_t> off, len;      // [nm*3]
+    std::vector<double> g0cdf, g2cdf;   // concatenated per (m, d)
+    std::vector<double> comp_cdf;       // [nm*3]
+    double S = 0;
+};
+void build_ktables(const SogSplit& sp, const double box[3], KTables* t);
+
+// Every k != 0 whose narrowest Gaussian factor exp(-s^2 k^2/2) is >= e^-45,
+// with the coefficient F^(k)/V of eq. (23).
+void enumerate_modes(const SogSplit& sp, const double box[3], std::vector<int32_t>* m, std::vector<double>* coef);
+
+// F^(k) of eq. (21).
+double far_hat(const SogSplit& sp, double k);
+
+}  // namespace rbsog

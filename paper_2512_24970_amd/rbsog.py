@@ -1,0 +1,276 @@
+"""ctypes binding of librbsog (C ABI in ``include/rbsog.h``).
+
+Argument marshalling only: every step of the force evaluation runs in the
+library's HIP kernels.  PyTorch provides device memory (tensors whose
+``data_ptr()`` is passed through) and the stream.  Loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbsog.so")
+
+MAX_SPECIES = 8
+MAX_SOG = 512
+FP64 = 0
+MIXED = 1
+
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_OOM", -5: "E_LIST_STALE",
+          -6: "E_NONNEUTRAL", -7: "E_BOX", -8: "E_NONFINITE", -9: "E_CAPACITY"}
+
+
+class RbsogError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Species(C.Structure):
+    _fields_ = [("q", C.c_double), ("mass", C.c_double)]
+
+
+class Pair(C.Structure):
+    _fields_ = [("A", C.c_double), ("sigma", C.c_double), ("rho", C.c_double), ("C", C.c_double),
+                ("D", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int32), ("n_species", C.c_int32), ("box", C.c_double * 3),
+        ("species", Species * MAX_SPECIES), ("pair", Pair * (MAX_SPECIES * MAX_SPECIES)),
+        ("r_core", C.c_double), ("r_shell", C.c_double), ("skin", C.c_double),
+        ("p_r", C.c_int32), ("p_f", C.c_int32), ("sog_eps", C.c_double), ("dt", C.c_double),
+        ("rebuild_every", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
+        ("replica", C.c_uint32), ("flags", C.c_uint32), ("coulomb_k", C.c_double),
+    ]
+
+
+class Energy(C.Structure):
+    _fields_ = [("u_core", C.c_double), ("u_shell", C.c_double), ("u_kspace", C.c_double),
+                ("u_self", C.c_double), ("u_total", C.c_double), ("kinetic", C.c_double),
+                ("p_corr", C.c_double * 3), ("max_disp", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: (list(getattr(self, k)) if k == "p_corr" else getattr(self, k)) for k, _ in self._fields_}
+
+
+ABI = {
+    # name: (restype, argtypes)
+    "rbsog_version": (C.c_char_p, []),
+    "rbsog_sog_params": (C.c_int, [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32]),
+    "rbsog_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "rbsog_destroy": (C.c_int, [C.c_void_p]),
+    "rbsog_last_error": (C.c_char_p, [C.c_void_p]),
+    "rbsog_set_system": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "rbsog_build_lists": (C.c_int, [C.c_void_p]),
+    "rbsog_compute_forces": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(Energy)]),
+    "rbsog_get_force_parts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rbsog_step": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Energy)]),
+    "rbsog_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64), C.c_int]),
+    "rbsog_get_list_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rbsog_get_lists_of": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "rbsog_get_shell_ranks": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "rbsog_get_kmodes": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_double)]),
+    "rbsog_get_rho": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rbsog_get_sog": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_int32), C.c_void_p, C.c_int32]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load librbsog.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2512_24970_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in ABI.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _np_ptr(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data)
+
+
+def make_params(sysp: dict, precision: int = FP64, n_atoms: int | None = None) -> Params:
+    """The ABI parameter block from a workload's physical parameters."""
+    p = Params()
+    sp = sysp["species"]
+    S = len(sp["q"])
+    p.n_atoms = int(n_atoms if n_atoms is not None else sysp.get("n", 0))
+    p.n_species = S
+    for a in range(3):
+        p.box[a] = float(sysp["box"][a])
+    for i in range(S):
+        p.species[i].q = float(sp["q"][i])
+        p.species[i].mass = float(sp["mass"][i])
+        for j in range(S):
+            pr = p.pair[i * MAX_SPECIES + j]
+            pr.A = float(sp["A"][i][j])
+            pr.sigma = float(sp["sigma"][i][j])
+            pr.rho = float(sp["rho"][i][j])
+            pr.C = float(sp["C"][i][j])
+            pr.D = float(sp["D"][i][j])
+    p.r_core = float(sysp["r_core"])
+    p.r_shell = float(sysp["r_shell"])
+    p.skin = float(sysp["skin"])
+    p.p_r = int(sysp["p_r"])
+    p.p_f = int(sysp["p_f"])
+    p.sog_eps = float(sysp.get("sog_eps", 1e-5))
+    p.dt = float(sysp.get("dt", 0.001))
+    p.rebuild_every = int(sysp.get("rebuild_every", 10))
+    p.precision = int(precision)
+    p.seed = int(sysp["seed"])
+    p.replica = int(sysp.get("replica", 0))
+    p.flags = 0
+    p.coulomb_k = float(sysp["coulomb_k"])
+    return p
+
+
+def rbsog_sog_params(eps: float, r_shell: float) -> dict:
+    b, s, xc = C.c_double(), C.c_double(), C.c_double()
+    M = C.c_int32()
+    w = np.zeros(MAX_SOG)
+    rc = lib().rbsog_sog_params(eps, r_shell, C.byref(b), C.byref(s), C.byref(xc), C.byref(M),
+                                w.ctypes.data_as(C.POINTER(C.c_double)), MAX_SOG)
+    if rc != 0:
+        raise RbsogError(rc, "rbsog_sog_params failed")
+    return {"b": b.value, "s": s.value, "x_c": xc.value, "M": M.value, "w": w[: M.value + 1].copy()}
+
+
+class Context:
+    """One rbsog_ctx: one system on one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch  # device memory and streams come from torch
+        self._torch = torch
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = C.c_void_p()
+        self._check(lib().rbsog_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)), "rbsog_create")
+        self._h = h
+        self.n = 0
+        self.params = None
+
+    def _check(self, rc: int, what: str):
+        if rc != 0:
+            msg = ""
+            if getattr(self, "_h", None):
+                m = lib().rbsog_last_error(self._h)
+                msg = m.decode() if m else ""
+            raise RbsogError(rc, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rbsog_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up --------------------------------------------------------------
+    def rbsog_set_system(self, params: Params, types, pos, vel=None):
+        """types/pos/vel: torch tensors on this device (int32 [N], float64 [N,3])."""
+        t = self._torch
+        types = t.as_tensor(types, dtype=t.int32, device=self.torch_device).contiguous()
+        pos = t.as_tensor(pos, dtype=t.float64, device=self.torch_device).contiguous()
+        vptr = None
+        if vel is not None:
+            vel = t.as_tensor(vel, dtype=t.float64, device=self.torch_device).contiguous()
+            vptr = C.c_void_p(vel.data_ptr())
+        params.n_atoms = int(types.numel())
+        self._check(lib().rbsog_set_system(self._h, C.byref(params), C.c_void_p(types.data_ptr()),
+                                           C.c_void_p(pos.data_ptr()), vptr, 1), "rbsog_set_system")
+        self.n = int(types.numel())
+        self.params = params
+
+    def rbsog_build_lists(self):
+        self._check(lib().rbsog_build_lists(self._h), "rbsog_build_lists")
+
+    # -- evaluation ------------------------------------------------------------
+    def rbsog_compute_forces(self, ev: int, want_energy: bool = True):
+        t = self._torch
+        f = t.empty((self.n, 3), dtype=t.float64, device=self.torch_device)
+        e = Energy()
+        self._check(lib().rbsog_compute_forces(self._h, ev, C.c_void_p(f.data_ptr()),
+                                               C.byref(e) if want_energy else None), "rbsog_compute_forces")
+        return f, (e.as_dict() if want_energy else None)
+
+    def rbsog_get_force_parts(self):
+        t = self._torch
+        fs = t.empty((self.n, 3), dtype=t.float64, device=self.torch_device)
+        fk = t.empty((self.n, 3), dtype=t.float64, device=self.torch_device)
+        self._check(lib().rbsog_get_force_parts(self._h, C.c_void_p(fs.data_ptr()), C.c_void_p(fk.data_ptr())),
+                    "rbsog_get_force_parts")
+        return fs, fk
+
+    def rbsog_step(self, n_steps: int, want_energy: bool = True):
+        e = Energy()
+        self._check(lib().rbsog_step(self._h, n_steps, C.byref(e) if want_energy else None), "rbsog_step")
+        return e.as_dict() if want_energy else None
+
+    def rbsog_get_state(self):
+        t = self._torch
+        out = [t.empty((self.n, 3), dtype=t.float64, device=self.torch_device) for _ in range(3)]
+        ev = C.c_uint64()
+        self._check(lib().rbsog_get_state(self._h, *[C.c_void_p(o.data_ptr()) for o in out], C.byref(ev), 1),
+                    "rbsog_get_state")
+        return out[0], out[1], out[2], int(ev.value)
+
+    # -- parity exports (host arrays) ----------------------------------------
+    def rbsog_get_list_counts(self):
+        nc = np.zeros(self.n, np.int32)
+        nk = np.zeros(self.n, np.int32)
+        self._check(lib().rbsog_get_list_counts(self._h, _np_ptr(nc), _np_ptr(nk)), "rbsog_get_list_counts")
+        return nc, nk
+
+    def rbsog_get_lists_of(self, i: int, n_core: int, n_cand: int):
+        core = np.zeros(max(n_core, 1), np.int32)
+        cand = np.zeros(max(n_cand, 1), np.int32)
+        self._check(lib().rbsog_get_lists_of(self._h, i, _np_ptr(core), _np_ptr(cand)), "rbsog_get_lists_of")
+        return core[:n_core], cand[:n_cand]
+
+    def rbsog_get_shell_ranks(self, ev: int):
+        P = max(self.params.p_r, 1)
+        nr = np.zeros(self.n, np.int32)
+        r = np.zeros((self.n, P), np.int32)
+        self._check(lib().rbsog_get_shell_ranks(self._h, ev, _np_ptr(nr), _np_ptr(r)), "rbsog_get_shell_ranks")
+        return nr, r
+
+    def rbsog_get_kmodes(self, ev: int):
+        P = max(self.params.p_f, 1)
+        m = np.zeros((P, 3), np.int32)
+        S = C.c_double()
+        self._check(lib().rbsog_get_kmodes(self._h, ev, _np_ptr(m), C.byref(S)), "rbsog_get_kmodes")
+        return m[: self.params.p_f], S.value
+
+    def rbsog_get_rho(self, n_modes: int):
+        rho = np.zeros((max(n_modes, 1), 2))
+        self._check(lib().rbsog_get_rho(self._h, _np_ptr(rho)), "rbsog_get_rho")
+        return rho[:n_modes]
+
+    def rbsog_get_sog(self) -> dict:
+        b, s, xc = C.c_double(), C.c_double(), C.c_double()
+        M = C.c_int32()
+        w = np.zeros(MAX_SOG)
+        self._check(lib().rbsog_get_sog(self._h, C.byref(b), C.byref(s), C.byref(xc), C.byref(M), _np_ptr(w),
+                                        MAX_SOG), "rbsog_get_sog")
+        return {"b": b.value, "s": s.value, "x_c": xc.value, "M": M.value, "w": w[: M.value + 1].copy()}
