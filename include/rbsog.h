@@ -41,7 +41,7 @@ typedef enum {
     RBSOG_E_STATE = -2,      /* call out of order (e.g. no system set) */
     RBSOG_E_HIP = -3,        /* a HIP runtime call failed */
     RBSOG_E_OOM = -4,        /* device allocation failed */
-    RBSOG_E_LIST_STALE = -5, /* an atom moved more than skin/2 since the list build */
+    RBSOG_E_LIST_STALE = -5, /* reserved: lists are rebuilt before they go stale */
     RBSOG_E_NONNEUTRAL = -6, /* total charge is not zero */
     RBSOG_E_BOX = -7,        /* box shorter than 2 (r_shell + skin) along some axis */
     RBSOG_E_NONFINITE = -8,  /* a non-finite force or position was produced */
@@ -81,6 +81,10 @@ typedef struct {
     uint32_t replica;      /* Philox stream id of this system */
     uint32_t flags;        /* reserved, 0 */
     double coulomb_k;      /* e^2/(4 pi eps0) in eV*Angstrom; <= 0 means 14.399645478 */
+    double t_target;       /* K; with tau_t > 0 a Berendsen thermostat rescales v at the start of
+                              each step by sqrt(1 + dt/tau_t (t_target/T - 1)), T from 3N-3
+                              degrees of freedom; <= 0 = NVE */
+    double tau_t;          /* ps; tau_t = dt rescales to t_target exactly every step */
 } rbsog_params;
 
 typedef struct {
@@ -92,6 +96,7 @@ typedef struct {
     double kinetic;
     double p_corr[3]; /* momentum correction F_corr of eq. (26) that was subtracted */
     double max_disp;  /* largest displacement since the last list build */
+    int64_t n_builds; /* list builds since the system was set */
 } rbsog_energy;
 
 /* Library version string. */
@@ -127,8 +132,7 @@ rbsog_status rbsog_build_lists(rbsog_ctx* ctx);
  * `eval` (shell batches of eq. 25, modes of eq. 28): F = F_core + F*_shell -
  * F_corr + F*_F (eqs. 24-27, 29).  Writes the force in user order to the
  * device array force_out[N][3] if non-NULL.  Energies are returned in e_out
- * if non-NULL (the call then synchronises).  Does not move atoms.  Returns
- * RBSOG_E_LIST_STALE if an atom moved more than skin/2 since the build. */
+ * if non-NULL (the call then synchronises).  Does not move atoms. */
 rbsog_status rbsog_compute_forces(rbsog_ctx* ctx, uint64_t eval, double* force_out, rbsog_energy* e_out);
 
 /* Force parts of the last evaluation in user order into device arrays
@@ -136,11 +140,11 @@ rbsog_status rbsog_compute_forces(rbsog_ctx* ctx, uint64_t eval, double* force_o
  * (eqs. 24-25), and the k-space part (eq. 29). */
 rbsog_status rbsog_get_force_parts(rbsog_ctx* ctx, double* f_short, double* f_kspace);
 
-/* n_steps velocity-Verlet steps: kick, drift (wrap), rebuild when the step
- * number is a multiple of rebuild_every, force with eval = step number,
- * kick.  The per-step work is captured once in a HIP graph and replayed.
- * e_last (may be NULL) receives the energies of the last step; the call
- * synchronises at the end. */
+/* n_steps velocity-Verlet steps: kick, drift (wrap), list rebuild when the
+ * step number is a multiple of rebuild_every or an atom has moved more than
+ * skin/2 since the last build (decided on the device), force with eval =
+ * step number, kick.  e_last (may be NULL) receives the energies of the last
+ * step; the call synchronises at the end. */
 rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last);
 
 /* Current positions, velocities, forces (user order, [N][3]) and the eval
@@ -150,13 +154,37 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last);
 rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* force, uint64_t* eval,
                              int ptrs_on_device);
 
+/* ---- kernel timing ------------------------------------------------------ */
+
+/* Kernel phases timed with HIP events on the context's stream. */
+typedef enum {
+    RBSOG_PHASE_BUILD = 0,     /* cell sort + list build */
+    RBSOG_PHASE_KSAMPLE = 1,   /* mode draws of eq. (28) */
+    RBSOG_PHASE_PAIR = 2,      /* shell batch + pair forces, eqs. (15), (24)-(25) */
+    RBSOG_PHASE_RHO = 3,       /* structure factors, eq. (22) */
+    RBSOG_PHASE_REDUCE = 4,    /* fixed-order reductions: rho, momentum correction, energies */
+    RBSOG_PHASE_KFORCE = 5,    /* k-space force, eq. (29), + closing half kick */
+    RBSOG_PHASE_INTEGRATE = 6, /* opening half kick + drift */
+    RBSOG_N_PHASES = 7
+} rbsog_phase;
+
+/* Turn per-phase event timing on or off (off by default).  While on, every
+ * phase launched on the stream is bracketed by two HIP events. */
+rbsog_status rbsog_profile_enable(rbsog_ctx* ctx, int enable);
+/* Synchronise, add up the timed phases since the last read and reset:
+ * ms[RBSOG_N_PHASES] total milliseconds, launches[RBSOG_N_PHASES] counts. */
+rbsog_status rbsog_profile_read(rbsog_ctx* ctx, double* ms, int64_t* launches);
+
 /* ---- parity exports (host outputs, synchronise) ----------------------- */
 
 /* Core and candidate list sizes n_core[N], n_cand[N]. */
 rbsog_status rbsog_get_list_counts(rbsog_ctx* ctx, int32_t* n_core, int32_t* n_cand);
-/* Lists of atom i: core neighbour ids ascending, candidate ids ascending. */
+/* Lists of atom i: core neighbour ids ascending; candidate ids in the
+ * canonical order the shell ranks refer to: by cell (grid of
+ * floor(L/(r_shell+skin)) cells per axis, one if below 3; cell index
+ * floor(x n_c/L) with x fastest), then by id. */
 rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_t* cand);
-/* Shell batch ranks (indices into the id-ascending candidate list, ascending)
+/* Shell batch ranks (indices into the ordered candidate list, ascending)
  * of every atom for evaluation `eval`: ranks[N][P_R]; unused slots are -1.
  * n_ranks[N] gets min(P_R, n_cand). */
 rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ranks, int32_t* ranks);

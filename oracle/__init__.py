@@ -45,6 +45,7 @@ class Params(C.Structure):
         ("A", C.c_double * (MAXS * MAXS)), ("sig", C.c_double * (MAXS * MAXS)),
         ("rho", C.c_double * (MAXS * MAXS)), ("C", C.c_double * (MAXS * MAXS)),
         ("D", C.c_double * (MAXS * MAXS)),
+        ("t_target", C.c_double), ("tau_t", C.c_double),
     ]
 
 
@@ -161,6 +162,8 @@ def make_params(sysp: dict) -> Params:
     p.coulomb_k = float(sysp["coulomb_k"])
     p.dt = float(sysp.get("dt", 0.001))
     p.sog_eps = float(sysp.get("sog_eps", 1e-5))
+    p.t_target = float(sysp.get("t_target", 0.0))
+    p.tau_t = float(sysp.get("tau_t", 0.0))
     for i in range(S):
         p.q[i] = float(sp["q"][i])
         p.mass[i] = float(sp["mass"][i])

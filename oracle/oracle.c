@@ -454,6 +454,9 @@ struct orc_ctx {
     int32_t* core;
     int32_t* cand_off;
     int32_t* cand;
+    double* ref;  /* [n][3] positions at the last list build */
+    int nc[3];    /* cell grid that orders shell candidates */
+    double cscale[3];
     orc_ktab kt;
     int have_kt;
 };
@@ -507,7 +510,37 @@ orc_ctx* orc_create(const orc_params* p, int32_t n, const int32_t* type,
         if (vel) memcpy(c->vel, vel, sizeof(double) * 3 * n);
     }
     for (int i = 0; i < n; ++i) wrap(&c->p, c->pos + 3 * i);
+    /* cells of side >= r_shell + skin; fewer than 3 along an axis -> one */
+    for (int a = 0; a < 3; ++a) {
+        int nc = (int)floor(c->p.box[a] / (c->p.r_shell + c->p.skin + 1e-9));
+        if (nc < 3) nc = 1;
+        c->nc[a] = nc;
+        c->cscale[a] = (double)nc / c->p.box[a];
+    }
     return c;
+}
+
+/* Cell of a wrapped position: floor(x n_c / L) per axis, x fastest. */
+static int cell_of(const orc_ctx* c, const double* x)
+{
+    int cc[3];
+    for (int a = 0; a < 3; ++a) {
+        int v = (int)(x[a] * c->cscale[a]);
+        cc[a] = v < 0 ? 0 : (v >= c->nc[a] ? c->nc[a] - 1 : v);
+    }
+    return (cc[2] * c->nc[1] + cc[1]) * c->nc[0] + cc[0];
+}
+
+typedef struct {
+    int cell, j;
+} cand_key;
+
+static int cand_cmp(const void* a, const void* b)
+{
+    const cand_key* x = (const cand_key*)a;
+    const cand_key* y = (const cand_key*)b;
+    if (x->cell != y->cell) return x->cell < y->cell ? -1 : 1;
+    return x->j < y->j ? -1 : (x->j > y->j ? 1 : 0);
 }
 
 void orc_destroy(orc_ctx* c)
@@ -521,11 +554,14 @@ void orc_destroy(orc_ctx* c)
     free(c->core);
     free(c->cand_off);
     free(c->cand);
+    free(c->ref);
     if (c->have_kt) ktab_free(&c->kt);
     free(c);
 }
 
-/* Core and candidate lists of atom i by a scan over every other atom. */
+/* Core and candidate lists of atom i by a scan over every other atom.
+ * Candidates are ordered by (cell of the candidate, atom index), the order
+ * that shell ranks refer to. */
 static void scan_atom(const orc_ctx* c, int i, int32_t* core, int* nc, int32_t* cand, int* nk, int count_only)
 {
     const orc_params* p = &c->p;
@@ -552,6 +588,16 @@ static void scan_atom(const orc_ctx* c, int i, int32_t* core, int* nc, int32_t* 
     }
     *nc = a;
     *nk = k;
+    if (!count_only && k > 1) {
+        cand_key* key = (cand_key*)malloc(sizeof(cand_key) * k);
+        for (int t = 0; t < k; ++t) {
+            key[t].cell = cell_of(c, c->pos + 3 * cand[t]);
+            key[t].j = cand[t];
+        }
+        qsort(key, k, sizeof(cand_key), cand_cmp);
+        for (int t = 0; t < k; ++t) cand[t] = key[t].j;
+        free(key);
+    }
 }
 
 int orc_build_lists(orc_ctx* c)
@@ -585,6 +631,9 @@ int orc_build_lists(orc_ctx* c)
     }
     free(nc);
     free(nk);
+    free(c->ref);
+    c->ref = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    if (n > 0) memcpy(c->ref, c->pos, sizeof(double) * 3 * n);
     return 0;
 }
 
@@ -959,7 +1008,8 @@ int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
 }
 
 /* Velocity Verlet: v += dt/2 F/m; r += dt v (wrapped); lists rebuilt when the
- * step number is a multiple of rebuild_every; F at eval index = step number;
+ * step number is a multiple of rebuild_every or when some atom has moved more
+ * than skin/2 since the last build; F at eval index = step number;
  * v += dt/2 F/m. */
 int orc_vv_steps(orc_ctx* c, int32_t n_steps, orc_energy* e_last)
 {
@@ -969,18 +1019,37 @@ int orc_vv_steps(orc_ctx* c, int32_t n_steps, orc_energy* e_last)
     double* f = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
     orc_energy e;
     memset(&e, 0, sizeof(e));
+    int thermo = p->t_target > 0.0 && p->tau_t > 0.0 && n > 1;
     for (int k = 0; k < n_steps; ++k) {
         uint64_t step = c->eval + 1;
+        /* Berendsen (weak coupling): v *= sqrt(1 + (dt/tau)(T0/T - 1)), with
+         * T from the current kinetic energy and 3N - 3 degrees of freedom */
+        double lam = 1.0;
+        if (thermo) {
+            double ke = kinetic(c);
+            if (ke > 0.0) {
+                double T = 2.0 * ke / ((3.0 * n - 3.0) * 8.617333262e-5);
+                double l2 = 1.0 + p->dt / p->tau_t * (p->t_target / T - 1.0);
+                lam = l2 > 0.0 ? sqrt(l2) : 0.0;
+            }
+        }
         for (int i = 0; i < n; ++i) {
             double a = 0.5 * p->dt * ORC_ACC / p->mass[c->type[i]];
             for (int x = 0; x < 3; ++x) {
-                c->vel[3 * i + x] += a * c->frc[3 * i + x];
+                c->vel[3 * i + x] = lam * c->vel[3 * i + x] + a * c->frc[3 * i + x];
                 c->pos[3 * i + x] += p->dt * c->vel[3 * i + x];
             }
             wrap(p, c->pos + 3 * i);
         }
         int every = p->rebuild_every > 0 ? p->rebuild_every : 1;
-        if (step % (uint64_t)every == 0) orc_build_lists(c);
+        int moved = 0;
+        double half2 = 0.25 * p->skin * p->skin;
+        for (int i = 0; i < n && !moved; ++i) {
+            double d[3];
+            min_image(p, c->pos + 3 * i, c->ref + 3 * i, d);
+            if (norm2(d) > half2) moved = 1;
+        }
+        if (step % (uint64_t)every == 0 || moved) orc_build_lists(c);
         orc_forces(c, step, f, &e);
         for (int i = 0; i < n; ++i) {
             double a = 0.5 * p->dt * ORC_ACC / p->mass[c->type[i]];

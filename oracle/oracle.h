@@ -55,6 +55,8 @@ typedef struct {
     double rho[ORC_MAXS * ORC_MAXS];
     double C[ORC_MAXS * ORC_MAXS];
     double D[ORC_MAXS * ORC_MAXS];
+    double t_target;        /* K; Berendsen thermostat when t_target > 0 and tau_t > 0 */
+    double tau_t;           /* ps */
 } orc_params;
 
 typedef struct {
@@ -103,7 +105,9 @@ orc_ctx* orc_create(const orc_params* p, int32_t n, const int32_t* type,
                     const double* pos, const double* vel);
 void orc_destroy(orc_ctx* c);
 /* Brute-force core list (r < r_core + skin) and shell candidates
- * (r_core - skin <= r < r_shell + skin), candidates in ascending atom index. */
+ * (r_core - skin <= r < r_shell + skin).  Candidates are ordered by (cell,
+ * atom index) on a grid of n_c = floor(L / (r_shell + skin)) cells per axis
+ * (one cell if that is below 3), cell = floor(x n_c / L) with x fastest. */
 int orc_build_lists(orc_ctx* c);
 int orc_list_counts(const orc_ctx* c, int32_t* n_core, int32_t* n_cand);
 int orc_list_atom(const orc_ctx* c, int32_t i, int32_t* core, int32_t* cand);
@@ -121,7 +125,8 @@ int orc_forces_kspace(orc_ctx* c, uint64_t eval, double* force, double* u_k);
 /* Structure factors rho(k) (eq. 22) for the given integer modes. */
 void orc_rho(const orc_ctx* c, int32_t n_modes, const int32_t* m, double* rho /*[n][2]*/);
 /* Velocity-Verlet steps; lists are rebuilt when the step number is a multiple
- * of rebuild_every.  Returns the eval index of the last force evaluation. */
+ * of rebuild_every or when an atom has moved more than skin/2 since the last
+ * build.  Returns the eval index of the last force evaluation. */
 int orc_vv_steps(orc_ctx* c, int32_t n_steps, orc_energy* e_last);
 void orc_get_state(const orc_ctx* c, double* pos, double* vel, double* force, uint64_t* eval);
 

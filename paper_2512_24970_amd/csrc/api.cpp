@@ -87,14 +87,61 @@ struct rbsog_ctx {
 
     // device memory
     DBuf atoms, sortbuf, cells, lists_core, lists_cand, counts, pair_tab, scalars;
-    DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, kin_part, export_tmp;
+    DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, kin_part, export_tmp, snap;
+
+    // phase timing
+    bool profiling = false;
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    int open_phase = -1;
+    hipEvent_t open_a = nullptr;
+
+    hipEvent_t take_event()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+        return e;
+    }
+    void begin(int phase)
+    {
+        if (!profiling) return;
+        open_phase = phase;
+        open_a = take_event();
+        (void)hipEventRecord(open_a, stream);
+    }
+    void end()
+    {
+        if (!profiling || open_phase < 0) return;
+        hipEvent_t b = take_event();
+        (void)hipEventRecord(b, stream);
+        recs.push_back(Rec{open_phase, open_a, b});
+        open_phase = -1;
+        open_a = nullptr;
+    }
 
     // step graph
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_kind = -1;  // 0: plain step, 1: step with rebuild
 
-    ~rbsog_ctx() { drop_graph(); }
+    ~rbsog_ctx()
+    {
+        drop_graph();
+        for (auto& r : recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
 
     void drop_graph()
     {
@@ -153,6 +200,8 @@ void validate(const rbsog_params* p)
     require(p->dt > 0.0, RBSOG_E_ARG, "dt <= 0");
     require(p->rebuild_every >= 1, RBSOG_E_ARG, "rebuild_every < 1");
     require(p->precision == RBSOG_FP64 || p->precision == RBSOG_MIXED, RBSOG_E_ARG, "unknown precision");
+    require(!(p->t_target > 0.0 && p->tau_t > 0.0) || p->tau_t >= p->dt, RBSOG_E_ARG, "tau_t < dt");
+    require(!(p->t_target > 0.0 && p->tau_t > 0.0) || p->n_atoms >= 2, RBSOG_E_ARG, "thermostat needs 2+ atoms");
     for (int a = 0; a < 3; ++a) {
         require(std::isfinite(p->box[a]) && p->box[a] > 0.0, RBSOG_E_ARG, "box must be positive");
         require(p->box[a] >= 2.0 * (p->r_shell + p->skin), RBSOG_E_BOX,
@@ -186,16 +235,13 @@ void plan_lists(rbsog_ctx* c, int cap_core, int cap_cand)
     s.cand_idx = c->lists_cand.as<int32_t>();
 }
 
-void enqueue_build(rbsog_ctx* c)
+void enqueue_build(rbsog_ctx* c, bool gate)
 {
     DevSys& s = c->s;
     if (s.n <= 0) return;
-    launch_bin(s, c->stream);
-    launch_scan(s.cell_count, s.cell_start, s.ncell, c->stream);
-    launch_scatter(s, c->stream);
-    launch_cell_sort(s, c->stream);
-    launch_gather(s, c->stream);
-    launch_lists(s, c->stream);
+    c->begin(RBSOG_PHASE_BUILD);
+    launch_build(s, gate, c->stream);
+    c->end();
 }
 
 DeviceScalars read_scalars(rbsog_ctx* c)
@@ -206,43 +252,98 @@ DeviceScalars read_scalars(rbsog_ctx* c)
     return h;
 }
 
+// Per-atom state (cell order) and device scalars at the start of a step call,
+// for a restart after a list overflow.
+void snapshot(rbsog_ctx* c, bool save)
+{
+    DevSys& s = c->s;
+    const size_t N = (size_t)std::max(s.n, 1);
+    const size_t bytes = N * (9 * sizeof(double) + 3 * sizeof(int32_t)) + sizeof(DeviceScalars);
+    if (save && c->snap.bytes < bytes) c->snap.alloc(bytes);
+    double* d = c->snap.as<double>();
+    double* arr[9] = {s.x, s.y, s.z, s.vx, s.vy, s.vz, s.fx, s.fy, s.fz};
+    int32_t* iar[3] = {s.type, s.id, s.inv};
+    int32_t* ip = reinterpret_cast<int32_t*>(d + 9 * N);
+    auto cp = [&](void* dst, const void* src, size_t b) {
+        HIP_OK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, c->stream));
+    };
+    for (int q = 0; q < 9; ++q) {
+        if (save)
+            cp(d + q * N, arr[q], sizeof(double) * s.n);
+        else
+            cp(arr[q], d + q * N, sizeof(double) * s.n);
+    }
+    for (int q = 0; q < 3; ++q) {
+        if (save)
+            cp(ip + q * N, iar[q], sizeof(int32_t) * s.n);
+        else
+            cp(iar[q], ip + q * N, sizeof(int32_t) * s.n);
+    }
+    void* sc_copy = ip + 3 * N;
+    if (save)
+        cp(sc_copy, s.sc, sizeof(DeviceScalars));
+    else
+        cp(s.sc, sc_copy, sizeof(DeviceScalars));
+}
+
+// Grow list capacities from the true counts of the last build.
+void grow_lists(rbsog_ctx* c)
+{
+    const DeviceScalars h = read_scalars(c);
+    const int mc = h.max_core, mk = h.max_cand;
+    const int cap_core = std::max(c->s.cap_core, round_up(mc + mc / 4 + 8, 32));
+    const int cap_cand = std::max(c->s.cap_cand, round_up(mk + mk / 4 + 8, 32));
+    require(cap_cand <= 4096 && cap_core <= 4096, RBSOG_E_CAPACITY, "neighbour list capacity above 4096");
+    c->drop_graph();
+    plan_lists(c, cap_core, cap_cand);
+}
+
 // Build; if a list or cell capacity overflowed, grow the lists and build again.
 void build_checked(rbsog_ctx* c)
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
         launch_clear_flags(c->s.sc, c->stream);
-        enqueue_build(c);
+        enqueue_build(c, false);
         DeviceScalars h = read_scalars(c);
         if (h.overflow == 0) return;
         if (h.overflow & 2) throw Error(RBSOG_E_CAPACITY, "a cell holds more than 2048 atoms");
-        // grow from the true maxima
-        std::vector<int32_t> nc(c->s.n), nk(c->s.n);
-        HIP_OK(hipMemcpy(nc.data(), c->s.core_cnt, sizeof(int32_t) * c->s.n, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(nk.data(), c->s.cand_cnt, sizeof(int32_t) * c->s.n, hipMemcpyDeviceToHost));
-        const int mc = *std::max_element(nc.begin(), nc.end());
-        const int mk = *std::max_element(nk.begin(), nk.end());
-        const int cap_core = std::max(c->s.cap_core, round_up(mc + mc / 4 + 8, 32));
-        const int cap_cand = std::max(c->s.cap_cand, round_up(mk + mk / 4 + 8, 32));
-        require(cap_cand <= 4096 && cap_core <= 4096, RBSOG_E_CAPACITY, "neighbour list capacity above 4096");
-        c->drop_graph();
-        plan_lists(c, cap_core, cap_cand);
+        if (h.overflow & 4) {
+            // a cell's stencil did not fit in LDS: larger stencil, then per-atom lists
+            c->s.list_mode = std::min(2, c->s.list_mode + 1);
+            c->drop_graph();
+            continue;
+        }
+        grow_lists(c);
     }
     throw Error(RBSOG_E_CAPACITY, "list capacity did not converge");
 }
 
 void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
 {
+    const bool ke = energy || (kick && c->s.thermo_c > 0.0);
     DevSys& s = c->s;
     KDev& k = c->k;
     hipStream_t st = c->stream;
     if (s.n <= 0) return;
-    if (k.sampled) launch_ksample(s, k, st);
+    if (k.sampled) {
+        c->begin(RBSOG_PHASE_KSAMPLE);
+        launch_ksample(s, k, st);
+        c->end();
+    }
+    c->begin(RBSOG_PHASE_PAIR);
     launch_pair(s, c->coef, c->mixed, energy, c->pair_part.as<double>(), c->n_pair_blocks, st);
+    c->end();
+    c->begin(RBSOG_PHASE_RHO);
     launch_rho(s, k, c->mixed, st);
+    c->end();
+    c->begin(RBSOG_PHASE_REDUCE);
     launch_rho_finalize(s, k, st);
     launch_finalize(s, k, c->pair_part.as<double>(), c->n_pair_blocks, st);
-    launch_kforce(s, k, c->mixed, kick, energy, c->kin_part.as<double>(), st);
-    if (energy) launch_kinetic_finalize(s, c->kin_part.as<double>(), c->n_kin_blocks, st);
+    c->end();
+    c->begin(RBSOG_PHASE_KFORCE);
+    launch_kforce(s, k, c->mixed, kick, ke, c->kin_part.as<double>(), st);
+    c->end();
+    if (ke) launch_kinetic_finalize(s, c->kin_part.as<double>(), c->n_kin_blocks, st);
 }
 
 void fill_energy(rbsog_ctx* c, const DeviceScalars& h, rbsog_energy* e)
@@ -255,23 +356,24 @@ void fill_energy(rbsog_ctx* c, const DeviceScalars& h, rbsog_energy* e)
     e->kinetic = h.kinetic;
     for (int a = 0; a < 3; ++a) e->p_corr[a] = h.p_corr[a];
     e->max_disp = std::sqrt(h.max_disp2);
+    e->n_builds = h.n_builds;
 }
 
 void check_flags(const DeviceScalars& h)
 {
     if (h.overflow) throw Error(RBSOG_E_CAPACITY, "list capacity exceeded during the step loop");
-    if (h.stale) throw Error(RBSOG_E_LIST_STALE, "an atom moved more than skin/2 since the last list build");
 }
 
-// One step on the stream: kick + drift, rebuild if due, forces, kick.
-void enqueue_step(rbsog_ctx* c, bool rebuild, bool energy)
+// One step on the stream: kick + drift, rebuild if scheduled or if an atom
+// moved more than skin/2 since the last build (decided on the device),
+// forces, kick.
+void enqueue_step(rbsog_ctx* c, bool scheduled, bool energy)
 {
+    c->begin(RBSOG_PHASE_INTEGRATE);
     launch_bump_eval(c->s.sc, c->stream);
-    launch_kick_drift(c->s, !rebuild, c->stream);
-    if (rebuild) {
-        enqueue_build(c);
-        launch_reset_disp(c->s.sc, c->stream);
-    }
+    launch_kick_drift(c->s, scheduled, c->stream);
+    c->end();
+    enqueue_build(c, true);
     enqueue_forces(c, energy, true);
 }
 
@@ -354,6 +456,10 @@ void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, c
     s.half_skin2 = 0.25 * p->skin * p->skin;
     s.dt = p->dt;
     s.coulomb_k = c->prm.coulomb_k;
+    const bool thermo = p->t_target > 0.0 && p->tau_t > 0.0;
+    s.thermo_c = thermo ? p->dt / p->tau_t : 0.0;
+    s.t_target = thermo ? p->t_target : 0.0;
+    s.dof_kb = (3.0 * n - 3.0) * 8.617333262e-5;
     s.p_r = p->p_r;
     s.replica = p->replica;
     s.seed = p->seed;
@@ -376,12 +482,12 @@ void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, c
         s.id = ip + N;
         s.inv = ip + 2 * N;
     }
-    c->sortbuf.alloc(N * (6 * sizeof(double) + 5 * sizeof(int32_t)));
+    c->sortbuf.alloc(N * (9 * sizeof(double) + 5 * sizeof(int32_t)));
     {
         double* d = c->sortbuf.as<double>();
-        double** slots[] = {&s.tx, &s.ty, &s.tz, &s.tvx, &s.tvy, &s.tvz};
-        for (int t = 0; t < 6; ++t) *slots[t] = d + t * N;
-        int32_t* ip = reinterpret_cast<int32_t*>(d + 6 * N);
+        double** slots[] = {&s.tx, &s.ty, &s.tz, &s.tvx, &s.tvy, &s.tvz, &s.tfx, &s.tfy, &s.tfz};
+        for (int t = 0; t < 9; ++t) *slots[t] = d + t * N;
+        int32_t* ip = reinterpret_cast<int32_t*>(d + 9 * N);
         s.ttype = ip;
         s.tid = ip + N;
         s.cell_of = ip + 2 * N;
@@ -423,9 +529,18 @@ void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, c
     const double vc = 4.0 / 3.0 * kPi * rcl * rcl * rcl;
     const double lo3 = lo > 0.0 ? lo * lo * lo : 0.0;
     const double vk = 4.0 / 3.0 * kPi * (hi * hi * hi - lo3);
-    const int cap_core = std::min(std::max(round_up((int)(1.35 * vc * rho_n) + 24, 32), 32), std::max(32, round_up(n, 32)));
-    const int cap_cand = std::min(std::max(round_up((int)(1.35 * vk * rho_n) + 24, 32), 32), std::max(32, round_up(n, 32)));
+    // room for local densities well above the mean (melting lattices, clusters);
+    // the step loop grows the lists if they still overflow
+    const int cap_core = std::min(std::max(round_up((int)(1.8 * vc * rho_n) + 32, 32), 32), std::max(32, round_up(n, 32)));
+    const int cap_cand = std::min(std::max(round_up((int)(1.5 * vk * rho_n) + 32, 32), 32), std::max(32, round_up(n, 32)));
     plan_lists(c, cap_core, cap_cand);
+    {
+        double cell_vol = 1.0;
+        for (int a = 0; a < 3; ++a) cell_vol *= p->box[a] / s.nc[a];
+        const int ncell_st = (s.nc[0] >= 3 ? 3 : 1) * (s.nc[1] >= 3 ? 3 : 1) * (s.nc[2] >= 3 ? 3 : 1);
+        const double stencil = std::min<double>(n, ncell_st * cell_vol * rho_n);
+        s.list_mode = stencil * 1.3 + 64 <= 2048 ? 0 : (stencil * 1.3 + 64 <= 4096 ? 1 : 2);
+    }
 
     // k-space
     KDev& k = c->k;
@@ -645,17 +760,38 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
             ctx->forces_valid = true;
         }
         launch_set_eval(ctx->s.sc, ctx->eval, ctx->stream);
-        const int every = ctx->prm.rebuild_every;
-        for (int k = 0; k < n_steps; ++k) {
-            const uint64_t step = ctx->eval + 1 + (uint64_t)k;
-            const bool rebuild = step % (uint64_t)every == 0;
-            const bool energy = e_last != nullptr && k == n_steps - 1;
-            enqueue_step(ctx, rebuild, energy);
+        if (ctx->s.thermo_c > 0.0) {
+            // velocity factor of the first step from the current velocities
+            launch_kinetic(ctx->s, ctx->kin_part.as<double>(), ctx->stream);
+            launch_kinetic_finalize(ctx->s, ctx->kin_part.as<double>(), ctx->n_kin_blocks, ctx->stream);
         }
-        ctx->eval += (uint64_t)n_steps;
-        DeviceScalars h = read_scalars(ctx);
-        if (e_last) fill_energy(ctx, h, e_last);
-        check_flags(h);
+        const int every = ctx->prm.rebuild_every;
+        // a list overflow inside the loop restarts the call from a snapshot
+        // with larger lists
+        for (int attempt = 0;; ++attempt) {
+            snapshot(ctx, true);
+            for (int k = 0; k < n_steps; ++k) {
+                const uint64_t step = ctx->eval + 1 + (uint64_t)k;
+                const bool scheduled = step % (uint64_t)every == 0;
+                const bool energy = e_last != nullptr && k == n_steps - 1;
+                enqueue_step(ctx, scheduled, energy);
+            }
+            DeviceScalars h = read_scalars(ctx);
+            if (h.overflow == 0) {
+                ctx->eval += (uint64_t)n_steps;
+                if (e_last) fill_energy(ctx, h, e_last);
+                check_flags(h);
+                return;
+            }
+            require(attempt < 4 && (h.overflow & 2) == 0, RBSOG_E_CAPACITY, "list capacity exceeded in the step loop");
+            if (h.overflow & 4)
+                ctx->s.list_mode = std::min(2, ctx->s.list_mode + 1);
+            else
+                grow_lists(ctx);
+            snapshot(ctx, false);
+            build_checked(ctx);
+            launch_set_eval(ctx->s.sc, ctx->eval, ctx->stream);
+        }
     });
 }
 
@@ -679,6 +815,33 @@ rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* f
             }
         }
         if (eval) *eval = ctx->eval;
+    });
+}
+
+rbsog_status rbsog_profile_enable(rbsog_ctx* ctx, int enable)
+{
+    return guarded(ctx, [&] { ctx->profiling = enable != 0; });
+}
+
+rbsog_status rbsog_profile_read(rbsog_ctx* ctx, double* ms, int64_t* launches)
+{
+    return guarded(ctx, [&] {
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        double acc[RBSOG_N_PHASES] = {0};
+        int64_t cnt[RBSOG_N_PHASES] = {0};
+        for (auto& r : ctx->recs) {
+            float t = 0.f;
+            HIP_OK(hipEventElapsedTime(&t, r.a, r.b));
+            acc[r.phase] += t;
+            cnt[r.phase] += 1;
+            ctx->pool.push_back(r.a);
+            ctx->pool.push_back(r.b);
+        }
+        ctx->recs.clear();
+        for (int q = 0; q < RBSOG_N_PHASES; ++q) {
+            if (ms) ms[q] = acc[q];
+            if (launches) launches[q] = cnt[q];
+        }
     });
 }
 

@@ -126,9 +126,13 @@ struct DeviceScalars {
     double u_core, u_shell, u_kspace, kinetic;
     double max_disp2;     // largest squared displacement since the build
     int32_t overflow;     // list or cell capacity exceeded
-    int32_t stale;        // an atom moved more than skin/2
+    int32_t rebuild;      // the lists are rebuilt in this step
     int32_t nonfinite;
     int32_t pad;
+    int64_t n_builds;     // list builds since the system was set
+    int32_t max_core;     // largest core / candidate list seen (true sizes)
+    int32_t max_cand;
+    double vscale;        // thermostat velocity factor for the next step
 };
 
 }  // namespace rbsog

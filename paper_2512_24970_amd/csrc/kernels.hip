@@ -1,10 +1,10 @@
 // HIP kernels of the IRBSOG evaluation for gfx950 (CDNA4, wave64).
 //
-// Layout: atoms in cell order as structure-of-arrays FP64; the core list is
-// stored in 64-atom tiles (entry k of the 64 atoms of a tile contiguous) so a
-// wavefront reads it coalesced; shell candidates are stored row-major per atom
-// in ascending atom id, so the shell batch of eq. (25) maps ranks to atoms the
-// same way on any device.  Every reduction runs in a fixed order, so FP64
+// Layout: atoms in (cell, id) order as structure-of-arrays FP64; the core
+// list is stored in 64-atom tiles (entry k of the 64 atoms of a tile
+// contiguous) so a wavefront reads it coalesced; shell candidates are stored
+// row-major per atom in (cell, id) order, the canonical order that the ranks
+// of the shell batch of eq. (25) refer to.  Every reduction runs in a fixed order, so FP64
 // results are bit-reproducible run to run.
 #include <hip/hip_runtime.h>
 
@@ -19,6 +19,12 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kCellCap = 2048;  // atoms per cell the in-cell sort can hold
+
+// Build kernels take `gate`: when set they run only if the rebuild flag is up
+// (set by the drift kernel), so a step can enqueue them unconditionally.
+#define RB_GATE                                        \
+    if (gate && s.sc->rebuild == 0) return;
+
 
 __device__ inline double wave_sum(double v)
 {
@@ -67,18 +73,26 @@ __device__ inline int cell_coord(double v, double scale, int nc)
 // ---------------------------------------------------------------- scalars
 __global__ void k_set_eval(DeviceScalars* sc, uint64_t eval) { sc->eval = eval; }
 __global__ void k_bump_eval(DeviceScalars* sc) { sc->eval += 1; }
-__global__ void k_reset_disp(DeviceScalars* sc) { sc->max_disp2 = 0.0; }
+// Closes a build: lower the flag, restart the displacement tracking.
+__global__ void k_build_done(DevSys s, int gate)
+{
+    RB_GATE
+    s.sc->rebuild = 0;
+    s.sc->max_disp2 = 0.0;
+    s.sc->n_builds += 1;
+}
 __global__ void k_clear_flags(DeviceScalars* sc)
 {
     sc->overflow = 0;
-    sc->stale = 0;
+    sc->rebuild = 0;
     sc->nonfinite = 0;
     sc->max_disp2 = 0.0;
 }
 
 // ---------------------------------------------------------------- cell sort
-__global__ void k_bin(DevSys s)
+__global__ void k_bin(DevSys s, int gate)
 {
+    RB_GATE
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const double x = wrap_coord(s.x[i], s.L[0], s.invL[0]);
@@ -96,8 +110,12 @@ __global__ void k_bin(DevSys s)
 }
 
 // Exclusive scan of count[0..n) into start[0..n], one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(int32_t* count, int32_t* start, int n)
+__global__ __launch_bounds__(1024) void k_scan(DevSys s, int gate)
 {
+    RB_GATE
+    int32_t* count = s.cell_count;
+    int32_t* start = s.cell_start;
+    const int n = s.ncell;
     __shared__ int32_t part[1024];
     const int t = threadIdx.x;
     const int per = (n + 1023) / 1024;
@@ -121,8 +139,9 @@ __global__ __launch_bounds__(1024) void k_scan(int32_t* count, int32_t* start, i
     if (t == 1023) start[n] = part[1023];
 }
 
-__global__ void k_scatter(DevSys s)
+__global__ void k_scatter(DevSys s, int gate)
 {
+    RB_GATE
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int d = s.cell_start[s.cell_of[i]] + s.slot_of[i];
@@ -132,13 +151,17 @@ __global__ void k_scatter(DevSys s)
     s.tvx[d] = s.vx[i];
     s.tvy[d] = s.vy[i];
     s.tvz[d] = s.vz[i];
+    s.tfx[d] = s.fx[i];
+    s.tfy[d] = s.fy[i];
+    s.tfz[d] = s.fz[i];
     s.ttype[d] = s.type[i];
     s.tid[d] = s.id[i];
 }
 
 // Within each cell, order atoms by id so the cell order is deterministic.
-__global__ __launch_bounds__(kBlock) void k_cell_sort(DevSys s)
+__global__ __launch_bounds__(kBlock) void k_cell_sort(DevSys s, int gate)
 {
+    RB_GATE
     __shared__ int32_t key[kCellCap];
     __shared__ int32_t val[kCellCap];
     const int c = blockIdx.x;
@@ -179,8 +202,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(DevSys s)
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) s.order[beg + t] = val[t];
 }
 
-__global__ void k_gather(DevSys s)
+__global__ void k_gather(DevSys s, int gate)
 {
+    RB_GATE
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= s.n) return;
     const int o = s.order[t];
@@ -194,6 +218,9 @@ __global__ void k_gather(DevSys s)
     s.vx[t] = s.tvx[o];
     s.vy[t] = s.tvy[o];
     s.vz[t] = s.tvz[o];
+    s.fx[t] = s.tfx[o];
+    s.fy[t] = s.tfy[o];
+    s.fz[t] = s.tfz[o];
     s.type[t] = s.ttype[o];
     const int id = s.tid[o];
     s.id[t] = id;
@@ -201,11 +228,13 @@ __global__ void k_gather(DevSys s)
 }
 
 // ---------------------------------------------------------------- lists
-// One 64-thread block per atom: the lanes sweep the neighbouring cells,
-// compact core and candidate entries with ballots, then sort the candidates
-// by atom id (bitonic network in LDS).
-__global__ __launch_bounds__(64) void k_lists(DevSys s)
+// Fallback for stencils that do not fit in LDS.  One 64-thread block per
+// atom: the lanes sweep the neighbouring cells, compact core and candidate
+// entries with ballots, then sort the candidates into cell order (bitonic
+// network in LDS).
+__global__ __launch_bounds__(64) void k_lists(DevSys s, int gate)
 {
+    RB_GATE
     extern __shared__ int32_t lsm[];
     const int capP2 = [&] {
         int p = 1;
@@ -254,7 +283,7 @@ __global__ __launch_bounds__(64) void k_lists(DevSys s)
                     if (is_cand) {
                         const int slot = ncand + __popcll(mk & below);
                         if (slot < s.cap_cand) {
-                            ckey[slot] = s.id[j];
+                            ckey[slot] = j;  // cell order = canonical candidate order
                             cval[slot] = j;
                         }
                     }
@@ -267,7 +296,11 @@ __global__ __launch_bounds__(64) void k_lists(DevSys s)
     if (lane == 0) {
         s.core_cnt[i] = ncore;
         s.cand_cnt[i] = ncand;
-        if (ncore > s.cap_core || ncand > s.cap_cand) atomicOr(&s.sc->overflow, 1);
+        if (ncore > s.cap_core || ncand > s.cap_cand) {
+            atomicOr(&s.sc->overflow, 1);
+            atomicMax(&s.sc->max_core, ncore);
+            atomicMax(&s.sc->max_cand, ncand);
+        }
     }
     const int nk = min(ncand, s.cap_cand);
     const int nc = min(ncore, s.cap_core);
@@ -301,6 +334,135 @@ __global__ __launch_bounds__(64) void k_lists(DevSys s)
     for (int t = lane; t < nk; t += 64) crow[t] = cval[t];
     int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
     for (int t = lane; t < nc; t += 64) ctile[(size_t)t * 64] = core[t];
+}
+
+// One 512-thread block per cell.  The atoms of the (up to) 27 neighbouring
+// cells are staged in LDS with the cells in ascending index; as atoms are
+// stored in (cell, id) order, the stencil is then in the canonical candidate
+// order and each atom of the cell, sweeping it with one wavefront and
+// ballot compaction, writes its candidates already ordered.
+constexpr int kListBlock = 512;
+
+template <int CAP>
+__global__ __launch_bounds__(kListBlock) void k_lists_cell(DevSys s, int gate)
+{
+    RB_GATE
+    __shared__ int32_t val[CAP];
+    __shared__ double px[CAP];
+    __shared__ double py[CAP];
+    __shared__ double pz[CAP];
+    __shared__ int cq[27];
+    __shared__ int cb[27];
+    __shared__ int coff[28];
+    const int c = blockIdx.x;
+    const int cx0 = c % s.nc[0];
+    const int cy0 = (c / s.nc[0]) % s.nc[1];
+    const int cz0 = c / (s.nc[0] * s.nc[1]);
+    // stencil: offsets -1..1 along axes with at least 3 cells, else 0
+    const int n0 = s.nc[0] >= 3 ? 3 : 1, n1 = s.nc[1] >= 3 ? 3 : 1, n2 = s.nc[2] >= 3 ? 3 : 1;
+    const int nst = n0 * n1 * n2;
+    if (threadIdx.x < nst) {
+        const int k = threadIdx.x;
+        const int ox = (n0 == 3) ? k % 3 - 1 : 0;
+        const int oy = (n1 == 3) ? (k / n0) % 3 - 1 : 0;
+        const int oz = (n2 == 3) ? k / (n0 * n1) - 1 : 0;
+        const int cx = (cx0 + ox + s.nc[0]) % s.nc[0];
+        const int cy = (cy0 + oy + s.nc[1]) % s.nc[1];
+        const int cz = (cz0 + oz + s.nc[2]) % s.nc[2];
+        cq[k] = (cz * s.nc[1] + cy) * s.nc[0] + cx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // ascending cell index
+        for (int a = 1; a < nst; ++a) {
+            const int v = cq[a];
+            int b = a - 1;
+            while (b >= 0 && cq[b] > v) {
+                cq[b + 1] = cq[b];
+                --b;
+            }
+            cq[b + 1] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nst) {
+        const int q = cq[threadIdx.x];
+        const int b = s.cell_start[q];
+        cb[threadIdx.x] = b;
+        coff[threadIdx.x + 1] = s.cell_start[q + 1] - b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        coff[0] = 0;
+        for (int k = 0; k < nst; ++k) coff[k + 1] += coff[k];
+    }
+    __syncthreads();
+    const int total = coff[nst];
+    if (total > CAP) {
+        // the stencil does not fit: the host moves to a larger stencil or the per-atom kernel
+        if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 4);
+        return;
+    }
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int k = 0;
+        while (coff[k + 1] <= t) ++k;
+        const int j = cb[k] + (t - coff[k]);
+        val[t] = j;
+        px[t] = s.x[j];
+        py[t] = s.y[j];
+        pz[t] = s.z[j];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int beg0 = s.cell_start[c];
+    const int cnt0 = s.cell_start[c + 1] - beg0;
+    for (int a = wave; a < cnt0; a += kListBlock / 64) {
+        const int i = beg0 + a;
+        const double xi = s.x[i], yi = s.y[i], zi = s.z[i];
+        int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
+        int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
+        int ncore = 0, ncand = 0;
+        for (int base = 0; base < total; base += 64) {
+            const int t = base + lane;
+            bool is_core = false, is_cand = false;
+            int j = -1;
+            if (t < total) {
+                j = val[t];
+                if (j != i) {
+                    const double dx = min_image(xi - px[t], s.L[0], s.invL[0]);
+                    const double dy = min_image(yi - py[t], s.L[1], s.invL[1]);
+                    const double dz = min_image(zi - pz[t], s.L[2], s.invL[2]);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    is_core = r2 < s.rc2_list;
+                    is_cand = r2 >= s.lo2_list && r2 < s.hi2_list;
+                }
+            }
+            const uint64_t mc = __ballot(is_core);
+            const uint64_t mk = __ballot(is_cand);
+            if (is_core) {
+                const int slot = ncore + __popcll(mc & below);
+                if (slot < s.cap_core) ctile[(size_t)slot * 64] = j;
+            }
+            if (is_cand) {
+                const int slot = ncand + __popcll(mk & below);
+                if (slot < s.cap_cand) crow[slot] = j;
+            }
+            ncore += __popcll(mc);
+            ncand += __popcll(mk);
+        }
+        if (lane == 0) {
+            s.core_cnt[i] = ncore;
+            s.cand_cnt[i] = ncand;
+            // same-address atomics serialise: only overflowing atoms report
+            if (ncore > s.cap_core || ncand > s.cap_cand) {
+                atomicOr(&s.sc->overflow, 1);
+                atomicMax(&s.sc->max_core, ncore);
+                atomicMax(&s.sc->max_cand, ncand);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------- pair forces
@@ -440,29 +602,52 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
     if (i < s.n) {
         const double xi = s.x[i], yi = s.y[i], zi = s.z[i];
         const int ti = s.type[i];
+        // pair force scalar for r2 of species pair (ti, tj)
+        auto pair_f = [&](int tj, double r2, double& u) -> double {
+            const int t = ti * S + tj;
+            if (MIXED) {
+                float uf = 0.f;
+                const double f = (double)pair_scalar_f32<ENERGY>(pcf[t], gf, (float)r2, uf);
+                u = uf;
+                return f;
+            }
+            return pair_scalar_f64<J, ENERGY>(pc[t], g, r2, u);
+        };
+        // Neighbours are fetched kU at a time (indices, then positions and
+        // types) before any arithmetic, so the gathers overlap; the sums still
+        // run in list order.
+        constexpr int kU = 4;
         // core sum, eq. (24)
         const int nc = min(s.core_cnt[i], s.cap_core);
         const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
-        for (int k = 0; k < nc; ++k) {
-            const int j = ctile[(size_t)k * 64];
-            const double dx = min_image(xi - s.x[j], s.L[0], s.invL[0]);
-            const double dy = min_image(yi - s.y[j], s.L[1], s.invL[1]);
-            const double dz = min_image(zi - s.z[j], s.L[2], s.invL[2]);
-            const double r2 = (dx * dx + dy * dy) + dz * dz;
-            if (r2 < s.rc2) {
-                const int t = ti * S + s.type[j];
-                double f, u = 0.0;
-                if (MIXED) {
-                    float uf = 0.f;
-                    f = (double)pair_scalar_f32<ENERGY>(pcf[t], gf, (float)r2, uf);
-                    u = uf;
-                } else {
-                    f = pair_scalar_f64<J, ENERGY>(pc[t], g, r2, u);
+        for (int k0 = 0; k0 < nc; k0 += kU) {
+            int jj[kU];
+            double X[kU], Y[kU], Z[kU];
+            int T[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) jj[u] = (k0 + u < nc) ? ctile[(size_t)(k0 + u) * 64] : i;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                X[u] = s.x[jj[u]];
+                Y[u] = s.y[jj[u]];
+                Z[u] = s.z[jj[u]];
+                T[u] = s.type[jj[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (k0 + u >= nc) break;
+                const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
+                const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
+                const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (r2 < s.rc2) {
+                    double uu = 0.0;
+                    const double f = pair_f(T[u], r2, uu);
+                    Fx = fma(f, dx, Fx);
+                    Fy = fma(f, dy, Fy);
+                    Fz = fma(f, dz, Fz);
+                    if (ENERGY) Uc += 0.5 * uu;
                 }
-                Fx = fma(f, dx, Fx);
-                Fy = fma(f, dy, Fy);
-                Fz = fma(f, dz, Fz);
-                if (ENERGY) Uc += 0.5 * u;
             }
         }
         // shell batch, eq. (25)
@@ -475,27 +660,38 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
         PhiloxStream st(s.seed, (uint32_t)s.id[i], (uint32_t)s.sc->eval, kTagShell, s.replica);
         if (!take_all) fm.clear(n);
         double Sx = 0.0, Sy = 0.0, Sz = 0.0, Su = 0.0;
-        for (int k = 0; k < cnt; ++k) {
-            const int e = take_all ? k : fm.step(st, n - s.p_r + k);
-            const int j = crow[e];
-            const double dx = min_image(xi - s.x[j], s.L[0], s.invL[0]);
-            const double dy = min_image(yi - s.y[j], s.L[1], s.invL[1]);
-            const double dz = min_image(zi - s.z[j], s.L[2], s.invL[2]);
-            const double r2 = (dx * dx + dy * dy) + dz * dz;
-            if (r2 >= s.rc2 && r2 < s.rs2) {
-                const int t = ti * S + s.type[j];
-                double f, u = 0.0;
-                if (MIXED) {
-                    float uf = 0.f;
-                    f = (double)pair_scalar_f32<ENERGY>(pcf[t], gf, (float)r2, uf);
-                    u = uf;
-                } else {
-                    f = pair_scalar_f64<J, ENERGY>(pc[t], g, r2, u);
+        for (int k0 = 0; k0 < cnt; k0 += kU) {
+            int jj[kU];
+            double X[kU], Y[kU], Z[kU];
+            int T[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                int e = 0;
+                if (k0 + u < cnt) e = take_all ? k0 + u : fm.step(st, n - s.p_r + k0 + u);
+                jj[u] = (k0 + u < cnt) ? crow[e] : i;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                X[u] = s.x[jj[u]];
+                Y[u] = s.y[jj[u]];
+                Z[u] = s.z[jj[u]];
+                T[u] = s.type[jj[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (k0 + u >= cnt) break;
+                const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
+                const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
+                const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (r2 >= s.rc2 && r2 < s.rs2) {
+                    double uu = 0.0;
+                    const double f = pair_f(T[u], r2, uu);
+                    Sx = fma(f, dx, Sx);
+                    Sy = fma(f, dy, Sy);
+                    Sz = fma(f, dz, Sz);
+                    if (ENERGY) Su += 0.5 * uu;
                 }
-                Sx = fma(f, dx, Sx);
-                Sy = fma(f, dy, Sy);
-                Sz = fma(f, dz, Sz);
-                if (ENERGY) Su += 0.5 * u;
             }
         }
         Fx = fma(wgt, Sx, Fx);
@@ -783,24 +979,49 @@ __global__ __launch_bounds__(kBlock) void k_kinetic_finalize(DevSys s, const dou
     double v = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[b];
     const double t = block_sum(v, red);
-    if (threadIdx.x == 0) s.sc->kinetic = t / kAccUnit;
+    if (threadIdx.x == 0) {
+        const double ke = t / kAccUnit;
+        s.sc->kinetic = ke;
+        double f = 1.0;
+        if (s.thermo_c > 0.0 && ke > 0.0) {
+            // Berendsen: lambda^2 = 1 + (dt/tau)(T0/T - 1)
+            const double T = 2.0 * ke / s.dof_kb;
+            const double l2 = 1.0 + s.thermo_c * (s.t_target / T - 1.0);
+            f = l2 > 0.0 ? sqrt(l2) : 0.0;
+        }
+        s.sc->vscale = f;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_kinetic(DevSys s, double* part)
+{
+    __shared__ double red[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double ke = 0.0;
+    if (i < s.n) {
+        const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+        ke = 0.5 * s.mass[s.type[i]] * (vx * vx + vy * vy + vz * vz);
+    }
+    const double b = block_sum(ke, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
 // ---------------------------------------------------------------- integrator
-// v += dt/2 F/m; r += dt v (wrapped); displacement since the build checked
-// against skin/2.
-template <bool CHECK>
-__global__ __launch_bounds__(kBlock) void k_kick_drift(DevSys s)
+// v += dt/2 F/m; r += dt v (wrapped); the displacement since the build is
+// checked against skin/2, which raises the rebuild flag, as does a build
+// scheduled for this step.
+__global__ __launch_bounds__(kBlock) void k_kick_drift(DevSys s, int scheduled)
 {
     __shared__ double red[4];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double d2 = 0.0;
+    const double lam = s.thermo_c > 0.0 ? s.sc->vscale : 1.0;
     if (i < s.n) {
         const int ti = s.type[i];
         const double a = 0.5 * s.dt * s.inv_mass_acc[ti];
-        const double vx = s.vx[i] + a * s.fx[i];
-        const double vy = s.vy[i] + a * s.fy[i];
-        const double vz = s.vz[i] + a * s.fz[i];
+        const double vx = lam * s.vx[i] + a * s.fx[i];
+        const double vy = lam * s.vy[i] + a * s.fy[i];
+        const double vz = lam * s.vz[i] + a * s.fz[i];
         s.vx[i] = vx;
         s.vy[i] = vy;
         s.vz[i] = vz;
@@ -810,15 +1031,15 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(DevSys s)
         s.x[i] = x;
         s.y[i] = y;
         s.z[i] = z;
-        if (CHECK) {
-            const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
-            const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
-            const double dz = min_image(z - s.zr[i], s.L[2], s.invL[2]);
-            d2 = (dx * dx + dy * dy) + dz * dz;
-            if (!(d2 <= s.half_skin2)) atomicOr(&s.sc->stale, 1);
-        }
+        const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
+        const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
+        const double dz = min_image(z - s.zr[i], s.L[2], s.invL[2]);
+        d2 = (dx * dx + dy * dy) + dz * dz;
     }
-    if (!CHECK) return;
+    // one flag update per wavefront that saw a displacement above skin/2
+    const uint64_t moved = __ballot(!(d2 <= s.half_skin2));
+    if (moved && (threadIdx.x & 63) == 0) atomicOr(&s.sc->rebuild, 1);
+    if (scheduled && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&s.sc->rebuild, 1);
     // block maximum, then a device-wide max on the bit pattern (d2 >= 0)
     double m = d2;
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
@@ -898,18 +1119,26 @@ void launch_set_eval(DeviceScalars* sc, uint64_t eval, hipStream_t st) { k_set_e
 void launch_bump_eval(DeviceScalars* sc, hipStream_t st) { k_bump_eval<<<1, 1, 0, st>>>(sc); }
 void launch_clear_flags(DeviceScalars* sc, hipStream_t st) { k_clear_flags<<<1, 1, 0, st>>>(sc); }
 
-void launch_bin(const DevSys& s, hipStream_t st) { k_bin<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s); }
-void launch_scan(int32_t* count, int32_t* start, int n, hipStream_t st) { k_scan<<<1, 1024, 0, st>>>(count, start, n); }
-void launch_scatter(const DevSys& s, hipStream_t st) { k_scatter<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s); }
-void launch_cell_sort(const DevSys& s, hipStream_t st) { k_cell_sort<<<s.ncell, kBlock, 0, st>>>(s); }
-void launch_gather(const DevSys& s, hipStream_t st) { k_gather<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s); }
-
-void launch_lists(const DevSys& s, hipStream_t st)
+void launch_build(const DevSys& s, bool gate, hipStream_t st)
 {
-    int capP2 = 1;
-    while (capP2 < s.cap_cand) capP2 <<= 1;
-    const size_t sm = sizeof(int32_t) * (2 * (size_t)capP2 + s.cap_core);
-    if (s.n > 0) k_lists<<<s.n, 64, sm, st>>>(s);
+    if (s.n <= 0) return;
+    const int g = gate ? 1 : 0;
+    k_bin<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, g);
+    k_scan<<<1, 1024, 0, st>>>(s, g);
+    k_scatter<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, g);
+    k_cell_sort<<<s.ncell, kBlock, 0, st>>>(s, g);
+    k_gather<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, g);
+    if (s.list_mode == 0) {
+        k_lists_cell<2048><<<s.ncell, kListBlock, 0, st>>>(s, g);
+    } else if (s.list_mode == 1) {
+        k_lists_cell<4096><<<s.ncell, kListBlock, 0, st>>>(s, g);
+    } else {
+        int capP2 = 1;
+        while (capP2 < s.cap_cand) capP2 <<= 1;
+        const size_t sm = sizeof(int32_t) * (2 * (size_t)capP2 + s.cap_core);
+        k_lists<<<s.n, 64, sm, st>>>(s, g);
+    }
+    k_build_done<<<1, 1, 0, st>>>(s, g);
 }
 
 void launch_ksample(const DevSys& s, const KDev& k, hipStream_t st)
@@ -990,16 +1219,15 @@ void launch_kinetic_finalize(const DevSys& s, const double* part, int nb, hipStr
     k_kinetic_finalize<<<1, kBlock, 0, st>>>(s, part, nb);
 }
 
-void launch_kick_drift(const DevSys& s, bool check, hipStream_t st)
+void launch_kinetic(const DevSys& s, double* part, hipStream_t st)
 {
-    if (s.n <= 0) return;
-    if (check)
-        k_kick_drift<true><<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s);
-    else
-        k_kick_drift<false><<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s);
+    if (s.n > 0) k_kinetic<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, part);
 }
 
-void launch_reset_disp(DeviceScalars* sc, hipStream_t st) { k_reset_disp<<<1, 1, 0, st>>>(sc); }
+void launch_kick_drift(const DevSys& s, bool scheduled, hipStream_t st)
+{
+    if (s.n > 0) k_kick_drift<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, scheduled ? 1 : 0);
+}
 
 void launch_to_user3(const DevSys& s, const double* ax, const double* ay, const double* az, double* out,
                      hipStream_t st)

@@ -28,8 +28,12 @@ struct DevSys {
     double rc2, rs2;                      // r_core^2, r_shell^2
     double half_skin2;
     double dt, coulomb_k;
+    double thermo_c;       // dt / tau_t (0: no thermostat)
+    double t_target;
+    double dof_kb;         // (3N - 3) k_B
     int p_r;
     int cap_core, cap_cand;
+    int list_mode;         // 0/1: per-cell list kernel with a 2048/4096-atom stencil, 2: per-atom kernel
     uint32_t replica;
     uint64_t seed;
     double q[kMaxSpecies];
@@ -43,7 +47,7 @@ struct DevSys {
     double *xr, *yr, *zr;     // positions at the last list build
     int32_t *type, *id, *inv;
     // sort scratch
-    double *tx, *ty, *tz, *tvx, *tvy, *tvz;
+    double *tx, *ty, *tz, *tvx, *tvy, *tvz, *tfx, *tfy, *tfz;
     int32_t *ttype, *tid, *cell_of, *slot_of, *order;
     int32_t *cell_count, *cell_start;
     // lists
@@ -81,13 +85,9 @@ void launch_set_eval(DeviceScalars* sc, uint64_t eval, hipStream_t st);
 void launch_bump_eval(DeviceScalars* sc, hipStream_t st);
 void launch_clear_flags(DeviceScalars* sc, hipStream_t st);
 
-// cell sort + lists
-void launch_bin(const DevSys& s, hipStream_t st);
-void launch_scan(int32_t* count, int32_t* start, int n, hipStream_t st);
-void launch_scatter(const DevSys& s, hipStream_t st);
-void launch_cell_sort(const DevSys& s, hipStream_t st);
-void launch_gather(const DevSys& s, hipStream_t st);
-void launch_lists(const DevSys& s, hipStream_t st);
+// cell sort + lists; with gate the kernels run only when the device-side
+// rebuild flag is up (and lower it at the end)
+void launch_build(const DevSys& s, bool gate, hipStream_t st);
 
 // forces
 void launch_ksample(const DevSys& s, const KDev& k, hipStream_t st);
@@ -98,13 +98,15 @@ void launch_rho_finalize(const DevSys& s, const KDev& k, hipStream_t st);
 void launch_finalize(const DevSys& s, const KDev& k, const double* pair_part, int n_pair_blocks, hipStream_t st);
 void launch_kforce(const DevSys& s, const KDev& k, bool mixed, bool kick, bool energy, double* kin_part,
                    hipStream_t st);
+// kinetic energy from the partials; with a thermostat also the velocity
+// factor of the next step
 void launch_kinetic_finalize(const DevSys& s, const double* kin_part, int n_blocks, hipStream_t st);
+// kinetic-energy partials of the current velocities
+void launch_kinetic(const DevSys& s, double* kin_part, hipStream_t st);
 
-// integrator
-// check: track the displacement since the build and flag a stale list (skip
-// when a rebuild follows in the same step)
-void launch_kick_drift(const DevSys& s, bool check, hipStream_t st);
-void launch_reset_disp(DeviceScalars* sc, hipStream_t st);
+// integrator: opening half kick and drift; raises the rebuild flag when an
+// atom moved more than skin/2 since the build, or when `scheduled`
+void launch_kick_drift(const DevSys& s, bool scheduled, hipStream_t st);
 
 // exports
 void launch_to_user3(const DevSys& s, const double* ax, const double* ay, const double* az, double* out,

@@ -47,13 +47,14 @@ class Params(C.Structure):
         ("p_r", C.c_int32), ("p_f", C.c_int32), ("sog_eps", C.c_double), ("dt", C.c_double),
         ("rebuild_every", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
         ("replica", C.c_uint32), ("flags", C.c_uint32), ("coulomb_k", C.c_double),
+        ("t_target", C.c_double), ("tau_t", C.c_double),
     ]
 
 
 class Energy(C.Structure):
     _fields_ = [("u_core", C.c_double), ("u_shell", C.c_double), ("u_kspace", C.c_double),
                 ("u_self", C.c_double), ("u_total", C.c_double), ("kinetic", C.c_double),
-                ("p_corr", C.c_double * 3), ("max_disp", C.c_double)]
+                ("p_corr", C.c_double * 3), ("max_disp", C.c_double), ("n_builds", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: (list(getattr(self, k)) if k == "p_corr" else getattr(self, k)) for k, _ in self._fields_}
@@ -73,6 +74,8 @@ ABI = {
     "rbsog_get_force_parts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbsog_step": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Energy)]),
     "rbsog_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64), C.c_int]),
+    "rbsog_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "rbsog_profile_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbsog_get_list_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbsog_get_lists_of": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "rbsog_get_shell_ranks": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
@@ -136,6 +139,8 @@ def make_params(sysp: dict, precision: int = FP64, n_atoms: int | None = None) -
     p.replica = int(sysp.get("replica", 0))
     p.flags = 0
     p.coulomb_k = float(sysp["coulomb_k"])
+    p.t_target = float(sysp.get("t_target", 0.0))
+    p.tau_t = float(sysp.get("tau_t", 0.0))
     return p
 
 
@@ -234,6 +239,18 @@ class Context:
         self._check(lib().rbsog_get_state(self._h, *[C.c_void_p(o.data_ptr()) for o in out], C.byref(ev), 1),
                     "rbsog_get_state")
         return out[0], out[1], out[2], int(ev.value)
+
+    # -- kernel timing -----------------------------------------------------------
+    PHASES = ["build", "ksample", "pair", "rho", "reduce", "kforce", "integrate"]
+
+    def rbsog_profile_enable(self, on: bool = True):
+        self._check(lib().rbsog_profile_enable(self._h, 1 if on else 0), "rbsog_profile_enable")
+
+    def rbsog_profile_read(self) -> dict:
+        ms = np.zeros(len(self.PHASES))
+        cnt = np.zeros(len(self.PHASES), np.int64)
+        self._check(lib().rbsog_profile_read(self._h, _np_ptr(ms), _np_ptr(cnt)), "rbsog_profile_read")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PHASES)}
 
     # -- parity exports (host arrays) ----------------------------------------
     def rbsog_get_list_counts(self):

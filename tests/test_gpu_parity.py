@@ -226,3 +226,92 @@ def test_invalid_inputs_rejected(nacl512):
         ctx.rbsog_set_system(p, torch.as_tensor(nacl512["types"], device=dev),
                              torch.as_tensor(nacl512["pos"], device=dev))
     assert e.value.code == -7
+
+
+def test_displacement_triggered_rebuilds_match_oracle(nacl512):
+    """skin = 0.2 A and no scheduled rebuild within the run: lists are rebuilt
+    whenever an ion has moved more than skin/2, on both sides, and the
+    trajectory still tracks the oracle."""
+    _say("case: vv 15 steps skin 0.2 nacl_512")
+    ctx, sysp = gpu_system(nacl512, skin=0.2, rebuild_every=1000)
+    osys = oracle_system(nacl512, sysp)
+    ctx.rbsog_compute_forces(0, want_energy=False)
+    osys.forces(0)
+    eg = ctx.rbsog_step(15)
+    osys.vv_steps(15)
+    assert eg["n_builds"] >= 3
+    pg, vg, fg, _ = ctx.rbsog_get_state()
+    po, vo, fo, _ = osys.state()
+    L = np.array(sysp["box"])
+    d = pg.cpu().numpy() - po
+    d -= L * np.rint(d / L)
+    assert np.abs(d).max() < 1e-9
+    assert rel_rms(fg.cpu().numpy(), fo) < 1e-9
+
+
+def _licl_small():
+    n = 8000
+    return W.config("licl_nacl_1m", n=n, box=329.0 * (n / 1e6) ** (1 / 3))
+
+
+@pytest.mark.parametrize("precision,tol", [(R.FP64, TOL64), (R.MIXED, TOL32)])
+def test_forces_licl_nacl_four_species(precision, tol):
+    """50:50 LiCl-NaCl with four species slots (Table 3), 8000 ions at the
+    density of the 10^6-ion workload."""
+    _say(f"case: forces licl_nacl 8000 precision {precision}")
+    _force_parity(_licl_small(), precision, tol, evs=(0, 3))
+
+
+@pytest.mark.parametrize("precision,tol", [(R.FP64, TOL64), (R.MIXED, TOL32)])
+def test_full_size_sampled_atoms(precision, tol):
+    """The 10^6-ion workload at its full size, in the launch configuration the
+    benchmark uses: modes bit-exact, rho(k) of every mode, and the short-range
+    and k-space forces of 300 sampled ions against the oracle computing them
+    one by one."""
+    _say(f"case: full size licl_nacl_1m precision {precision}")
+    cfg = W.config("licl_nacl_1m")
+    ev = 2
+    ctx, sysp = gpu_system(cfg, precision)
+    fg, eg = ctx.rbsog_compute_forces(ev)
+    fs_g, fk_g = ctx.rbsog_get_force_parts()
+    mg, Sg = ctx.rbsog_get_kmodes(ev)
+    rho_g = ctx.rbsog_get_rho(len(mg))
+    osys = oracle_system(cfg, sysp)
+    mo, So = O.kmodes(osys.params, ev)
+    assert np.array_equal(mg, mo)
+    rho_o = osys.rho(mo)
+    e_rho = rel_rms(rho_g, rho_o)
+    _say(f"  rho rel rms {e_rho:.2e}")
+    assert e_rho <= tol
+    sel = np.sort(np.random.default_rng(7).choice(len(cfg["types"]), 300, replace=False)).astype(np.int32)
+    fs_o = osys.forces_short_atoms(ev, sel)
+    V = float(np.prod(sysp["box"]))
+    fk_o = osys.kforce_atoms(mo, rho_o, So / (len(mo) * V), sel)
+    e_s = rel_rms(fs_g.cpu().numpy()[sel], fs_o)
+    e_k = rel_rms(fk_g.cpu().numpy()[sel], fk_o)
+    _say(f"  sampled atoms: short {e_s:.2e} kspace {e_k:.2e}")
+    assert e_s <= tol
+    assert e_k <= tol
+    # total = short - p_corr + kspace, and the correction is the mean short force
+    f_tot = fg.cpu().numpy()
+    assert rel_rms(f_tot[sel], fs_o - np.array(eg["p_corr"]) + fk_o) <= tol
+    assert np.abs(f_tot.sum(0)).max() < 1e-6 * np.abs(f_tot).max() * len(f_tot) ** 0.5
+
+
+def test_velocity_verlet_with_thermostat_matches_oracle(nacl512):
+    """Berendsen rescaling (tau = dt) at the start of every step, on both sides."""
+    _say("case: vv 12 steps thermostat nacl_512")
+    ctx, sysp = gpu_system(nacl512, t_target=1200.0, tau_t=0.001)
+    osys = oracle_system(nacl512, sysp)
+    ctx.rbsog_compute_forces(0, want_energy=False)
+    osys.forces(0)
+    eg = ctx.rbsog_step(12)
+    eo = osys.vv_steps(12)
+    pg, vg, fg, _ = ctx.rbsog_get_state()
+    po, vo, fo, _ = osys.state()
+    L = np.array(sysp["box"])
+    d = pg.cpu().numpy() - po
+    d -= L * np.rint(d / L)
+    assert np.abs(d).max() < 1e-9
+    assert rel_rms(vg.cpu().numpy(), vo) < 1e-9
+    assert eg["kinetic"] == pytest.approx(eo["kinetic"], rel=1e-9)

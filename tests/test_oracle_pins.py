@@ -520,3 +520,21 @@ def test_bmh_terms_match_lattice_sums(term):
     assert E == pytest.approx(ref, rel=1e-12)
     assert e["u_kspace"] == 0.0
     assert np.abs(f).max() < 1e-12 * max(1.0, abs(ref))
+
+
+def test_berendsen_thermostat_holds_temperature():
+    """With the random-batch force on, NVE heats the melt (the estimator's
+    noise adds kinetic energy every step); a Berendsen thermostat with
+    tau = dt rescales to the target at the start of each step and keeps T
+    near it.  Temperature from 3N - 3 degrees of freedom."""
+    cfg = W.config("nacl_small")
+    n = len(cfg["types"])
+    T0 = cfg["T"]
+    temps = {}
+    for label, over in [("nve", {}), ("nvt", dict(t_target=T0, tau_t=0.001))]:
+        s = O.System(dict(cfg["sys"], **over), cfg["types"], cfg["pos"], cfg["vel"])
+        s.forces(0)
+        e = s.vv_steps(40)
+        temps[label] = 2 * e["kinetic"] / ((3 * n - 3) * W.KB)
+    assert abs(temps["nvt"] - T0) / T0 < 0.05
+    assert temps["nve"] > temps["nvt"]
