@@ -82,17 +82,79 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int):
             "energy": e1, "energy_warm": e0, "T_end": T, "force0": f0}
 
 
-def roofline(precision: str, res: dict, n: int, p_f: int) -> dict:
-    kernels = {k: v for k, v in res["phases"].items() if k in ("kforce", "rho") and v[1] > 0}
-    name = max(kernels, key=lambda k: kernels[k][0])
-    ms, launches = kernels[name]
+# Pair-kernel model (per atom, FMA = 2): a distance test is 17 flops (three
+# differences, minimum image 9, r^2 5); an evaluated pair is 123 flops, with
+# an FP64 exp counted as 20 and an rsqrt as 8 (two exps, five squarings, six
+# Gaussian weights, a 13-term polynomial, BMH terms, force assembly).
+FLOPS_TEST, FLOPS_PAIR = 17, 123
+
+KERNEL_OF_PHASE = {"pair": "k_pair", "rho": "k_rho", "kforce": "k_kforce"}
+
+
+def pair_flops_per_atom(sysp: dict, n: int) -> float:
+    L = sysp["box"]
+    rho_n = n / (L[0] * L[1] * L[2])
+    rc, rs, sk, pr = sysp["r_core"], sysp["r_shell"], sysp["skin"], sysp["p_r"]
+    v = lambda r: 4.0 / 3.0 * math.pi * r ** 3
+    core_list = v(rc + sk) * rho_n
+    core = v(rc) * rho_n
+    cand = (v(rs + sk) - v(max(rc - sk, 0.0))) * rho_n
+    valid = (v(rs) - v(rc)) * rho_n / cand
+    batch = min(pr, cand) if pr > 0 else cand
+    return (core_list + batch) * FLOPS_TEST + (core + valid * batch) * FLOPS_PAIR
+
+
+def kernel_roofline(precision: str, phase: str, ms: float, launches: int, n: int, sysp: dict) -> dict:
     avg = ms / launches * 1e-3
-    flops = FLOPS_PER_PAIR[(precision, name)] * float(n) * float(p_f)
+    if phase == "pair":
+        flops = pair_flops_per_atom(sysp, n) * n
+    else:
+        flops = FLOPS_PER_PAIR[(precision, phase)] * float(n) * float(sysp["p_f"])
     ach = flops / avg / 1e12
-    return {"bound": "alu", "kernel": name, "achieved": round(ach, 3), "peak": PEAK_VALU_TFLOPS,
+    return {"bound": "alu", "kernel": KERNEL_OF_PHASE[phase], "achieved": round(ach, 3), "peak": PEAK_VALU_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / PEAK_VALU_TFLOPS, 4), "traffic": None,
-            "avg_launch_ms": round(ms / launches, 4), "launches": launches,
-            "flops_per_launch": flops}
+            "avg_launch_ms": round(ms / launches, 4), "launches": launches, "flops_per_launch": flops}
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "licl_nacl_1m_traffic.md")
+    src = os.path.join(HERE, "paper_2512_24970_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    for line in open(path):
+        if line.startswith("traffic_json:"):
+            d = json.loads(line.split(":", 1)[1])
+            if d.get("source_sha1") == sha and kernel in d.get("bytes_per_launch", {}):
+                return d["bytes_per_launch"][kernel]
+    return None
+
+
+def roofline(precision: str, res: dict, n: int, sysp: dict) -> dict:
+    """The dominant kernel (largest time in the timed steps) and the others."""
+    phases = {k: v for k, v in res["phases"].items() if k in KERNEL_OF_PHASE and v[1] > 0}
+    lines = {k: kernel_roofline(precision, k, v[0], v[1], n, sysp) for k, v in phases.items()}
+    top = max(phases, key=lambda k: phases[k][0])
+    out = dict(lines[top])
+    out["traffic"] = traffic_from_profiles(out["kernel"] + ("<mixed>" if precision == "mixed" else "<fp64>"))
+    out["others"] = {lines[k]["kernel"]: {"achieved": lines[k]["achieved"], "frac": lines[k]["frac"],
+                                         "avg_launch_ms": lines[k]["avg_launch_ms"]}
+                     for k in lines if k != top}
+    return out
+
+
+def copy_probe(nbytes: int, reps: int = 5) -> None:
+    """A plain device copy of known size, to calibrate the HBM byte counters."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}))
 
 
 def cpu_baseline(cfg, n_sample: int, ev: int = 1):
@@ -134,7 +196,11 @@ def main() -> int:
     ap.add_argument("--workload", default="licl_nacl_1m")
     ap.add_argument("--forms", default="mixed,fp64", help="comma list of mixed,fp64; the first is reported")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="atoms in the CPU-baseline sample (0: skip)")
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     args = ap.parse_args()
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -173,7 +239,7 @@ def main() -> int:
             "r_shell": cfg["sys"]["r_shell"], "skin": cfg["sys"]["skin"], "p_r": cfg["sys"]["p_r"], "p_f": p_f,
             "rebuild_every": cfg["sys"]["rebuild_every"], "dt_ps": cfg["sys"]["dt"], "form": head,
         },
-        "roofline": roofline(head, r, n, p_f),
+        "roofline": roofline(head, r, n, cfg["sys"]),
         "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
     }
     line["T_end_K"] = round(r["T_end"], 1)
@@ -183,7 +249,7 @@ def main() -> int:
     for f in forms[1:]:
         rf = results[f]
         line[f] = {"value": rf["value"], "ms_per_step": rf["ms_per_step"], "T_end_K": round(rf["T_end"], 1),
-                   "roofline": roofline(f, rf, n, p_f),
+                   "roofline": roofline(f, rf, n, cfg["sys"]),
                    "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in rf["phases"].items()}}
     if args.cpu_sample > 0:
         _log(f"[bench] cpu baseline: oracle on {args.cpu_sample} atoms")

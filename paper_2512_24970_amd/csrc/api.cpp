@@ -258,20 +258,24 @@ void snapshot(rbsog_ctx* c, bool save)
 {
     DevSys& s = c->s;
     const size_t N = (size_t)std::max(s.n, 1);
-    const size_t bytes = N * (9 * sizeof(double) + 3 * sizeof(int32_t)) + sizeof(DeviceScalars);
+    const size_t bytes = N * (10 * sizeof(double) + 3 * sizeof(int32_t)) + sizeof(DeviceScalars);
     if (save && c->snap.bytes < bytes) c->snap.alloc(bytes);
     double* d = c->snap.as<double>();
-    double* arr[9] = {s.x, s.y, s.z, s.vx, s.vy, s.vz, s.fx, s.fy, s.fz};
+    double* arr[6] = {s.vx, s.vy, s.vz, s.fx, s.fy, s.fz};
     int32_t* iar[3] = {s.type, s.id, s.inv};
-    int32_t* ip = reinterpret_cast<int32_t*>(d + 9 * N);
+    int32_t* ip = reinterpret_cast<int32_t*>(d + 10 * N);
     auto cp = [&](void* dst, const void* src, size_t b) {
         HIP_OK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, c->stream));
     };
-    for (int q = 0; q < 9; ++q) {
+    if (save)
+        cp(d, s.p, sizeof(double4) * s.n);
+    else
+        cp(s.p, d, sizeof(double4) * s.n);
+    for (int q = 0; q < 6; ++q) {
         if (save)
-            cp(d + q * N, arr[q], sizeof(double) * s.n);
+            cp(d + (4 + q) * N, arr[q], sizeof(double) * s.n);
         else
-            cp(arr[q], d + q * N, sizeof(double) * s.n);
+            cp(arr[q], d + (4 + q) * N, sizeof(double) * s.n);
     }
     for (int q = 0; q < 3; ++q) {
         if (save)
@@ -469,25 +473,26 @@ void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, c
         s.inv_mass_acc[t] = kAccUnit / s.mass[t];
     }
 
-    // per-atom arrays: 15 double + 3 int32 per atom
+    // per-atom arrays: a packed position record, 12 doubles, 3 int32
     const size_t N = (size_t)std::max(n, 1);
-    c->atoms.alloc(N * (15 * sizeof(double) + 3 * sizeof(int32_t)));
+    c->atoms.alloc(N * (sizeof(double4) + 12 * sizeof(double) + 3 * sizeof(int32_t)));
     {
-        double* d = c->atoms.as<double>();
-        double** slots[] = {&s.x, &s.y, &s.z, &s.vx, &s.vy, &s.vz, &s.fx, &s.fy, &s.fz,
-                            &s.fsx, &s.fsy, &s.fsz, &s.xr, &s.yr, &s.zr};
-        for (int t = 0; t < 15; ++t) *slots[t] = d + t * N;
-        int32_t* ip = reinterpret_cast<int32_t*>(d + 15 * N);
+        s.p = c->atoms.as<double4>();
+        double* d = reinterpret_cast<double*>(s.p + N);
+        double** slots[] = {&s.vx, &s.vy, &s.vz, &s.fx, &s.fy, &s.fz, &s.fsx, &s.fsy, &s.fsz, &s.xr, &s.yr, &s.zr};
+        for (int t = 0; t < 12; ++t) *slots[t] = d + t * N;
+        int32_t* ip = reinterpret_cast<int32_t*>(d + 12 * N);
         s.type = ip;
         s.id = ip + N;
         s.inv = ip + 2 * N;
     }
-    c->sortbuf.alloc(N * (9 * sizeof(double) + 5 * sizeof(int32_t)));
+    c->sortbuf.alloc(N * (sizeof(double4) + 6 * sizeof(double) + 5 * sizeof(int32_t)));
     {
-        double* d = c->sortbuf.as<double>();
-        double** slots[] = {&s.tx, &s.ty, &s.tz, &s.tvx, &s.tvy, &s.tvz, &s.tfx, &s.tfy, &s.tfz};
-        for (int t = 0; t < 9; ++t) *slots[t] = d + t * N;
-        int32_t* ip = reinterpret_cast<int32_t*>(d + 9 * N);
+        s.tp = c->sortbuf.as<double4>();
+        double* d = reinterpret_cast<double*>(s.tp + N);
+        double** slots[] = {&s.tvx, &s.tvy, &s.tvz, &s.tfx, &s.tfy, &s.tfz};
+        for (int t = 0; t < 6; ++t) *slots[t] = d + t * N;
+        int32_t* ip = reinterpret_cast<int32_t*>(d + 6 * N);
         s.ttype = ip;
         s.tid = ip + N;
         s.cell_of = ip + 2 * N;
@@ -803,12 +808,15 @@ rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* f
         DevSys& s = ctx->s;
         const size_t bytes = sizeof(double) * 3 * (size_t)s.n;
         double* outs[3] = {pos, vel, force};
-        const double* src[3][3] = {{s.x, s.y, s.z}, {s.vx, s.vy, s.vz}, {s.fx, s.fy, s.fz}};
+        const double* src[3][3] = {{nullptr, nullptr, nullptr}, {s.vx, s.vy, s.vz}, {s.fx, s.fy, s.fz}};
         if (!ptrs_on_device && s.n > 0 && (pos || vel || force)) ctx->export_tmp.alloc(bytes);
         for (int q = 0; q < 3; ++q) {
             if (!outs[q] || s.n <= 0) continue;
             double* dst = ptrs_on_device ? outs[q] : ctx->export_tmp.as<double>();
-            launch_to_user3(s, src[q][0], src[q][1], src[q][2], dst, ctx->stream);
+            if (q == 0)
+                launch_pos_to_user(s, dst, ctx->stream);
+            else
+                launch_to_user3(s, src[q][0], src[q][1], src[q][2], dst, ctx->stream);
             if (!ptrs_on_device) {
                 HIP_OK(hipMemcpyAsync(outs[q], dst, bytes, hipMemcpyDeviceToHost, ctx->stream));
                 HIP_OK(hipStreamSynchronize(ctx->stream));

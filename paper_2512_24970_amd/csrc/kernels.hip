@@ -70,6 +70,16 @@ __device__ inline int cell_coord(double v, double scale, int nc)
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (block b on XCD b mod 8), each
+// XCD with its own L2.  Renumbering so that XCD x gets a contiguous range of
+// logical blocks keeps spatially neighbouring atoms (cell order) on one L2.
+__device__ inline int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // ---------------------------------------------------------------- scalars
 __global__ void k_set_eval(DeviceScalars* sc, uint64_t eval) { sc->eval = eval; }
 __global__ void k_bump_eval(DeviceScalars* sc) { sc->eval += 1; }
@@ -93,20 +103,40 @@ __global__ void k_clear_flags(DeviceScalars* sc)
 __global__ void k_bin(DevSys s, int gate)
 {
     RB_GATE
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.n) return;
-    const double x = wrap_coord(s.x[i], s.L[0], s.invL[0]);
-    const double y = wrap_coord(s.y[i], s.L[1], s.invL[1]);
-    const double z = wrap_coord(s.z[i], s.L[2], s.invL[2]);
-    s.x[i] = x;
-    s.y[i] = y;
-    s.z[i] = z;
+    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    // lanes past the end take part in the wavefront votes with a done flag
+    const bool live = i0 < s.n;
+    const int i = live ? i0 : s.n - 1;
+    const double4 P = s.p[i];
+    const double x = wrap_coord(P.x, s.L[0], s.invL[0]);
+    const double y = wrap_coord(P.y, s.L[1], s.invL[1]);
+    const double z = wrap_coord(P.z, s.L[2], s.invL[2]);
     const int cx = cell_coord(x, s.cell_scale[0], s.nc[0]);
     const int cy = cell_coord(y, s.cell_scale[1], s.nc[1]);
     const int cz = cell_coord(z, s.cell_scale[2], s.nc[2]);
     const int c = (cz * s.nc[1] + cy) * s.nc[0] + cx;
-    s.cell_of[i] = c;
-    s.slot_of[i] = atomicAdd(&s.cell_count[c], 1);
+    if (live) {
+        s.p[i] = make_double4(x, y, z, P.w);
+        s.cell_of[i] = c;
+    }
+    // atoms of a wavefront mostly share a cell (cell order from the last
+    // build): one atomic per distinct cell, slots handed out by ballot rank
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool done = !live;
+    while (__ballot(!done)) {
+        const uint64_t pending = __ballot(!done);
+        const int leader = __builtin_ctzll(pending);
+        const int cl = __shfl(c, leader, 64);
+        const uint64_t same = __ballot(!done && c == cl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&s.cell_count[cl], __popcll(same));
+        base = __shfl(base, leader, 64);
+        if (!done && c == cl) {
+            s.slot_of[i] = base + __popcll(same & below);
+            done = true;
+        }
+    }
 }
 
 // Exclusive scan of count[0..n) into start[0..n], one block of 1024 threads.
@@ -145,9 +175,7 @@ __global__ void k_scatter(DevSys s, int gate)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int d = s.cell_start[s.cell_of[i]] + s.slot_of[i];
-    s.tx[d] = s.x[i];
-    s.ty[d] = s.y[i];
-    s.tz[d] = s.z[i];
+    s.tp[d] = s.p[i];
     s.tvx[d] = s.vx[i];
     s.tvy[d] = s.vy[i];
     s.tvz[d] = s.vz[i];
@@ -208,13 +236,11 @@ __global__ void k_gather(DevSys s, int gate)
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= s.n) return;
     const int o = s.order[t];
-    const double x = s.tx[o], y = s.ty[o], z = s.tz[o];
-    s.x[t] = x;
-    s.y[t] = y;
-    s.z[t] = z;
-    s.xr[t] = x;
-    s.yr[t] = y;
-    s.zr[t] = z;
+    const double4 P = s.tp[o];
+    s.p[t] = P;
+    s.xr[t] = P.x;
+    s.yr[t] = P.y;
+    s.zr[t] = P.z;
     s.vx[t] = s.tvx[o];
     s.vy[t] = s.tvy[o];
     s.vz[t] = s.tvz[o];
@@ -247,7 +273,8 @@ __global__ __launch_bounds__(64) void k_lists(DevSys s, int gate)
 
     const int i = blockIdx.x;
     const int lane = threadIdx.x;
-    const double xi = s.x[i], yi = s.y[i], zi = s.z[i];
+    const double4 Pi = s.p[i];
+    const double xi = Pi.x, yi = Pi.y, zi = Pi.z;
     const int ci[3] = {cell_coord(xi, s.cell_scale[0], s.nc[0]), cell_coord(yi, s.cell_scale[1], s.nc[1]),
                        cell_coord(zi, s.cell_scale[2], s.nc[2])};
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -267,9 +294,10 @@ __global__ __launch_bounds__(64) void k_lists(DevSys s, int gate)
                     const int j = base + lane;
                     bool is_core = false, is_cand = false;
                     if (j < end && j != i) {
-                        const double dx = min_image(xi - s.x[j], s.L[0], s.invL[0]);
-                        const double dy = min_image(yi - s.y[j], s.L[1], s.invL[1]);
-                        const double dz = min_image(zi - s.z[j], s.L[2], s.invL[2]);
+                        const double4 Pj = s.p[j];
+                        const double dx = min_image(xi - Pj.x, s.L[0], s.invL[0]);
+                        const double dy = min_image(yi - Pj.y, s.L[1], s.invL[1]);
+                        const double dz = min_image(zi - Pj.z, s.L[2], s.invL[2]);
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
                         is_core = r2 < s.rc2_list;
                         is_cand = r2 >= s.lo2_list && r2 < s.hi2_list;
@@ -354,7 +382,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(DevSys s, int gate)
     __shared__ int cq[27];
     __shared__ int cb[27];
     __shared__ int coff[28];
-    const int c = blockIdx.x;
+    const int c = xcd_block(blockIdx.x, gridDim.x);
     const int cx0 = c % s.nc[0];
     const int cy0 = (c / s.nc[0]) % s.nc[1];
     const int cz0 = c / (s.nc[0] * s.nc[1]);
@@ -407,9 +435,10 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(DevSys s, int gate)
         while (coff[k + 1] <= t) ++k;
         const int j = cb[k] + (t - coff[k]);
         val[t] = j;
-        px[t] = s.x[j];
-        py[t] = s.y[j];
-        pz[t] = s.z[j];
+        const double4 P = s.p[j];
+        px[t] = P.x;
+        py[t] = P.y;
+        pz[t] = P.z;
     }
     __syncthreads();
 
@@ -418,48 +447,79 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(DevSys s, int gate)
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int beg0 = s.cell_start[c];
     const int cnt0 = s.cell_start[c + 1] - beg0;
-    for (int a = wave; a < cnt0; a += kListBlock / 64) {
-        const int i = beg0 + a;
-        const double xi = s.x[i], yi = s.y[i], zi = s.z[i];
-        int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
-        int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
-        int ncore = 0, ncand = 0;
+    // With at least 5 cells along every axis and no stencil cell across the
+    // box edge, every |d| < 2 L/n_c <= 0.4 L, so rint(d/L) = 0 and the
+    // minimum image leaves d unchanged: skipping it gives the same bits.
+    const bool interior = s.nc[0] >= 5 && s.nc[1] >= 5 && s.nc[2] >= 5 && cx0 > 0 && cx0 < s.nc[0] - 1 &&
+                          cy0 > 0 && cy0 < s.nc[1] - 1 && cz0 > 0 && cz0 < s.nc[2] - 1;
+    // each wavefront sweeps the stencil for kA atoms at once: one LDS read
+    // serves kA independent distance tests
+    constexpr int kA = 4;
+    constexpr int kW = kListBlock / 64;
+    for (int a0 = wave; a0 < cnt0; a0 += kW * kA) {
+        int iu[kA], ncore[kA], ncand[kA];
+        double xu[kA], yu[kA], zu[kA];
+        int32_t* crow[kA];
+        int32_t* ctile[kA];
+#pragma unroll
+        for (int u = 0; u < kA; ++u) {
+            const int a = a0 + u * kW;
+            iu[u] = a < cnt0 ? beg0 + a : -1;
+            const double4 Pi = s.p[a < cnt0 ? beg0 + a : beg0];
+            xu[u] = Pi.x;
+            yu[u] = Pi.y;
+            zu[u] = Pi.z;
+            const int ii = a < cnt0 ? beg0 + a : beg0;
+            crow[u] = s.cand_idx + (size_t)ii * s.cap_cand;
+            ctile[u] = s.core_idx + (size_t)(ii >> 6) * s.cap_core * 64 + (ii & 63);
+            ncore[u] = 0;
+            ncand[u] = 0;
+        }
         for (int base = 0; base < total; base += 64) {
             const int t = base + lane;
-            bool is_core = false, is_cand = false;
-            int j = -1;
-            if (t < total) {
-                j = val[t];
-                if (j != i) {
-                    const double dx = min_image(xi - px[t], s.L[0], s.invL[0]);
-                    const double dy = min_image(yi - py[t], s.L[1], s.invL[1]);
-                    const double dz = min_image(zi - pz[t], s.L[2], s.invL[2]);
+            const bool in = t < total;
+            const int j = in ? val[t] : -1;
+            const double pxj = in ? px[t] : 0.0, pyj = in ? py[t] : 0.0, pzj = in ? pz[t] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kA; ++u) {
+                bool is_core = false, is_cand = false;
+                if (in && iu[u] >= 0 && j != iu[u]) {
+                    double dx = xu[u] - pxj, dy = yu[u] - pyj, dz = zu[u] - pzj;
+                    if (!interior) {
+                        dx = min_image(dx, s.L[0], s.invL[0]);
+                        dy = min_image(dy, s.L[1], s.invL[1]);
+                        dz = min_image(dz, s.L[2], s.invL[2]);
+                    }
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                     is_core = r2 < s.rc2_list;
                     is_cand = r2 >= s.lo2_list && r2 < s.hi2_list;
                 }
+                const uint64_t mc = __ballot(is_core);
+                const uint64_t mk = __ballot(is_cand);
+                if (is_core) {
+                    const int slot = ncore[u] + __popcll(mc & below);
+                    if (slot < s.cap_core) ctile[u][(size_t)slot * 64] = j;
+                }
+                if (is_cand) {
+                    const int slot = ncand[u] + __popcll(mk & below);
+                    if (slot < s.cap_cand) crow[u][slot] = j;
+                }
+                ncore[u] += __popcll(mc);
+                ncand[u] += __popcll(mk);
             }
-            const uint64_t mc = __ballot(is_core);
-            const uint64_t mk = __ballot(is_cand);
-            if (is_core) {
-                const int slot = ncore + __popcll(mc & below);
-                if (slot < s.cap_core) ctile[(size_t)slot * 64] = j;
-            }
-            if (is_cand) {
-                const int slot = ncand + __popcll(mk & below);
-                if (slot < s.cap_cand) crow[slot] = j;
-            }
-            ncore += __popcll(mc);
-            ncand += __popcll(mk);
         }
-        if (lane == 0) {
-            s.core_cnt[i] = ncore;
-            s.cand_cnt[i] = ncand;
-            // same-address atomics serialise: only overflowing atoms report
-            if (ncore > s.cap_core || ncand > s.cap_cand) {
-                atomicOr(&s.sc->overflow, 1);
-                atomicMax(&s.sc->max_core, ncore);
-                atomicMax(&s.sc->max_cand, ncand);
+#pragma unroll
+        for (int u = 0; u < kA; ++u) {
+            const int i = iu[u];
+            if (lane == 0 && i >= 0) {
+                s.core_cnt[i] = ncore[u];
+                s.cand_cnt[i] = ncand[u];
+                // same-address atomics serialise: only overflowing atoms report
+                if (ncore[u] > s.cap_core || ncand[u] > s.cap_cand) {
+                    atomicOr(&s.sc->overflow, 1);
+                    atomicMax(&s.sc->max_core, ncore[u]);
+                    atomicMax(&s.sc->max_cand, ncand[u]);
+                }
             }
         }
     }
@@ -597,10 +657,11 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
     }
     __syncthreads();
 
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, Uc = 0.0, Us = 0.0;
     if (i < s.n) {
-        const double xi = s.x[i], yi = s.y[i], zi = s.z[i];
+        const double4 Pi = s.p[i];
+        const double xi = Pi.x, yi = Pi.y, zi = Pi.z;
         const int ti = s.type[i];
         // pair force scalar for r2 of species pair (ti, tj)
         auto pair_f = [&](int tj, double r2, double& u) -> double {
@@ -615,7 +676,9 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
         };
         // Neighbours are fetched kU at a time (indices, then positions and
         // types) before any arithmetic, so the gathers overlap; the sums still
-        // run in list order.
+        // run in list order.  Core-list lines are read once: non-temporal
+        // loads keep them from evicting the positions that neighbours re-read
+        // (a candidate row is re-read by its own lane, so it stays cached).
         constexpr int kU = 4;
         // core sum, eq. (24)
         const int nc = min(s.core_cnt[i], s.cap_core);
@@ -625,13 +688,15 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
             double X[kU], Y[kU], Z[kU];
             int T[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) jj[u] = (k0 + u < nc) ? ctile[(size_t)(k0 + u) * 64] : i;
+            for (int u = 0; u < kU; ++u)
+                jj[u] = (k0 + u < nc) ? __builtin_nontemporal_load(ctile + (size_t)(k0 + u) * 64) : i;
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                X[u] = s.x[jj[u]];
-                Y[u] = s.y[jj[u]];
-                Z[u] = s.z[jj[u]];
-                T[u] = s.type[jj[u]];
+                const double4 Q = s.p[jj[u]];
+                X[u] = Q.x;
+                Y[u] = Q.y;
+                Z[u] = Q.z;
+                T[u] = (int)Q.w;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
@@ -658,7 +723,14 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
         const double wgt = take_all ? 1.0 : (double)n / (double)s.p_r;
         FloydMask fm{mask_sm + threadIdx.x, (int)blockDim.x};
         PhiloxStream st(s.seed, (uint32_t)s.id[i], (uint32_t)s.sc->eval, kTagShell, s.replica);
-        if (!take_all) fm.clear(n);
+        if (!take_all) {
+            // draw the whole batch first, then visit the ranks in ascending
+            // order: the candidate row is swept once, line by line
+            fm.clear(n);
+            for (int k = 0; k < cnt; ++k) fm.step(st, n - s.p_r + k);
+        }
+        int w_cur = 0;  // ascending walk over the set bits of the mask
+        uint32_t m_cur = take_all ? 0u : fm.m[0];
         double Sx = 0.0, Sy = 0.0, Sz = 0.0, Su = 0.0;
         for (int k0 = 0; k0 < cnt; k0 += kU) {
             int jj[kU];
@@ -667,15 +739,24 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 int e = 0;
-                if (k0 + u < cnt) e = take_all ? k0 + u : fm.step(st, n - s.p_r + k0 + u);
+                if (k0 + u < cnt) {
+                    if (take_all) {
+                        e = k0 + u;
+                    } else {
+                        while (m_cur == 0u) m_cur = fm.m[(++w_cur) * fm.stride];
+                        e = w_cur * 32 + __builtin_ctz(m_cur);
+                        m_cur &= m_cur - 1u;
+                    }
+                }
                 jj[u] = (k0 + u < cnt) ? crow[e] : i;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                X[u] = s.x[jj[u]];
-                Y[u] = s.y[jj[u]];
-                Z[u] = s.z[jj[u]];
-                T[u] = s.type[jj[u]];
+                const double4 Q = s.p[jj[u]];
+                X[u] = Q.x;
+                Y[u] = Q.y;
+                Z[u] = Q.z;
+                T[u] = (int)Q.w;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
@@ -698,9 +779,9 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
         Fy = fma(wgt, Sy, Fy);
         Fz = fma(wgt, Sz, Fz);
         if (ENERGY) Us = wgt * Su;
-        s.fsx[i] = Fx;
-        s.fsy[i] = Fy;
-        s.fsz[i] = Fz;
+        __builtin_nontemporal_store(Fx, s.fsx + i);
+        __builtin_nontemporal_store(Fy, s.fsy + i);
+        __builtin_nontemporal_store(Fz, s.fsz + i);
     }
     const double bx = block_sum(Fx, red);
     const double by = block_sum(Fy, red);
@@ -833,9 +914,10 @@ __global__ __launch_bounds__(kBlock) void k_rho(DevSys s, KDev k)
     const int a1 = min(s.n, a0 + k.chunk);
     double re = 0.0, im = 0.0;
     for (int a = a0 + wave; a < a1; a += 4) {
-        const double ux = s.x[a] * s.u1024[0];
-        const double uy = s.y[a] * s.u1024[1];
-        const double uz = s.z[a] * s.u1024[2];
+        const double4 P = s.p[a];
+        const double ux = P.x * s.u1024[0];
+        const double uy = P.y * s.u1024[1];
+        const double uz = P.z * s.u1024[2];
         const double q = s.q[s.type[a]];
         const double t = fma(mz, uz, fma(my, uy, mx * ux));
         double c, sn;
@@ -924,9 +1006,10 @@ __global__ __launch_bounds__(kBlock) void k_kforce(DevSys s, KDev k, double* kin
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double ke = 0.0;
     if (i < s.n) {
-        const double ux = s.x[i] * s.u1024[0];
-        const double uy = s.y[i] * s.u1024[1];
-        const double uz = s.z[i] * s.u1024[2];
+        const double4 P = s.p[i];
+        const double ux = P.x * s.u1024[0];
+        const double uy = P.y * s.u1024[1];
+        const double uz = P.z * s.u1024[2];
         double Gx = 0.0, Gy = 0.0, Gz = 0.0;
         for (int p = 0; p < k.n_modes; ++p) {
             const ModeRec mr = k.modes[p];
@@ -1025,12 +1108,11 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(DevSys s, int scheduled)
         s.vx[i] = vx;
         s.vy[i] = vy;
         s.vz[i] = vz;
-        const double x = wrap_coord(s.x[i] + s.dt * vx, s.L[0], s.invL[0]);
-        const double y = wrap_coord(s.y[i] + s.dt * vy, s.L[1], s.invL[1]);
-        const double z = wrap_coord(s.z[i] + s.dt * vz, s.L[2], s.invL[2]);
-        s.x[i] = x;
-        s.y[i] = y;
-        s.z[i] = z;
+        const double4 P = s.p[i];
+        const double x = wrap_coord(P.x + s.dt * vx, s.L[0], s.invL[0]);
+        const double y = wrap_coord(P.y + s.dt * vy, s.L[1], s.invL[1]);
+        const double z = wrap_coord(P.z + s.dt * vz, s.L[2], s.invL[2]);
+        s.p[i] = make_double4(x, y, z, P.w);
         const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
         const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
         const double dz = min_image(z - s.zr[i], s.L[2], s.invL[2]);
@@ -1062,6 +1144,17 @@ __global__ void k_to_user3(DevSys s, const double* ax, const double* ay, const d
     out[u + 2] = az[i];
 }
 
+__global__ void k_pos_to_user(DevSys s, double* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const size_t u = (size_t)s.id[i] * 3;
+    const double4 P = s.p[i];
+    out[u] = P.x;
+    out[u + 1] = P.y;
+    out[u + 2] = P.z;
+}
+
 __global__ void k_kspace_part(DevSys s, double* out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1078,9 +1171,7 @@ __global__ void k_from_user(DevSys s, const int32_t* type, const double* pos, co
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
-    s.x[i] = pos[3 * (size_t)i];
-    s.y[i] = pos[3 * (size_t)i + 1];
-    s.z[i] = pos[3 * (size_t)i + 2];
+    s.p[i] = make_double4(pos[3 * (size_t)i], pos[3 * (size_t)i + 1], pos[3 * (size_t)i + 2], (double)type[i]);
     s.vx[i] = vel ? vel[3 * (size_t)i] : 0.0;
     s.vy[i] = vel ? vel[3 * (size_t)i + 1] : 0.0;
     s.vz[i] = vel ? vel[3 * (size_t)i + 2] : 0.0;
@@ -1233,6 +1324,11 @@ void launch_to_user3(const DevSys& s, const double* ax, const double* ay, const 
                      hipStream_t st)
 {
     if (s.n > 0) k_to_user3<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, ax, ay, az, out);
+}
+
+void launch_pos_to_user(const DevSys& s, double* out, hipStream_t st)
+{
+    if (s.n > 0) k_pos_to_user<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, out);
 }
 
 void launch_kspace_part(const DevSys& s, double* out, hipStream_t st)

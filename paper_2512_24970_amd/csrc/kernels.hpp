@@ -40,14 +40,17 @@ struct DevSys {
     double inv_mass_acc[kMaxSpecies];  // kAccUnit / m
     double mass[kMaxSpecies];
 
-    // atoms (cell order)
-    double *x, *y, *z, *vx, *vy, *vz;
+    // atoms (cell order); positions packed with the species so a neighbour
+    // gather touches one 32-byte record
+    double4* p;               // x, y, z, type (as a double)
+    double *vx, *vy, *vz;
     double *fx, *fy, *fz;     // total force of the last evaluation
     double *fsx, *fsy, *fsz;  // short-range force before the momentum correction
     double *xr, *yr, *zr;     // positions at the last list build
     int32_t *type, *id, *inv;
     // sort scratch
-    double *tx, *ty, *tz, *tvx, *tvy, *tvz, *tfx, *tfy, *tfz;
+    double4* tp;
+    double *tvx, *tvy, *tvz, *tfx, *tfy, *tfz;
     int32_t *ttype, *tid, *cell_of, *slot_of, *order;
     int32_t *cell_count, *cell_start;
     // lists
@@ -111,6 +114,7 @@ void launch_kick_drift(const DevSys& s, bool scheduled, hipStream_t st);
 // exports
 void launch_to_user3(const DevSys& s, const double* ax, const double* ay, const double* az, double* out,
                      hipStream_t st);
+void launch_pos_to_user(const DevSys& s, double* out, hipStream_t st);
 void launch_kspace_part(const DevSys& s, double* out, hipStream_t st);
 void launch_shell_ranks(const DevSys& s, int32_t* out, int32_t* n_out, hipStream_t st);
 void launch_from_user(const DevSys& s, const int32_t* type, const double* pos, const double* vel, hipStream_t st);
