@@ -445,7 +445,6 @@ void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, c
         if (nc < 3) nc = 1;
         s.nc[a] = nc;
         s.cell_scale[a] = (double)nc / p->box[a];
-        s.u1024[a] = (double)kTableSize / p->box[a];
         s.two_pi_L[a] = 2.0 * kPi / p->box[a];
         s.ncell *= nc;
     }
@@ -595,7 +594,9 @@ void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, c
     k.n_modes_pad = std::max(1, tiles) * 64;
     const int max_chunks = std::max(1, (n + 255) / 256);
     k.n_chunks = std::min(max_chunks, std::max(1, (2048 + std::max(tiles, 1) - 1) / std::max(tiles, 1)));
-    k.chunk = std::max(1, (n + k.n_chunks - 1) / k.n_chunks);
+    // a multiple of 16 atoms: the rho kernel splits a chunk into four
+    // quarters read four atoms at a time
+    k.chunk = (std::max(1, (n + k.n_chunks - 1) / k.n_chunks) + 15) & ~15;
     k.n_chunks = std::max(1, (n + k.chunk - 1) / k.chunk);
     c->kmodes.alloc(std::max<size_t>(1, (size_t)k.n_modes) * (sizeof(ModeRec) + 3 * sizeof(int32_t)));
     k.modes = c->kmodes.as<ModeRec>();
@@ -603,7 +604,7 @@ void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, c
     if (!k.sampled && k.n_modes > 0) {
         std::vector<ModeRec> recs(k.n_modes);
         for (int q = 0; q < k.n_modes; ++q) {
-            recs[q] = ModeRec{(double)em[3 * q], (double)em[3 * q + 1], (double)em[3 * q + 2], 0.0, 0.0, ecoef[q], 0.0, 0.0};
+            recs[q] = ModeRec{(double)em[3 * q], (double)em[3 * q + 1], (double)em[3 * q + 2], 0.0, 0.0, ecoef[q], 0.0, 0.0f, 0.0f};
         }
         HIP_OK(hipMemcpy(k.modes, recs.data(), sizeof(ModeRec) * k.n_modes, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(k.m, em.data(), sizeof(int32_t) * em.size(), hipMemcpyHostToDevice));

@@ -10,6 +10,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -874,7 +875,8 @@ __global__ void k_ksample(DevSys s, KDev k)
     r.B = 0.0;
     r.coef = k.coef_scale / k2;
     r.e = 0.0;
-    r.pad = 0.0;
+    r.Af = 0.0f;
+    r.Bf = 0.0f;
     k.modes[p] = r;
 }
 
@@ -893,44 +895,97 @@ __device__ inline void sincos1024(double t, const double2* tab, double& c, doubl
     s = fma(T.y, cd, T.x * sd);
 }
 
+// Phase in turns (MIXED) or in units of 2 pi / 1024 (FP64) of one atom
+// against one mode whose integer vector already carries the box scale.
+__device__ inline double mode_phase(double kx, double ky, double kz, const double4& P)
+{
+    return fma(kz, P.z, fma(ky, P.y, kx * P.x));
+}
+
+// FP32 sine and cosine of a phase in turns: the fractional turn (one FP64
+// op) is rounded to FP32 and fed to the hardware sin/cos, which take turns.
+__device__ inline void sincos_turns_f32(double t, float& c, float& s)
+{
+    const float fr = (float)__builtin_amdgcn_fract(t);
+    c = __builtin_amdgcn_cosf(fr);
+    s = __builtin_amdgcn_sinf(fr);
+}
+
 // rho(k) of eq. (22) over one atom chunk for 64 modes: one mode per lane,
-// the four waves of the block take every fourth atom, atoms read through the
-// scalar unit.  Partial sums per chunk, reduced later in a fixed order.
+// each of the four waves of the block takes a contiguous quarter of the
+// chunk, four atoms per iteration, atoms read through the scalar unit.
+// Partial sums per chunk, reduced later in a fixed order.  The mixed form
+// sums the four FP32 products q cos, q sin of an iteration in FP32 and adds
+// that to the FP64 accumulators.
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_rho(DevSys s, KDev k)
 {
-    __shared__ double2 tab[kTableSize];
+    __shared__ double2 tab[MIXED ? 1 : kTableSize];
     __shared__ double red[4][64][2];
-    for (int t = threadIdx.x; t < kTableSize; t += blockDim.x)
-        tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
+    using qreal = typename std::conditional<MIXED, float, double>::type;
+    __shared__ qreal qs[kMaxSpecies];
+    if (!MIXED)
+        for (int t = threadIdx.x; t < kTableSize; t += blockDim.x)
+            tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
+    if (threadIdx.x < kMaxSpecies) qs[threadIdx.x] = (qreal)s.q[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int p = blockIdx.y * 64 + lane;
     const bool ok = p < k.n_modes;
-    const ModeRec mr = ok ? k.modes[p] : ModeRec{0, 0, 0, 0, 0, 0, 0, 0};
-    const double mx = mr.mx, my = mr.my, mz = mr.mz;
-    const int a0 = blockIdx.x * k.chunk;
-    const int a1 = min(s.n, a0 + k.chunk);
+    const ModeRec mr = ok ? k.modes[p] : ModeRec{};
+    const double sc = MIXED ? 1.0 : (double)kTableSize;
+    const double kx = mr.mx * (sc * s.invL[0]);
+    const double ky = mr.my * (sc * s.invL[1]);
+    const double kz = mr.mz * (sc * s.invL[2]);
+    // chunk and its quarters are multiples of four atoms (host guarantees
+    // chunk % 16 == 0), so the type quadruples below are aligned
+    const int qw = k.chunk >> 2;
+    const int a0 = blockIdx.x * k.chunk + wave * qw;
+    const int a1 = min(s.n, a0 + qw);
     double re = 0.0, im = 0.0;
-    for (int a = a0 + wave; a < a1; a += 4) {
-        const double4 P = s.p[a];
-        const double ux = P.x * s.u1024[0];
-        const double uy = P.y * s.u1024[1];
-        const double uz = P.z * s.u1024[2];
-        const double q = s.q[s.type[a]];
-        const double t = fma(mz, uz, fma(my, uy, mx * ux));
-        double c, sn;
+    int a = a0;
+    for (; a + 4 <= a1; a += 4) {
+        const double4 P0 = s.p[a], P1 = s.p[a + 1], P2 = s.p[a + 2], P3 = s.p[a + 3];
+        const int4 T = *reinterpret_cast<const int4*>(s.type + a);
+        const qreal q0 = qs[T.x], q1 = qs[T.y], q2 = qs[T.z], q3 = qs[T.w];
+        const double t0 = mode_phase(kx, ky, kz, P0), t1 = mode_phase(kx, ky, kz, P1);
+        const double t2 = mode_phase(kx, ky, kz, P2), t3 = mode_phase(kx, ky, kz, P3);
         if (MIXED) {
-            const double f = t * (1.0 / kTableSize);
-            const float fr = (float)(f - rint(f));
-            c = (double)__builtin_amdgcn_cosf(fr);
-            sn = (double)__builtin_amdgcn_sinf(fr);
+            float c0, s0, c1, s1, c2, s2, c3, s3;
+            sincos_turns_f32(t0, c0, s0);
+            sincos_turns_f32(t1, c1, s1);
+            sincos_turns_f32(t2, c2, s2);
+            sincos_turns_f32(t3, c3, s3);
+            const float rs = fmaf(q3, c3, fmaf(q2, c2, fmaf(q1, c1, q0 * c0)));
+            const float is = fmaf(q3, s3, fmaf(q2, s2, fmaf(q1, s1, q0 * s0)));
+            re += (double)rs;
+            im += (double)is;
         } else {
-            sincos1024(t, tab, c, sn);
+            double c0, s0, c1, s1, c2, s2, c3, s3;
+            sincos1024(t0, tab, c0, s0);
+            sincos1024(t1, tab, c1, s1);
+            sincos1024(t2, tab, c2, s2);
+            sincos1024(t3, tab, c3, s3);
+            re = fma(q3, c3, fma(q2, c2, fma(q1, c1, fma(q0, c0, re))));
+            im = fma(q3, s3, fma(q2, s2, fma(q1, s1, fma(q0, s0, im))));
         }
-        re = fma(q, c, re);
-        im = fma(q, sn, im);
+    }
+    for (; a < a1; ++a) {
+        const double4 P = s.p[a];
+        const qreal q = qs[s.type[a]];
+        const double t = mode_phase(kx, ky, kz, P);
+        if (MIXED) {
+            float c, sn;
+            sincos_turns_f32(t, c, sn);
+            re += (double)(q * c);
+            im += (double)(q * sn);
+        } else {
+            double c, sn;
+            sincos1024(t, tab, c, sn);
+            re = fma(q, c, re);
+            im = fma(q, sn, im);
+        }
     }
     red[wave][lane][0] = re;
     red[wave][lane][1] = im;
@@ -965,6 +1020,8 @@ __global__ __launch_bounds__(64) void k_rho_finalize(KDev k)
         r.A = cf * im;
         r.B = cf * re;
         r.e = cf * (re * re + im * im);
+        r.Af = (float)r.A;
+        r.Bf = (float)r.B;
     }
 }
 
@@ -993,48 +1050,59 @@ __global__ __launch_bounds__(kBlock) void k_finalize(DevSys s, KDev k, const dou
 }
 
 // k-space force of eq. (29) (or eq. 23) on one atom per lane, looping over all
-// modes; adds the short-range force minus the momentum correction, optionally
-// the closing half kick of velocity Verlet.
+// modes two at a time; adds the short-range force minus the momentum
+// correction, optionally the closing half kick of velocity Verlet.  The mixed
+// form takes Im(e^{-i theta} rho) coef in FP32 and accumulates in FP64.
 template <bool MIXED, bool KICK, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_kforce(DevSys s, KDev k, double* kin_part)
 {
-    __shared__ double2 tab[kTableSize];
+    __shared__ double2 tab[MIXED ? 1 : kTableSize];
     __shared__ double red[4];
-    for (int t = threadIdx.x; t < kTableSize; t += blockDim.x)
-        tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
-    __syncthreads();
+    if (!MIXED) {
+        for (int t = threadIdx.x; t < kTableSize; t += blockDim.x)
+            tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
+        __syncthreads();
+    }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double ke = 0.0;
     if (i < s.n) {
-        const double4 P = s.p[i];
-        const double ux = P.x * s.u1024[0];
-        const double uy = P.y * s.u1024[1];
-        const double uz = P.z * s.u1024[2];
+        const double4 Pi = s.p[i];
+        const double sc = MIXED ? 1.0 : (double)kTableSize;
+        // scaled position: phase = m . u
+        const double4 U = make_double4(Pi.x * (sc * s.invL[0]), Pi.y * (sc * s.invL[1]),
+                                       Pi.z * (sc * s.invL[2]), 0.0);
         double Gx = 0.0, Gy = 0.0, Gz = 0.0;
-        for (int p = 0; p < k.n_modes; ++p) {
-            const ModeRec mr = k.modes[p];
-            const double t = fma(mr.mz, uz, fma(mr.my, uy, mr.mx * ux));
-            double c, sn;
+        auto one = [&](const ModeRec& mr) {
+            const double t = mode_phase(mr.mx, mr.my, mr.mz, U);
+            double w;
             if (MIXED) {
-                const double f = t * (1.0 / kTableSize);
-                const float fr = (float)(f - rint(f));
-                c = (double)__builtin_amdgcn_cosf(fr);
-                sn = (double)__builtin_amdgcn_sinf(fr);
+                float c, sn;
+                sincos_turns_f32(t, c, sn);
+                // Im(e^{-i theta} rho) * coef = c * A - s * B
+                w = (double)fmaf(c, mr.Af, -(sn * mr.Bf));
             } else {
+                double c, sn;
                 sincos1024(t, tab, c, sn);
+                w = fma(c, mr.A, -(sn * mr.B));
             }
-            // Im(e^{-i theta} rho) * coef = c * A - s * B
-            const double w = fma(c, mr.A, -(sn * mr.B));
             Gx = fma(w, mr.mx, Gx);
             Gy = fma(w, mr.my, Gy);
             Gz = fma(w, mr.mz, Gz);
+        };
+        int p = 0;
+        for (; p + 2 <= k.n_modes; p += 2) {
+            const ModeRec m0 = k.modes[p];
+            const ModeRec m1 = k.modes[p + 1];
+            one(m0);
+            one(m1);
         }
+        if (p < k.n_modes) one(k.modes[p]);
         const int ti = s.type[i];
         const double qk = -s.coulomb_k * s.q[ti];
-        const DeviceScalars* sc = s.sc;
-        const double fx = s.fsx[i] - sc->p_corr[0] + qk * s.two_pi_L[0] * Gx;
-        const double fy = s.fsy[i] - sc->p_corr[1] + qk * s.two_pi_L[1] * Gy;
-        const double fz = s.fsz[i] - sc->p_corr[2] + qk * s.two_pi_L[2] * Gz;
+        const DeviceScalars* scal = s.sc;
+        const double fx = s.fsx[i] - scal->p_corr[0] + qk * s.two_pi_L[0] * Gx;
+        const double fy = s.fsy[i] - scal->p_corr[1] + qk * s.two_pi_L[1] * Gy;
+        const double fz = s.fsz[i] - scal->p_corr[2] + qk * s.two_pi_L[2] * Gz;
         s.fx[i] = fx;
         s.fy[i] = fy;
         s.fz[i] = fz;

@@ -11,7 +11,7 @@ struct ModeRec {
     double A, B;        // coef * Im rho, coef * Re rho
     double coef;        // S/(P_F V k^2), or F^(k)/V for the full sum
     double e;           // coef * |rho|^2
-    double pad;
+    float Af, Bf;       // A and B rounded to FP32 (mixed force kernel)
 };
 
 // Everything the kernels read or write.  Per-atom arrays are in cell order.
@@ -22,7 +22,6 @@ struct DevSys {
     double cell_scale[3];  // n_c / L
     int nc[3];
     int ncell;
-    double u1024[3];       // 1024 / L: phase in units of 2 pi / 1024
     double two_pi_L[3];
     double rc2_list, lo2_list, hi2_list;  // (r_core+skin)^2, (r_core-skin)^2, (r_shell+skin)^2
     double rc2, rs2;                      // r_core^2, r_shell^2
