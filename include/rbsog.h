@@ -11,9 +11,13 @@
  *    or aborts across the ABI; rbsog_last_error() holds the message of the
  *    last failed call of a context.
  *  - One context owns one HIP stream (the caller's, or the default stream)
- *    and the device memory of one system.  A context is not thread safe.
+ *    and the device memory of one system, or of a batch of independent
+ *    systems (replicas) that every kernel launch covers at once.  A context
+ *    is not thread safe.
  *  - Per-atom arrays passed in or out are in the caller's atom order ("user
- *    order", atom index = id) and row-major [N][3] for vectors.  Inside, the
+ *    order", atom index = id) and row-major [N][3] for vectors.  For a batch
+ *    the systems' rows follow each other in system order (system r starts at
+ *    row n_atoms[0] + ... + n_atoms[r-1]) and N is the total.  Inside, the
  *    library keeps atoms sorted by cell; that order never leaks out.
  *  - Pointer arguments are owned by the caller and only read or written
  *    during the call (device outputs are written by work enqueued on the
@@ -120,9 +124,27 @@ const char* rbsog_last_error(const rbsog_ctx* ctx);
  * set up the SOG split and the k-space sampling tables (eq. 28) and copy
  * type[N], pos[N][3] and vel[N][3] (vel may be NULL = zero) into device
  * memory.  Pointers are device pointers if ptrs_on_device != 0, else host.
- * Builds the lists.  Synchronises. */
+ * Builds the lists.  Synchronises.  Replaces any system or batch the context
+ * held; equivalent to rbsog_set_batch with one system. */
 rbsog_status rbsog_set_system(rbsog_ctx* ctx, const rbsog_params* p, const int32_t* type,
                               const double* pos, const double* vel, int ptrs_on_device);
+
+/* Batched form: n_sys independent systems (replicas, Section 2.2 applied to
+ * each) held by one context and advanced together, every kernel launch
+ * covering all of them.  p[n_sys] gives each system's parameters; n_atoms,
+ * box, p_r, p_f, seed, replica, t_target and tau_t may differ, every other
+ * field must be equal across the batch (else RBSOG_E_ARG).  type, pos and
+ * vel hold the systems' rows one after another.  Each system is evaluated
+ * exactly as it would be alone in its own context (same lists, shell
+ * batches, modes and reduction order), so its results equal a single-system
+ * run with the same parameters.  Synchronises. */
+rbsog_status rbsog_set_batch(rbsog_ctx* ctx, int32_t n_sys, const rbsog_params* p, const int32_t* type,
+                             const double* pos, const double* vel, int ptrs_on_device);
+/* Number of systems held (1 after rbsog_set_system). */
+rbsog_status rbsog_n_systems(rbsog_ctx* ctx, int32_t* n_sys);
+/* Choose the system (0 <= r < n_sys) that the parity exports below
+ * (list counts, lists, shell ranks, modes, rho) refer to; 0 after a set. */
+rbsog_status rbsog_select_system(rbsog_ctx* ctx, int32_t r);
 
 /* Rebuild the cell order and the core/shell-candidate lists at the current
  * positions (Section 2.2 core-shell lists). */
@@ -130,9 +152,10 @@ rbsog_status rbsog_build_lists(rbsog_ctx* ctx);
 
 /* One IRBSOG force evaluation at the current positions with Philox counter
  * `eval` (shell batches of eq. 25, modes of eq. 28): F = F_core + F*_shell -
- * F_corr + F*_F (eqs. 24-27, 29).  Writes the force in user order to the
- * device array force_out[N][3] if non-NULL.  Energies are returned in e_out
- * if non-NULL (the call then synchronises).  Does not move atoms. */
+ * F_corr + F*_F (eqs. 24-27, 29), for every system held.  Writes the force
+ * in user order to the device array force_out[N][3] if non-NULL.  Energies
+ * are returned in e_out[n_sys] (one record per system) if non-NULL (the call
+ * then synchronises).  Does not move atoms. */
 rbsog_status rbsog_compute_forces(rbsog_ctx* ctx, uint64_t eval, double* force_out, rbsog_energy* e_out);
 
 /* Force parts of the last evaluation in user order into device arrays
@@ -143,8 +166,9 @@ rbsog_status rbsog_get_force_parts(rbsog_ctx* ctx, double* f_short, double* f_ks
 /* n_steps velocity-Verlet steps: kick, drift (wrap), list rebuild when the
  * step number is a multiple of rebuild_every or an atom has moved more than
  * skin/2 since the last build (decided on the device), force with eval =
- * step number, kick.  e_last (may be NULL) receives the energies of the last
- * step; the call synchronises at the end. */
+ * step number, kick.  Each system of a batch decides its own rebuilds.
+ * e_last[n_sys] (may be NULL) receives the energies of the last step; the
+ * call synchronises at the end. */
 rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last);
 
 /* Current positions, velocities, forces (user order, [N][3]) and the eval
@@ -176,6 +200,8 @@ rbsog_status rbsog_profile_enable(rbsog_ctx* ctx, int enable);
 rbsog_status rbsog_profile_read(rbsog_ctx* ctx, double* ms, int64_t* launches);
 
 /* ---- parity exports (host outputs, synchronise) ----------------------- */
+/* These refer to the system chosen by rbsog_select_system; atom ids are that
+ * system's own (0..n_atoms-1). */
 
 /* Core and candidate list sizes n_core[N], n_cand[N]. */
 rbsog_status rbsog_get_list_counts(rbsog_ctx* ctx, int32_t* n_core, int32_t* n_cand);

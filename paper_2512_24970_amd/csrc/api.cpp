@@ -1,5 +1,5 @@
 // C ABI of librbsog (declared in include/rbsog.h): context, validation,
-// planning, kernel sequencing, HIP-graph replay of the step loop, exports.
+// planning of a batch of systems, kernel sequencing, exports.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,22 +70,27 @@ struct rbsog_ctx {
     std::string err;
 
     bool have_system = false;
-    rbsog_params prm{};
+    int R = 0;                       // systems in the batch
+    std::vector<rbsog_params> prm;   // per system, defaults filled in
     bool mixed = false;
     SogSplit sog;
     int chain = 1;
     SogCoef coef{};
-    KTables kt;
-    double u_self = 0.0;
-    uint64_t eval = 0;       // eval index of the last force evaluation
+    std::vector<KTables> kt;
+    std::vector<double> u_self;
+    std::vector<int> slot_off;       // first atom slot of each system (multiple of 256)
+    int n_slots = 0;                 // atom slots of the batch arrays
+    int n_user = 0;                  // atoms of the batch (rows of the caller's arrays)
+    int sel = 0;                     // system the parity exports refer to
+    uint64_t eval = 0;               // eval index of the last force evaluation
     bool forces_valid = false;
 
-    DevSys s{};
-    KDev k{};
-    int n_pair_blocks = 0;
-    int n_kin_blocks = 0;
+    std::vector<DevSys> hs;          // host images of the device system records
+    std::vector<KDev> hk;
+    Plan plan;
 
     // device memory
+    DBuf d_sys, d_kd, d_maps;
     DBuf atoms, sortbuf, cells, lists_core, lists_cand, counts, pair_tab, scalars;
     DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, kin_part, export_tmp, snap;
 
@@ -128,34 +133,21 @@ struct rbsog_ctx {
         open_a = nullptr;
     }
 
-    // step graph
-    hipGraphExec_t graph_exec = nullptr;
-    hipGraph_t graph = nullptr;
-    int graph_kind = -1;  // 0: plain step, 1: step with rebuild
-
     ~rbsog_ctx()
     {
-        drop_graph();
         for (auto& r : recs) {
             (void)hipEventDestroy(r.a);
             (void)hipEventDestroy(r.b);
         }
         for (auto e : pool) (void)hipEventDestroy(e);
     }
-
-    void drop_graph()
-    {
-        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        graph_exec = nullptr;
-        graph = nullptr;
-        graph_kind = -1;
-    }
 };
 
 namespace {
 
 constexpr int kBlock = 256;
+constexpr double kCoulombDefault = 14.399645478425668;
+constexpr double kBoltzmann = 8.617333262e-5;  // eV/K
 
 rbsog_status fail(rbsog_ctx* c, rbsog_status code, const std::string& msg)
 {
@@ -189,6 +181,7 @@ void require(bool ok, rbsog_status code, const std::string& msg)
 }
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
+int blocks_for(int n, int b) { return (n + b - 1) / b; }
 
 void validate(const rbsog_params* p)
 {
@@ -220,85 +213,173 @@ void validate(const rbsog_params* p)
     }
 }
 
-DevSys& sys(rbsog_ctx* c) { return c->s; }
+// Parameters that every system of a batch shares (one SOG split, one pair
+// table, one integrator schedule).
+void require_shared(const rbsog_params& a, const rbsog_params& b)
+{
+    bool same = a.n_species == b.n_species && a.r_core == b.r_core && a.r_shell == b.r_shell &&
+                a.skin == b.skin && a.sog_eps == b.sog_eps && a.dt == b.dt && a.rebuild_every == b.rebuild_every &&
+                a.precision == b.precision && a.coulomb_k == b.coulomb_k;
+    for (int i = 0; same && i < a.n_species; ++i) {
+        same = a.species[i].q == b.species[i].q && a.species[i].mass == b.species[i].mass;
+        for (int j = 0; same && j < a.n_species; ++j) {
+            const rbsog_pair& x = a.pair[i * RBSOG_MAX_SPECIES + j];
+            const rbsog_pair& y = b.pair[i * RBSOG_MAX_SPECIES + j];
+            same = x.A == y.A && x.sigma == y.sigma && x.rho == y.rho && x.C == y.C && x.D == y.D;
+        }
+    }
+    require(same, RBSOG_E_ARG,
+            "systems of a batch must share species, pair table, radii, skin, sog_eps, dt, rebuild_every, "
+            "precision and coulomb_k");
+}
+
+// Device copies of the system records, after a host-side change.
+void upload_sys(rbsog_ctx* c)
+{
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipMemcpy(c->d_sys.p, c->hs.data(), sizeof(DevSys) * c->R, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->d_kd.p, c->hk.data(), sizeof(KDev) * c->R, hipMemcpyHostToDevice));
+}
+
+// Plan of system r alone (parity exports).
+Plan one(const rbsog_ctx* c, int r)
+{
+    Plan P;
+    const DevSys& s = c->hs[r];
+    const KDev& k = c->hk[r];
+    P.sys = c->d_sys.as<DevSys>() + r;
+    P.kd = c->d_kd.as<KDev>() + r;
+    P.sc = c->scalars.as<DeviceScalars>() + r;
+    P.R = 1;
+    P.atoms.blocks = blocks_for(s.n, kBlock);
+    P.cells.blocks = s.n > 0 ? s.ncell : 0;
+    P.atom1.blocks = s.n;
+    // an empty system draws no modes and sums no structure factors
+    P.modes64.blocks = (s.n > 0 && k.sampled) ? blocks_for(k.n_modes, 64) : 0;
+    P.rho.blocks = (s.n > 0 && k.n_modes > 0) ? k.n_chunks * blocks_for(k.n_modes, 64) : 0;
+    P.modes1.blocks = s.n > 0 ? k.n_modes : 0;
+    P.list_mode = c->plan.list_mode;
+    P.cap_core = c->plan.cap_core;
+    P.cap_cand = c->plan.cap_cand;
+    return P;
+}
+
+// Block maps of the batch launches (none for a single system).
+void plan_launches(rbsog_ctx* c)
+{
+    Plan& P = c->plan;
+    P.sys = c->d_sys.as<DevSys>();
+    P.kd = c->d_kd.as<KDev>();
+    P.sc = c->scalars.as<DeviceScalars>();
+    P.R = c->R;
+    if (c->R == 1) {
+        const Plan o = one(c, 0);
+        P.atoms = o.atoms;
+        P.cells = o.cells;
+        P.atom1 = o.atom1;
+        P.modes64 = o.modes64;
+        P.rho = o.rho;
+        P.modes1 = o.modes1;
+        return;
+    }
+    std::vector<int2> m[6];
+    for (int r = 0; r < c->R; ++r) {
+        const Plan o = one(c, r);
+        const Shape* sh[6] = {&o.atoms, &o.cells, &o.atom1, &o.modes64, &o.rho, &o.modes1};
+        for (int q = 0; q < 6; ++q)
+            for (int b = 0; b < sh[q]->blocks; ++b) m[q].push_back(make_int2(r, b));
+    }
+    size_t total = 0;
+    for (auto& v : m) total += v.size();
+    c->d_maps.alloc(sizeof(int2) * std::max<size_t>(1, total));
+    int2* d = c->d_maps.as<int2>();
+    Shape* dst[6] = {&P.atoms, &P.cells, &P.atom1, &P.modes64, &P.rho, &P.modes1};
+    for (int q = 0; q < 6; ++q) {
+        dst[q]->blocks = (int)m[q].size();
+        dst[q]->map = d;
+        if (!m[q].empty()) HIP_OK(hipMemcpy(d, m[q].data(), sizeof(int2) * m[q].size(), hipMemcpyHostToDevice));
+        d += m[q].size();
+    }
+}
 
 void plan_lists(rbsog_ctx* c, int cap_core, int cap_cand)
 {
-    DevSys& s = c->s;
-    const int n = s.n;
-    s.cap_core = cap_core;
-    s.cap_cand = cap_cand;
-    const size_t tiles = (size_t)(n + 63) / 64;
-    c->lists_core.alloc(sizeof(int32_t) * std::max<size_t>(1, tiles * 64 * cap_core));
-    c->lists_cand.alloc(sizeof(int32_t) * std::max<size_t>(1, (size_t)n * cap_cand));
-    s.core_idx = c->lists_core.as<int32_t>();
-    s.cand_idx = c->lists_cand.as<int32_t>();
+    c->plan.cap_core = cap_core;
+    c->plan.cap_cand = cap_cand;
+    const size_t slots = (size_t)std::max(c->n_slots, 64);
+    c->lists_core.alloc(sizeof(int32_t) * slots * cap_core);
+    c->lists_cand.alloc(sizeof(int32_t) * slots * cap_cand);
+    for (int r = 0; r < c->R; ++r) {
+        DevSys& s = c->hs[r];
+        s.cap_core = cap_core;
+        s.cap_cand = cap_cand;
+        // slot offsets are multiples of 64: whole core-list tiles per system
+        s.core_idx = c->lists_core.as<int32_t>() + (size_t)c->slot_off[r] * cap_core;
+        s.cand_idx = c->lists_cand.as<int32_t>() + (size_t)c->slot_off[r] * cap_cand;
+    }
+    upload_sys(c);
 }
 
 void enqueue_build(rbsog_ctx* c, bool gate)
 {
-    DevSys& s = c->s;
-    if (s.n <= 0) return;
     c->begin(RBSOG_PHASE_BUILD);
-    launch_build(s, gate, c->stream);
+    launch_build(c->plan, gate, c->stream);
     c->end();
 }
 
-DeviceScalars read_scalars(rbsog_ctx* c)
+std::vector<DeviceScalars> read_scalars(rbsog_ctx* c)
 {
-    DeviceScalars h{};
-    HIP_OK(hipMemcpyAsync(&h, c->s.sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    std::vector<DeviceScalars> h(c->R);
+    HIP_OK(hipMemcpyAsync(h.data(), c->plan.sc, sizeof(DeviceScalars) * c->R, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     return h;
 }
 
-// Per-atom state (cell order) and device scalars at the start of a step call,
-// for a restart after a list overflow.
+int any_overflow(const std::vector<DeviceScalars>& h)
+{
+    int o = 0;
+    for (const auto& x : h) o |= x.overflow;
+    return o;
+}
+
+// Per-atom state (cell order) and device scalars of every system at the start
+// of a step call, for a restart after a list overflow.
 void snapshot(rbsog_ctx* c, bool save)
 {
-    DevSys& s = c->s;
-    const size_t N = (size_t)std::max(s.n, 1);
-    const size_t bytes = N * (10 * sizeof(double) + 3 * sizeof(int32_t)) + sizeof(DeviceScalars);
+    const size_t N = (size_t)std::max(c->n_slots, 1);
+    const size_t bytes = N * (sizeof(double4) + 6 * sizeof(double) + 3 * sizeof(int32_t)) +
+                         sizeof(DeviceScalars) * c->R;
     if (save && c->snap.bytes < bytes) c->snap.alloc(bytes);
-    double* d = c->snap.as<double>();
-    double* arr[6] = {s.vx, s.vy, s.vz, s.fx, s.fy, s.fz};
-    int32_t* iar[3] = {s.type, s.id, s.inv};
-    int32_t* ip = reinterpret_cast<int32_t*>(d + 10 * N);
-    auto cp = [&](void* dst, const void* src, size_t b) {
-        HIP_OK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, c->stream));
+    const DevSys& s = c->hs[0];  // system 0 starts at slot 0: its pointers are the batch arrays
+    char* d = c->snap.as<char>();
+    struct Arr {
+        void* p;
+        size_t b;
     };
-    if (save)
-        cp(d, s.p, sizeof(double4) * s.n);
-    else
-        cp(s.p, d, sizeof(double4) * s.n);
-    for (int q = 0; q < 6; ++q) {
+    const Arr arr[] = {{s.p, sizeof(double4)}, {s.vx, 8}, {s.vy, 8}, {s.vz, 8}, {s.fx, 8}, {s.fy, 8},
+                       {s.fz, 8},              {s.type, 4}, {s.id, 4}, {s.inv, 4},
+                       {c->plan.sc, 0}};
+    for (const Arr& a : arr) {
+        const size_t b = a.b ? a.b * N : sizeof(DeviceScalars) * c->R;
         if (save)
-            cp(d + (4 + q) * N, arr[q], sizeof(double) * s.n);
+            HIP_OK(hipMemcpyAsync(d, a.p, b, hipMemcpyDeviceToDevice, c->stream));
         else
-            cp(arr[q], d + (4 + q) * N, sizeof(double) * s.n);
+            HIP_OK(hipMemcpyAsync(a.p, d, b, hipMemcpyDeviceToDevice, c->stream));
+        d += b;
     }
-    for (int q = 0; q < 3; ++q) {
-        if (save)
-            cp(ip + q * N, iar[q], sizeof(int32_t) * s.n);
-        else
-            cp(iar[q], ip + q * N, sizeof(int32_t) * s.n);
-    }
-    void* sc_copy = ip + 3 * N;
-    if (save)
-        cp(sc_copy, s.sc, sizeof(DeviceScalars));
-    else
-        cp(s.sc, sc_copy, sizeof(DeviceScalars));
 }
 
 // Grow list capacities from the true counts of the last build.
 void grow_lists(rbsog_ctx* c)
 {
-    const DeviceScalars h = read_scalars(c);
-    const int mc = h.max_core, mk = h.max_cand;
-    const int cap_core = std::max(c->s.cap_core, round_up(mc + mc / 4 + 8, 32));
-    const int cap_cand = std::max(c->s.cap_cand, round_up(mk + mk / 4 + 8, 32));
+    int mc = 0, mk = 0;
+    for (const auto& h : read_scalars(c)) {
+        mc = std::max(mc, h.max_core);
+        mk = std::max(mk, h.max_cand);
+    }
+    const int cap_core = std::max(c->plan.cap_core, round_up(mc + mc / 4 + 8, 32));
+    const int cap_cand = std::max(c->plan.cap_cand, round_up(mk + mk / 4 + 8, 32));
     require(cap_cand <= 4096 && cap_core <= 4096, RBSOG_E_CAPACITY, "neighbour list capacity above 4096");
-    c->drop_graph();
     plan_lists(c, cap_core, cap_cand);
 }
 
@@ -306,15 +387,14 @@ void grow_lists(rbsog_ctx* c)
 void build_checked(rbsog_ctx* c)
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
-        launch_clear_flags(c->s.sc, c->stream);
+        launch_clear_flags(c->plan, c->stream);
         enqueue_build(c, false);
-        DeviceScalars h = read_scalars(c);
-        if (h.overflow == 0) return;
-        if (h.overflow & 2) throw Error(RBSOG_E_CAPACITY, "a cell holds more than 2048 atoms");
-        if (h.overflow & 4) {
+        const int o = any_overflow(read_scalars(c));
+        if (o == 0) return;
+        if (o & 2) throw Error(RBSOG_E_CAPACITY, "a cell holds more than 2048 atoms");
+        if (o & 4) {
             // a cell's stencil did not fit in LDS: larger stencil, then per-atom lists
-            c->s.list_mode = std::min(2, c->s.list_mode + 1);
-            c->drop_graph();
+            c->plan.list_mode = std::min(2, c->plan.list_mode + 1);
             continue;
         }
         grow_lists(c);
@@ -322,233 +402,318 @@ void build_checked(rbsog_ctx* c)
     throw Error(RBSOG_E_CAPACITY, "list capacity did not converge");
 }
 
+bool any_thermostat(const rbsog_ctx* c)
+{
+    for (const auto& s : c->hs)
+        if (s.thermo_c > 0.0) return true;
+    return false;
+}
+
 void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
 {
-    const bool ke = energy || (kick && c->s.thermo_c > 0.0);
-    DevSys& s = c->s;
-    KDev& k = c->k;
+    const bool ke = energy || (kick && any_thermostat(c));
+    const Plan& P = c->plan;
     hipStream_t st = c->stream;
-    if (s.n <= 0) return;
-    if (k.sampled) {
+    if (P.atoms.blocks <= 0) return;
+    if (P.modes64.blocks > 0) {
         c->begin(RBSOG_PHASE_KSAMPLE);
-        launch_ksample(s, k, st);
+        launch_ksample(P, st);
         c->end();
     }
     c->begin(RBSOG_PHASE_PAIR);
-    launch_pair(s, c->coef, c->mixed, energy, c->pair_part.as<double>(), c->n_pair_blocks, st);
+    launch_pair(P, c->coef, c->mixed, energy, st);
     c->end();
     c->begin(RBSOG_PHASE_RHO);
-    launch_rho(s, k, c->mixed, st);
+    launch_rho(P, c->mixed, st);
     c->end();
     c->begin(RBSOG_PHASE_REDUCE);
-    launch_rho_finalize(s, k, st);
-    launch_finalize(s, k, c->pair_part.as<double>(), c->n_pair_blocks, st);
+    launch_rho_finalize(P, st);
+    launch_finalize(P, st);
     c->end();
     c->begin(RBSOG_PHASE_KFORCE);
-    launch_kforce(s, k, c->mixed, kick, ke, c->kin_part.as<double>(), st);
+    launch_kforce(P, c->mixed, kick, ke, st);
     c->end();
-    if (ke) launch_kinetic_finalize(s, c->kin_part.as<double>(), c->n_kin_blocks, st);
+    if (ke) launch_kinetic_finalize(P, st);
 }
 
-void fill_energy(rbsog_ctx* c, const DeviceScalars& h, rbsog_energy* e)
+void fill_energy(rbsog_ctx* c, const std::vector<DeviceScalars>& hv, rbsog_energy* e)
 {
-    e->u_core = h.u_core;
-    e->u_shell = h.u_shell;
-    e->u_kspace = h.u_kspace;
-    e->u_self = c->u_self;
-    e->u_total = h.u_core + h.u_shell + h.u_kspace - c->u_self;
-    e->kinetic = h.kinetic;
-    for (int a = 0; a < 3; ++a) e->p_corr[a] = h.p_corr[a];
-    e->max_disp = std::sqrt(h.max_disp2);
-    e->n_builds = h.n_builds;
+    for (int r = 0; r < c->R; ++r) {
+        const DeviceScalars& h = hv[r];
+        e[r].u_core = h.u_core;
+        e[r].u_shell = h.u_shell;
+        e[r].u_kspace = h.u_kspace;
+        e[r].u_self = c->u_self[r];
+        e[r].u_total = h.u_core + h.u_shell + h.u_kspace - c->u_self[r];
+        e[r].kinetic = h.kinetic;
+        for (int a = 0; a < 3; ++a) e[r].p_corr[a] = h.p_corr[a];
+        e[r].max_disp = std::sqrt(h.max_disp2);
+        e[r].n_builds = h.n_builds;
+    }
 }
 
-void check_flags(const DeviceScalars& h)
+void check_flags(const std::vector<DeviceScalars>& h)
 {
-    if (h.overflow) throw Error(RBSOG_E_CAPACITY, "list capacity exceeded during the step loop");
+    if (any_overflow(h)) throw Error(RBSOG_E_CAPACITY, "list capacity exceeded during the step loop");
 }
 
-// One step on the stream: kick + drift, rebuild if scheduled or if an atom
-// moved more than skin/2 since the last build (decided on the device),
-// forces, kick.
+// One step on the stream: kick + drift, rebuild of the systems whose step is
+// scheduled or where an atom moved more than skin/2 since their last build
+// (decided on the device), forces, kick.
 void enqueue_step(rbsog_ctx* c, bool scheduled, bool energy)
 {
     c->begin(RBSOG_PHASE_INTEGRATE);
-    launch_bump_eval(c->s.sc, c->stream);
-    launch_kick_drift(c->s, scheduled, c->stream);
+    launch_bump_eval(c->plan, c->stream);
+    launch_kick_drift(c->plan, scheduled, c->stream);
     c->end();
     enqueue_build(c, true);
     enqueue_forces(c, energy, true);
 }
 
-void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, const double* pos,
-                     const double* vel, int on_device)
+// Geometry, cutoffs, species and integrator constants of one system.
+void init_devsys(const rbsog_params& p, int n, DevSys& s)
 {
-    validate(p);
-    const int n = p->n_atoms;
-    require(n == 0 || (type && pos), RBSOG_E_ARG, "type and pos are required");
-    // host copies of the inputs for validation
-    std::vector<int32_t> ht(n);
-    std::vector<double> hp(3 * (size_t)n), hv;
-    if (n > 0) {
-        if (on_device) {
-            HIP_OK(hipMemcpy(ht.data(), type, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
-            HIP_OK(hipMemcpy(hp.data(), pos, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
-        } else {
-            std::memcpy(ht.data(), type, sizeof(int32_t) * n);
-            std::memcpy(hp.data(), pos, sizeof(double) * 3 * n);
-        }
-        if (vel) {
-            hv.resize(3 * (size_t)n);
-            if (on_device)
-                HIP_OK(hipMemcpy(hv.data(), vel, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
-            else
-                std::memcpy(hv.data(), vel, sizeof(double) * 3 * n);
-        }
-    }
-    double qsum = 0.0, qabs = 0.0;
-    for (int i = 0; i < n; ++i) {
-        require(ht[i] >= 0 && ht[i] < p->n_species, RBSOG_E_ARG, "atom type out of range");
-        qsum += p->species[ht[i]].q;
-        qabs += std::fabs(p->species[ht[i]].q);
-    }
-    for (double v : hp) require(std::isfinite(v), RBSOG_E_NONFINITE, "non-finite position");
-    for (double v : hv) require(std::isfinite(v), RBSOG_E_NONFINITE, "non-finite velocity");
-    require(std::fabs(qsum) <= 1e-9 * std::max(1.0, qabs), RBSOG_E_NONNEUTRAL, "system is not charge neutral");
-
-    // SOG split and coefficients
-    c->drop_graph();
-    c->prm = *p;
-    if (!(c->prm.coulomb_k > 0.0)) c->prm.coulomb_k = 14.399645478425668;
-    if (!(c->prm.sog_eps > 0.0)) c->prm.sog_eps = 1e-5;
-    c->mixed = p->precision == RBSOG_MIXED;
-    std::string err;
-    if (!sog_split(c->prm.sog_eps, p->r_shell, &c->sog, &err)) throw Error(RBSOG_E_ARG, err);
-    sog_base(c->prm.sog_eps, &c->chain);
-    if (!sog_kernel_coef(c->sog, c->chain, p->r_shell, c->mixed, &c->coef, &err)) throw Error(RBSOG_E_ARG, err);
-    double wsum = 0.0;
-    for (double w : c->sog.w) wsum += w;
-    double q2 = 0.0;
-    for (int i = 0; i < n; ++i) q2 += p->species[ht[i]].q * p->species[ht[i]].q;
-    c->u_self = 0.5 * c->prm.coulomb_k * q2 * wsum;
-
-    DevSys& s = c->s;
     s = DevSys{};
     s.n = n;
-    s.n_species = p->n_species;
-    const double cutoff = p->r_shell + p->skin;
+    s.n_species = p.n_species;
+    const double cutoff = p.r_shell + p.skin;
     s.ncell = 1;
     for (int a = 0; a < 3; ++a) {
-        s.L[a] = p->box[a];
-        s.invL[a] = 1.0 / p->box[a];
-        int nc = (int)std::floor(p->box[a] / (cutoff + 1e-9));
+        s.L[a] = p.box[a];
+        s.invL[a] = 1.0 / p.box[a];
+        int nc = (int)std::floor(p.box[a] / (cutoff + 1e-9));
         if (nc < 3) nc = 1;
         s.nc[a] = nc;
-        s.cell_scale[a] = (double)nc / p->box[a];
-        s.two_pi_L[a] = 2.0 * kPi / p->box[a];
+        s.cell_scale[a] = (double)nc / p.box[a];
+        s.two_pi_L[a] = 2.0 * kPi / p.box[a];
         s.ncell *= nc;
     }
-    const double rcl = p->r_core + p->skin;
+    const double rcl = p.r_core + p.skin;
     s.rc2_list = rcl * rcl;
-    const double lo = p->r_core - p->skin;
+    const double lo = p.r_core - p.skin;
     s.lo2_list = lo > 0.0 ? lo * lo : 0.0;
-    const double hi = p->r_shell + p->skin;
+    const double hi = p.r_shell + p.skin;
     s.hi2_list = hi * hi;
-    s.rc2 = p->r_core * p->r_core;
-    s.rs2 = p->r_shell * p->r_shell;
-    s.half_skin2 = 0.25 * p->skin * p->skin;
-    s.dt = p->dt;
-    s.coulomb_k = c->prm.coulomb_k;
-    const bool thermo = p->t_target > 0.0 && p->tau_t > 0.0;
-    s.thermo_c = thermo ? p->dt / p->tau_t : 0.0;
-    s.t_target = thermo ? p->t_target : 0.0;
-    s.dof_kb = (3.0 * n - 3.0) * 8.617333262e-5;
-    s.p_r = p->p_r;
-    s.replica = p->replica;
-    s.seed = p->seed;
-    for (int t = 0; t < RBSOG_MAX_SPECIES; ++t) {
-        s.q[t] = t < p->n_species ? p->species[t].q : 0.0;
-        s.mass[t] = t < p->n_species ? p->species[t].mass : 1.0;
-        s.inv_mass_acc[t] = kAccUnit / s.mass[t];
+    s.rc2 = p.r_core * p.r_core;
+    s.rs2 = p.r_shell * p.r_shell;
+    s.half_skin2 = 0.25 * p.skin * p.skin;
+    s.dt = p.dt;
+    s.coulomb_k = p.coulomb_k;
+    const bool thermo = p.t_target > 0.0 && p.tau_t > 0.0;
+    s.thermo_c = thermo ? p.dt / p.tau_t : 0.0;
+    s.t_target = thermo ? p.t_target : 0.0;
+    s.dof_kb = (3.0 * n - 3.0) * kBoltzmann;
+    s.p_r = p.p_r;
+    s.replica = p.replica;
+    s.seed = p.seed;
+}
+
+// Host copies of the caller's arrays (validation; staging of host inputs).
+void fetch_inputs(const int32_t* type, const double* pos, const double* vel, int n, int on_device,
+                  std::vector<int32_t>& ht, std::vector<double>& hp, std::vector<double>& hv)
+{
+    ht.resize(n);
+    hp.resize(3 * (size_t)n);
+    hv.clear();
+    if (n <= 0) return;
+    if (on_device) {
+        HIP_OK(hipMemcpy(ht.data(), type, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(hp.data(), pos, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(ht.data(), type, sizeof(int32_t) * n);
+        std::memcpy(hp.data(), pos, sizeof(double) * 3 * n);
+    }
+    if (vel) {
+        hv.resize(3 * (size_t)n);
+        if (on_device)
+            HIP_OK(hipMemcpy(hv.data(), vel, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+        else
+            std::memcpy(hv.data(), vel, sizeof(double) * 3 * n);
+    }
+}
+
+void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32_t* type, const double* pos,
+                    const double* vel, int on_device)
+{
+    require(R >= 1, RBSOG_E_ARG, "a batch needs at least one system");
+    require(params != nullptr, RBSOG_E_ARG, "params is NULL");
+    std::vector<rbsog_params> prm(params, params + R);
+    for (auto& p : prm) {
+        validate(&p);
+        if (!(p.coulomb_k > 0.0)) p.coulomb_k = kCoulombDefault;
+        if (!(p.sog_eps > 0.0)) p.sog_eps = 1e-5;
+    }
+    for (int r = 1; r < R; ++r) require_shared(prm[0], prm[r]);
+    std::vector<int> user_off(R + 1, 0), slot_off(R + 1, 0);
+    for (int r = 0; r < R; ++r) {
+        const int n = prm[r].n_atoms;
+        require((int64_t)user_off[r] + n < (1ll << 30), RBSOG_E_ARG, "batch too large");
+        user_off[r + 1] = user_off[r] + n;
+        slot_off[r + 1] = slot_off[r] + round_up(n, kBlock);
+    }
+    const int n_user = user_off[R];
+    require(n_user == 0 || (type && pos), RBSOG_E_ARG, "type and pos are required");
+    std::vector<int32_t> ht;
+    std::vector<double> hp, hv;
+    fetch_inputs(type, pos, vel, n_user, on_device, ht, hp, hv);
+    for (double v : hp) require(std::isfinite(v), RBSOG_E_NONFINITE, "non-finite position");
+    for (double v : hv) require(std::isfinite(v), RBSOG_E_NONFINITE, "non-finite velocity");
+    std::vector<double> q2(R, 0.0);
+    for (int r = 0; r < R; ++r) {
+        double qsum = 0.0, qabs = 0.0;
+        for (int i = user_off[r]; i < user_off[r + 1]; ++i) {
+            require(ht[i] >= 0 && ht[i] < prm[r].n_species, RBSOG_E_ARG, "atom type out of range");
+            const double q = prm[r].species[ht[i]].q;
+            qsum += q;
+            qabs += std::fabs(q);
+            q2[r] += q * q;
+        }
+        require(std::fabs(qsum) <= 1e-9 * std::max(1.0, qabs), RBSOG_E_NONNEUTRAL,
+                R == 1 ? "system is not charge neutral" : "a system of the batch is not charge neutral");
     }
 
-    // per-atom arrays: a packed position record, 12 doubles, 3 int32
-    const size_t N = (size_t)std::max(n, 1);
+    // SOG split and coefficients (shared)
+    const rbsog_params& p0 = prm[0];
+    c->mixed = p0.precision == RBSOG_MIXED;
+    std::string err;
+    if (!sog_split(p0.sog_eps, p0.r_shell, &c->sog, &err)) throw Error(RBSOG_E_ARG, err);
+    sog_base(p0.sog_eps, &c->chain);
+    if (!sog_kernel_coef(c->sog, c->chain, p0.r_shell, c->mixed, &c->coef, &err)) throw Error(RBSOG_E_ARG, err);
+    double wsum = 0.0;
+    for (double w : c->sog.w) wsum += w;
+
+    c->R = R;
+    c->prm = prm;
+    c->sel = 0;
+    c->slot_off.assign(slot_off.begin(), slot_off.end() - 1);
+    c->n_slots = slot_off[R];
+    c->n_user = n_user;
+    c->u_self.assign(R, 0.0);
+    c->hs.assign(R, DevSys{});
+    c->hk.assign(R, KDev{});
+    c->kt.assign(R, KTables{});
+    for (int r = 0; r < R; ++r) {
+        init_devsys(prm[r], prm[r].n_atoms, c->hs[r]);
+        c->hs[r].user_off = user_off[r];
+        c->u_self[r] = 0.5 * p0.coulomb_k * q2[r] * wsum;
+    }
+    c->d_sys.alloc(sizeof(DevSys) * R);
+    c->d_kd.alloc(sizeof(KDev) * R);
+
+    // per-atom arrays of the batch: a packed position record, 12 doubles,
+    // 3 int32 per slot; system r owns slots [slot_off[r], slot_off[r] + n_r)
+    const size_t N = (size_t)std::max(c->n_slots, 1);
     c->atoms.alloc(N * (sizeof(double4) + 12 * sizeof(double) + 3 * sizeof(int32_t)));
-    {
-        s.p = c->atoms.as<double4>();
-        double* d = reinterpret_cast<double*>(s.p + N);
-        double** slots[] = {&s.vx, &s.vy, &s.vz, &s.fx, &s.fy, &s.fz, &s.fsx, &s.fsy, &s.fsz, &s.xr, &s.yr, &s.zr};
-        for (int t = 0; t < 12; ++t) *slots[t] = d + t * N;
-        int32_t* ip = reinterpret_cast<int32_t*>(d + 12 * N);
-        s.type = ip;
-        s.id = ip + N;
-        s.inv = ip + 2 * N;
-    }
     c->sortbuf.alloc(N * (sizeof(double4) + 6 * sizeof(double) + 5 * sizeof(int32_t)));
-    {
-        s.tp = c->sortbuf.as<double4>();
-        double* d = reinterpret_cast<double*>(s.tp + N);
-        double** slots[] = {&s.tvx, &s.tvy, &s.tvz, &s.tfx, &s.tfy, &s.tfz};
-        for (int t = 0; t < 6; ++t) *slots[t] = d + t * N;
-        int32_t* ip = reinterpret_cast<int32_t*>(d + 6 * N);
-        s.ttype = ip;
-        s.tid = ip + N;
-        s.cell_of = ip + 2 * N;
-        s.slot_of = ip + 3 * N;
-        s.order = ip + 4 * N;
-    }
-    c->cells.alloc(sizeof(int32_t) * (2 * (size_t)s.ncell + 1));
-    s.cell_count = c->cells.as<int32_t>();
-    s.cell_start = s.cell_count + s.ncell;
-    HIP_OK(hipMemsetAsync(s.cell_count, 0, sizeof(int32_t) * s.ncell, c->stream));
     c->counts.alloc(2 * sizeof(int32_t) * N);
-    s.core_cnt = c->counts.as<int32_t>();
-    s.cand_cnt = s.core_cnt + N;
-    HIP_OK(hipMemsetAsync(s.core_cnt, 0, 2 * sizeof(int32_t) * N, c->stream));
+    HIP_OK(hipMemsetAsync(c->counts.p, 0, 2 * sizeof(int32_t) * N, c->stream));
+    size_t n_cells = 0;
+    for (const auto& s : c->hs) n_cells += 2 * (size_t)s.ncell + 1;
+    c->cells.alloc(sizeof(int32_t) * n_cells);
+    HIP_OK(hipMemsetAsync(c->cells.p, 0, sizeof(int32_t) * n_cells, c->stream));
+    size_t n_blocks = 0;
+    for (const auto& s : c->hs) n_blocks += blocks_for(s.n, kBlock);
+    c->pair_part.alloc(sizeof(double) * kPairPart * std::max<size_t>(1, n_blocks));
+    c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_blocks));
+    c->scalars.alloc(sizeof(DeviceScalars) * R);
+    HIP_OK(hipMemsetAsync(c->scalars.p, 0, sizeof(DeviceScalars) * R, c->stream));
+    {
+        double4* P = c->atoms.as<double4>();
+        double* d = reinterpret_cast<double*>(P + N);
+        int32_t* ip = reinterpret_cast<int32_t*>(d + 12 * N);
+        double4* TP = c->sortbuf.as<double4>();
+        double* td = reinterpret_cast<double*>(TP + N);
+        int32_t* tip = reinterpret_cast<int32_t*>(td + 6 * N);
+        int32_t* cells = c->cells.as<int32_t>();
+        size_t blk = 0;
+        for (int r = 0; r < R; ++r) {
+            DevSys& s = c->hs[r];
+            const size_t o = (size_t)c->slot_off[r];
+            s.p = P + o;
+            double** slots[] = {&s.vx, &s.vy, &s.vz, &s.fx, &s.fy, &s.fz, &s.fsx, &s.fsy, &s.fsz, &s.xr, &s.yr, &s.zr};
+            for (int t = 0; t < 12; ++t) *slots[t] = d + t * N + o;
+            s.type = ip + o;
+            s.id = ip + N + o;
+            s.inv = ip + 2 * N + o;
+            s.tp = TP + o;
+            double** tslots[] = {&s.tvx, &s.tvy, &s.tvz, &s.tfx, &s.tfy, &s.tfz};
+            for (int t = 0; t < 6; ++t) *tslots[t] = td + t * N + o;
+            s.ttype = tip + o;
+            s.tid = tip + N + o;
+            s.cell_of = tip + 2 * N + o;
+            s.slot_of = tip + 3 * N + o;
+            s.order = tip + 4 * N + o;
+            s.core_cnt = c->counts.as<int32_t>() + o;
+            s.cand_cnt = c->counts.as<int32_t>() + N + o;
+            s.cell_count = cells;
+            s.cell_start = cells + s.ncell;
+            cells += 2 * (size_t)s.ncell + 1;
+            s.pair_part = c->pair_part.as<double>() + blk * kPairPart;
+            s.kin_part = c->kin_part.as<double>() + blk;
+            blk += blocks_for(s.n, kBlock);
+            s.sc = c->scalars.as<DeviceScalars>() + r;
+        }
+    }
 
-    // pair coefficient table
-    std::vector<PairCoef> pcs(p->n_species * p->n_species);
-    for (int i = 0; i < p->n_species; ++i)
-        for (int j = 0; j < p->n_species; ++j) {
-            const rbsog_pair& a = p->pair[i * RBSOG_MAX_SPECIES + j];
-            PairCoef& pc = pcs[i * p->n_species + j];
-            pc.qq = c->prm.coulomb_k * p->species[i].q * p->species[j].q;
+    // pair coefficient table (shared)
+    std::vector<PairCoef> pcs(p0.n_species * p0.n_species);
+    for (int i = 0; i < p0.n_species; ++i)
+        for (int j = 0; j < p0.n_species; ++j) {
+            const rbsog_pair& a = p0.pair[i * RBSOG_MAX_SPECIES + j];
+            PairCoef& pc = pcs[i * p0.n_species + j];
+            pc.qq = p0.coulomb_k * p0.species[i].q * p0.species[j].q;
             pc.A = a.A;
             pc.sig = a.sigma;
             pc.irho = a.rho > 0.0 ? 1.0 / a.rho : 0.0;
             pc.C = a.C;
             pc.D = a.D;
         }
-    c->pair_tab.alloc(sizeof(PairCoef) * pcs.size());
+    SpeciesDev spc{};
+    for (int t = 0; t < RBSOG_MAX_SPECIES; ++t) {
+        spc.q[t] = t < p0.n_species ? p0.species[t].q : 0.0;
+        spc.mass[t] = t < p0.n_species ? p0.species[t].mass : 1.0;
+        spc.inv_mass_acc[t] = kAccUnit / spc.mass[t];
+    }
+    const size_t pair_bytes = round_up((int)(sizeof(PairCoef) * pcs.size()), 256);
+    c->pair_tab.alloc(pair_bytes + sizeof(SpeciesDev));
     HIP_OK(hipMemcpy(c->pair_tab.p, pcs.data(), sizeof(PairCoef) * pcs.size(), hipMemcpyHostToDevice));
-    s.pair = c->pair_tab.as<PairCoef>();
-    c->scalars.alloc(sizeof(DeviceScalars));
-    s.sc = c->scalars.as<DeviceScalars>();
-    HIP_OK(hipMemsetAsync(s.sc, 0, sizeof(DeviceScalars), c->stream));
-
-    // list capacities from the density
-    const double V = p->box[0] * p->box[1] * p->box[2];
-    const double rho_n = n / V;
-    const double vc = 4.0 / 3.0 * kPi * rcl * rcl * rcl;
-    const double lo3 = lo > 0.0 ? lo * lo * lo : 0.0;
-    const double vk = 4.0 / 3.0 * kPi * (hi * hi * hi - lo3);
-    // room for local densities well above the mean (melting lattices, clusters);
-    // the step loop grows the lists if they still overflow
-    const int cap_core = std::min(std::max(round_up((int)(1.8 * vc * rho_n) + 32, 32), 32), std::max(32, round_up(n, 32)));
-    const int cap_cand = std::min(std::max(round_up((int)(1.5 * vk * rho_n) + 32, 32), 32), std::max(32, round_up(n, 32)));
-    plan_lists(c, cap_core, cap_cand);
-    {
-        double cell_vol = 1.0;
-        for (int a = 0; a < 3; ++a) cell_vol *= p->box[a] / s.nc[a];
-        const int ncell_st = (s.nc[0] >= 3 ? 3 : 1) * (s.nc[1] >= 3 ? 3 : 1) * (s.nc[2] >= 3 ? 3 : 1);
-        const double stencil = std::min<double>(n, ncell_st * cell_vol * rho_n);
-        s.list_mode = stencil * 1.3 + 64 <= 2048 ? 0 : (stencil * 1.3 + 64 <= 4096 ? 1 : 2);
+    SpeciesDev* d_spc = reinterpret_cast<SpeciesDev*>(c->pair_tab.as<char>() + pair_bytes);
+    HIP_OK(hipMemcpy(d_spc, &spc, sizeof(SpeciesDev), hipMemcpyHostToDevice));
+    for (auto& s : c->hs) {
+        s.pair = c->pair_tab.as<PairCoef>();
+        s.spc = d_spc;
     }
 
-    // k-space
-    KDev& k = c->k;
-    k = KDev{};
+    // list capacities from the densest system; the list kernel from the
+    // largest stencil
+    int cap_core = 32, cap_cand = 32, list_mode = 0, n_max = 0;
+    for (int r = 0; r < R; ++r) {
+        const rbsog_params& p = prm[r];
+        const DevSys& s = c->hs[r];
+        const int n = s.n;
+        n_max = std::max(n_max, n);
+        const double V = p.box[0] * p.box[1] * p.box[2];
+        const double rho_n = n / V;
+        const double rcl = p.r_core + p.skin, lo = p.r_core - p.skin, hi = p.r_shell + p.skin;
+        const double vc = 4.0 / 3.0 * kPi * rcl * rcl * rcl;
+        const double lo3 = lo > 0.0 ? lo * lo * lo : 0.0;
+        const double vk = 4.0 / 3.0 * kPi * (hi * hi * hi - lo3);
+        // room for local densities well above the mean (melting lattices,
+        // clusters); the step loop grows the lists if they still overflow
+        cap_core = std::max(cap_core, round_up((int)(1.8 * vc * rho_n) + 32, 32));
+        cap_cand = std::max(cap_cand, round_up((int)(1.5 * vk * rho_n) + 32, 32));
+        double cell_vol = 1.0;
+        for (int a = 0; a < 3; ++a) cell_vol *= p.box[a] / s.nc[a];
+        const int ncell_st = (s.nc[0] >= 3 ? 3 : 1) * (s.nc[1] >= 3 ? 3 : 1) * (s.nc[2] >= 3 ? 3 : 1);
+        const double stencil = std::min<double>(n, ncell_st * cell_vol * rho_n);
+        list_mode = std::max(list_mode, stencil * 1.3 + 64 <= 2048 ? 0 : (stencil * 1.3 + 64 <= 4096 ? 1 : 2));
+    }
+    cap_core = std::min(cap_core, std::max(32, round_up(n_max, 32)));
+    cap_cand = std::min(cap_cand, std::max(32, round_up(n_max, 32)));
+    c->plan.list_mode = list_mode;
+
+    // k-space: the shared sincos table, then per system its sampling tables
+    // (or enumerated modes) and mode arrays
     std::vector<double> table(2 * kTableSize);
     for (int j = 0; j < kTableSize; ++j) {
         table[2 * j] = std::cos(2.0 * kPi * j / kTableSize);
@@ -556,89 +721,118 @@ void set_system_impl(rbsog_ctx* c, const rbsog_params* p, const int32_t* type, c
     }
     c->ktab.alloc(sizeof(double) * table.size());
     HIP_OK(hipMemcpy(c->ktab.p, table.data(), sizeof(double) * table.size(), hipMemcpyHostToDevice));
-    k.table = c->ktab.as<double>();
-    std::vector<int32_t> em;
-    std::vector<double> ecoef;
-    if (p->p_f > 0) {
-        build_ktables(c->sog, p->box, &c->kt);
-        k.sampled = 1;
-        k.n_modes = p->p_f;
-        k.nm = c->kt.nm;
-        k.S = c->kt.S;
-        k.coef_scale = c->kt.S / ((double)p->p_f * V);
-        const size_t nt = c->kt.g0cdf.size();
-        const size_t bytes = sizeof(double) * (2 * nt + c->kt.comp_cdf.size()) + sizeof(int32_t) * 2 * c->kt.off.size();
-        c->kcdf.alloc(bytes);
-        double* d = c->kcdf.as<double>();
-        HIP_OK(hipMemcpy(d, c->kt.g0cdf.data(), sizeof(double) * nt, hipMemcpyHostToDevice));
-        HIP_OK(hipMemcpy(d + nt, c->kt.g2cdf.data(), sizeof(double) * nt, hipMemcpyHostToDevice));
-        HIP_OK(hipMemcpy(d + 2 * nt, c->kt.comp_cdf.data(), sizeof(double) * c->kt.comp_cdf.size(),
-                         hipMemcpyHostToDevice));
-        int32_t* ip = reinterpret_cast<int32_t*>(d + 2 * nt + c->kt.comp_cdf.size());
-        HIP_OK(hipMemcpy(ip, c->kt.off.data(), sizeof(int32_t) * c->kt.off.size(), hipMemcpyHostToDevice));
-        HIP_OK(hipMemcpy(ip + c->kt.off.size(), c->kt.len.data(), sizeof(int32_t) * c->kt.len.size(),
-                         hipMemcpyHostToDevice));
-        k.g0cdf = d;
-        k.g2cdf = d + nt;
-        k.comp_cdf = d + 2 * nt;
-        k.off = ip;
-        k.len = ip + c->kt.off.size();
-    } else {
-        enumerate_modes(c->sog, p->box, &em, &ecoef);
-        k.sampled = 0;
-        k.n_modes = (int)ecoef.size();
-        k.S = 0.0;
-        c->kt = KTables{};
-    }
-    const int tiles = (k.n_modes + 63) / 64;
-    k.n_modes_pad = std::max(1, tiles) * 64;
-    const int max_chunks = std::max(1, (n + 255) / 256);
-    k.n_chunks = std::min(max_chunks, std::max(1, (2048 + std::max(tiles, 1) - 1) / std::max(tiles, 1)));
-    // a multiple of 16 atoms: the rho kernel splits a chunk into four
-    // quarters read four atoms at a time
-    k.chunk = (std::max(1, (n + k.n_chunks - 1) / k.n_chunks) + 15) & ~15;
-    k.n_chunks = std::max(1, (n + k.chunk - 1) / k.chunk);
-    c->kmodes.alloc(std::max<size_t>(1, (size_t)k.n_modes) * (sizeof(ModeRec) + 3 * sizeof(int32_t)));
-    k.modes = c->kmodes.as<ModeRec>();
-    k.m = reinterpret_cast<int32_t*>(k.modes + std::max(1, k.n_modes));
-    if (!k.sampled && k.n_modes > 0) {
-        std::vector<ModeRec> recs(k.n_modes);
-        for (int q = 0; q < k.n_modes; ++q) {
-            recs[q] = ModeRec{(double)em[3 * q], (double)em[3 * q + 1], (double)em[3 * q + 2], 0.0, 0.0, ecoef[q], 0.0, 0.0f, 0.0f};
+    std::vector<std::vector<int32_t>> em(R);
+    std::vector<std::vector<double>> ecoef(R);
+    size_t cdf_doubles = 0, cdf_ints = 0, n_modes_all = 0, rho_part_all = 0;
+    for (int r = 0; r < R; ++r) {
+        const rbsog_params& p = prm[r];
+        KDev& k = c->hk[r];
+        k = KDev{};
+        k.table = c->ktab.as<double>();
+        const double V = p.box[0] * p.box[1] * p.box[2];
+        if (p.p_f > 0) {
+            build_ktables(c->sog, p.box, &c->kt[r]);
+            const KTables& t = c->kt[r];
+            k.sampled = 1;
+            k.n_modes = p.p_f;
+            k.nm = t.nm;
+            k.S = t.S;
+            k.coef_scale = t.S / ((double)p.p_f * V);
+            cdf_doubles += 2 * t.g0cdf.size() + t.comp_cdf.size();
+            cdf_ints += 2 * t.off.size();
+        } else {
+            enumerate_modes(c->sog, p.box, &em[r], &ecoef[r]);
+            k.sampled = 0;
+            k.n_modes = (int)ecoef[r].size();
+            k.S = 0.0;
         }
-        HIP_OK(hipMemcpy(k.modes, recs.data(), sizeof(ModeRec) * k.n_modes, hipMemcpyHostToDevice));
-        HIP_OK(hipMemcpy(k.m, em.data(), sizeof(int32_t) * em.size(), hipMemcpyHostToDevice));
+        const int n = c->hs[r].n;
+        const int tiles = (k.n_modes + 63) / 64;
+        k.n_modes_pad = std::max(1, tiles) * 64;
+        const int max_chunks = std::max(1, (n + 255) / 256);
+        k.n_chunks = std::min(max_chunks, std::max(1, (2048 + std::max(tiles, 1) - 1) / std::max(tiles, 1)));
+        // a multiple of 16 atoms: the rho kernel splits a chunk into four
+        // quarters read four atoms at a time
+        k.chunk = (std::max(1, (n + k.n_chunks - 1) / k.n_chunks) + 15) & ~15;
+        k.n_chunks = std::max(1, (n + k.chunk - 1) / k.chunk);
+        n_modes_all += (size_t)k.n_modes;
+        rho_part_all += 2 * (size_t)k.n_chunks * k.n_modes_pad;
     }
-    c->krho_part.alloc(sizeof(double) * 2 * (size_t)k.n_chunks * k.n_modes_pad);
-    k.rho_part = c->krho_part.as<double>();
-    c->krho.alloc(sizeof(double) * 2 * std::max<size_t>(1, (size_t)k.n_modes));
-    k.rho = c->krho.as<double>();
+    c->kcdf.alloc(sizeof(double) * std::max<size_t>(1, cdf_doubles) + sizeof(int32_t) * cdf_ints);
+    c->kmodes.alloc(std::max<size_t>(1, n_modes_all) * (sizeof(ModeRec) + 3 * sizeof(int32_t)));
+    c->krho_part.alloc(sizeof(double) * std::max<size_t>(1, rho_part_all));
+    c->krho.alloc(sizeof(double) * 2 * std::max<size_t>(1, n_modes_all));
+    {
+        double* dd = c->kcdf.as<double>();
+        int32_t* di = reinterpret_cast<int32_t*>(dd + cdf_doubles);
+        ModeRec* mr = c->kmodes.as<ModeRec>();
+        int32_t* mm = reinterpret_cast<int32_t*>(mr + std::max<size_t>(1, n_modes_all));
+        double* rp = c->krho_part.as<double>();
+        double* rh = c->krho.as<double>();
+        auto put = [](void* dst, const void* src, size_t b) {
+            if (b) HIP_OK(hipMemcpy(dst, src, b, hipMemcpyHostToDevice));
+        };
+        for (int r = 0; r < R; ++r) {
+            KDev& k = c->hk[r];
+            if (k.sampled) {
+                const KTables& t = c->kt[r];
+                const size_t nt = t.g0cdf.size();
+                put(dd, t.g0cdf.data(), sizeof(double) * nt);
+                put(dd + nt, t.g2cdf.data(), sizeof(double) * nt);
+                put(dd + 2 * nt, t.comp_cdf.data(), sizeof(double) * t.comp_cdf.size());
+                k.g0cdf = dd;
+                k.g2cdf = dd + nt;
+                k.comp_cdf = dd + 2 * nt;
+                dd += 2 * nt + t.comp_cdf.size();
+                put(di, t.off.data(), sizeof(int32_t) * t.off.size());
+                put(di + t.off.size(), t.len.data(), sizeof(int32_t) * t.len.size());
+                k.off = di;
+                k.len = di + t.off.size();
+                di += 2 * t.off.size();
+            }
+            k.modes = mr;
+            k.m = mm;
+            if (!k.sampled && k.n_modes > 0) {
+                std::vector<ModeRec> recs(k.n_modes);
+                for (int q = 0; q < k.n_modes; ++q)
+                    recs[q] = ModeRec{(double)em[r][3 * q], (double)em[r][3 * q + 1], (double)em[r][3 * q + 2],
+                                      0.0, 0.0, ecoef[r][q], 0.0, 0.0f, 0.0f};
+                put(k.modes, recs.data(), sizeof(ModeRec) * k.n_modes);
+                put(k.m, em[r].data(), sizeof(int32_t) * em[r].size());
+            }
+            mr += k.n_modes;
+            mm += 3 * (size_t)k.n_modes;
+            k.rho_part = rp;
+            rp += 2 * (size_t)k.n_chunks * k.n_modes_pad;
+            k.rho = rh;
+            rh += 2 * (size_t)k.n_modes;
+        }
+    }
 
-    c->n_pair_blocks = (n + kBlock - 1) / kBlock;
-    c->n_kin_blocks = c->n_pair_blocks;
-    c->pair_part.alloc(sizeof(double) * kPairPart * std::max(1, c->n_pair_blocks));
-    c->kin_part.alloc(sizeof(double) * std::max(1, c->n_kin_blocks));
+    plan_lists(c, cap_core, cap_cand);  // also uploads the system records
+    plan_launches(c);
 
     // inputs
-    if (n > 0) {
+    if (n_user > 0) {
         const int32_t* dt_ = type;
         const double* dp = pos;
         const double* dv = vel;
         DBuf stage;
         if (!on_device) {
-            stage.alloc(sizeof(int32_t) * n + sizeof(double) * 6 * (size_t)n);
+            stage.alloc(sizeof(int32_t) * n_user + sizeof(double) * 6 * (size_t)n_user);
             double* sp = stage.as<double>();
-            HIP_OK(hipMemcpy(sp, hp.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(sp, hp.data(), sizeof(double) * 3 * n_user, hipMemcpyHostToDevice));
             dp = sp;
             if (vel) {
-                HIP_OK(hipMemcpy(sp + 3 * (size_t)n, hv.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice));
-                dv = sp + 3 * (size_t)n;
+                HIP_OK(hipMemcpy(sp + 3 * (size_t)n_user, hv.data(), sizeof(double) * 3 * n_user,
+                                 hipMemcpyHostToDevice));
+                dv = sp + 3 * (size_t)n_user;
             }
-            int32_t* tp = reinterpret_cast<int32_t*>(sp + 6 * (size_t)n);
-            HIP_OK(hipMemcpy(tp, ht.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+            int32_t* tp = reinterpret_cast<int32_t*>(sp + 6 * (size_t)n_user);
+            HIP_OK(hipMemcpy(tp, ht.data(), sizeof(int32_t) * n_user, hipMemcpyHostToDevice));
             dt_ = tp;
         }
-        launch_from_user(s, dt_, dp, dv, c->stream);
+        launch_from_user(c->plan, dt_, dp, dv, c->stream);
         HIP_OK(hipStreamSynchronize(c->stream));
     }
     c->have_system = true;
@@ -654,7 +848,7 @@ void need_system(rbsog_ctx* c) { require(c->have_system, RBSOG_E_STATE, "no syst
 
 extern "C" {
 
-const char* rbsog_version(void) { return "librbsog 0.1 (gfx950)"; }
+const char* rbsog_version(void) { return "librbsog 0.2 (gfx950)"; }
 
 rbsog_status rbsog_sog_params(double eps, double r_shell, double* b, double* s, double* x_c, int32_t* M, double* w,
                               int32_t w_cap)
@@ -714,7 +908,34 @@ rbsog_status rbsog_set_system(rbsog_ctx* ctx, const rbsog_params* p, const int32
 {
     return guarded(ctx, [&] {
         ctx->have_system = false;
-        set_system_impl(ctx, p, type, pos, vel, ptrs_on_device);
+        set_batch_impl(ctx, 1, p, type, pos, vel, ptrs_on_device);
+    });
+}
+
+rbsog_status rbsog_set_batch(rbsog_ctx* ctx, int32_t n_sys, const rbsog_params* p, const int32_t* type,
+                             const double* pos, const double* vel, int ptrs_on_device)
+{
+    return guarded(ctx, [&] {
+        ctx->have_system = false;
+        set_batch_impl(ctx, n_sys, p, type, pos, vel, ptrs_on_device);
+    });
+}
+
+rbsog_status rbsog_n_systems(rbsog_ctx* ctx, int32_t* n_sys)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        require(n_sys != nullptr, RBSOG_E_ARG, "n_sys is NULL");
+        *n_sys = ctx->R;
+    });
+}
+
+rbsog_status rbsog_select_system(rbsog_ctx* ctx, int32_t r)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        require(r >= 0 && r < ctx->R, RBSOG_E_ARG, "system index out of range");
+        ctx->sel = r;
     });
 }
 
@@ -730,13 +951,13 @@ rbsog_status rbsog_compute_forces(rbsog_ctx* ctx, uint64_t eval, double* force_o
 {
     return guarded(ctx, [&] {
         need_system(ctx);
-        launch_set_eval(ctx->s.sc, eval, ctx->stream);
+        launch_set_eval(ctx->plan, eval, ctx->stream);
         enqueue_forces(ctx, e_out != nullptr, false);
         ctx->eval = eval;
         ctx->forces_valid = true;
-        if (force_out) launch_to_user3(ctx->s, ctx->s.fx, ctx->s.fy, ctx->s.fz, force_out, ctx->stream);
+        if (force_out) launch_to_user3(ctx->plan, Field::force, force_out, ctx->stream);
         if (e_out) {
-            DeviceScalars h = read_scalars(ctx);
+            const auto h = read_scalars(ctx);
             fill_energy(ctx, h, e_out);
             check_flags(h);
         }
@@ -748,8 +969,8 @@ rbsog_status rbsog_get_force_parts(rbsog_ctx* ctx, double* f_short, double* f_ks
     return guarded(ctx, [&] {
         need_system(ctx);
         require(ctx->forces_valid, RBSOG_E_STATE, "no force evaluation yet");
-        if (f_short) launch_to_user3(ctx->s, ctx->s.fsx, ctx->s.fsy, ctx->s.fsz, f_short, ctx->stream);
-        if (f_kspace) launch_kspace_part(ctx->s, f_kspace, ctx->stream);
+        if (f_short) launch_to_user3(ctx->plan, Field::short_force, f_short, ctx->stream);
+        if (f_kspace) launch_kspace_part(ctx->plan, f_kspace, ctx->stream);
     });
 }
 
@@ -761,17 +982,17 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
         if (n_steps == 0) return;
         if (!ctx->forces_valid) {
             // forces at the current positions start the integrator
-            launch_set_eval(ctx->s.sc, ctx->eval, ctx->stream);
+            launch_set_eval(ctx->plan, ctx->eval, ctx->stream);
             enqueue_forces(ctx, false, false);
             ctx->forces_valid = true;
         }
-        launch_set_eval(ctx->s.sc, ctx->eval, ctx->stream);
-        if (ctx->s.thermo_c > 0.0) {
+        launch_set_eval(ctx->plan, ctx->eval, ctx->stream);
+        if (any_thermostat(ctx)) {
             // velocity factor of the first step from the current velocities
-            launch_kinetic(ctx->s, ctx->kin_part.as<double>(), ctx->stream);
-            launch_kinetic_finalize(ctx->s, ctx->kin_part.as<double>(), ctx->n_kin_blocks, ctx->stream);
+            launch_kinetic(ctx->plan, ctx->stream);
+            launch_kinetic_finalize(ctx->plan, ctx->stream);
         }
-        const int every = ctx->prm.rebuild_every;
+        const int every = ctx->prm[0].rebuild_every;
         // a list overflow inside the loop restarts the call from a snapshot
         // with larger lists
         for (int attempt = 0;; ++attempt) {
@@ -782,21 +1003,25 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
                 const bool energy = e_last != nullptr && k == n_steps - 1;
                 enqueue_step(ctx, scheduled, energy);
             }
-            DeviceScalars h = read_scalars(ctx);
-            if (h.overflow == 0) {
+            const auto h = read_scalars(ctx);
+            const int o = any_overflow(h);
+            if (o == 0) {
                 ctx->eval += (uint64_t)n_steps;
                 if (e_last) fill_energy(ctx, h, e_last);
-                check_flags(h);
                 return;
             }
-            require(attempt < 4 && (h.overflow & 2) == 0, RBSOG_E_CAPACITY, "list capacity exceeded in the step loop");
-            if (h.overflow & 4)
-                ctx->s.list_mode = std::min(2, ctx->s.list_mode + 1);
+            require(attempt < 4 && (o & 2) == 0, RBSOG_E_CAPACITY, "list capacity exceeded in the step loop");
+            if (o & 4)
+                ctx->plan.list_mode = std::min(2, ctx->plan.list_mode + 1);
             else
                 grow_lists(ctx);
             snapshot(ctx, false);
             build_checked(ctx);
-            launch_set_eval(ctx->s.sc, ctx->eval, ctx->stream);
+            launch_set_eval(ctx->plan, ctx->eval, ctx->stream);
+            if (any_thermostat(ctx)) {
+                launch_kinetic(ctx->plan, ctx->stream);
+                launch_kinetic_finalize(ctx->plan, ctx->stream);
+            }
         }
     });
 }
@@ -806,18 +1031,17 @@ rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* f
 {
     return guarded(ctx, [&] {
         need_system(ctx);
-        DevSys& s = ctx->s;
-        const size_t bytes = sizeof(double) * 3 * (size_t)s.n;
+        const int n = ctx->n_user;
+        const size_t bytes = sizeof(double) * 3 * (size_t)n;
         double* outs[3] = {pos, vel, force};
-        const double* src[3][3] = {{nullptr, nullptr, nullptr}, {s.vx, s.vy, s.vz}, {s.fx, s.fy, s.fz}};
-        if (!ptrs_on_device && s.n > 0 && (pos || vel || force)) ctx->export_tmp.alloc(bytes);
+        if (!ptrs_on_device && n > 0 && (pos || vel || force)) ctx->export_tmp.alloc(bytes);
         for (int q = 0; q < 3; ++q) {
-            if (!outs[q] || s.n <= 0) continue;
+            if (!outs[q] || n <= 0) continue;
             double* dst = ptrs_on_device ? outs[q] : ctx->export_tmp.as<double>();
             if (q == 0)
-                launch_pos_to_user(s, dst, ctx->stream);
+                launch_pos_to_user(ctx->plan, dst, ctx->stream);
             else
-                launch_to_user3(s, src[q][0], src[q][1], src[q][2], dst, ctx->stream);
+                launch_to_user3(ctx->plan, q == 1 ? Field::velocity : Field::force, dst, ctx->stream);
             if (!ptrs_on_device) {
                 HIP_OK(hipMemcpyAsync(outs[q], dst, bytes, hipMemcpyDeviceToHost, ctx->stream));
                 HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -858,13 +1082,14 @@ rbsog_status rbsog_get_list_counts(rbsog_ctx* ctx, int32_t* n_core, int32_t* n_c
 {
     return guarded(ctx, [&] {
         need_system(ctx);
-        const int n = ctx->s.n;
+        const DevSys& s = ctx->hs[ctx->sel];
+        const int n = s.n;
         std::vector<int32_t> nc(n), nk(n), id(n);
         HIP_OK(hipStreamSynchronize(ctx->stream));
         if (n > 0) {
-            HIP_OK(hipMemcpy(nc.data(), ctx->s.core_cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
-            HIP_OK(hipMemcpy(nk.data(), ctx->s.cand_cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
-            HIP_OK(hipMemcpy(id.data(), ctx->s.id, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(nc.data(), s.core_cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(nk.data(), s.cand_cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(id.data(), s.id, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
         }
         for (int t = 0; t < n; ++t) {
             if (n_core) n_core[id[t]] = nc[t];
@@ -877,7 +1102,7 @@ rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_
 {
     return guarded(ctx, [&] {
         need_system(ctx);
-        DevSys& s = ctx->s;
+        const DevSys& s = ctx->hs[ctx->sel];
         require(i >= 0 && i < s.n, RBSOG_E_ARG, "atom index out of range");
         HIP_OK(hipStreamSynchronize(ctx->stream));
         std::vector<int32_t> id(s.n);
@@ -911,15 +1136,16 @@ rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ran
 {
     return guarded(ctx, [&] {
         need_system(ctx);
-        DevSys& s = ctx->s;
+        const DevSys& s = ctx->hs[ctx->sel];
+        const Plan P1 = one(ctx, ctx->sel);
         const int P = std::max(s.p_r, 1);
         DBuf out;
         out.alloc(sizeof(int32_t) * ((size_t)s.n * P + s.n + 1));
         int32_t* r = out.as<int32_t>();
         int32_t* cnt = r + (size_t)s.n * P;
-        launch_set_eval(s.sc, eval, ctx->stream);
-        launch_shell_ranks(s, r, cnt, ctx->stream);
-        launch_set_eval(s.sc, ctx->eval, ctx->stream);
+        launch_set_eval(P1, eval, ctx->stream);
+        launch_shell_ranks(P1, r, cnt, ctx->stream);
+        launch_set_eval(P1, ctx->eval, ctx->stream);
         HIP_OK(hipStreamSynchronize(ctx->stream));
         std::vector<int32_t> h((size_t)s.n * P), hc(s.n);
         if (s.n > 0) {
@@ -941,13 +1167,14 @@ rbsog_status rbsog_get_kmodes(rbsog_ctx* ctx, uint64_t eval, int32_t* m, double*
 {
     return guarded(ctx, [&] {
         need_system(ctx);
-        KDev& k = ctx->k;
+        const KDev& k = ctx->hk[ctx->sel];
         if (S) *S = k.S;
         if (!m || k.n_modes <= 0) return;
         if (k.sampled) {
-            launch_set_eval(ctx->s.sc, eval, ctx->stream);
-            launch_ksample(ctx->s, k, ctx->stream);
-            launch_set_eval(ctx->s.sc, ctx->eval, ctx->stream);
+            const Plan P1 = one(ctx, ctx->sel);
+            launch_set_eval(P1, eval, ctx->stream);
+            launch_ksample(P1, ctx->stream);
+            launch_set_eval(P1, ctx->eval, ctx->stream);
         }
         HIP_OK(hipStreamSynchronize(ctx->stream));
         HIP_OK(hipMemcpy(m, k.m, sizeof(int32_t) * 3 * (size_t)k.n_modes, hipMemcpyDeviceToHost));
@@ -959,9 +1186,10 @@ rbsog_status rbsog_get_rho(rbsog_ctx* ctx, double* rho)
     return guarded(ctx, [&] {
         need_system(ctx);
         require(rho != nullptr, RBSOG_E_ARG, "rho is NULL");
+        const KDev& k = ctx->hk[ctx->sel];
         HIP_OK(hipStreamSynchronize(ctx->stream));
-        if (ctx->k.n_modes > 0)
-            HIP_OK(hipMemcpy(rho, ctx->k.rho, sizeof(double) * 2 * (size_t)ctx->k.n_modes, hipMemcpyDeviceToHost));
+        if (k.n_modes > 0)
+            HIP_OK(hipMemcpy(rho, k.rho, sizeof(double) * 2 * (size_t)k.n_modes, hipMemcpyDeviceToHost));
     });
 }
 

@@ -26,6 +26,55 @@ constexpr int kCellCap = 2048;  // atoms per cell the in-cell sort can hold
 #define RB_GATE                                        \
     if (gate && s.sc->rebuild == 0) return;
 
+// Pointers read from device memory are generic (flat) to the compiler; every
+// buffer here is global memory, and saying so (through an integer, which the
+// compiler does not fold back) turns flat loads and stores into global ones.
+template <class T>
+__device__ inline T* glob(T* p)
+{
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
+__device__ inline DevSys global_view(DevSys s)
+{
+    s.p = glob(s.p);
+    s.vx = glob(s.vx), s.vy = glob(s.vy), s.vz = glob(s.vz);
+    s.fx = glob(s.fx), s.fy = glob(s.fy), s.fz = glob(s.fz);
+    s.fsx = glob(s.fsx), s.fsy = glob(s.fsy), s.fsz = glob(s.fsz);
+    s.xr = glob(s.xr), s.yr = glob(s.yr), s.zr = glob(s.zr);
+    s.type = glob(s.type), s.id = glob(s.id), s.inv = glob(s.inv);
+    s.tp = glob(s.tp);
+    s.tvx = glob(s.tvx), s.tvy = glob(s.tvy), s.tvz = glob(s.tvz);
+    s.tfx = glob(s.tfx), s.tfy = glob(s.tfy), s.tfz = glob(s.tfz);
+    s.ttype = glob(s.ttype), s.tid = glob(s.tid), s.cell_of = glob(s.cell_of);
+    s.slot_of = glob(s.slot_of), s.order = glob(s.order);
+    s.cell_count = glob(s.cell_count), s.cell_start = glob(s.cell_start);
+    s.core_cnt = glob(s.core_cnt), s.core_idx = glob(s.core_idx);
+    s.cand_cnt = glob(s.cand_cnt), s.cand_idx = glob(s.cand_idx);
+    s.pair = glob(s.pair), s.sc = glob(s.sc), s.spc = glob(s.spc);
+    s.pair_part = glob(s.pair_part), s.kin_part = glob(s.kin_part);
+    return s;
+}
+
+__device__ inline KDev global_view(KDev k)
+{
+    k.table = glob(k.table);
+    k.off = glob(k.off), k.len = glob(k.len);
+    k.g0cdf = glob(k.g0cdf), k.g2cdf = glob(k.g2cdf), k.comp_cdf = glob(k.comp_cdf);
+    k.m = glob(k.m), k.modes = glob(k.modes);
+    k.rho_part = glob(k.rho_part), k.rho = glob(k.rho);
+    return k;
+}
+
+// A launch covers every system of a batch: block b of the grid works on local
+// block bmap[b].y of system bmap[b].x (no map: system 0, local block b).  The
+// system record is read through the scalar unit at the start of the block.
+#define RB_ARGS const DevSys* __restrict__ sys, const int2* __restrict__ bmap
+#define RB_SYS(gb)                                                        \
+    const int2 rb_m = bmap ? bmap[(gb)] : make_int2(0, (int)(gb));        \
+    const DevSys s = global_view(sys[rb_m.x]);                            \
+    const int lb = rb_m.y;
+
 
 __device__ inline double wave_sum(double v)
 {
@@ -82,29 +131,41 @@ __device__ inline int xcd_block(int b, int nb)
 }
 
 // ---------------------------------------------------------------- scalars
-__global__ void k_set_eval(DeviceScalars* sc, uint64_t eval) { sc->eval = eval; }
-__global__ void k_bump_eval(DeviceScalars* sc) { sc->eval += 1; }
-// Closes a build: lower the flag, restart the displacement tracking.
-__global__ void k_build_done(DevSys s, int gate)
+__global__ void k_set_eval(DeviceScalars* sc, int R, uint64_t eval)
 {
-    RB_GATE
-    s.sc->rebuild = 0;
-    s.sc->max_disp2 = 0.0;
-    s.sc->n_builds += 1;
+    for (int r = threadIdx.x; r < R; r += blockDim.x) sc[r].eval = eval;
 }
-__global__ void k_clear_flags(DeviceScalars* sc)
+__global__ void k_bump_eval(DeviceScalars* sc, int R)
 {
-    sc->overflow = 0;
-    sc->rebuild = 0;
-    sc->nonfinite = 0;
-    sc->max_disp2 = 0.0;
+    for (int r = threadIdx.x; r < R; r += blockDim.x) sc[r].eval += 1;
+}
+// Closes a build: lower the flag, restart the displacement tracking.
+__global__ void k_build_done(const DevSys* __restrict__ sys, int R, int gate)
+{
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        DeviceScalars* sc = glob(sys[r].sc);
+        if (gate && sc->rebuild == 0) continue;
+        sc->rebuild = 0;
+        sc->max_disp2 = 0.0;
+        sc->n_builds += 1;
+    }
+}
+__global__ void k_clear_flags(DeviceScalars* sc, int R)
+{
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        sc[r].overflow = 0;
+        sc[r].rebuild = 0;
+        sc[r].nonfinite = 0;
+        sc[r].max_disp2 = 0.0;
+    }
 }
 
 // ---------------------------------------------------------------- cell sort
-__global__ void k_bin(DevSys s, int gate)
+__global__ void k_bin(RB_ARGS, int gate)
 {
+    RB_SYS(blockIdx.x)
     RB_GATE
-    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i0 = lb * blockDim.x + threadIdx.x;
     // lanes past the end take part in the wavefront votes with a done flag
     const bool live = i0 < s.n;
     const int i = live ? i0 : s.n - 1;
@@ -140,9 +201,11 @@ __global__ void k_bin(DevSys s, int gate)
     }
 }
 
-// Exclusive scan of count[0..n) into start[0..n], one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(DevSys s, int gate)
+// Exclusive scan of count[0..n) into start[0..n], one block of 1024 threads
+// per system.
+__global__ __launch_bounds__(1024) void k_scan(const DevSys* __restrict__ sys, int gate)
 {
+    const DevSys s = global_view(sys[blockIdx.x]);
     RB_GATE
     int32_t* count = s.cell_count;
     int32_t* start = s.cell_start;
@@ -170,10 +233,11 @@ __global__ __launch_bounds__(1024) void k_scan(DevSys s, int gate)
     if (t == 1023) start[n] = part[1023];
 }
 
-__global__ void k_scatter(DevSys s, int gate)
+__global__ void k_scatter(RB_ARGS, int gate)
 {
+    RB_SYS(blockIdx.x)
     RB_GATE
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = lb * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int d = s.cell_start[s.cell_of[i]] + s.slot_of[i];
     s.tp[d] = s.p[i];
@@ -188,12 +252,13 @@ __global__ void k_scatter(DevSys s, int gate)
 }
 
 // Within each cell, order atoms by id so the cell order is deterministic.
-__global__ __launch_bounds__(kBlock) void k_cell_sort(DevSys s, int gate)
+__global__ __launch_bounds__(kBlock) void k_cell_sort(RB_ARGS, int gate)
 {
+    RB_SYS(blockIdx.x)
     RB_GATE
     __shared__ int32_t key[kCellCap];
     __shared__ int32_t val[kCellCap];
-    const int c = blockIdx.x;
+    const int c = lb;
     const int beg = s.cell_start[c];
     const int cnt = s.cell_start[c + 1] - beg;
     if (cnt > kCellCap) {
@@ -231,10 +296,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(DevSys s, int gate)
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) s.order[beg + t] = val[t];
 }
 
-__global__ void k_gather(DevSys s, int gate)
+__global__ void k_gather(RB_ARGS, int gate)
 {
+    RB_SYS(blockIdx.x)
     RB_GATE
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = lb * blockDim.x + threadIdx.x;
     if (t >= s.n) return;
     const int o = s.order[t];
     const double4 P = s.tp[o];
@@ -259,8 +325,9 @@ __global__ void k_gather(DevSys s, int gate)
 // atom: the lanes sweep the neighbouring cells, compact core and candidate
 // entries with ballots, then sort the candidates into cell order (bitonic
 // network in LDS).
-__global__ __launch_bounds__(64) void k_lists(DevSys s, int gate)
+__global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
 {
+    RB_SYS(blockIdx.x)
     RB_GATE
     extern __shared__ int32_t lsm[];
     const int capP2 = [&] {
@@ -272,7 +339,7 @@ __global__ __launch_bounds__(64) void k_lists(DevSys s, int gate)
     int32_t* cval = lsm + capP2;
     int32_t* core = lsm + 2 * capP2;
 
-    const int i = blockIdx.x;
+    const int i = lb;
     const int lane = threadIdx.x;
     const double4 Pi = s.p[i];
     const double xi = Pi.x, yi = Pi.y, zi = Pi.z;
@@ -373,8 +440,9 @@ __global__ __launch_bounds__(64) void k_lists(DevSys s, int gate)
 constexpr int kListBlock = 512;
 
 template <int CAP>
-__global__ __launch_bounds__(kListBlock) void k_lists_cell(DevSys s, int gate)
+__global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
 {
+    RB_SYS(xcd_block(blockIdx.x, gridDim.x))
     RB_GATE
     __shared__ int32_t val[CAP];
     __shared__ double px[CAP];
@@ -383,7 +451,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(DevSys s, int gate)
     __shared__ int cq[27];
     __shared__ int cb[27];
     __shared__ int coff[28];
-    const int c = xcd_block(blockIdx.x, gridDim.x);
+    const int c = lb;
     const int cx0 = c % s.nc[0];
     const int cy0 = (c / s.nc[0]) % s.nc[1];
     const int cz0 = c / (s.nc[0] * s.nc[1]);
@@ -644,8 +712,9 @@ struct FloydMask {
 };
 
 template <bool MIXED, bool ENERGY, int J>
-__global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF gf, double* part)
+__global__ __launch_bounds__(kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf)
 {
+    RB_SYS(xcd_block(blockIdx.x, gridDim.x))
     extern __shared__ uint32_t mask_sm[];
     __shared__ PairCoef pc[kMaxSpecies * kMaxSpecies];
     __shared__ PairCoefF pcf[kMaxSpecies * kMaxSpecies];
@@ -658,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
     }
     __syncthreads();
 
-    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int i = lb * blockDim.x + threadIdx.x;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, Uc = 0.0, Us = 0.0;
     if (i < s.n) {
         const double4 Pi = s.p[i];
@@ -793,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
         bs = block_sum(Us, red);
     }
     if (threadIdx.x == 0) {
-        double* p = part + (size_t)blockIdx.x * kPairPart;
+        double* p = s.pair_part + (size_t)lb * kPairPart;
         p[0] = bx;
         p[1] = by;
         p[2] = bz;
@@ -803,10 +872,11 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevSys s, SogCoef g, SogCoefF g
 }
 
 // Export of the shell ranks drawn by the pair kernel (same selection code).
-__global__ __launch_bounds__(kBlock) void k_shell_ranks(DevSys s, int32_t* out, int32_t* n_out)
+__global__ __launch_bounds__(kBlock) void k_shell_ranks(RB_ARGS, int32_t* out, int32_t* n_out)
 {
+    RB_SYS(blockIdx.x)
     extern __shared__ uint32_t mask_sm[];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = lb * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int n = min(s.cand_cnt[i], s.cap_cand);
     const int P = s.p_r;
@@ -840,9 +910,11 @@ __device__ inline int first_above(const double* cdf, int len, double u)
 
 // Draw the P_F modes of eq. (28): component (m, d) by its mass, then the
 // three axis indices from their 1D lattice distributions, then signs.
-__global__ void k_ksample(DevSys s, KDev k)
+__global__ void k_ksample(RB_ARGS, const KDev* __restrict__ kd)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    RB_SYS(blockIdx.x)
+    const KDev k = global_view(kd[rb_m.x]);
+    const int p = lb * blockDim.x + threadIdx.x;
     if (p >= k.n_modes) return;
     PhiloxStream st(s.seed, (uint32_t)p, (uint32_t)s.sc->eval, kTagKmode, s.replica);
     const double uc = st.uniform();
@@ -918,8 +990,12 @@ __device__ inline void sincos_turns_f32(double t, float& c, float& s)
 // sums the four FP32 products q cos, q sin of an iteration in FP32 and adds
 // that to the FP64 accumulators.
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_rho(DevSys s, KDev k)
+__global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict__ kd)
 {
+    RB_SYS(blockIdx.x)
+    const KDev k = global_view(kd[rb_m.x]);
+    const int chunk = lb % k.n_chunks;
+    const int tile = lb / k.n_chunks;
     __shared__ double2 tab[MIXED ? 1 : kTableSize];
     __shared__ double red[4][64][2];
     using qreal = typename std::conditional<MIXED, float, double>::type;
@@ -927,11 +1003,11 @@ __global__ __launch_bounds__(kBlock) void k_rho(DevSys s, KDev k)
     if (!MIXED)
         for (int t = threadIdx.x; t < kTableSize; t += blockDim.x)
             tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
-    if (threadIdx.x < kMaxSpecies) qs[threadIdx.x] = (qreal)s.q[threadIdx.x];
+    if (threadIdx.x < kMaxSpecies) qs[threadIdx.x] = (qreal)s.spc->q[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int p = blockIdx.y * 64 + lane;
+    const int p = tile * 64 + lane;
     const bool ok = p < k.n_modes;
     const ModeRec mr = ok ? k.modes[p] : ModeRec{};
     const double sc = MIXED ? 1.0 : (double)kTableSize;
@@ -941,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void k_rho(DevSys s, KDev k)
     // chunk and its quarters are multiples of four atoms (host guarantees
     // chunk % 16 == 0), so the type quadruples below are aligned
     const int qw = k.chunk >> 2;
-    const int a0 = blockIdx.x * k.chunk + wave * qw;
+    const int a0 = chunk * k.chunk + wave * qw;
     const int a1 = min(s.n, a0 + qw);
     double re = 0.0, im = 0.0;
     int a = a0;
@@ -993,16 +1069,19 @@ __global__ __launch_bounds__(kBlock) void k_rho(DevSys s, KDev k)
     if (wave == 0 && ok) {
         const double r = ((red[0][lane][0] + red[1][lane][0]) + red[2][lane][0]) + red[3][lane][0];
         const double i = ((red[0][lane][1] + red[1][lane][1]) + red[2][lane][1]) + red[3][lane][1];
-        double* o = k.rho_part + ((size_t)blockIdx.x * k.n_modes_pad + p) * 2;
+        double* o = k.rho_part + ((size_t)chunk * k.n_modes_pad + p) * 2;
         o[0] = r;
         o[1] = i;
     }
 }
 
 // rho_p = sum over chunks (fixed tree), then the per-mode force coefficients.
-__global__ __launch_bounds__(64) void k_rho_finalize(KDev k)
+__global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __restrict__ kd)
 {
-    const int p = blockIdx.x;
+    RB_SYS(blockIdx.x)
+    (void)s;
+    const KDev k = global_view(kd[rb_m.x]);
+    const int p = lb;
     const int lane = threadIdx.x;
     double re = 0.0, im = 0.0;
     for (int c = lane; c < k.n_chunks; c += 64) {
@@ -1025,15 +1104,20 @@ __global__ __launch_bounds__(64) void k_rho_finalize(KDev k)
     }
 }
 
-// Momentum correction (eq. 26) and energy sums; one block.
-__global__ __launch_bounds__(kBlock) void k_finalize(DevSys s, KDev k, const double* part, int nb)
+// Momentum correction (eq. 26) and energy sums; one block per system.
+__global__ __launch_bounds__(kBlock) void k_finalize(const DevSys* __restrict__ sys, const KDev* __restrict__ kd)
 {
+    const DevSys s = global_view(sys[blockIdx.x]);
+    const KDev k = global_view(kd[blockIdx.x]);
+    const double* part = s.pair_part;
+    const int nb = (s.n + kBlock - 1) / kBlock;
     __shared__ double red[4];
     double v[kPairPart] = {0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nb; b += blockDim.x)
         for (int c = 0; c < kPairPart; ++c) v[c] += part[(size_t)b * kPairPart + c];
     double ue = 0.0;
-    for (int p = threadIdx.x; p < k.n_modes; p += blockDim.x) ue += k.modes[p].e;
+    const int nm = s.n > 0 ? k.n_modes : 0;  // an empty system sums no modes
+    for (int p = threadIdx.x; p < nm; p += blockDim.x) ue += k.modes[p].e;
     double tot[kPairPart];
     for (int c = 0; c < kPairPart; ++c) tot[c] = block_sum(v[c], red);
     const double ut = block_sum(ue, red);
@@ -1054,8 +1138,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(DevSys s, KDev k, const dou
 // correction, optionally the closing half kick of velocity Verlet.  The mixed
 // form takes Im(e^{-i theta} rho) coef in FP32 and accumulates in FP64.
 template <bool MIXED, bool KICK, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_kforce(DevSys s, KDev k, double* kin_part)
+__global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restrict__ kd)
 {
+    RB_SYS(blockIdx.x)
+    const KDev k = global_view(kd[rb_m.x]);
     __shared__ double2 tab[MIXED ? 1 : kTableSize];
     __shared__ double red[4];
     if (!MIXED) {
@@ -1063,7 +1149,7 @@ __global__ __launch_bounds__(kBlock) void k_kforce(DevSys s, KDev k, double* kin
             tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
         __syncthreads();
     }
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = lb * blockDim.x + threadIdx.x;
     double ke = 0.0;
     if (i < s.n) {
         const double4 Pi = s.p[i];
@@ -1098,7 +1184,7 @@ __global__ __launch_bounds__(kBlock) void k_kforce(DevSys s, KDev k, double* kin
         }
         if (p < k.n_modes) one(k.modes[p]);
         const int ti = s.type[i];
-        const double qk = -s.coulomb_k * s.q[ti];
+        const double qk = -s.coulomb_k * s.spc->q[ti];
         const DeviceScalars* scal = s.sc;
         const double fx = s.fsx[i] - scal->p_corr[0] + qk * s.two_pi_L[0] * Gx;
         const double fy = s.fsy[i] - scal->p_corr[1] + qk * s.two_pi_L[1] * Gy;
@@ -1107,25 +1193,28 @@ __global__ __launch_bounds__(kBlock) void k_kforce(DevSys s, KDev k, double* kin
         s.fy[i] = fy;
         s.fz[i] = fz;
         if (KICK) {
-            const double a = 0.5 * s.dt * s.inv_mass_acc[ti];
+            const double a = 0.5 * s.dt * s.spc->inv_mass_acc[ti];
             const double vx = s.vx[i] + a * fx, vy = s.vy[i] + a * fy, vz = s.vz[i] + a * fz;
             s.vx[i] = vx;
             s.vy[i] = vy;
             s.vz[i] = vz;
-            if (ENERGY) ke = 0.5 * s.mass[ti] * (vx * vx + vy * vy + vz * vz);
+            if (ENERGY) ke = 0.5 * s.spc->mass[ti] * (vx * vx + vy * vy + vz * vz);
         } else if (ENERGY) {
             const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
-            ke = 0.5 * s.mass[ti] * (vx * vx + vy * vy + vz * vz);
+            ke = 0.5 * s.spc->mass[ti] * (vx * vx + vy * vy + vz * vz);
         }
     }
     if (ENERGY) {
         const double b = block_sum(ke, red);
-        if (threadIdx.x == 0) kin_part[blockIdx.x] = b;
+        if (threadIdx.x == 0) s.kin_part[lb] = b;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_kinetic_finalize(DevSys s, const double* part, int nb)
+__global__ __launch_bounds__(kBlock) void k_kinetic_finalize(const DevSys* __restrict__ sys)
 {
+    const DevSys s = global_view(sys[blockIdx.x]);
+    const double* part = s.kin_part;
+    const int nb = (s.n + kBlock - 1) / kBlock;
     __shared__ double red[4];
     double v = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[b];
@@ -1144,32 +1233,34 @@ __global__ __launch_bounds__(kBlock) void k_kinetic_finalize(DevSys s, const dou
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_kinetic(DevSys s, double* part)
+__global__ __launch_bounds__(kBlock) void k_kinetic(RB_ARGS)
 {
+    RB_SYS(blockIdx.x)
     __shared__ double red[4];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = lb * blockDim.x + threadIdx.x;
     double ke = 0.0;
     if (i < s.n) {
         const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
-        ke = 0.5 * s.mass[s.type[i]] * (vx * vx + vy * vy + vz * vz);
+        ke = 0.5 * s.spc->mass[s.type[i]] * (vx * vx + vy * vy + vz * vz);
     }
     const double b = block_sum(ke, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = b;
+    if (threadIdx.x == 0) s.kin_part[lb] = b;
 }
 
 // ---------------------------------------------------------------- integrator
 // v += dt/2 F/m; r += dt v (wrapped); the displacement since the build is
 // checked against skin/2, which raises the rebuild flag, as does a build
 // scheduled for this step.
-__global__ __launch_bounds__(kBlock) void k_kick_drift(DevSys s, int scheduled)
+__global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
 {
+    RB_SYS(blockIdx.x)
     __shared__ double red[4];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = lb * blockDim.x + threadIdx.x;
     double d2 = 0.0;
     const double lam = s.thermo_c > 0.0 ? s.sc->vscale : 1.0;
     if (i < s.n) {
         const int ti = s.type[i];
-        const double a = 0.5 * s.dt * s.inv_mass_acc[ti];
+        const double a = 0.5 * s.dt * s.spc->inv_mass_acc[ti];
         const double vx = lam * s.vx[i] + a * s.fx[i];
         const double vy = lam * s.vy[i] + a * s.fy[i];
         const double vz = lam * s.vz[i] + a * s.fz[i];
@@ -1189,7 +1280,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(DevSys s, int scheduled)
     // one flag update per wavefront that saw a displacement above skin/2
     const uint64_t moved = __ballot(!(d2 <= s.half_skin2));
     if (moved && (threadIdx.x & 63) == 0) atomicOr(&s.sc->rebuild, 1);
-    if (scheduled && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&s.sc->rebuild, 1);
+    if (scheduled && lb == 0 && threadIdx.x == 0) atomicOr(&s.sc->rebuild, 1);
     // block maximum, then a device-wide max on the bit pattern (d2 >= 0)
     double m = d2;
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
@@ -1202,32 +1293,38 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(DevSys s, int scheduled)
 }
 
 // ---------------------------------------------------------------- exports
-__global__ void k_to_user3(DevSys s, const double* ax, const double* ay, const double* az, double* out)
+__global__ void k_to_user3(RB_ARGS, int field, double* out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
-    const size_t u = (size_t)s.id[i] * 3;
+    const double* ax = field == 0 ? s.fx : (field == 1 ? s.fsx : s.vx);
+    const double* ay = field == 0 ? s.fy : (field == 1 ? s.fsy : s.vy);
+    const double* az = field == 0 ? s.fz : (field == 1 ? s.fsz : s.vz);
+    const size_t u = ((size_t)s.user_off + s.id[i]) * 3;
     out[u] = ax[i];
     out[u + 1] = ay[i];
     out[u + 2] = az[i];
 }
 
-__global__ void k_pos_to_user(DevSys s, double* out)
+__global__ void k_pos_to_user(RB_ARGS, double* out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
-    const size_t u = (size_t)s.id[i] * 3;
+    const size_t u = ((size_t)s.user_off + s.id[i]) * 3;
     const double4 P = s.p[i];
     out[u] = P.x;
     out[u + 1] = P.y;
     out[u + 2] = P.z;
 }
 
-__global__ void k_kspace_part(DevSys s, double* out)
+__global__ void k_kspace_part(RB_ARGS, double* out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
-    const size_t u = (size_t)s.id[i] * 3;
+    const size_t u = ((size_t)s.user_off + s.id[i]) * 3;
     const DeviceScalars* sc = s.sc;
     out[u] = s.fx[i] - (s.fsx[i] - sc->p_corr[0]);
     out[u + 1] = s.fy[i] - (s.fsy[i] - sc->p_corr[1]);
@@ -1235,18 +1332,20 @@ __global__ void k_kspace_part(DevSys s, double* out)
 }
 
 // Initial load: user order in, identity cell order (sorted at the first build).
-__global__ void k_from_user(DevSys s, const int32_t* type, const double* pos, const double* vel)
+__global__ void k_from_user(RB_ARGS, const int32_t* type, const double* pos, const double* vel)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
-    s.p[i] = make_double4(pos[3 * (size_t)i], pos[3 * (size_t)i + 1], pos[3 * (size_t)i + 2], (double)type[i]);
-    s.vx[i] = vel ? vel[3 * (size_t)i] : 0.0;
-    s.vy[i] = vel ? vel[3 * (size_t)i + 1] : 0.0;
-    s.vz[i] = vel ? vel[3 * (size_t)i + 2] : 0.0;
+    const size_t u = (size_t)s.user_off + i;
+    s.p[i] = make_double4(pos[3 * u], pos[3 * u + 1], pos[3 * u + 2], (double)type[u]);
+    s.vx[i] = vel ? vel[3 * u] : 0.0;
+    s.vy[i] = vel ? vel[3 * u + 1] : 0.0;
+    s.vz[i] = vel ? vel[3 * u + 2] : 0.0;
     s.fx[i] = 0.0;
     s.fy[i] = 0.0;
     s.fz[i] = 0.0;
-    s.type[i] = type[i];
+    s.type[i] = type[u];
     s.id[i] = i;
     s.inv[i] = i;
 }
@@ -1274,44 +1373,46 @@ SogCoefF to_f32(const SogCoef& g)
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-void launch_set_eval(DeviceScalars* sc, uint64_t eval, hipStream_t st) { k_set_eval<<<1, 1, 0, st>>>(sc, eval); }
-void launch_bump_eval(DeviceScalars* sc, hipStream_t st) { k_bump_eval<<<1, 1, 0, st>>>(sc); }
-void launch_clear_flags(DeviceScalars* sc, hipStream_t st) { k_clear_flags<<<1, 1, 0, st>>>(sc); }
+void launch_set_eval(const Plan& P, uint64_t eval, hipStream_t st) { k_set_eval<<<1, 64, 0, st>>>(P.sc, P.R, eval); }
+void launch_bump_eval(const Plan& P, hipStream_t st) { k_bump_eval<<<1, 64, 0, st>>>(P.sc, P.R); }
+void launch_clear_flags(const Plan& P, hipStream_t st) { k_clear_flags<<<1, 64, 0, st>>>(P.sc, P.R); }
 
-void launch_build(const DevSys& s, bool gate, hipStream_t st)
+#define RB_MAP(shape) P.sys, P.shape.map
+
+void launch_build(const Plan& P, bool gate, hipStream_t st)
 {
-    if (s.n <= 0) return;
+    if (P.atoms.blocks <= 0) return;
     const int g = gate ? 1 : 0;
-    k_bin<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, g);
-    k_scan<<<1, 1024, 0, st>>>(s, g);
-    k_scatter<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, g);
-    k_cell_sort<<<s.ncell, kBlock, 0, st>>>(s, g);
-    k_gather<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, g);
-    if (s.list_mode == 0) {
-        k_lists_cell<2048><<<s.ncell, kListBlock, 0, st>>>(s, g);
-    } else if (s.list_mode == 1) {
-        k_lists_cell<4096><<<s.ncell, kListBlock, 0, st>>>(s, g);
+    k_bin<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), g);
+    k_scan<<<P.R, 1024, 0, st>>>(P.sys, g);
+    k_scatter<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), g);
+    k_cell_sort<<<P.cells.blocks, kBlock, 0, st>>>(RB_MAP(cells), g);
+    k_gather<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), g);
+    if (P.list_mode == 0) {
+        k_lists_cell<2048><<<P.cells.blocks, kListBlock, 0, st>>>(RB_MAP(cells), g);
+    } else if (P.list_mode == 1) {
+        k_lists_cell<4096><<<P.cells.blocks, kListBlock, 0, st>>>(RB_MAP(cells), g);
     } else {
         int capP2 = 1;
-        while (capP2 < s.cap_cand) capP2 <<= 1;
-        const size_t sm = sizeof(int32_t) * (2 * (size_t)capP2 + s.cap_core);
-        k_lists<<<s.n, 64, sm, st>>>(s, g);
+        while (capP2 < P.cap_cand) capP2 <<= 1;
+        const size_t sm = sizeof(int32_t) * (2 * (size_t)capP2 + P.cap_core);
+        k_lists<<<P.atom1.blocks, 64, sm, st>>>(RB_MAP(atom1), g);
     }
-    k_build_done<<<1, 1, 0, st>>>(s, g);
+    k_build_done<<<1, 64, 0, st>>>(P.sys, P.R, g);
 }
 
-void launch_ksample(const DevSys& s, const KDev& k, hipStream_t st)
+void launch_ksample(const Plan& P, hipStream_t st)
 {
-    if (k.n_modes > 0) k_ksample<<<blocks_for(k.n_modes, 64), 64, 0, st>>>(s, k);
+    if (P.modes64.blocks > 0) k_ksample<<<P.modes64.blocks, 64, 0, st>>>(RB_MAP(modes64), P.kd);
 }
 
-void launch_pair(const DevSys& s, const SogCoef& g, bool mixed, bool energy, double* part, int n_blocks,
-                 hipStream_t st)
+void launch_pair(const Plan& P, const SogCoef& g, bool mixed, bool energy, hipStream_t st)
 {
-    const size_t sm = sizeof(uint32_t) * (size_t)((s.cap_cand + 31) / 32) * kBlock;
+    const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * kBlock;
     const SogCoefF gf = to_f32(g);
-    if (n_blocks <= 0) return;
-#define RB_PAIR(M, E, J) k_pair<M, E, J><<<n_blocks, kBlock, sm, st>>>(s, g, gf, part)
+    const int nb = P.atoms.blocks;
+    if (nb <= 0) return;
+#define RB_PAIR(M, E, J) k_pair<M, E, J><<<nb, kBlock, sm, st>>>(RB_MAP(atoms), g, gf)
     if (mixed) {
         if (energy)
             RB_PAIR(true, true, 1);
@@ -1331,32 +1432,30 @@ void launch_pair(const DevSys& s, const SogCoef& g, bool mixed, bool energy, dou
 #undef RB_PAIR
 }
 
-void launch_rho(const DevSys& s, const KDev& k, bool mixed, hipStream_t st)
+void launch_rho(const Plan& P, bool mixed, hipStream_t st)
 {
-    if (k.n_modes <= 0 || s.n <= 0) return;
-    dim3 grid(k.n_chunks, (k.n_modes + 63) / 64);
+    if (P.rho.blocks <= 0) return;
     if (mixed)
-        k_rho<true><<<grid, kBlock, 0, st>>>(s, k);
+        k_rho<true><<<P.rho.blocks, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
     else
-        k_rho<false><<<grid, kBlock, 0, st>>>(s, k);
+        k_rho<false><<<P.rho.blocks, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
 }
 
-void launch_rho_finalize(const DevSys&, const KDev& k, hipStream_t st)
+void launch_rho_finalize(const Plan& P, hipStream_t st)
 {
-    if (k.n_modes > 0) k_rho_finalize<<<k.n_modes, 64, 0, st>>>(k);
+    if (P.modes1.blocks > 0) k_rho_finalize<<<P.modes1.blocks, 64, 0, st>>>(RB_MAP(modes1), P.kd);
 }
 
-void launch_finalize(const DevSys& s, const KDev& k, const double* part, int nb, hipStream_t st)
+void launch_finalize(const Plan& P, hipStream_t st)
 {
-    k_finalize<<<1, kBlock, 0, st>>>(s, k, part, nb);
+    if (P.R > 0) k_finalize<<<P.R, kBlock, 0, st>>>(P.sys, P.kd);
 }
 
-void launch_kforce(const DevSys& s, const KDev& k, bool mixed, bool kick, bool energy, double* kin_part,
-                   hipStream_t st)
+void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st)
 {
-    if (s.n <= 0) return;
-    const int nb = blocks_for(s.n, kBlock);
-#define RB_KF(M, K, E) k_kforce<M, K, E><<<nb, kBlock, 0, st>>>(s, k, kin_part)
+    const int nb = P.atoms.blocks;
+    if (nb <= 0) return;
+#define RB_KF(M, K, E) k_kforce<M, K, E><<<nb, kBlock, 0, st>>>(RB_MAP(atoms), P.kd)
     if (mixed) {
         if (kick) {
             if (energy) RB_KF(true, true, true); else RB_KF(true, true, false);
@@ -1373,46 +1472,47 @@ void launch_kforce(const DevSys& s, const KDev& k, bool mixed, bool kick, bool e
 #undef RB_KF
 }
 
-void launch_kinetic_finalize(const DevSys& s, const double* part, int nb, hipStream_t st)
+void launch_kinetic_finalize(const Plan& P, hipStream_t st)
 {
-    k_kinetic_finalize<<<1, kBlock, 0, st>>>(s, part, nb);
+    if (P.R > 0) k_kinetic_finalize<<<P.R, kBlock, 0, st>>>(P.sys);
 }
 
-void launch_kinetic(const DevSys& s, double* part, hipStream_t st)
+void launch_kinetic(const Plan& P, hipStream_t st)
 {
-    if (s.n > 0) k_kinetic<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, part);
+    if (P.atoms.blocks > 0) k_kinetic<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms));
 }
 
-void launch_kick_drift(const DevSys& s, bool scheduled, hipStream_t st)
+void launch_kick_drift(const Plan& P, bool scheduled, hipStream_t st)
 {
-    if (s.n > 0) k_kick_drift<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, scheduled ? 1 : 0);
+    if (P.atoms.blocks > 0) k_kick_drift<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), scheduled ? 1 : 0);
 }
 
-void launch_to_user3(const DevSys& s, const double* ax, const double* ay, const double* az, double* out,
-                     hipStream_t st)
+void launch_to_user3(const Plan& P, Field f, double* out, hipStream_t st)
 {
-    if (s.n > 0) k_to_user3<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, ax, ay, az, out);
+    if (P.atoms.blocks > 0) k_to_user3<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), (int)f, out);
 }
 
-void launch_pos_to_user(const DevSys& s, double* out, hipStream_t st)
+void launch_pos_to_user(const Plan& P, double* out, hipStream_t st)
 {
-    if (s.n > 0) k_pos_to_user<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, out);
+    if (P.atoms.blocks > 0) k_pos_to_user<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), out);
 }
 
-void launch_kspace_part(const DevSys& s, double* out, hipStream_t st)
+void launch_kspace_part(const Plan& P, double* out, hipStream_t st)
 {
-    if (s.n > 0) k_kspace_part<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, out);
+    if (P.atoms.blocks > 0) k_kspace_part<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), out);
 }
 
-void launch_shell_ranks(const DevSys& s, int32_t* out, int32_t* n_out, hipStream_t st)
+void launch_shell_ranks(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st)
 {
-    const size_t sm = sizeof(uint32_t) * (size_t)((s.cap_cand + 31) / 32) * kBlock;
-    if (s.n > 0) k_shell_ranks<<<blocks_for(s.n, kBlock), kBlock, sm, st>>>(s, out, n_out);
+    const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * kBlock;
+    if (P.atoms.blocks > 0) k_shell_ranks<<<P.atoms.blocks, kBlock, sm, st>>>(RB_MAP(atoms), out, n_out);
 }
 
-void launch_from_user(const DevSys& s, const int32_t* type, const double* pos, const double* vel, hipStream_t st)
+void launch_from_user(const Plan& P, const int32_t* type, const double* pos, const double* vel, hipStream_t st)
 {
-    if (s.n > 0) k_from_user<<<blocks_for(s.n, kBlock), kBlock, 0, st>>>(s, type, pos, vel);
+    if (P.atoms.blocks > 0) k_from_user<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), type, pos, vel);
 }
+
+#undef RB_MAP
 
 }  // namespace rbsog

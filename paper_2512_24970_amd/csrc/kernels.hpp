@@ -1,4 +1,5 @@
-// Device data of one system and the kernel launchers (defined in kernels.hip).
+// Device data of the systems of a batch and the kernel launchers (defined in
+// kernels.hip).  A single system is a batch of one.
 #pragma once
 
 #include "common.hpp"
@@ -14,10 +15,20 @@ struct ModeRec {
     float Af, Bf;       // A and B rounded to FP32 (mixed force kernel)
 };
 
-// Everything the kernels read or write.  Per-atom arrays are in cell order.
+// Per-species constants, indexed by atom type.
+struct SpeciesDev {
+    double q[kMaxSpecies];
+    double inv_mass_acc[kMaxSpecies];  // kAccUnit / m
+    double mass[kMaxSpecies];
+};
+
+// Everything the kernels read or write about one system of a batch.  Per-atom
+// arrays are this system's slices of the batch arrays, in cell order, and
+// every atom, cell and list index is local to the system.
 struct DevSys {
     int n;
     int n_species;
+    int user_off;          // first row of this system in the caller's [N][3] arrays
     double L[3], invL[3];
     double cell_scale[3];  // n_c / L
     int nc[3];
@@ -32,12 +43,9 @@ struct DevSys {
     double dof_kb;         // (3N - 3) k_B
     int p_r;
     int cap_core, cap_cand;
-    int list_mode;         // 0/1: per-cell list kernel with a 2048/4096-atom stencil, 2: per-atom kernel
     uint32_t replica;
     uint64_t seed;
-    double q[kMaxSpecies];
-    double inv_mass_acc[kMaxSpecies];  // kAccUnit / m
-    double mass[kMaxSpecies];
+    const struct SpeciesDev* spc;  // per-species constants (shared by a batch)
 
     // atoms (cell order); positions packed with the species so a neighbour
     // gather touches one 32-byte record
@@ -57,6 +65,8 @@ struct DevSys {
     // pair coefficients [S*S]
     const PairCoef* pair;
     DeviceScalars* sc;
+    double* pair_part;     // [ceil(n/256)][kPairPart] block partials of the pair kernel
+    double* kin_part;      // [ceil(n/256)] kinetic-energy block partials
 };
 
 struct KDev {
@@ -83,39 +93,62 @@ struct KDev {
 // Block partial sums written by the pair kernel: F (3), u_core, u_shell.
 constexpr int kPairPart = 5;
 
-void launch_set_eval(DeviceScalars* sc, uint64_t eval, hipStream_t st);
-void launch_bump_eval(DeviceScalars* sc, hipStream_t st);
-void launch_clear_flags(DeviceScalars* sc, hipStream_t st);
+// The grid of one launch over a batch: block b works on local block map[b].y
+// of system map[b].x.  A null map means one system (system 0, local block b).
+struct Shape {
+    const int2* map = nullptr;
+    int blocks = 0;
+};
 
-// cell sort + lists; with gate the kernels run only when the device-side
-// rebuild flag is up (and lower it at the end)
-void launch_build(const DevSys& s, bool gate, hipStream_t st);
+// Launch plan of a batch (or of one system of it, see api.cpp).
+struct Plan {
+    const DevSys* sys = nullptr;  // device array [R]
+    const KDev* kd = nullptr;     // device array [R]
+    DeviceScalars* sc = nullptr;  // device array [R] (sys[r].sc == sc + r)
+    int R = 0;
+    Shape atoms;    // 256-atom blocks of every system
+    Shape cells;    // one block per cell
+    Shape atom1;    // one block per atom (per-atom list kernel)
+    Shape modes64;  // 64-mode blocks of the systems that draw modes
+    Shape rho;      // rho blocks: local block = mode tile * n_chunks + chunk
+    Shape modes1;   // one block per mode
+    int list_mode = 0;  // 0/1: per-cell list kernel with a 2048/4096-atom stencil, 2: per-atom kernel
+    int cap_core = 0, cap_cand = 0;
+};
+
+void launch_set_eval(const Plan& P, uint64_t eval, hipStream_t st);
+void launch_bump_eval(const Plan& P, hipStream_t st);
+void launch_clear_flags(const Plan& P, hipStream_t st);
+
+// cell sort + lists; with gate the kernels of a system run only when its
+// device-side rebuild flag is up (and lower it at the end)
+void launch_build(const Plan& P, bool gate, hipStream_t st);
 
 // forces
-void launch_ksample(const DevSys& s, const KDev& k, hipStream_t st);
-void launch_pair(const DevSys& s, const SogCoef& sog, bool mixed, bool energy, double* part, int n_blocks,
-                 hipStream_t st);
-void launch_rho(const DevSys& s, const KDev& k, bool mixed, hipStream_t st);
-void launch_rho_finalize(const DevSys& s, const KDev& k, hipStream_t st);
-void launch_finalize(const DevSys& s, const KDev& k, const double* pair_part, int n_pair_blocks, hipStream_t st);
-void launch_kforce(const DevSys& s, const KDev& k, bool mixed, bool kick, bool energy, double* kin_part,
-                   hipStream_t st);
+void launch_ksample(const Plan& P, hipStream_t st);
+void launch_pair(const Plan& P, const SogCoef& sog, bool mixed, bool energy, hipStream_t st);
+void launch_rho(const Plan& P, bool mixed, hipStream_t st);
+void launch_rho_finalize(const Plan& P, hipStream_t st);
+void launch_finalize(const Plan& P, hipStream_t st);
+void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st);
 // kinetic energy from the partials; with a thermostat also the velocity
 // factor of the next step
-void launch_kinetic_finalize(const DevSys& s, const double* kin_part, int n_blocks, hipStream_t st);
+void launch_kinetic_finalize(const Plan& P, hipStream_t st);
 // kinetic-energy partials of the current velocities
-void launch_kinetic(const DevSys& s, double* kin_part, hipStream_t st);
+void launch_kinetic(const Plan& P, hipStream_t st);
 
-// integrator: opening half kick and drift; raises the rebuild flag when an
-// atom moved more than skin/2 since the build, or when `scheduled`
-void launch_kick_drift(const DevSys& s, bool scheduled, hipStream_t st);
+// integrator: opening half kick and drift; raises the rebuild flag of a
+// system when one of its atoms moved more than skin/2 since its build, or
+// when `scheduled`
+void launch_kick_drift(const Plan& P, bool scheduled, hipStream_t st);
 
-// exports
-void launch_to_user3(const DevSys& s, const double* ax, const double* ay, const double* az, double* out,
-                     hipStream_t st);
-void launch_pos_to_user(const DevSys& s, double* out, hipStream_t st);
-void launch_kspace_part(const DevSys& s, double* out, hipStream_t st);
-void launch_shell_ranks(const DevSys& s, int32_t* out, int32_t* n_out, hipStream_t st);
-void launch_from_user(const DevSys& s, const int32_t* type, const double* pos, const double* vel, hipStream_t st);
+// exports into the caller's [N][3] arrays (row user_off + id)
+enum class Field { force = 0, short_force = 1, velocity = 2 };
+void launch_to_user3(const Plan& P, Field f, double* out, hipStream_t st);
+void launch_pos_to_user(const Plan& P, double* out, hipStream_t st);
+void launch_kspace_part(const Plan& P, double* out, hipStream_t st);
+// shell ranks of one system (P.R == 1) into out[n][P_R], n_out[n] by atom id
+void launch_shell_ranks(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st);
+void launch_from_user(const Plan& P, const int32_t* type, const double* pos, const double* vel, hipStream_t st);
 
 }  // namespace rbsog

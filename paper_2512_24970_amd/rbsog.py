@@ -69,6 +69,10 @@ ABI = {
     "rbsog_destroy": (C.c_int, [C.c_void_p]),
     "rbsog_last_error": (C.c_char_p, [C.c_void_p]),
     "rbsog_set_system": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "rbsog_set_batch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int]),
+    "rbsog_n_systems": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "rbsog_select_system": (C.c_int, [C.c_void_p, C.c_int32]),
     "rbsog_build_lists": (C.c_int, [C.c_void_p]),
     "rbsog_compute_forces": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(Energy)]),
     "rbsog_get_force_parts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -156,7 +160,9 @@ def rbsog_sog_params(eps: float, r_shell: float) -> dict:
 
 
 class Context:
-    """One rbsog_ctx: one system on one device and stream."""
+    """One rbsog_ctx: one system, or a batch of systems, on one device and
+    stream.  Energies come back as one dict per system (a dict for a single
+    system); per-atom arrays hold the systems' rows one after another."""
 
     def __init__(self, device: int = 0, stream=None):
         import torch  # device memory and streams come from torch
@@ -171,6 +177,9 @@ class Context:
         self._h = h
         self.n = 0
         self.params = None
+        self.params_list = []
+        self.R = 0
+        self.sel = 0
 
     def _check(self, rc: int, what: str):
         if rc != 0:
@@ -206,6 +215,42 @@ class Context:
                                            C.c_void_p(pos.data_ptr()), vptr, 1), "rbsog_set_system")
         self.n = int(types.numel())
         self.params = params
+        self.params_list = [params]
+        self.R = 1
+        self.sel = 0
+
+    def rbsog_set_batch(self, params_list, types, pos, vel=None):
+        """params_list: one Params per system (n_atoms set); types/pos/vel:
+        the systems' rows concatenated, torch tensors on this device."""
+        t = self._torch
+        types = t.as_tensor(types, dtype=t.int32, device=self.torch_device).contiguous()
+        pos = t.as_tensor(pos, dtype=t.float64, device=self.torch_device).contiguous()
+        vptr = None
+        if vel is not None:
+            vel = t.as_tensor(vel, dtype=t.float64, device=self.torch_device).contiguous()
+            vptr = C.c_void_p(vel.data_ptr())
+        R = len(params_list)
+        arr = (Params * R)(*params_list)
+        self._check(lib().rbsog_set_batch(self._h, R, arr, C.c_void_p(types.data_ptr()),
+                                          C.c_void_p(pos.data_ptr()), vptr, 1), "rbsog_set_batch")
+        self.n = int(types.numel())
+        self.params_list = list(params_list)
+        self.params = self.params_list[0]
+        self.R = R
+        self.sel = 0
+
+    def rbsog_n_systems(self) -> int:
+        n = C.c_int32()
+        self._check(lib().rbsog_n_systems(self._h, C.byref(n)), "rbsog_n_systems")
+        return int(n.value)
+
+    def rbsog_select_system(self, r: int):
+        self._check(lib().rbsog_select_system(self._h, r), "rbsog_select_system")
+        self.sel = r
+
+    def _energies(self, e):
+        out = [e[r].as_dict() for r in range(self.R)]
+        return out[0] if self.R == 1 else out
 
     def rbsog_build_lists(self):
         self._check(lib().rbsog_build_lists(self._h), "rbsog_build_lists")
@@ -214,10 +259,10 @@ class Context:
     def rbsog_compute_forces(self, ev: int, want_energy: bool = True):
         t = self._torch
         f = t.empty((self.n, 3), dtype=t.float64, device=self.torch_device)
-        e = Energy()
+        e = (Energy * max(self.R, 1))()
         self._check(lib().rbsog_compute_forces(self._h, ev, C.c_void_p(f.data_ptr()),
-                                               C.byref(e) if want_energy else None), "rbsog_compute_forces")
-        return f, (e.as_dict() if want_energy else None)
+                                               e if want_energy else None), "rbsog_compute_forces")
+        return f, (self._energies(e) if want_energy else None)
 
     def rbsog_get_force_parts(self):
         t = self._torch
@@ -228,9 +273,9 @@ class Context:
         return fs, fk
 
     def rbsog_step(self, n_steps: int, want_energy: bool = True):
-        e = Energy()
-        self._check(lib().rbsog_step(self._h, n_steps, C.byref(e) if want_energy else None), "rbsog_step")
-        return e.as_dict() if want_energy else None
+        e = (Energy * max(self.R, 1))()
+        self._check(lib().rbsog_step(self._h, n_steps, e if want_energy else None), "rbsog_step")
+        return self._energies(e) if want_energy else None
 
     def rbsog_get_state(self):
         t = self._torch
@@ -252,10 +297,14 @@ class Context:
         self._check(lib().rbsog_profile_read(self._h, _np_ptr(ms), _np_ptr(cnt)), "rbsog_profile_read")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PHASES)}
 
-    # -- parity exports (host arrays) ----------------------------------------
+    # -- parity exports (host arrays) of the selected system -----------------
+    @property
+    def _sel_n(self) -> int:
+        return int(self.params_list[self.sel].n_atoms)
+
     def rbsog_get_list_counts(self):
-        nc = np.zeros(self.n, np.int32)
-        nk = np.zeros(self.n, np.int32)
+        nc = np.zeros(self._sel_n, np.int32)
+        nk = np.zeros(self._sel_n, np.int32)
         self._check(lib().rbsog_get_list_counts(self._h, _np_ptr(nc), _np_ptr(nk)), "rbsog_get_list_counts")
         return nc, nk
 
@@ -266,18 +315,18 @@ class Context:
         return core[:n_core], cand[:n_cand]
 
     def rbsog_get_shell_ranks(self, ev: int):
-        P = max(self.params.p_r, 1)
-        nr = np.zeros(self.n, np.int32)
-        r = np.zeros((self.n, P), np.int32)
+        P = max(self.params_list[self.sel].p_r, 1)
+        nr = np.zeros(self._sel_n, np.int32)
+        r = np.zeros((self._sel_n, P), np.int32)
         self._check(lib().rbsog_get_shell_ranks(self._h, ev, _np_ptr(nr), _np_ptr(r)), "rbsog_get_shell_ranks")
         return nr, r
 
     def rbsog_get_kmodes(self, ev: int):
-        P = max(self.params.p_f, 1)
-        m = np.zeros((P, 3), np.int32)
+        p_f = self.params_list[self.sel].p_f
+        m = np.zeros((max(p_f, 1), 3), np.int32)
         S = C.c_double()
         self._check(lib().rbsog_get_kmodes(self._h, ev, _np_ptr(m), C.byref(S)), "rbsog_get_kmodes")
-        return m[: self.params.p_f], S.value
+        return m[:p_f], S.value
 
     def rbsog_get_rho(self, n_modes: int):
         rho = np.zeros((max(n_modes, 1), 2))

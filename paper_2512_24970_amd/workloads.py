@@ -177,10 +177,31 @@ def config(name: str, **over) -> dict:
     d.update(over)
     box = d["box"]
     boxv = list(box) if isinstance(box, (list, tuple)) else [box, box, box]
-    types, pos, vel = _melt(d["n"], boxv[0], d["T"], d["species"], d["cat"], d["frac"], d["seed"],
-                            d.get("jitter", 0.3))
+    types, pos, vel = _melt(d["n"], boxv[0], d["T"], d["species"], d["cat"], d["frac"],
+                            d.get("melt_seed", d["seed"]), d.get("jitter", 0.3))
     sysp = dict(species=d["species"], box=boxv, r_core=d["r_core"], r_shell=d["r_shell"], skin=d["skin"],
                 p_r=d["p_r"], p_f=d["p_f"], seed=d["seed"], coulomb_k=COULOMB_K, dt=d.get("dt", 0.001),
                 sog_eps=d.get("sog_eps", 1e-5), rebuild_every=d.get("rebuild_every", 10),
                 replica=d.get("replica", 0))
     return dict(name=name, sys=sysp, types=types, pos=pos, vel=vel, T=d["T"])
+
+
+def replica_batch(n_rep: int = 64, n_min: int = 512, n_max: int = 32768, density: float = 0.0319,
+                  seed: int = BASE_SEED + 4) -> list:
+    """A batch of molten-NaCl replicas of varied size (the batched workload).
+
+    Replica r: N_r = 2 round(exp(U(ln n_min, ln n_max)) / 2) ions, cubic box
+    L_r = (N_r / density)^(1/3), T_r ~ U(1100, 1400) K, Table 1, r_core 5,
+    r_shell 10, skin 1, P_R 20, P_F 100.  All replicas share one Philox key
+    (`seed`) and differ in their stream id (replica = r) and in the seed of
+    their initial melt.  Returns one config dict per replica.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = 2 * np.round(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_rep)) / 2)
+    temps = rng.uniform(1100.0, 1400.0, n_rep)
+    out = []
+    for r in range(n_rep):
+        n = int(sizes[r])
+        out.append(config("nacl_512", n=n, box=(n / density) ** (1.0 / 3.0), T=float(temps[r]), seed=seed,
+                          replica=r, melt_seed=seed * 1000 + r))
+    return out

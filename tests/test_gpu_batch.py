@@ -1,0 +1,189 @@
+"""Batched form: several independent systems in one context, every kernel
+launch covering all of them.  Each system must come out exactly as it does
+alone in its own context (bitwise, same lists, batches, modes and reduction
+order), and match the oracle run on that system alone."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2512_24970_amd import rbsog as R
+from paper_2512_24970_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_rms(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return math.sqrt(((a - b) ** 2).sum() / max((b ** 2).sum(), 1e-300))
+
+
+def _small_batch(**over):
+    """Five replicas of 566..3000 ions (boxes 26-45 A), each with its own
+    size, temperature, melt and Philox stream."""
+    cfgs = W.replica_batch(n_rep=5, n_max=3000, seed=W.BASE_SEED + 40)
+    for c in cfgs:
+        c["sys"] = dict(c["sys"], **over)
+    return cfgs
+
+
+def _gpu_batch(cfgs, precision):
+    import torch
+    dev = torch.device("cuda", 0)
+    ctx = R.Context(0)
+    plist = [R.make_params(c["sys"], precision, n_atoms=len(c["types"])) for c in cfgs]
+    types = np.concatenate([c["types"] for c in cfgs])
+    pos = np.concatenate([c["pos"] for c in cfgs])
+    vel = np.concatenate([c["vel"] for c in cfgs])
+    ctx.rbsog_set_batch(plist, torch.as_tensor(types, device=dev), torch.as_tensor(pos, device=dev),
+                        torch.as_tensor(vel, device=dev))
+    offs = np.concatenate([[0], np.cumsum([len(c["types"]) for c in cfgs])])
+    return ctx, offs
+
+
+def _gpu_single(cfg, precision):
+    import torch
+    dev = torch.device("cuda", 0)
+    ctx = R.Context(0)
+    p = R.make_params(cfg["sys"], precision, n_atoms=len(cfg["types"]))
+    ctx.rbsog_set_system(p, torch.as_tensor(cfg["types"], device=dev), torch.as_tensor(cfg["pos"], device=dev),
+                         torch.as_tensor(cfg["vel"], device=dev))
+    return ctx
+
+
+@pytest.mark.parametrize("precision", [R.FP64, R.MIXED])
+def test_batch_equals_single_systems(precision):
+    _say(f"case: batch of 5 vs single contexts, precision {precision}")
+    cfgs = _small_batch()
+    ctx, offs = _gpu_batch(cfgs, precision)
+    assert ctx.rbsog_n_systems() == 5
+    fb, eb = ctx.rbsog_compute_forces(3)
+    fb = fb.cpu().numpy()
+    for r, c in enumerate(cfgs):
+        one = _gpu_single(c, precision)
+        f1, e1 = one.rbsog_compute_forces(3)
+        assert np.array_equal(fb[offs[r]:offs[r + 1]], f1.cpu().numpy()), f"system {r}"
+        for key in ("u_core", "u_shell", "u_kspace", "u_self", "u_total"):
+            assert eb[r][key] == e1[key], (r, key)
+        ctx.rbsog_select_system(r)
+        m_b, S_b = ctx.rbsog_get_kmodes(3)
+        m_1, S_1 = one.rbsog_get_kmodes(3)
+        assert np.array_equal(m_b, m_1) and S_b == S_1
+        del one
+
+
+def test_batch_matches_oracle():
+    _say("case: batch of 5 vs oracle, fp64")
+    cfgs = _small_batch()
+    ctx, offs = _gpu_batch(cfgs, R.FP64)
+    ev = 7
+    fb, eb = ctx.rbsog_compute_forces(ev)
+    fb = fb.cpu().numpy()
+    for r, c in enumerate(cfgs):
+        osys = O.System(c["sys"], c["types"], c["pos"], c["vel"])
+        fo, eo = osys.forces(ev)
+        err = rel_rms(fb[offs[r]:offs[r + 1]], fo)
+        _say(f"  system {r} (N={len(c['types'])}): force rel rms {err:.2e}")
+        assert err <= TOL64
+        assert eb[r]["u_total"] == pytest.approx(eo["u_total"], rel=1e-11)
+        ctx.rbsog_select_system(r)
+        mg, _ = ctx.rbsog_get_kmodes(ev)
+        mo, _ = O.kmodes(osys.params, ev)
+        assert np.array_equal(mg, mo)
+        nr, rk = ctx.rbsog_get_shell_ranks(ev)
+        for i in range(0, len(c["types"]), 97):
+            ro = osys.shell_ranks(i, ev)
+            assert nr[i] == len(ro) and np.array_equal(rk[i, : nr[i]], ro), (r, i)
+
+
+def test_batch_velocity_verlet_matches_oracle():
+    """12 steps with a Berendsen thermostat towards each replica's own
+    temperature and a 0.3 A skin: every replica rebuilds on its own schedule
+    (displacement-triggered) and tracks its oracle trajectory."""
+    _say("case: batch of 5 vv 12 steps vs oracle")
+    cfgs = _small_batch(skin=0.3, rebuild_every=1000, tau_t=0.002)
+    for c in cfgs:
+        c["sys"]["t_target"] = c["T"]
+    ctx, offs = _gpu_batch(cfgs, R.FP64)
+    ctx.rbsog_compute_forces(0, want_energy=False)
+    eg = ctx.rbsog_step(12)
+    pg, vg, fg, evg = ctx.rbsog_get_state()
+    pg, vg, fg = pg.cpu().numpy(), vg.cpu().numpy(), fg.cpu().numpy()
+    assert evg == 12
+    builds = []
+    for r, c in enumerate(cfgs):
+        osys = O.System(c["sys"], c["types"], c["pos"], c["vel"])
+        osys.forces(0)
+        eo = osys.vv_steps(12)
+        po, vo, fo, _ = osys.state()
+        sl = slice(offs[r], offs[r + 1])
+        L = np.array(c["sys"]["box"])
+        d = pg[sl] - po
+        d -= L * np.rint(d / L)
+        assert np.abs(d).max() < 1e-9, r
+        assert rel_rms(vg[sl], vo) < 1e-9, r
+        assert rel_rms(fg[sl], fo) < 1e-9, r
+        assert eg[r]["kinetic"] == pytest.approx(eo["kinetic"], rel=1e-9)
+        builds.append(eg[r]["n_builds"])
+    _say(f"  builds per replica: {builds}")
+    assert max(builds) >= 2
+
+
+def test_batch_rejects_bad_input():
+    import torch
+    dev = torch.device("cuda", 0)
+    cfgs = _small_batch()
+    plist = [R.make_params(c["sys"], R.FP64, n_atoms=len(c["types"])) for c in cfgs]
+    plist[2].r_core = 4.5  # shared parameter differs
+    types = np.concatenate([c["types"] for c in cfgs])
+    pos = np.concatenate([c["pos"] for c in cfgs])
+    ctx = R.Context(0)
+    with pytest.raises(R.RbsogError) as e:
+        ctx.rbsog_set_batch(plist, torch.as_tensor(types, device=dev), torch.as_tensor(pos, device=dev))
+    assert e.value.code == -1
+    plist = [R.make_params(c["sys"], R.FP64, n_atoms=len(c["types"])) for c in cfgs]
+    bad = types.copy()
+    n0 = len(cfgs[0]["types"])
+    bad[n0 + 1] = 1 - bad[n0 + 1]  # second replica no longer neutral
+    with pytest.raises(R.RbsogError) as e:
+        ctx.rbsog_set_batch(plist, torch.as_tensor(bad, device=dev), torch.as_tensor(pos, device=dev))
+    assert e.value.code == -6
+
+
+def test_full_batch_of_64_replicas():
+    """The 64-replica workload (600664 ions, 566..32742 per replica) in the
+    benchmark's mixed form: every replica bitwise equal to its own
+    single-system run; the two smallest also against the oracle."""
+    _say("case: 64 replicas mixed vs single contexts")
+    cfgs = W.replica_batch()
+    ctx, offs = _gpu_batch(cfgs, R.MIXED)
+    ev = 2
+    fb, eb = ctx.rbsog_compute_forces(ev)
+    fb = fb.cpu().numpy()
+    assert np.isfinite(fb).all()
+    for r, c in enumerate(cfgs):
+        one = _gpu_single(c, R.MIXED)
+        f1, e1 = one.rbsog_compute_forces(ev)
+        assert np.array_equal(fb[offs[r]:offs[r + 1]], f1.cpu().numpy()), f"replica {r}"
+        assert eb[r]["u_total"] == e1["u_total"]
+        del one
+    sizes = np.diff(offs)
+    for r in np.argsort(sizes)[:2]:
+        c = cfgs[r]
+        fo, _ = O.System(c["sys"], c["types"], c["pos"], c["vel"]).forces(ev)
+        err = rel_rms(fb[offs[r]:offs[r + 1]], fo)
+        _say(f"  replica {r} (N={sizes[r]}): mixed force rel rms vs oracle {err:.2e}")
+        assert err <= TOL32

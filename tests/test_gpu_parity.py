@@ -262,31 +262,47 @@ def test_forces_licl_nacl_four_species(precision, tol):
     _force_parity(_licl_small(), precision, tol, evs=(0, 3))
 
 
-@pytest.mark.parametrize("precision,tol", [(R.FP64, TOL64), (R.MIXED, TOL32)])
-def test_full_size_sampled_atoms(precision, tol):
-    """The 10^6-ion workload at its full size, in the launch configuration the
-    benchmark uses: modes bit-exact, rho(k) of every mode, and the short-range
-    and k-space forces of 300 sampled ions against the oracle computing them
-    one by one."""
-    _say(f"case: full size licl_nacl_1m precision {precision}")
-    cfg = W.config("licl_nacl_1m")
+_FULL = {}
+
+
+def _full_size_oracle(name, ev):
+    """Workload, oracle modes, rho(k) of every mode and the short-range and
+    k-space forces of 300 sampled ions; shared by both precision forms."""
+    key = (name, ev)
+    if key not in _FULL:
+        _FULL.clear()
+        cfg = W.config(name)
+        osys = oracle_system(cfg, cfg["sys"])
+        mo, So = O.kmodes(osys.params, ev)
+        rho_o = osys.rho(mo)
+        sel = np.sort(np.random.default_rng(7).choice(len(cfg["types"]), 300, replace=False)).astype(np.int32)
+        fs_o = osys.forces_short_atoms(ev, sel)
+        V = float(np.prod(cfg["sys"]["box"]))
+        fk_o = osys.kforce_atoms(mo, rho_o, So / (len(mo) * V), sel)
+        _FULL[key] = (cfg, mo, rho_o, sel, fs_o, fk_o)
+    return _FULL[key]
+
+
+@pytest.mark.parametrize("name,precision,tol", [("licl_nacl_1m", R.FP64, TOL64), ("licl_nacl_1m", R.MIXED, TOL32),
+                                                ("nacl_5m", R.MIXED, TOL32), ("nacl_5m", R.FP64, TOL64)])
+def test_full_size_sampled_atoms(name, precision, tol):
+    """The 10^6-ion four-species workload and the 5*10^6-ion NaCl melt
+    (P_F = 1000) at full size, in the launch configuration the benchmark
+    uses: modes bit-exact, rho(k) of every mode, and the short-range and
+    k-space forces of 300 sampled ions against the oracle computing them one
+    by one."""
+    _say(f"case: full size {name} precision {precision}")
     ev = 2
+    cfg, mo, rho_o, sel, fs_o, fk_o = _full_size_oracle(name, ev)
     ctx, sysp = gpu_system(cfg, precision)
     fg, eg = ctx.rbsog_compute_forces(ev)
     fs_g, fk_g = ctx.rbsog_get_force_parts()
     mg, Sg = ctx.rbsog_get_kmodes(ev)
     rho_g = ctx.rbsog_get_rho(len(mg))
-    osys = oracle_system(cfg, sysp)
-    mo, So = O.kmodes(osys.params, ev)
     assert np.array_equal(mg, mo)
-    rho_o = osys.rho(mo)
     e_rho = rel_rms(rho_g, rho_o)
     _say(f"  rho rel rms {e_rho:.2e}")
     assert e_rho <= tol
-    sel = np.sort(np.random.default_rng(7).choice(len(cfg["types"]), 300, replace=False)).astype(np.int32)
-    fs_o = osys.forces_short_atoms(ev, sel)
-    V = float(np.prod(sysp["box"]))
-    fk_o = osys.kforce_atoms(mo, rho_o, So / (len(mo) * V), sel)
     e_s = rel_rms(fs_g.cpu().numpy()[sel], fs_o)
     e_k = rel_rms(fk_g.cpu().numpy()[sel], fk_o)
     _say(f"  sampled atoms: short {e_s:.2e} kspace {e_k:.2e}")
