@@ -7,6 +7,12 @@ r_core 5.5 A, r_shell 11 A, skin 1 A, P_R = 30, P_F = 500, lists rebuilt every
 with jitter, Berendsen thermostat at 1150 K with tau = dt.  Both precision forms run:
 FP32-mixed (the reported value) and plain FP64 (reported beside it).
 
+The batched form runs beside it: 64 molten-NaCl replicas of 566..32742 ions
+(600664 in all) in one context, FP32-mixed, launch shapes autotuned, each step
+replayed from a captured HIP graph; its aggregate atom-steps/s is reported
+against the same replicas stepped one after another, each in its own context
+with plain launches.
+
 Prints one JSON line.  The roofline object describes the dominant kernel of
 the reported form, timed with HIP events on the library's stream during the
 timed steps; its algorithmic flop count per (atom, mode) pair is fixed below.
@@ -80,6 +86,74 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int):
     T = 2 * e1["kinetic"] / ((3 * n - 3) * 8.617333262e-5)
     return {"seconds": dt, "value": n * steps / dt, "ms_per_step": 1e3 * dt / steps, "phases": prof,
             "energy": e1, "energy_warm": e0, "T_end": T, "force0": f0}
+
+
+def _batch_inputs(cfgs, dev):
+    import torch
+    cat = lambda k: torch.as_tensor(np.concatenate([c[k] for c in cfgs]), device=dev)
+    return cat("types"), cat("pos"), cat("vel")
+
+
+def run_batch(n_rep: int, steps: int, warmup: int):
+    """Aggregate throughput of the batched form, and of the same replicas run
+    one after another (own context each, plain launches)."""
+    import torch
+    from paper_2512_24970_amd import rbsog as R
+    from paper_2512_24970_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    cfgs = W.replica_batch(n_rep=n_rep)
+    for c in cfgs:
+        c["sys"] = dict(c["sys"], t_target=c["T"], tau_t=c["sys"]["dt"])
+    n_tot = sum(len(c["types"]) for c in cfgs)
+    stream = torch.cuda.Stream(device=dev)
+    ctx = R.Context(0, stream=stream)
+    plist = [R.make_params(c["sys"], R.MIXED, n_atoms=len(c["types"])) for c in cfgs]
+    ctx.rbsog_set_batch(plist, *_batch_inputs(cfgs, dev))
+    tuning = ctx.rbsog_autotune(3)
+    ctx.rbsog_use_graphs(True)
+    _log(f"[bench] batch: {n_rep} replicas, {n_tot} ions, tuning {tuning}; warmup {warmup} steps")
+    ctx.rbsog_step(warmup)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    e = ctx.rbsog_step(steps)
+    stream.synchronize()
+    dt_b = time.perf_counter() - t0
+    # kernel phases of the batched step (kernel by kernel while timed)
+    ctx.rbsog_profile_read()
+    ctx.rbsog_profile_enable(True)
+    ctx.rbsog_step(10)
+    prof = ctx.rbsog_profile_read()
+    ctx.rbsog_profile_enable(False)
+    ctx.close()
+    _log(f"[bench] batch: {steps} steps in {dt_b:.3f} s -> {n_tot * steps / dt_b:.4g} atom-steps/s")
+    # the same replicas, one context each, stepped one after another
+    ctxs = []
+    for c in cfgs:
+        x = R.Context(0)
+        x.rbsog_set_system(R.make_params(c["sys"], R.MIXED, n_atoms=len(c["types"])), *_batch_inputs([c], dev))
+        x.rbsog_step(warmup, want_energy=False)
+        ctxs.append(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x in ctxs:
+        x.rbsog_step(steps, want_energy=False)
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    for x in ctxs:
+        x.close()
+    _log(f"[bench] sequential: {steps} steps x {n_rep} contexts in {dt_s:.3f} s -> "
+         f"{n_tot * steps / dt_s:.4g} atom-steps/s")
+    T = [2 * x["kinetic"] / ((3 * len(c["types"]) - 3) * 8.617333262e-5) for x, c in zip(e, cfgs)]
+    return {
+        "workload": f"nacl_replicas{n_rep}", "n_systems": n_rep, "n_atoms": n_tot,
+        "sizes": [int(len(c["types"])) for c in cfgs][:8] + ["..."],
+        "form": "mixed", "value": n_tot * steps / dt_b, "unit": "atom-steps/s",
+        "ms_per_step": 1e3 * dt_b / steps, "graph": True, "tuning": tuning,
+        "sequential_value": n_tot * steps / dt_s, "sequential_ms_per_step": 1e3 * dt_s / steps,
+        "speedup_vs_sequential": dt_s / dt_b,
+        "phases_ms_per_step": {k: round(v[0] / 10, 4) for k, v in prof.items()},
+        "T_end_K_range": [round(min(T), 1), round(max(T), 1)],
+    }
 
 
 # Pair-kernel model (per atom, FMA = 2): a distance test is 17 flops (three
@@ -197,6 +271,7 @@ def main() -> int:
     ap.add_argument("--forms", default="mixed,fp64", help="comma list of mixed,fp64; the first is reported")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="atoms in the CPU-baseline sample (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--batch", type=int, default=64, help="replicas in the batched-form leg (0: skip)")
     args = ap.parse_args()
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
@@ -251,6 +326,8 @@ def main() -> int:
         line[f] = {"value": rf["value"], "ms_per_step": rf["ms_per_step"], "T_end_K": round(rf["T_end"], 1),
                    "roofline": roofline(f, rf, n, cfg["sys"]),
                    "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in rf["phases"].items()}}
+    if args.batch > 0:
+        line["batch"] = run_batch(args.batch, args.steps, args.warmup)
     if args.cpu_sample > 0:
         _log(f"[bench] cpu baseline: oracle on {args.cpu_sample} atoms")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)

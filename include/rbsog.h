@@ -178,6 +178,33 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last);
 rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* force, uint64_t* eval,
                              int ptrs_on_device);
 
+/* ---- launch shapes and step graphs -------------------------------------- */
+
+/* Launch shapes of the hot kernels.  No choice changes a result bit: partial
+ * sums are taken per 64-atom wavefront and every structure factor is summed
+ * over the atoms in the same order whatever the shape. */
+typedef struct {
+    int32_t pair_block; /* atoms per workgroup of the pair kernel: 64, 128, 256 (default 256) */
+    int32_t pair_ku;    /* neighbour positions fetched ahead per lane (shell-batch tile): 4, 8 (4) */
+    int32_t rho_mpl;    /* k-modes per lane of the rho kernel (64 rho_mpl per workgroup): 1, 2 (1) */
+    int32_t kf_block;   /* atoms per workgroup of the k-space force kernel: 64, 128, 256 (256) */
+} rbsog_tuning;
+
+/* Time every candidate shape of each hot kernel with `reps` launches at the
+ * current positions (HIP events on the context's stream) and keep the
+ * fastest; the chosen shapes are returned in `chosen` (may be NULL).  Leaves
+ * positions, velocities and forces as they were.  Synchronises. */
+rbsog_status rbsog_autotune(rbsog_ctx* ctx, int32_t reps, rbsog_tuning* chosen);
+/* Set or read the shapes directly (values outside the lists: RBSOG_E_ARG). */
+rbsog_status rbsog_set_tuning(rbsog_ctx* ctx, const rbsog_tuning* t);
+rbsog_status rbsog_get_tuning(rbsog_ctx* ctx, rbsog_tuning* t);
+/* With enable != 0, rbsog_step replays each step as one captured HIP graph
+ * (captured on first use per variant: scheduled rebuild or not, energies or
+ * not; recaptured after list growth or a tuning change).  Needs the context
+ * to have a non-default stream; while phase timing is on, steps are launched
+ * kernel by kernel.  Off by default. */
+rbsog_status rbsog_use_graphs(rbsog_ctx* ctx, int enable);
+
 /* ---- kernel timing ------------------------------------------------------ */
 
 /* Kernel phases timed with HIP events on the context's stream. */

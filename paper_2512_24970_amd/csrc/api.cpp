@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <functional>
+#include <initializer_list>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -133,8 +135,20 @@ struct rbsog_ctx {
         open_a = nullptr;
     }
 
+    // step graphs, [scheduled rebuild][energies], captured on first use
+    bool use_graph = false;
+    hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
+    void drop_graphs()
+    {
+        for (auto& g : graphs) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    }
+
     ~rbsog_ctx()
     {
+        drop_graphs();
         for (auto& r : recs) {
             (void)hipEventDestroy(r.a);
             (void)hipEventDestroy(r.b);
@@ -251,12 +265,15 @@ Plan one(const rbsog_ctx* c, int r)
     P.kd = c->d_kd.as<KDev>() + r;
     P.sc = c->scalars.as<DeviceScalars>() + r;
     P.R = 1;
+    P.tune = c->plan.tune;
     P.atoms.blocks = blocks_for(s.n, kBlock);
+    P.pair_atoms.blocks = blocks_for(s.n, P.tune.pair_block);
+    P.kf_atoms.blocks = blocks_for(s.n, P.tune.kf_block);
     P.cells.blocks = s.n > 0 ? s.ncell : 0;
     P.atom1.blocks = s.n;
     // an empty system draws no modes and sums no structure factors
     P.modes64.blocks = (s.n > 0 && k.sampled) ? blocks_for(k.n_modes, 64) : 0;
-    P.rho.blocks = (s.n > 0 && k.n_modes > 0) ? k.n_chunks * blocks_for(k.n_modes, 64) : 0;
+    P.rho.blocks = (s.n > 0 && k.n_modes > 0) ? k.n_chunks * blocks_for(k.n_modes, 64 * P.tune.rho_mpl) : 0;
     P.modes1.blocks = s.n > 0 ? k.n_modes : 0;
     P.list_mode = c->plan.list_mode;
     P.cap_core = c->plan.cap_core;
@@ -264,37 +281,37 @@ Plan one(const rbsog_ctx* c, int r)
     return P;
 }
 
-// Block maps of the batch launches (none for a single system).
+// Block maps of the batch launches (none for a single system).  Called again
+// whenever the tuning changes the shapes.
 void plan_launches(rbsog_ctx* c)
 {
+    HIP_OK(hipStreamSynchronize(c->stream));  // the old maps may still be in use
+    c->drop_graphs();
     Plan& P = c->plan;
     P.sys = c->d_sys.as<DevSys>();
     P.kd = c->d_kd.as<KDev>();
     P.sc = c->scalars.as<DeviceScalars>();
     P.R = c->R;
+    constexpr int kShapes = 8;
+    Shape* dst[kShapes] = {&P.atoms, &P.pair_atoms, &P.kf_atoms, &P.cells, &P.atom1, &P.modes64, &P.rho, &P.modes1};
     if (c->R == 1) {
         const Plan o = one(c, 0);
-        P.atoms = o.atoms;
-        P.cells = o.cells;
-        P.atom1 = o.atom1;
-        P.modes64 = o.modes64;
-        P.rho = o.rho;
-        P.modes1 = o.modes1;
+        const Shape* sh[kShapes] = {&o.atoms, &o.pair_atoms, &o.kf_atoms, &o.cells, &o.atom1, &o.modes64, &o.rho, &o.modes1};
+        for (int q = 0; q < kShapes; ++q) *dst[q] = *sh[q];
         return;
     }
-    std::vector<int2> m[6];
+    std::vector<int2> m[kShapes];
     for (int r = 0; r < c->R; ++r) {
         const Plan o = one(c, r);
-        const Shape* sh[6] = {&o.atoms, &o.cells, &o.atom1, &o.modes64, &o.rho, &o.modes1};
-        for (int q = 0; q < 6; ++q)
+        const Shape* sh[kShapes] = {&o.atoms, &o.pair_atoms, &o.kf_atoms, &o.cells, &o.atom1, &o.modes64, &o.rho, &o.modes1};
+        for (int q = 0; q < kShapes; ++q)
             for (int b = 0; b < sh[q]->blocks; ++b) m[q].push_back(make_int2(r, b));
     }
     size_t total = 0;
     for (auto& v : m) total += v.size();
     c->d_maps.alloc(sizeof(int2) * std::max<size_t>(1, total));
     int2* d = c->d_maps.as<int2>();
-    Shape* dst[6] = {&P.atoms, &P.cells, &P.atom1, &P.modes64, &P.rho, &P.modes1};
-    for (int q = 0; q < 6; ++q) {
+    for (int q = 0; q < kShapes; ++q) {
         dst[q]->blocks = (int)m[q].size();
         dst[q]->map = d;
         if (!m[q].empty()) HIP_OK(hipMemcpy(d, m[q].data(), sizeof(int2) * m[q].size(), hipMemcpyHostToDevice));
@@ -304,6 +321,7 @@ void plan_launches(rbsog_ctx* c)
 
 void plan_lists(rbsog_ctx* c, int cap_core, int cap_cand)
 {
+    c->drop_graphs();
     c->plan.cap_core = cap_core;
     c->plan.cap_cand = cap_cand;
     const size_t slots = (size_t)std::max(c->n_slots, 64);
@@ -395,6 +413,7 @@ void build_checked(rbsog_ctx* c)
         if (o & 4) {
             // a cell's stencil did not fit in LDS: larger stencil, then per-atom lists
             c->plan.list_mode = std::min(2, c->plan.list_mode + 1);
+            c->drop_graphs();
             continue;
         }
         grow_lists(c);
@@ -468,6 +487,107 @@ void enqueue_step(rbsog_ctx* c, bool scheduled, bool energy)
     c->end();
     enqueue_build(c, true);
     enqueue_forces(c, energy, true);
+}
+
+// The same step as one HIP graph launch: the kernel sequence of each variant
+// is captured once and replayed (it holds kernels only).  Needs a non-default
+// stream; phase timing records no events inside a graph, so it falls back to
+// plain launches while timing is on.
+void launch_step(rbsog_ctx* c, bool scheduled, bool energy)
+{
+    if (!c->use_graph || c->profiling || c->stream == nullptr) {
+        enqueue_step(c, scheduled, energy);
+        return;
+    }
+    hipGraphExec_t& g = c->graphs[(scheduled ? 2 : 0) + (energy ? 1 : 0)];
+    if (!g) {
+        hipGraph_t graph = nullptr;
+        HIP_OK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_step(c, scheduled, energy);
+        HIP_OK(hipStreamEndCapture(c->stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_OK(e);
+    }
+    HIP_OK(hipGraphLaunch(g, c->stream));
+}
+
+double time_ms(rbsog_ctx* c, int reps, const std::function<void()>& f)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    f();  // warm
+    HIP_OK(hipEventRecord(a, c->stream));
+    for (int r = 0; r < reps; ++r) f();
+    HIP_OK(hipEventRecord(b, c->stream));
+    HIP_OK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
+// Time each kernel under its candidate launch shapes at the current positions
+// and keep the fastest.  Every candidate computes the same bits, so the
+// evaluations it repeats leave the state as it was.
+void autotune(rbsog_ctx* c, int reps)
+{
+    const bool was_profiling = c->profiling;
+    c->profiling = false;
+    hipStream_t st = c->stream;
+    launch_set_eval(c->plan, c->eval, st);
+    enqueue_forces(c, false, false);
+    Tuning best = c->plan.tune;
+    auto try_shape = [&](Tuning t) {
+        c->plan.tune = t;
+        plan_launches(c);
+    };
+    double tb = 1e300;
+    for (int bs : {64, 128, 256})
+        for (int ku : {4, 8}) {
+            Tuning t = best;
+            t.pair_block = bs;
+            t.pair_ku = ku;
+            try_shape(t);
+            const double ms = time_ms(c, reps, [&] { launch_pair(c->plan, c->coef, c->mixed, false, st); });
+            if (ms < tb) {
+                tb = ms;
+                best.pair_block = bs;
+                best.pair_ku = ku;
+            }
+        }
+    tb = 1e300;
+    for (int mpl : {1, 2}) {
+        Tuning t = best;
+        t.rho_mpl = mpl;
+        try_shape(t);
+        const double ms = time_ms(c, reps, [&] { launch_rho(c->plan, c->mixed, st); });
+        if (ms < tb) {
+            tb = ms;
+            best.rho_mpl = mpl;
+        }
+    }
+    try_shape(best);
+    launch_rho_finalize(c->plan, st);
+    launch_finalize(c->plan, st);
+    tb = 1e300;
+    for (int bs : {64, 128, 256}) {
+        Tuning t = best;
+        t.kf_block = bs;
+        try_shape(t);
+        const double ms = time_ms(c, reps, [&] { launch_kforce(c->plan, c->mixed, false, false, st); });
+        if (ms < tb) {
+            tb = ms;
+            best.kf_block = bs;
+        }
+    }
+    try_shape(best);
+    enqueue_forces(c, false, false);
+    HIP_OK(hipStreamSynchronize(st));
+    c->forces_valid = true;
+    c->profiling = was_profiling;
 }
 
 // Geometry, cutoffs, species and integrator constants of one system.
@@ -582,9 +702,11 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     double wsum = 0.0;
     for (double w : c->sog.w) wsum += w;
 
+    c->drop_graphs();
     c->R = R;
     c->prm = prm;
     c->sel = 0;
+    c->plan.tune = Tuning{};
     c->slot_off.assign(slot_off.begin(), slot_off.end() - 1);
     c->n_slots = slot_off[R];
     c->n_user = n_user;
@@ -611,10 +733,10 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     for (const auto& s : c->hs) n_cells += 2 * (size_t)s.ncell + 1;
     c->cells.alloc(sizeof(int32_t) * n_cells);
     HIP_OK(hipMemsetAsync(c->cells.p, 0, sizeof(int32_t) * n_cells, c->stream));
-    size_t n_blocks = 0;
-    for (const auto& s : c->hs) n_blocks += blocks_for(s.n, kBlock);
-    c->pair_part.alloc(sizeof(double) * kPairPart * std::max<size_t>(1, n_blocks));
-    c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_blocks));
+    size_t n_waves = 0;
+    for (const auto& s : c->hs) n_waves += blocks_for(s.n, 64);
+    c->pair_part.alloc(sizeof(double) * kPairPart * std::max<size_t>(1, n_waves));
+    c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
     c->scalars.alloc(sizeof(DeviceScalars) * R);
     HIP_OK(hipMemsetAsync(c->scalars.p, 0, sizeof(DeviceScalars) * R, c->stream));
     {
@@ -625,7 +747,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
         double* td = reinterpret_cast<double*>(TP + N);
         int32_t* tip = reinterpret_cast<int32_t*>(td + 6 * N);
         int32_t* cells = c->cells.as<int32_t>();
-        size_t blk = 0;
+        size_t wav = 0;
         for (int r = 0; r < R; ++r) {
             DevSys& s = c->hs[r];
             const size_t o = (size_t)c->slot_off[r];
@@ -648,9 +770,9 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             s.cell_count = cells;
             s.cell_start = cells + s.ncell;
             cells += 2 * (size_t)s.ncell + 1;
-            s.pair_part = c->pair_part.as<double>() + blk * kPairPart;
-            s.kin_part = c->kin_part.as<double>() + blk;
-            blk += blocks_for(s.n, kBlock);
+            s.pair_part = c->pair_part.as<double>() + wav * kPairPart;
+            s.kin_part = c->kin_part.as<double>() + wav;
+            wav += blocks_for(s.n, 64);
             s.sc = c->scalars.as<DeviceScalars>() + r;
         }
     }
@@ -939,6 +1061,55 @@ rbsog_status rbsog_select_system(rbsog_ctx* ctx, int32_t r)
     });
 }
 
+rbsog_status rbsog_autotune(rbsog_ctx* ctx, int32_t reps, rbsog_tuning* chosen)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        require(reps >= 1, RBSOG_E_ARG, "reps < 1");
+        autotune(ctx, reps);
+        if (chosen) {
+            const Tuning& t = ctx->plan.tune;
+            *chosen = rbsog_tuning{t.pair_block, t.pair_ku, t.rho_mpl, t.kf_block};
+        }
+    });
+}
+
+rbsog_status rbsog_set_tuning(rbsog_ctx* ctx, const rbsog_tuning* t)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        require(t != nullptr, RBSOG_E_ARG, "tuning is NULL");
+        auto one_of = [](int v, std::initializer_list<int> ok) {
+            for (int x : ok)
+                if (v == x) return true;
+            return false;
+        };
+        require(one_of(t->pair_block, {64, 128, 256}) && one_of(t->pair_ku, {4, 8}) && one_of(t->rho_mpl, {1, 2}) &&
+                    one_of(t->kf_block, {64, 128, 256}),
+                RBSOG_E_ARG, "tuning value out of range");
+        ctx->plan.tune = Tuning{t->pair_block, t->pair_ku, t->rho_mpl, t->kf_block};
+        plan_launches(ctx);
+    });
+}
+
+rbsog_status rbsog_get_tuning(rbsog_ctx* ctx, rbsog_tuning* t)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        require(t != nullptr, RBSOG_E_ARG, "tuning is NULL");
+        const Tuning& u = ctx->plan.tune;
+        *t = rbsog_tuning{u.pair_block, u.pair_ku, u.rho_mpl, u.kf_block};
+    });
+}
+
+rbsog_status rbsog_use_graphs(rbsog_ctx* ctx, int enable)
+{
+    return guarded(ctx, [&] {
+        ctx->drop_graphs();
+        ctx->use_graph = enable != 0;
+    });
+}
+
 rbsog_status rbsog_build_lists(rbsog_ctx* ctx)
 {
     return guarded(ctx, [&] {
@@ -1001,7 +1172,7 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
                 const uint64_t step = ctx->eval + 1 + (uint64_t)k;
                 const bool scheduled = step % (uint64_t)every == 0;
                 const bool energy = e_last != nullptr && k == n_steps - 1;
-                enqueue_step(ctx, scheduled, energy);
+                launch_step(ctx, scheduled, energy);
             }
             const auto h = read_scalars(ctx);
             const int o = any_overflow(h);
@@ -1011,10 +1182,12 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
                 return;
             }
             require(attempt < 4 && (o & 2) == 0, RBSOG_E_CAPACITY, "list capacity exceeded in the step loop");
-            if (o & 4)
+            if (o & 4) {
                 ctx->plan.list_mode = std::min(2, ctx->plan.list_mode + 1);
-            else
+                ctx->drop_graphs();
+            } else {
                 grow_lists(ctx);
+            }
             snapshot(ctx, false);
             build_checked(ctx);
             launch_set_eval(ctx->plan, ctx->eval, ctx->stream);

@@ -83,15 +83,26 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// Sum of v over a 256-thread block in a fixed order; valid in thread 0.
-__device__ inline double block_sum(double v, double* red /*[4]*/)
+// Per-wavefront partial sums: atom i's wavefront (atoms 64w .. 64w+63 of its
+// system, whatever the block size) writes entry w.  Later reductions run
+// over the entries in order, so results do not depend on the block size.
+__device__ inline void wave_partial(double v, int i, int n, double* part, int stride, int c)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && (i & ~63) < n) part[(size_t)(i >> 6) * stride + c] = v;
+}
+
+// Sum of v over a block of up to 1024 threads in a fixed order; valid in
+// thread 0.
+__device__ inline double block_sum(double v, double* red /*[blockDim.x / 64]*/)
 {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
     double t = 0.0;
-    if (threadIdx.x == 0) t = ((red[0] + red[1]) + red[2]) + red[3];
+    if (threadIdx.x == 0)
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
     __syncthreads();
     return t;
 }
@@ -711,14 +722,13 @@ struct FloydMask {
     }
 };
 
-template <bool MIXED, bool ENERGY, int J>
+template <bool MIXED, bool ENERGY, int J, int KU>
 __global__ __launch_bounds__(kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf)
 {
     RB_SYS(xcd_block(blockIdx.x, gridDim.x))
     extern __shared__ uint32_t mask_sm[];
     __shared__ PairCoef pc[kMaxSpecies * kMaxSpecies];
     __shared__ PairCoefF pcf[kMaxSpecies * kMaxSpecies];
-    __shared__ double red[4];
     const int S = s.n_species;
     for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
         const PairCoef c = s.pair[t];
@@ -749,7 +759,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf
         // run in list order.  Core-list lines are read once: non-temporal
         // loads keep them from evicting the positions that neighbours re-read
         // (a candidate row is re-read by its own lane, so it stays cached).
-        constexpr int kU = 4;
+        constexpr int kU = KU;
         // core sum, eq. (24)
         const int nc = min(s.core_cnt[i], s.cap_core);
         const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
@@ -853,22 +863,11 @@ __global__ __launch_bounds__(kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf
         __builtin_nontemporal_store(Fy, s.fsy + i);
         __builtin_nontemporal_store(Fz, s.fsz + i);
     }
-    const double bx = block_sum(Fx, red);
-    const double by = block_sum(Fy, red);
-    const double bz = block_sum(Fz, red);
-    double bu = 0.0, bs = 0.0;
-    if (ENERGY) {
-        bu = block_sum(Uc, red);
-        bs = block_sum(Us, red);
-    }
-    if (threadIdx.x == 0) {
-        double* p = s.pair_part + (size_t)lb * kPairPart;
-        p[0] = bx;
-        p[1] = by;
-        p[2] = bz;
-        p[3] = bu;
-        p[4] = bs;
-    }
+    wave_partial(Fx, i, s.n, s.pair_part, kPairPart, 0);
+    wave_partial(Fy, i, s.n, s.pair_part, kPairPart, 1);
+    wave_partial(Fz, i, s.n, s.pair_part, kPairPart, 2);
+    wave_partial(Uc, i, s.n, s.pair_part, kPairPart, 3);
+    wave_partial(Us, i, s.n, s.pair_part, kPairPart, 4);
 }
 
 // Export of the shell ranks drawn by the pair kernel (same selection code).
@@ -983,13 +982,14 @@ __device__ inline void sincos_turns_f32(double t, float& c, float& s)
     s = __builtin_amdgcn_sinf(fr);
 }
 
-// rho(k) of eq. (22) over one atom chunk for 64 modes: one mode per lane,
-// each of the four waves of the block takes a contiguous quarter of the
-// chunk, four atoms per iteration, atoms read through the scalar unit.
-// Partial sums per chunk, reduced later in a fixed order.  The mixed form
-// sums the four FP32 products q cos, q sin of an iteration in FP32 and adds
-// that to the FP64 accumulators.
-template <bool MIXED>
+// rho(k) of eq. (22) over one atom chunk for 64 MPL modes: MPL modes per
+// lane, each of the four waves of the block takes a contiguous quarter of the
+// chunk, four atoms per iteration, atoms read through the scalar unit (one
+// read serves 64 MPL modes).  Partial sums per chunk, reduced later in a fixed
+// order; MPL changes neither the per-mode summation order nor the result.
+// The mixed form sums the four FP32 products q cos, q sin of an iteration in
+// FP32 and adds that to the FP64 accumulators.
+template <bool MIXED, int MPL>
 __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict__ kd)
 {
     RB_SYS(blockIdx.x)
@@ -997,7 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict_
     const int chunk = lb % k.n_chunks;
     const int tile = lb / k.n_chunks;
     __shared__ double2 tab[MIXED ? 1 : kTableSize];
-    __shared__ double red[4][64][2];
+    __shared__ double red[4][64 * MPL][2];
     using qreal = typename std::conditional<MIXED, float, double>::type;
     __shared__ qreal qs[kMaxSpecies];
     if (!MIXED)
@@ -1007,71 +1007,90 @@ __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict_
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int p = tile * 64 + lane;
-    const bool ok = p < k.n_modes;
-    const ModeRec mr = ok ? k.modes[p] : ModeRec{};
     const double sc = MIXED ? 1.0 : (double)kTableSize;
-    const double kx = mr.mx * (sc * s.invL[0]);
-    const double ky = mr.my * (sc * s.invL[1]);
-    const double kz = mr.mz * (sc * s.invL[2]);
+    double kx[MPL], ky[MPL], kz[MPL], re[MPL], im[MPL];
+#pragma unroll
+    for (int j = 0; j < MPL; ++j) {
+        const int p = tile * 64 * MPL + 64 * j + lane;
+        const ModeRec mr = p < k.n_modes ? k.modes[p] : ModeRec{};
+        kx[j] = mr.mx * (sc * s.invL[0]);
+        ky[j] = mr.my * (sc * s.invL[1]);
+        kz[j] = mr.mz * (sc * s.invL[2]);
+        re[j] = 0.0;
+        im[j] = 0.0;
+    }
     // chunk and its quarters are multiples of four atoms (host guarantees
     // chunk % 16 == 0), so the type quadruples below are aligned
     const int qw = k.chunk >> 2;
     const int a0 = chunk * k.chunk + wave * qw;
     const int a1 = min(s.n, a0 + qw);
-    double re = 0.0, im = 0.0;
     int a = a0;
     for (; a + 4 <= a1; a += 4) {
         const double4 P0 = s.p[a], P1 = s.p[a + 1], P2 = s.p[a + 2], P3 = s.p[a + 3];
         const int4 T = *reinterpret_cast<const int4*>(s.type + a);
         const qreal q0 = qs[T.x], q1 = qs[T.y], q2 = qs[T.z], q3 = qs[T.w];
-        const double t0 = mode_phase(kx, ky, kz, P0), t1 = mode_phase(kx, ky, kz, P1);
-        const double t2 = mode_phase(kx, ky, kz, P2), t3 = mode_phase(kx, ky, kz, P3);
-        if (MIXED) {
-            float c0, s0, c1, s1, c2, s2, c3, s3;
-            sincos_turns_f32(t0, c0, s0);
-            sincos_turns_f32(t1, c1, s1);
-            sincos_turns_f32(t2, c2, s2);
-            sincos_turns_f32(t3, c3, s3);
-            const float rs = fmaf(q3, c3, fmaf(q2, c2, fmaf(q1, c1, q0 * c0)));
-            const float is = fmaf(q3, s3, fmaf(q2, s2, fmaf(q1, s1, q0 * s0)));
-            re += (double)rs;
-            im += (double)is;
-        } else {
-            double c0, s0, c1, s1, c2, s2, c3, s3;
-            sincos1024(t0, tab, c0, s0);
-            sincos1024(t1, tab, c1, s1);
-            sincos1024(t2, tab, c2, s2);
-            sincos1024(t3, tab, c3, s3);
-            re = fma(q3, c3, fma(q2, c2, fma(q1, c1, fma(q0, c0, re))));
-            im = fma(q3, s3, fma(q2, s2, fma(q1, s1, fma(q0, s0, im))));
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) {
+            const double t0 = mode_phase(kx[j], ky[j], kz[j], P0), t1 = mode_phase(kx[j], ky[j], kz[j], P1);
+            const double t2 = mode_phase(kx[j], ky[j], kz[j], P2), t3 = mode_phase(kx[j], ky[j], kz[j], P3);
+            if (MIXED) {
+                float c0, s0, c1, s1, c2, s2, c3, s3;
+                sincos_turns_f32(t0, c0, s0);
+                sincos_turns_f32(t1, c1, s1);
+                sincos_turns_f32(t2, c2, s2);
+                sincos_turns_f32(t3, c3, s3);
+                const float rs = fmaf(q3, c3, fmaf(q2, c2, fmaf(q1, c1, q0 * c0)));
+                const float is = fmaf(q3, s3, fmaf(q2, s2, fmaf(q1, s1, q0 * s0)));
+                re[j] += (double)rs;
+                im[j] += (double)is;
+            } else {
+                double c0, s0, c1, s1, c2, s2, c3, s3;
+                sincos1024(t0, tab, c0, s0);
+                sincos1024(t1, tab, c1, s1);
+                sincos1024(t2, tab, c2, s2);
+                sincos1024(t3, tab, c3, s3);
+                re[j] = fma(q3, c3, fma(q2, c2, fma(q1, c1, fma(q0, c0, re[j]))));
+                im[j] = fma(q3, s3, fma(q2, s2, fma(q1, s1, fma(q0, s0, im[j]))));
+            }
         }
     }
     for (; a < a1; ++a) {
         const double4 P = s.p[a];
         const qreal q = qs[s.type[a]];
-        const double t = mode_phase(kx, ky, kz, P);
-        if (MIXED) {
-            float c, sn;
-            sincos_turns_f32(t, c, sn);
-            re += (double)(q * c);
-            im += (double)(q * sn);
-        } else {
-            double c, sn;
-            sincos1024(t, tab, c, sn);
-            re = fma(q, c, re);
-            im = fma(q, sn, im);
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) {
+            const double t = mode_phase(kx[j], ky[j], kz[j], P);
+            if (MIXED) {
+                float c, sn;
+                sincos_turns_f32(t, c, sn);
+                re[j] += (double)(q * c);
+                im[j] += (double)(q * sn);
+            } else {
+                double c, sn;
+                sincos1024(t, tab, c, sn);
+                re[j] = fma(q, c, re[j]);
+                im[j] = fma(q, sn, im[j]);
+            }
         }
     }
-    red[wave][lane][0] = re;
-    red[wave][lane][1] = im;
+#pragma unroll
+    for (int j = 0; j < MPL; ++j) {
+        red[wave][64 * j + lane][0] = re[j];
+        red[wave][64 * j + lane][1] = im[j];
+    }
     __syncthreads();
-    if (wave == 0 && ok) {
-        const double r = ((red[0][lane][0] + red[1][lane][0]) + red[2][lane][0]) + red[3][lane][0];
-        const double i = ((red[0][lane][1] + red[1][lane][1]) + red[2][lane][1]) + red[3][lane][1];
-        double* o = k.rho_part + ((size_t)chunk * k.n_modes_pad + p) * 2;
-        o[0] = r;
-        o[1] = i;
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) {
+            const int p = tile * 64 * MPL + 64 * j + lane;
+            if (p >= k.n_modes) continue;
+            const int l = 64 * j + lane;
+            const double r = ((red[0][l][0] + red[1][l][0]) + red[2][l][0]) + red[3][l][0];
+            const double i = ((red[0][l][1] + red[1][l][1]) + red[2][l][1]) + red[3][l][1];
+            double* o = k.rho_part + ((size_t)chunk * k.n_modes_pad + p) * 2;
+            o[0] = r;
+            o[1] = i;
+        }
     }
 }
 
@@ -1104,14 +1123,15 @@ __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __rest
     }
 }
 
-// Momentum correction (eq. 26) and energy sums; one block per system.
-__global__ __launch_bounds__(kBlock) void k_finalize(const DevSys* __restrict__ sys, const KDev* __restrict__ kd)
+// Momentum correction (eq. 26) and energy sums; one 1024-thread block per
+// system.
+__global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sys, const KDev* __restrict__ kd)
 {
     const DevSys s = global_view(sys[blockIdx.x]);
     const KDev k = global_view(kd[blockIdx.x]);
     const double* part = s.pair_part;
-    const int nb = (s.n + kBlock - 1) / kBlock;
-    __shared__ double red[4];
+    const int nb = (s.n + 63) / 64;  // wavefront partials
+    __shared__ double red[16];
     double v[kPairPart] = {0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nb; b += blockDim.x)
         for (int c = 0; c < kPairPart; ++c) v[c] += part[(size_t)b * kPairPart + c];
@@ -1143,7 +1163,6 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
     RB_SYS(blockIdx.x)
     const KDev k = global_view(kd[rb_m.x]);
     __shared__ double2 tab[MIXED ? 1 : kTableSize];
-    __shared__ double red[4];
     if (!MIXED) {
         for (int t = threadIdx.x; t < kTableSize; t += blockDim.x)
             tab[t] = make_double2(k.table[2 * t], k.table[2 * t + 1]);
@@ -1204,18 +1223,15 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
             ke = 0.5 * s.spc->mass[ti] * (vx * vx + vy * vy + vz * vz);
         }
     }
-    if (ENERGY) {
-        const double b = block_sum(ke, red);
-        if (threadIdx.x == 0) s.kin_part[lb] = b;
-    }
+    if (ENERGY) wave_partial(ke, i, s.n, s.kin_part, 1, 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_kinetic_finalize(const DevSys* __restrict__ sys)
+__global__ __launch_bounds__(1024) void k_kinetic_finalize(const DevSys* __restrict__ sys)
 {
     const DevSys s = global_view(sys[blockIdx.x]);
     const double* part = s.kin_part;
-    const int nb = (s.n + kBlock - 1) / kBlock;
-    __shared__ double red[4];
+    const int nb = (s.n + 63) / 64;  // wavefront partials
+    __shared__ double red[16];
     double v = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[b];
     const double t = block_sum(v, red);
@@ -1236,15 +1252,13 @@ __global__ __launch_bounds__(kBlock) void k_kinetic_finalize(const DevSys* __res
 __global__ __launch_bounds__(kBlock) void k_kinetic(RB_ARGS)
 {
     RB_SYS(blockIdx.x)
-    __shared__ double red[4];
     const int i = lb * blockDim.x + threadIdx.x;
     double ke = 0.0;
     if (i < s.n) {
         const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
         ke = 0.5 * s.spc->mass[s.type[i]] * (vx * vx + vy * vy + vz * vz);
     }
-    const double b = block_sum(ke, red);
-    if (threadIdx.x == 0) s.kin_part[lb] = b;
+    wave_partial(ke, i, s.n, s.kin_part, 1, 0);
 }
 
 // ---------------------------------------------------------------- integrator
@@ -1406,13 +1420,13 @@ void launch_ksample(const Plan& P, hipStream_t st)
     if (P.modes64.blocks > 0) k_ksample<<<P.modes64.blocks, 64, 0, st>>>(RB_MAP(modes64), P.kd);
 }
 
-void launch_pair(const Plan& P, const SogCoef& g, bool mixed, bool energy, hipStream_t st)
+template <int KU>
+void launch_pair_ku(const Plan& P, const SogCoef& g, const SogCoefF& gf, bool mixed, bool energy, hipStream_t st)
 {
-    const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * kBlock;
-    const SogCoefF gf = to_f32(g);
-    const int nb = P.atoms.blocks;
-    if (nb <= 0) return;
-#define RB_PAIR(M, E, J) k_pair<M, E, J><<<nb, kBlock, sm, st>>>(RB_MAP(atoms), g, gf)
+    const int bs = P.tune.pair_block;
+    const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * bs;
+    const int nb = P.pair_atoms.blocks;
+#define RB_PAIR(M, E, J) k_pair<M, E, J, KU><<<nb, bs, sm, st>>>(RB_MAP(pair_atoms), g, gf)
     if (mixed) {
         if (energy)
             RB_PAIR(true, true, 1);
@@ -1432,13 +1446,31 @@ void launch_pair(const Plan& P, const SogCoef& g, bool mixed, bool energy, hipSt
 #undef RB_PAIR
 }
 
+void launch_pair(const Plan& P, const SogCoef& g, bool mixed, bool energy, hipStream_t st)
+{
+    if (P.pair_atoms.blocks <= 0) return;
+    const SogCoefF gf = to_f32(g);
+    if (P.tune.pair_ku == 8)
+        launch_pair_ku<8>(P, g, gf, mixed, energy, st);
+    else
+        launch_pair_ku<4>(P, g, gf, mixed, energy, st);
+}
+
 void launch_rho(const Plan& P, bool mixed, hipStream_t st)
 {
     if (P.rho.blocks <= 0) return;
-    if (mixed)
-        k_rho<true><<<P.rho.blocks, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
-    else
-        k_rho<false><<<P.rho.blocks, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+    const int nb = P.rho.blocks;
+    if (P.tune.rho_mpl == 2) {
+        if (mixed)
+            k_rho<true, 2><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+        else
+            k_rho<false, 2><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+    } else {
+        if (mixed)
+            k_rho<true, 1><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+        else
+            k_rho<false, 1><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+    }
 }
 
 void launch_rho_finalize(const Plan& P, hipStream_t st)
@@ -1448,14 +1480,15 @@ void launch_rho_finalize(const Plan& P, hipStream_t st)
 
 void launch_finalize(const Plan& P, hipStream_t st)
 {
-    if (P.R > 0) k_finalize<<<P.R, kBlock, 0, st>>>(P.sys, P.kd);
+    if (P.R > 0) k_finalize<<<P.R, 1024, 0, st>>>(P.sys, P.kd);
 }
 
 void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st)
 {
-    const int nb = P.atoms.blocks;
+    const int nb = P.kf_atoms.blocks;
+    const int bs = P.tune.kf_block;
     if (nb <= 0) return;
-#define RB_KF(M, K, E) k_kforce<M, K, E><<<nb, kBlock, 0, st>>>(RB_MAP(atoms), P.kd)
+#define RB_KF(M, K, E) k_kforce<M, K, E><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd)
     if (mixed) {
         if (kick) {
             if (energy) RB_KF(true, true, true); else RB_KF(true, true, false);
@@ -1474,7 +1507,7 @@ void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_
 
 void launch_kinetic_finalize(const Plan& P, hipStream_t st)
 {
-    if (P.R > 0) k_kinetic_finalize<<<P.R, kBlock, 0, st>>>(P.sys);
+    if (P.R > 0) k_kinetic_finalize<<<P.R, 1024, 0, st>>>(P.sys);
 }
 
 void launch_kinetic(const Plan& P, hipStream_t st)

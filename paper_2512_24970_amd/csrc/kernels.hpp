@@ -65,8 +65,8 @@ struct DevSys {
     // pair coefficients [S*S]
     const PairCoef* pair;
     DeviceScalars* sc;
-    double* pair_part;     // [ceil(n/256)][kPairPart] block partials of the pair kernel
-    double* kin_part;      // [ceil(n/256)] kinetic-energy block partials
+    double* pair_part;     // [ceil(n/64)][kPairPart] wavefront partials of the pair kernel
+    double* kin_part;      // [ceil(n/64)] kinetic-energy wavefront partials
 };
 
 struct KDev {
@@ -90,7 +90,7 @@ struct KDev {
     double* rho;          // [n_modes][2]
 };
 
-// Block partial sums written by the pair kernel: F (3), u_core, u_shell.
+// Per-wavefront partial sums written by the pair kernel: F (3), u_core, u_shell.
 constexpr int kPairPart = 5;
 
 // The grid of one launch over a batch: block b works on local block map[b].y
@@ -100,6 +100,15 @@ struct Shape {
     int blocks = 0;
 };
 
+// Launch shapes chosen by the autotuner.  None of them changes a result bit:
+// partial sums are per wavefront and each mode's sum runs in the same order.
+struct Tuning {
+    int pair_block = 256;  // atoms per pair-kernel workgroup (64, 128, 256)
+    int pair_ku = 4;       // neighbours fetched ahead in the pair kernel (4, 8)
+    int rho_mpl = 1;       // modes per lane in the rho kernel (1, 2)
+    int kf_block = 256;    // atoms per k-space force workgroup (64, 128, 256)
+};
+
 // Launch plan of a batch (or of one system of it, see api.cpp).
 struct Plan {
     const DevSys* sys = nullptr;  // device array [R]
@@ -107,13 +116,16 @@ struct Plan {
     DeviceScalars* sc = nullptr;  // device array [R] (sys[r].sc == sc + r)
     int R = 0;
     Shape atoms;    // 256-atom blocks of every system
+    Shape pair_atoms;  // tune.pair_block-atom blocks (pair kernel)
+    Shape kf_atoms;    // tune.kf_block-atom blocks (k-space force kernel)
     Shape cells;    // one block per cell
     Shape atom1;    // one block per atom (per-atom list kernel)
     Shape modes64;  // 64-mode blocks of the systems that draw modes
-    Shape rho;      // rho blocks: local block = mode tile * n_chunks + chunk
+    Shape rho;      // rho blocks: local block = mode tile * n_chunks + chunk (tiles of 64 rho_mpl modes)
     Shape modes1;   // one block per mode
     int list_mode = 0;  // 0/1: per-cell list kernel with a 2048/4096-atom stencil, 2: per-atom kernel
     int cap_core = 0, cap_cand = 0;
+    Tuning tune;
 };
 
 void launch_set_eval(const Plan& P, uint64_t eval, hipStream_t st);

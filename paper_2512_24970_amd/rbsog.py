@@ -51,6 +51,13 @@ class Params(C.Structure):
     ]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("pair_block", C.c_int32), ("pair_ku", C.c_int32), ("rho_mpl", C.c_int32), ("kf_block", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Energy(C.Structure):
     _fields_ = [("u_core", C.c_double), ("u_shell", C.c_double), ("u_kspace", C.c_double),
                 ("u_self", C.c_double), ("u_total", C.c_double), ("kinetic", C.c_double),
@@ -73,6 +80,10 @@ ABI = {
                                   C.c_int]),
     "rbsog_n_systems": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "rbsog_select_system": (C.c_int, [C.c_void_p, C.c_int32]),
+    "rbsog_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "rbsog_set_tuning": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rbsog_get_tuning": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rbsog_use_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "rbsog_build_lists": (C.c_int, [C.c_void_p]),
     "rbsog_compute_forces": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(Energy)]),
     "rbsog_get_force_parts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -248,6 +259,33 @@ class Context:
         self._check(lib().rbsog_select_system(self._h, r), "rbsog_select_system")
         self.sel = r
 
+    def rbsog_autotune(self, reps: int = 3) -> dict:
+        t = Tuning()
+        self._check(lib().rbsog_autotune(self._h, reps, C.byref(t)), "rbsog_autotune")
+        return t.as_dict()
+
+    def rbsog_set_tuning(self, **kw):
+        t = Tuning()
+        self._check(lib().rbsog_get_tuning(self._h, C.byref(t)), "rbsog_get_tuning")
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        self._check(lib().rbsog_set_tuning(self._h, C.byref(t)), "rbsog_set_tuning")
+
+    def rbsog_get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib().rbsog_get_tuning(self._h, C.byref(t)), "rbsog_get_tuning")
+        return t.as_dict()
+
+    def rbsog_use_graphs(self, on: bool = True):
+        self._check(lib().rbsog_use_graphs(self._h, 1 if on else 0), "rbsog_use_graphs")
+
+    def _order_outputs(self):
+        """Device outputs are written on the context's stream: make torch's
+        current stream wait for them when the two differ."""
+        cur = self._torch.cuda.current_stream(self.torch_device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
+
     def _energies(self, e):
         out = [e[r].as_dict() for r in range(self.R)]
         return out[0] if self.R == 1 else out
@@ -262,6 +300,7 @@ class Context:
         e = (Energy * max(self.R, 1))()
         self._check(lib().rbsog_compute_forces(self._h, ev, C.c_void_p(f.data_ptr()),
                                                e if want_energy else None), "rbsog_compute_forces")
+        self._order_outputs()
         return f, (self._energies(e) if want_energy else None)
 
     def rbsog_get_force_parts(self):
@@ -270,6 +309,7 @@ class Context:
         fk = t.empty((self.n, 3), dtype=t.float64, device=self.torch_device)
         self._check(lib().rbsog_get_force_parts(self._h, C.c_void_p(fs.data_ptr()), C.c_void_p(fk.data_ptr())),
                     "rbsog_get_force_parts")
+        self._order_outputs()
         return fs, fk
 
     def rbsog_step(self, n_steps: int, want_energy: bool = True):
@@ -283,6 +323,7 @@ class Context:
         ev = C.c_uint64()
         self._check(lib().rbsog_get_state(self._h, *[C.c_void_p(o.data_ptr()) for o in out], C.byref(ev), 1),
                     "rbsog_get_state")
+        self._order_outputs()
         return out[0], out[1], out[2], int(ev.value)
 
     # -- kernel timing -----------------------------------------------------------

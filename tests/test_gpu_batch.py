@@ -187,3 +187,71 @@ def test_full_batch_of_64_replicas():
         err = rel_rms(fb[offs[r]:offs[r + 1]], fo)
         _say(f"  replica {r} (N={sizes[r]}): mixed force rel rms vs oracle {err:.2e}")
         assert err <= TOL32
+
+
+def _trajectory(ctx, chunks=(4, 4, 4)):
+    """Forces at step 0, then the state after each chunk of steps."""
+    f0, _ = ctx.rbsog_compute_forces(0, want_energy=False)
+    out = [f0.cpu().numpy()]
+    for k in chunks:
+        e = ctx.rbsog_step(k)
+        p, v, f, _ = ctx.rbsog_get_state()
+        out += [p.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy()]
+        out.append(np.array([x["u_total"] for x in (e if isinstance(e, list) else [e])]))
+    return out
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("precision", [R.FP64, R.MIXED])
+def test_tuning_changes_no_bit(precision):
+    """Every launch shape the tuner can pick gives bitwise the same forces and
+    12-step trajectory (with rebuilds) as the default shapes; so does the
+    autotuned one."""
+    _say(f"case: tuning shapes, batch of 5, precision {precision}")
+    cfgs = _small_batch(skin=0.3, rebuild_every=5)
+    ctx, _ = _gpu_batch(cfgs, precision)
+    ref = _trajectory(ctx)
+    shapes = [dict(pair_block=64, pair_ku=8, rho_mpl=2, kf_block=64),
+              dict(pair_block=128, pair_ku=4, rho_mpl=2, kf_block=128)]
+    for sh in shapes:
+        ctx, _ = _gpu_batch(cfgs, precision)
+        ctx.rbsog_set_tuning(**sh)
+        assert ctx.rbsog_get_tuning() == sh
+        assert _same(_trajectory(ctx), ref), sh
+    ctx, _ = _gpu_batch(cfgs, precision)
+    chosen = ctx.rbsog_autotune(2)
+    _say(f"  autotuned: {chosen}")
+    assert _same(_trajectory(ctx), ref)
+
+
+def test_step_graph_replays_match_eager():
+    """Steps replayed from captured HIP graphs (on a stream of the context's
+    own) equal kernel-by-kernel steps bitwise, at every checkpoint between
+    replays, including steps with scheduled and displacement rebuilds."""
+    import torch
+    _say("case: step graphs vs eager, batch of 5 fp64")
+    cfgs = _small_batch(skin=0.3, rebuild_every=5)
+    ctx, _ = _gpu_batch(cfgs, R.FP64)
+    ref = _trajectory(ctx)
+    stream = torch.cuda.Stream(device=0)
+    dev = torch.device("cuda", 0)
+    g = R.Context(0, stream=stream)
+    plist = [R.make_params(c["sys"], R.FP64, n_atoms=len(c["types"])) for c in cfgs]
+    g.rbsog_set_batch(plist, torch.as_tensor(np.concatenate([c["types"] for c in cfgs]), device=dev),
+                      torch.as_tensor(np.concatenate([c["pos"] for c in cfgs]), device=dev),
+                      torch.as_tensor(np.concatenate([c["vel"] for c in cfgs]), device=dev))
+    g.rbsog_use_graphs(True)
+    got = _trajectory(g)
+    stream.synchronize()
+    assert _same(got, ref)
+
+
+def test_invalid_tuning_rejected():
+    cfgs = _small_batch()
+    ctx, _ = _gpu_batch(cfgs[:1], R.FP64)
+    with pytest.raises(R.RbsogError) as e:
+        ctx.rbsog_set_tuning(pair_block=96)
+    assert e.value.code == -1
