@@ -54,7 +54,10 @@ def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(cfg, precision: str, steps: int, warmup: int):
+TUNING_KEYS = ("pair_block", "pair_ku", "rho_mpl", "kf_block")
+
+
+def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto"):
     import torch
     from paper_2512_24970_amd import rbsog as R
     dev = torch.device("cuda", 0)
@@ -66,7 +69,12 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int):
     p = R.make_params(sysp, prec, n_atoms=len(cfg["types"]))
     ctx.rbsog_set_system(p, torch.as_tensor(cfg["types"], device=dev), torch.as_tensor(cfg["pos"], device=dev),
                          torch.as_tensor(cfg["vel"], device=dev))
-    _log(f"[bench] {precision}: system set, warmup {warmup} steps")
+    if tuning == "auto":
+        tuning = ctx.rbsog_autotune(3)
+    else:
+        ctx.rbsog_set_tuning(**dict(zip(TUNING_KEYS, (int(v) for v in tuning.split(",")))))
+        tuning = ctx.rbsog_get_tuning()
+    _log(f"[bench] {precision}: system set, tuning {tuning}, warmup {warmup} steps")
     f0, _ = ctx.rbsog_compute_forces(0, want_energy=False)
     f0 = f0.cpu().numpy()
     e0 = ctx.rbsog_step(warmup) if warmup > 0 else None
@@ -85,7 +93,7 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int):
     ctx.close()
     T = 2 * e1["kinetic"] / ((3 * n - 3) * 8.617333262e-5)
     return {"seconds": dt, "value": n * steps / dt, "ms_per_step": 1e3 * dt / steps, "phases": prof,
-            "energy": e1, "energy_warm": e0, "T_end": T, "force0": f0}
+            "energy": e1, "energy_warm": e0, "T_end": T, "force0": f0, "tuning": tuning}
 
 
 def _batch_inputs(cfgs, dev):
@@ -214,6 +222,11 @@ def roofline(precision: str, res: dict, n: int, sysp: dict) -> dict:
     top = max(phases, key=lambda k: phases[k][0])
     out = dict(lines[top])
     out["traffic"] = traffic_from_profiles(out["kernel"] + ("<mixed>" if precision == "mixed" else "<fp64>"))
+    if out["traffic"]:
+        # the measured HBM bytes against the HBM peak, beside the VALU view
+        gbs = out["traffic"] / (out["avg_launch_ms"] * 1e-3) / 1e9
+        out["traffic_GBps"] = round(gbs, 1)
+        out["traffic_frac_of_hbm_peak"] = round(gbs / PEAK_HBM_GBS, 4)
     out["others"] = {lines[k]["kernel"]: {"achieved": lines[k]["achieved"], "frac": lines[k]["frac"],
                                          "avg_launch_ms": lines[k]["avg_launch_ms"]}
                      for k in lines if k != top}
@@ -269,9 +282,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="licl_nacl_1m")
     ap.add_argument("--forms", default="mixed,fp64", help="comma list of mixed,fp64; the first is reported")
-    ap.add_argument("--cpu-sample", type=int, default=2000, help="atoms in the CPU-baseline sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=20000, help="atoms in the CPU-baseline sample (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--batch", type=int, default=64, help="replicas in the batched-form leg (0: skip)")
+    ap.add_argument("--tuning", default="auto",
+                    help="launch shapes of the single-system runs: auto (autotuned) or "
+                         "pair_block,pair_ku,rho_mpl,kf_block")
     args = ap.parse_args()
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
@@ -291,7 +307,7 @@ def main() -> int:
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {}
     for f in forms:
-        results[f] = run_gpu(cfg, f, args.steps, args.warmup)
+        results[f] = run_gpu(cfg, f, args.steps, args.warmup, args.tuning)
     head = forms[0]
     r = results[head]
     p_f = int(cfg["sys"]["p_f"])
@@ -316,6 +332,7 @@ def main() -> int:
         },
         "roofline": roofline(head, r, n, cfg["sys"]),
         "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
+        "tuning": r["tuning"],
     }
     line["T_end_K"] = round(r["T_end"], 1)
     if "mixed" in results and "fp64" in results:
@@ -324,6 +341,7 @@ def main() -> int:
     for f in forms[1:]:
         rf = results[f]
         line[f] = {"value": rf["value"], "ms_per_step": rf["ms_per_step"], "T_end_K": round(rf["T_end"], 1),
+                   "tuning": rf["tuning"],
                    "roofline": roofline(f, rf, n, cfg["sys"]),
                    "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in rf["phases"].items()}}
     if args.batch > 0:
