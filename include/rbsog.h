@@ -234,8 +234,9 @@ rbsog_status rbsog_profile_read(rbsog_ctx* ctx, double* ms, int64_t* launches);
 rbsog_status rbsog_get_list_counts(rbsog_ctx* ctx, int32_t* n_core, int32_t* n_cand);
 /* Lists of atom i: core neighbour ids ascending; candidate ids in the
  * canonical order the shell ranks refer to: by cell (grid of
- * floor(L/(r_shell+skin)) cells per axis, one if below 3; cell index
- * floor(x n_c/L) with x fastest), then by id. */
+ * n_c = 2 floor(L/(r_shell+skin)) cells per axis, one where
+ * floor(L/(r_shell+skin)) is below 3; cell index floor(x n_c/L) with x
+ * fastest), then by id. */
 rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_t* cand);
 /* Shell batch ranks (indices into the ordered candidate list, ascending)
  * of every atom for evaluation `eval`: ranks[N][P_R]; unused slots are -1.

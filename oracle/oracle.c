@@ -510,17 +510,20 @@ orc_ctx* orc_create(const orc_params* p, int32_t n, const int32_t* type,
         if (vel) memcpy(c->vel, vel, sizeof(double) * 3 * n);
     }
     for (int i = 0; i < n; ++i) wrap(&c->p, c->pos + 3 * i);
-    /* cells of side >= r_shell + skin; fewer than 3 along an axis -> one */
+    /* ordering grid: twice floor(L / (r_shell + skin)) cells per axis, so
+       cells of side >= (r_shell + skin) / 2; one cell along an axis where
+       floor(L / (r_shell + skin)) is below 3 */
     for (int a = 0; a < 3; ++a) {
         int nc = (int)floor(c->p.box[a] / (c->p.r_shell + c->p.skin + 1e-9));
-        if (nc < 3) nc = 1;
+        nc = nc < 3 ? 1 : 2 * nc;
         c->nc[a] = nc;
         c->cscale[a] = (double)nc / c->p.box[a];
     }
     return c;
 }
 
-/* Cell of a wrapped position: floor(x n_c / L) per axis, x fastest. */
+/* Cell of a wrapped position on the ordering grid: floor(x n_c / L) per
+   axis, x fastest. */
 static int cell_of(const orc_ctx* c, const double* x)
 {
     int cc[3];

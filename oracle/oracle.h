@@ -106,8 +106,9 @@ orc_ctx* orc_create(const orc_params* p, int32_t n, const int32_t* type,
 void orc_destroy(orc_ctx* c);
 /* Brute-force core list (r < r_core + skin) and shell candidates
  * (r_core - skin <= r < r_shell + skin).  Candidates are ordered by (cell,
- * atom index) on a grid of n_c = floor(L / (r_shell + skin)) cells per axis
- * (one cell if that is below 3), cell = floor(x n_c / L) with x fastest. */
+ * atom index) on a grid of n_c = 2 floor(L / (r_shell + skin)) cells per
+ * axis (one cell where floor(L / (r_shell + skin)) is below 3), cell =
+ * floor(x n_c / L) with x fastest. */
 int orc_build_lists(orc_ctx* c);
 int orc_list_counts(const orc_ctx* c, int32_t* n_core, int32_t* n_cand);
 int orc_list_atom(const orc_ctx* c, int32_t i, int32_t* core, int32_t* cand);

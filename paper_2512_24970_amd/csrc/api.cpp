@@ -605,6 +605,9 @@ void init_devsys(const rbsog_params& p, int n, DevSys& s)
         if (nc < 3) nc = 1;
         s.nc[a] = nc;
         s.cell_scale[a] = (double)nc / p.box[a];
+        // candidates are ordered on a grid of half-size cells
+        s.nf[a] = nc >= 3 ? 2 * nc : 1;
+        s.fine_scale[a] = (double)s.nf[a] / p.box[a];
         s.two_pi_L[a] = 2.0 * kPi / p.box[a];
         s.ncell *= nc;
     }

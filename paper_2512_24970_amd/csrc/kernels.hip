@@ -131,6 +131,16 @@ __device__ inline int cell_coord(double v, double scale, int nc)
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
+// Cell of a wrapped position on the ordering grid (x fastest); candidates
+// are listed in ascending (this cell, index).
+__device__ inline int fine_cell(const DevSys& s, const double4& P)
+{
+    const int fx = cell_coord(P.x, s.fine_scale[0], s.nf[0]);
+    const int fy = cell_coord(P.y, s.fine_scale[1], s.nf[1]);
+    const int fz = cell_coord(P.z, s.fine_scale[2], s.nf[2]);
+    return (fz * s.nf[1] + fy) * s.nf[0] + fx;
+}
+
 // Workgroups are dealt to the 8 XCDs in turn (block b on XCD b mod 8), each
 // XCD with its own L2.  Renumbering so that XCD x gets a contiguous range of
 // logical blocks keeps spatially neighbouring atoms (cell order) on one L2.
@@ -334,21 +344,21 @@ __global__ void k_gather(RB_ARGS, int gate)
 // ---------------------------------------------------------------- lists
 // Fallback for stencils that do not fit in LDS.  One 64-thread block per
 // atom: the lanes sweep the neighbouring cells, compact core and candidate
-// entries with ballots, then sort the candidates into cell order (bitonic
-// network in LDS).
+// entries with ballots, then sort the candidates into the canonical order,
+// (cell of the ordering grid, index), with a bitonic network in LDS.
 __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
 {
     RB_SYS(blockIdx.x)
     RB_GATE
-    extern __shared__ int32_t lsm[];
+    extern __shared__ long long lsm64[];
     const int capP2 = [&] {
         int p = 1;
         while (p < s.cap_cand) p <<= 1;
         return p;
     }();
-    int32_t* ckey = lsm;
-    int32_t* cval = lsm + capP2;
-    int32_t* core = lsm + 2 * capP2;
+    long long* ckey = lsm64;
+    int32_t* cval = reinterpret_cast<int32_t*>(lsm64 + capP2);
+    int32_t* core = cval + capP2;
 
     const int i = lb;
     const int lane = threadIdx.x;
@@ -372,8 +382,10 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
                 for (int base = beg; base < end; base += 64) {
                     const int j = base + lane;
                     bool is_core = false, is_cand = false;
+                    long long order_key = 0;
                     if (j < end && j != i) {
                         const double4 Pj = s.p[j];
+                        order_key = ((long long)fine_cell(s, Pj) << 32) | j;
                         const double dx = min_image(xi - Pj.x, s.L[0], s.invL[0]);
                         const double dy = min_image(yi - Pj.y, s.L[1], s.invL[1]);
                         const double dz = min_image(zi - Pj.z, s.L[2], s.invL[2]);
@@ -390,7 +402,7 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
                     if (is_cand) {
                         const int slot = ncand + __popcll(mk & below);
                         if (slot < s.cap_cand) {
-                            ckey[slot] = j;  // cell order = canonical candidate order
+                            ckey[slot] = order_key;
                             cval[slot] = j;
                         }
                     }
@@ -414,7 +426,7 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
     int P = 1;
     while (P < nk) P <<= 1;
     for (int t = nk + lane; t < P; t += 64) {
-        ckey[t] = INT_MAX;
+        ckey[t] = LLONG_MAX;
         cval[t] = -1;
     }
     __syncthreads();
@@ -424,7 +436,7 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
                 const int u = t ^ j;
                 if (u > t) {
                     const bool up = (t & k) == 0;
-                    const int32_t a = ckey[t], b = ckey[u];
+                    const long long a = ckey[t], b = ckey[u];
                     if ((a > b) == up) {
                         ckey[t] = b;
                         ckey[u] = a;
@@ -443,12 +455,27 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
     for (int t = lane; t < nc; t += 64) ctile[(size_t)t * 64] = core[t];
 }
 
-// One 512-thread block per cell.  The atoms of the (up to) 27 neighbouring
-// cells are staged in LDS with the cells in ascending index; as atoms are
-// stored in (cell, id) order, the stencil is then in the canonical candidate
-// order and each atom of the cell, sweeping it with one wavefront and
-// ballot compaction, writes its candidates already ordered.
+// One 512-thread block per list cell (side >= r_shell + skin).  The atoms of
+// the (up to) 27 neighbouring list cells are staged in LDS and sorted there
+// by cell of the ordering grid (half the side, 6 x 6 x 6 of them around the
+// block's cell), stably, so the staged array is in canonical candidate order.
+// Each ordering cell of the block (2 x 2 x 2) then needs only the 5 x 5 x 5
+// ordering cells around it, which are a few dozen runs of the staged array;
+// a wavefront takes up to kListA atoms of one such cell and sweeps its runs,
+// one candidate per lane, testing every candidate against all its atoms and
+// compacting hits with ballots straight into the lists.
 constexpr int kListBlock = 512;
+constexpr int kRegion = 216;  // ordering cells staged per block, at most 6 x 6 x 6
+constexpr int kMaxRuns = 64;  // runs of window cells per ordering cell (<= 50)
+constexpr int kListA = 4;     // atoms per sweep
+
+__device__ inline int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Rank of this lane among the set lanes of m below it.
+__device__ inline int mbcnt64(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
 
 template <int CAP>
 __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
@@ -459,38 +486,45 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
     __shared__ double px[CAP];
     __shared__ double py[CAP];
     __shared__ double pz[CAP];
+    __shared__ uint8_t key[CAP];        // region cell of each staged atom, staging order
+    __shared__ int lcnt[kRegion];       // atoms per region cell
+    __shared__ int cstart[kRegion];     // first sorted position of each region cell
+    __shared__ int rcell[kRegion];      // region cell of each rank (ascending global index)
+    __shared__ int run_beg[8][kMaxRuns];
+    __shared__ int run_pre[8][kMaxRuns + 1];
+    __shared__ int n_runs[8];
     __shared__ int cq[27];
     __shared__ int cb[27];
     __shared__ int coff[28];
+    __shared__ int bad;
     const int c = lb;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int cx0 = c % s.nc[0];
     const int cy0 = (c / s.nc[0]) % s.nc[1];
     const int cz0 = c / (s.nc[0] * s.nc[1]);
-    // stencil: offsets -1..1 along axes with at least 3 cells, else 0
-    const int n0 = s.nc[0] >= 3 ? 3 : 1, n1 = s.nc[1] >= 3 ? 3 : 1, n2 = s.nc[2] >= 3 ? 3 : 1;
+    // stencil: offsets -1..1 along axes with at least 3 list cells, else 0
+    const bool sx = s.nc[0] >= 3, sy = s.nc[1] >= 3, sz = s.nc[2] >= 3;
+    const int n0 = sx ? 3 : 1, n1 = sy ? 3 : 1, n2 = sz ? 3 : 1;
     const int nst = n0 * n1 * n2;
     if (threadIdx.x < nst) {
         const int k = threadIdx.x;
-        const int ox = (n0 == 3) ? k % 3 - 1 : 0;
-        const int oy = (n1 == 3) ? (k / n0) % 3 - 1 : 0;
-        const int oz = (n2 == 3) ? k / (n0 * n1) - 1 : 0;
+        const int ox = sx ? k % 3 - 1 : 0;
+        const int oy = sy ? (k / n0) % 3 - 1 : 0;
+        const int oz = sz ? k / (n0 * n1) - 1 : 0;
         const int cx = (cx0 + ox + s.nc[0]) % s.nc[0];
         const int cy = (cy0 + oy + s.nc[1]) % s.nc[1];
         const int cz = (cz0 + oz + s.nc[2]) % s.nc[2];
         cq[k] = (cz * s.nc[1] + cy) * s.nc[0] + cx;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {  // ascending cell index
-        for (int a = 1; a < nst; ++a) {
-            const int v = cq[a];
-            int b = a - 1;
-            while (b >= 0 && cq[b] > v) {
-                cq[b + 1] = cq[b];
-                --b;
-            }
-            cq[b + 1] = v;
-        }
-    }
+    // region of ordering cells: 6 per split axis starting 2 below the block's
+    // first one, 1 otherwise
+    const int R0 = sx ? 6 : 1, R1 = sy ? 6 : 1, R2 = sz ? 6 : 1;
+    const int R = R0 * R1 * R2;
+    const int gx0 = sx ? 2 * cx0 - 2 : 0, gy0 = sy ? 2 * cy0 - 2 : 0, gz0 = sz ? 2 * cz0 - 2 : 0;
+    for (int q = threadIdx.x; q < R; q += blockDim.x) lcnt[q] = 0;
+    if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     if (threadIdx.x < nst) {
         const int q = cq[threadIdx.x];
@@ -510,88 +544,235 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
         if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 4);
         return;
     }
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        int k = 0;
-        while (coff[k + 1] <= t) ++k;
-        const int j = cb[k] + (t - coff[k]);
-        val[t] = j;
-        const double4 P = s.p[j];
-        px[t] = P.x;
-        py[t] = P.y;
-        pz[t] = P.z;
+    // stage: every thread keeps its atoms in registers until their sorted
+    // position is known
+    constexpr int kPer = CAP / kListBlock;
+    double rx[kPer], ry[kPer], rz[kPer];
+    int rj[kPer], rq[kPer], r0[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int t = threadIdx.x + u * kListBlock;
+        rq[u] = -1;
+        if (t < total) {
+            int k = 0;
+            while (coff[k + 1] <= t) ++k;
+            const int j = cb[k] + (t - coff[k]);
+            const double4 P = s.p[j];
+            rx[u] = P.x;
+            ry[u] = P.y;
+            rz[u] = P.z;
+            rj[u] = j;
+            r0[u] = coff[k];
+            const int lx = sx ? wrap_index(cell_coord(P.x, s.fine_scale[0], s.nf[0]) - gx0, s.nf[0]) : 0;
+            const int ly = sy ? wrap_index(cell_coord(P.y, s.fine_scale[1], s.nf[1]) - gy0, s.nf[1]) : 0;
+            const int lz = sz ? wrap_index(cell_coord(P.z, s.fine_scale[2], s.nf[2]) - gz0, s.nf[2]) : 0;
+            const int q = (lz * R1 + ly) * R0 + lx;
+            rq[u] = q;
+            key[t] = (uint8_t)q;
+            atomicAdd(&lcnt[q], 1);
+        }
     }
     __syncthreads();
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int beg0 = s.cell_start[c];
-    const int cnt0 = s.cell_start[c + 1] - beg0;
-    // With at least 5 cells along every axis and no stencil cell across the
-    // box edge, every |d| < 2 L/n_c <= 0.4 L, so rint(d/L) = 0 and the
+    // rank of each region cell in ascending global index: lexicographic in
+    // (z, y, x) of the wrapped global coordinates, so per-axis ranks combine
+    for (int q = threadIdx.x; q < R; q += blockDim.x) {
+        const int lx = q % R0, ly = (q / R0) % R1, lz = q / (R0 * R1);
+        auto axis_rank = [](int l, int g0, int n, int Ra) {
+            const int g = wrap_index(g0 + l, n);
+            int r = 0;
+            for (int m = 0; m < Ra; ++m) r += wrap_index(g0 + m, n) < g;
+            return r;
+        };
+        const int rank = (axis_rank(lz, gz0, s.nf[2], R2) * R1 + axis_rank(ly, gy0, s.nf[1], R1)) * R0 +
+                         axis_rank(lx, gx0, s.nf[0], R0);
+        rcell[rank] = q;
+    }
+    __syncthreads();
+    // first sorted position of each region cell: exclusive scan over ranks
+    if (wave == 0) {
+        int carry = 0;
+        for (int r0c = 0; r0c < R; r0c += 64) {
+            const int r = r0c + lane;
+            const int q = r < R ? rcell[r] : 0;
+            const int v = r < R ? lcnt[q] : 0;
+            int x = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (r < R) cstart[q] = carry + x - v;
+            carry += __shfl(x, 63, 64);
+        }
+    }
+    __syncthreads();
+    // stable scatter: within a region cell, staging order (= index order)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int t = threadIdx.x + u * kListBlock;
+        if (rq[u] >= 0) {
+            int r = 0;
+            for (int t2 = r0[u]; t2 < t; ++t2) r += key[t2] == rq[u];
+            const int d = cstart[rq[u]] + r;
+            px[d] = rx[u];
+            py[d] = ry[u];
+            pz[d] = rz[u];
+            val[d] = rj[u];
+        }
+    }
+    // ordering cells of the block: 2 per split axis
+    const int F0 = sx ? 2 : 1, F1 = sy ? 2 : 1, F2 = sz ? 2 : 1;
+    const int F = F0 * F1 * F2;
+    auto own_cell = [&](int f) {
+        const int fx = f % F0, fy = (f / F0) % F1, fz = f / (F0 * F1);
+        return ((sz ? 2 + fz : 0) * R1 + (sy ? 2 + fy : 0)) * R0 + (sx ? 2 + fx : 0);
+    };
+    // runs of the window (+-2 cells per split axis) of ordering cell `wave`,
+    // in rank order; consecutive ranks in the window form one run
+    if (wave < F) {
+        const int f = wave;
+        const int q0 = own_cell(f);
+        const int ox = q0 % R0, oy = (q0 / R0) % R1, oz = q0 / (R0 * R1);
+        uint64_t m[4];
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const int r = ch * 64 + lane;
+            bool sel = false;
+            if (r < R) {
+                const int q = rcell[r];
+                const int lx = q % R0, ly = (q / R0) % R1, lz = q / (R0 * R1);
+                sel = abs(lx - ox) <= 2 && abs(ly - oy) <= 2 && abs(lz - oz) <= 2;
+            }
+            m[ch] = __ballot(sel);
+        }
+        int nb = 0;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const uint64_t prev = (m[ch] << 1) | (ch > 0 ? (m[ch - 1] >> 63) : 0ull);
+            const uint64_t bm = m[ch] & ~prev;
+            const int r = ch * 64 + lane;
+            if ((bm >> lane) & 1ull) {
+                const int k = nb + __popcll(bm & below);
+                if (k < kMaxRuns) run_beg[f][k] = cstart[rcell[r]];
+            }
+            nb += __popcll(bm);
+        }
+        // run ends: the first sorted position after the last window rank of the run
+        int ne = 0;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const uint64_t next = (m[ch] >> 1) | (ch < 3 ? (m[ch + 1] << 63) : 0ull);
+            const uint64_t em = m[ch] & ~next;
+            const int r = ch * 64 + lane;
+            if ((em >> lane) & 1ull) {
+                const int k = ne + __popcll(em & below);
+                const int q = rcell[r];
+                if (k < kMaxRuns) run_pre[f][k + 1] = cstart[q] + lcnt[q];  // run end for now
+            }
+            ne += __popcll(em);
+        }
+        if (nb > kMaxRuns && lane == 0) bad = 1;
+        // lengths -> prefix (one chunk: nb <= 64)
+        const int k = lane;
+        const int len = k < min(nb, kMaxRuns) ? run_pre[f][k + 1] - run_beg[f][k] : 0;
+        int x = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (k < min(nb, kMaxRuns)) run_pre[f][k + 1] = x;
+        if (lane == 0) {
+            run_pre[f][0] = 0;
+            n_runs[f] = min(nb, kMaxRuns);
+        }
+    }
+    __syncthreads();
+    if (bad) {
+        if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 4);
+        return;
+    }
+    // With at least 5 list cells along every axis and no stencil cell across
+    // the box edge, every |d| < 2 L/n_c <= 0.4 L, so rint(d/L) = 0 and the
     // minimum image leaves d unchanged: skipping it gives the same bits.
     const bool interior = s.nc[0] >= 5 && s.nc[1] >= 5 && s.nc[2] >= 5 && cx0 > 0 && cx0 < s.nc[0] - 1 &&
                           cy0 > 0 && cy0 < s.nc[1] - 1 && cz0 > 0 && cz0 < s.nc[2] - 1;
-    // each wavefront sweeps the stencil for kA atoms at once: one LDS read
-    // serves kA independent distance tests
-    constexpr int kA = 4;
-    constexpr int kW = kListBlock / 64;
-    for (int a0 = wave; a0 < cnt0; a0 += kW * kA) {
-        int iu[kA], ncore[kA], ncand[kA];
-        double xu[kA], yu[kA], zu[kA];
-        int32_t* crow[kA];
-        int32_t* ctile[kA];
+    // work units: (ordering cell f, group of kListA of its atoms), dealt to
+    // the wavefronts in turn
+    int n_units = 0;
+    for (int f = 0; f < F; ++f) n_units += (lcnt[own_cell(f)] + kListA - 1) / kListA;
+    for (int unit = wave; unit < n_units; unit += kListBlock / 64) {
+        int f = 0, g = unit;
+        for (;; ++f) {
+            const int nu = (lcnt[own_cell(f)] + kListA - 1) / kListA;
+            if (g < nu) break;
+            g -= nu;
+        }
+        const int q0 = own_cell(f);
+        const int a0 = cstart[q0] + g * kListA;
+        const int na = min(kListA, cstart[q0] + lcnt[q0] - a0);
+        // atoms of the unit (indices and list rows in scalar registers); a
+        // missing one (index -1) takes part in the sweep but never matches
+        double xu[kListA], yu[kListA], zu[kListA];
+        int iu[kListA], ncore[kListA], ncand[kListA];
+        int32_t* crow[kListA];
+        int32_t* ccol[kListA];
 #pragma unroll
-        for (int u = 0; u < kA; ++u) {
-            const int a = a0 + u * kW;
-            iu[u] = a < cnt0 ? beg0 + a : -1;
-            const double4 Pi = s.p[a < cnt0 ? beg0 + a : beg0];
-            xu[u] = Pi.x;
-            yu[u] = Pi.y;
-            zu[u] = Pi.z;
-            const int ii = a < cnt0 ? beg0 + a : beg0;
+        for (int u = 0; u < kListA; ++u) {
+            const bool here = u < na;
+            const int a = here ? a0 + u : a0;
+            xu[u] = px[a];
+            yu[u] = py[a];
+            zu[u] = pz[a];
+            iu[u] = here ? __builtin_amdgcn_readfirstlane(val[a]) : -1;
+            const int ii = here ? iu[u] : 0;
             crow[u] = s.cand_idx + (size_t)ii * s.cap_cand;
-            ctile[u] = s.core_idx + (size_t)(ii >> 6) * s.cap_core * 64 + (ii & 63);
+            ccol[u] = s.core_idx + (size_t)(ii >> 6) * s.cap_core * 64 + (ii & 63);
             ncore[u] = 0;
             ncand[u] = 0;
         }
-        for (int base = 0; base < total; base += 64) {
-            const int t = base + lane;
-            const bool in = t < total;
-            const int j = in ? val[t] : -1;
-            const double pxj = in ? px[t] : 0.0, pyj = in ? py[t] : 0.0, pzj = in ? pz[t] : 0.0;
+        const int* rb = run_beg[f];
+        const int* rp = run_pre[f];
+        const int W = rp[n_runs[f]];  // window size
+        const int cmax = s.cap_core - 1, kmax = s.cap_cand - 1;
+        int k = 0;                    // run cursor of this lane
+        for (int t0 = 0; t0 < W; t0 += 64) {
+            const int t = t0 + lane;
+            const bool in = t < W;
+            int idx = 0;
+            if (in) {
+                while (rp[k + 1] <= t) ++k;
+                idx = rb[k] + (t - rp[k]);
+            }
+            const int j = in ? val[idx] : -1;
+            const double pxj = px[idx], pyj = py[idx], pzj = pz[idx];
 #pragma unroll
-            for (int u = 0; u < kA; ++u) {
-                bool is_core = false, is_cand = false;
-                if (in && iu[u] >= 0 && j != iu[u]) {
-                    double dx = xu[u] - pxj, dy = yu[u] - pyj, dz = zu[u] - pzj;
-                    if (!interior) {
-                        dx = min_image(dx, s.L[0], s.invL[0]);
-                        dy = min_image(dy, s.L[1], s.invL[1]);
-                        dz = min_image(dz, s.L[2], s.invL[2]);
-                    }
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    is_core = r2 < s.rc2_list;
-                    is_cand = r2 >= s.lo2_list && r2 < s.hi2_list;
+            for (int u = 0; u < kListA; ++u) {
+                double dx = xu[u] - pxj, dy = yu[u] - pyj, dz = zu[u] - pzj;
+                if (!interior) {
+                    dx = min_image(dx, s.L[0], s.invL[0]);
+                    dy = min_image(dy, s.L[1], s.invL[1]);
+                    dz = min_image(dz, s.L[2], s.invL[2]);
                 }
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                // j = -1 marks an empty lane; iu = -1 an empty atom
+                const bool ok = j >= 0 && iu[u] >= 0 && j != iu[u];
+                const bool is_core = ok && r2 < s.rc2_list;
+                const bool is_cand = ok && r2 >= s.lo2_list && r2 < s.hi2_list;
                 const uint64_t mc = __ballot(is_core);
                 const uint64_t mk = __ballot(is_cand);
-                if (is_core) {
-                    const int slot = ncore[u] + __popcll(mc & below);
-                    if (slot < s.cap_core) ctile[u][(size_t)slot * 64] = j;
-                }
-                if (is_cand) {
-                    const int slot = ncand[u] + __popcll(mk & below);
-                    if (slot < s.cap_cand) crow[u][slot] = j;
-                }
+                // slots past the capacity land on the last entry: the counts
+                // report the overflow and the host builds again
+                if (is_core) ccol[u][(size_t)min(ncore[u] + mbcnt64(mc), cmax) * 64] = j;
+                if (is_cand) crow[u][min(ncand[u] + mbcnt64(mk), kmax)] = j;
                 ncore[u] += __popcll(mc);
                 ncand[u] += __popcll(mk);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kA; ++u) {
+        for (int u = 0; u < kListA; ++u) {
             const int i = iu[u];
-            if (lane == 0 && i >= 0) {
+            if (lane == 0 && u < na) {
                 s.core_cnt[i] = ncore[u];
                 s.cand_cnt[i] = ncand[u];
                 // same-address atomics serialise: only overflowing atoms report
@@ -1409,7 +1590,7 @@ void launch_build(const Plan& P, bool gate, hipStream_t st)
     } else {
         int capP2 = 1;
         while (capP2 < P.cap_cand) capP2 <<= 1;
-        const size_t sm = sizeof(int32_t) * (2 * (size_t)capP2 + P.cap_core);
+        const size_t sm = sizeof(long long) * (size_t)capP2 + sizeof(int32_t) * ((size_t)capP2 + P.cap_core);
         k_lists<<<P.atom1.blocks, 64, sm, st>>>(RB_MAP(atom1), g);
     }
     k_build_done<<<1, 64, 0, st>>>(P.sys, P.R, g);

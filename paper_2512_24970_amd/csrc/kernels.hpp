@@ -31,6 +31,8 @@ struct DevSys {
     int user_off;          // first row of this system in the caller's [N][3] arrays
     double L[3], invL[3];
     double cell_scale[3];  // n_c / L
+    int nf[3];             // ordering grid: 2 n_c cells per axis (1 where n_c = 1)
+    double fine_scale[3];  // n_f / L
     int nc[3];
     int ncell;
     double two_pi_L[3];
