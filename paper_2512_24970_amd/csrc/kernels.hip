@@ -486,8 +486,8 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
     __shared__ double px[CAP];
     __shared__ double py[CAP];
     __shared__ double pz[CAP];
-    __shared__ uint8_t key[CAP];        // region cell of each staged atom, staging order
     __shared__ int lcnt[kRegion];       // atoms per region cell
+    __shared__ int lcur[kRegion];       // next free sorted position of each region cell
     __shared__ int cstart[kRegion];     // first sorted position of each region cell
     __shared__ int rcell[kRegion];      // region cell of each rank (ascending global index)
     __shared__ int run_beg[8][kMaxRuns];
@@ -544,34 +544,56 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
         if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 4);
         return;
     }
-    // stage: every thread keeps its atoms in registers until their sorted
-    // position is known
-    constexpr int kPer = CAP / kListBlock;
-    double rx[kPer], ry[kPer], rz[kPer];
-    int rj[kPer], rq[kPer], r0[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int t = threadIdx.x + u * kListBlock;
-        rq[u] = -1;
-        if (t < total) {
-            int k = 0;
-            while (coff[k + 1] <= t) ++k;
-            const int j = cb[k] + (t - coff[k]);
-            const double4 P = s.p[j];
-            rx[u] = P.x;
-            ry[u] = P.y;
-            rz[u] = P.z;
-            rj[u] = j;
-            r0[u] = coff[k];
-            const int lx = sx ? wrap_index(cell_coord(P.x, s.fine_scale[0], s.nf[0]) - gx0, s.nf[0]) : 0;
-            const int ly = sy ? wrap_index(cell_coord(P.y, s.fine_scale[1], s.nf[1]) - gy0, s.nf[1]) : 0;
-            const int lz = sz ? wrap_index(cell_coord(P.z, s.fine_scale[2], s.nf[2]) - gz0, s.nf[2]) : 0;
-            const int q = (lz * R1 + ly) * R0 + lx;
-            rq[u] = q;
-            key[t] = (uint8_t)q;
-            atomicAdd(&lcnt[q], 1);
+    // stage, sorted by region cell and stably (index order) within one:
+    // every region cell lies in one stencil cell, so each wavefront takes
+    // whole stencil cells and ranks their atoms with ballots, first to count
+    // (pass 0), then, once the cells' first positions are known, to place
+    // (pass 1; the positions are read again)
+    auto region_cell = [&](const double4& P) {
+        const int lx = sx ? wrap_index(cell_coord(P.x, s.fine_scale[0], s.nf[0]) - gx0, s.nf[0]) : 0;
+        const int ly = sy ? wrap_index(cell_coord(P.y, s.fine_scale[1], s.nf[1]) - gy0, s.nf[1]) : 0;
+        const int lz = sz ? wrap_index(cell_coord(P.z, s.fine_scale[2], s.nf[2]) - gz0, s.nf[2]) : 0;
+        return (lz * R1 + ly) * R0 + lx;
+    };
+    auto stage_pass = [&](bool place) {
+        for (int k = wave; k < nst; k += kListBlock / 64) {
+            const int b = cb[k], n = coff[k + 1] - coff[k];
+            for (int base = 0; base < n; base += 64) {
+                const bool live = base + lane < n;
+                const int j = b + base + lane;
+                double4 P = make_double4(0.0, 0.0, 0.0, 0.0);
+                int q = -1;
+                if (live) {
+                    P = s.p[j];
+                    q = region_cell(P);
+                }
+                bool pending = live;
+                uint64_t pm = __ballot(pending);
+                while (pm) {
+                    const int leader = __builtin_ctzll(pm);
+                    const int ql = __shfl(q, leader, 64);
+                    const bool mine = pending && q == ql;
+                    const uint64_t m = __ballot(mine);
+                    if (place) {
+                        const int first = lcur[ql];
+                        if (mine) {
+                            const int d = first + mbcnt64(m);
+                            px[d] = P.x;
+                            py[d] = P.y;
+                            pz[d] = P.z;
+                            val[d] = j;
+                        }
+                        if (lane == leader) lcur[ql] = first + __popcll(m);
+                    } else if (lane == leader) {
+                        lcnt[ql] += __popcll(m);
+                    }
+                    if (mine) pending = false;
+                    pm = __ballot(pending);
+                }
+            }
         }
-    }
+    };
+    stage_pass(false);
     __syncthreads();
     // rank of each region cell in ascending global index: lexicographic in
     // (z, y, x) of the wrapped global coordinates, so per-axis ranks combine
@@ -601,25 +623,15 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
                 const int y = __shfl_up(x, o, 64);
                 if (lane >= o) x += y;
             }
-            if (r < R) cstart[q] = carry + x - v;
+            if (r < R) {
+                cstart[q] = carry + x - v;
+                lcur[q] = carry + x - v;
+            }
             carry += __shfl(x, 63, 64);
         }
     }
     __syncthreads();
-    // stable scatter: within a region cell, staging order (= index order)
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int t = threadIdx.x + u * kListBlock;
-        if (rq[u] >= 0) {
-            int r = 0;
-            for (int t2 = r0[u]; t2 < t; ++t2) r += key[t2] == rq[u];
-            const int d = cstart[rq[u]] + r;
-            px[d] = rx[u];
-            py[d] = ry[u];
-            pz[d] = rz[u];
-            val[d] = rj[u];
-        }
-    }
+    stage_pass(true);
     // ordering cells of the block: 2 per split axis
     const int F0 = sx ? 2 : 1, F1 = sy ? 2 : 1, F2 = sz ? 2 : 1;
     const int F = F0 * F1 * F2;
@@ -755,16 +767,22 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
                     dz = min_image(dz, s.L[2], s.invL[2]);
                 }
                 const double r2 = (dx * dx + dy * dy) + dz * dz;
-                // j = -1 marks an empty lane; iu = -1 an empty atom
-                const bool ok = j >= 0 && iu[u] >= 0 && j != iu[u];
-                const bool is_core = ok && r2 < s.rc2_list;
-                const bool is_cand = ok && r2 >= s.lo2_list && r2 < s.hi2_list;
+                // j = -1 marks an empty lane; iu = -1 an empty atom (bitwise
+                // operators: no short-circuit branches)
+                const bool ok = (j >= 0) & (iu[u] >= 0) & (j != iu[u]);
+                const bool is_core = ok & (r2 < s.rc2_list);
+                const bool is_cand = ok & (r2 >= s.lo2_list) & (r2 < s.hi2_list);
                 const uint64_t mc = __ballot(is_core);
                 const uint64_t mk = __ballot(is_cand);
-                // slots past the capacity land on the last entry: the counts
-                // report the overflow and the host builds again
-                if (is_core) ccol[u][(size_t)min(ncore[u] + mbcnt64(mc), cmax) * 64] = j;
-                if (is_cand) crow[u][min(ncand[u] + mbcnt64(mk), kmax)] = j;
+                // Every lane stores (no exec-mask branches): a miss goes to the
+                // last entry of the atom's row, which is never read (a count
+                // that reaches it is an overflow), and so do hits past the
+                // capacity; the counts report the overflow and the host
+                // builds again with longer rows.
+                const uint32_t sc_ = (uint32_t)(is_core ? min(ncore[u] + mbcnt64(mc), cmax - 1) : cmax);
+                const uint32_t sk_ = (uint32_t)(is_cand ? min(ncand[u] + mbcnt64(mk), kmax - 1) : kmax);
+                *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ccol[u]) + sc_ * 256u) = j;
+                *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(crow[u]) + sk_ * 4u) = j;
                 ncore[u] += __popcll(mc);
                 ncand[u] += __popcll(mk);
             }
@@ -775,11 +793,12 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
             if (lane == 0 && u < na) {
                 s.core_cnt[i] = ncore[u];
                 s.cand_cnt[i] = ncand[u];
-                // same-address atomics serialise: only overflowing atoms report
-                if (ncore[u] > s.cap_core || ncand[u] > s.cap_cand) {
+                // same-address atomics serialise: only overflowing atoms
+                // report; the last entry of a row is not usable here
+                if (ncore[u] >= s.cap_core || ncand[u] >= s.cap_cand) {
                     atomicOr(&s.sc->overflow, 1);
-                    atomicMax(&s.sc->max_core, ncore[u]);
-                    atomicMax(&s.sc->max_cand, ncand[u]);
+                    atomicMax(&s.sc->max_core, ncore[u] + 1);
+                    atomicMax(&s.sc->max_cand, ncand[u] + 1);
                 }
             }
         }
