@@ -922,13 +922,20 @@ struct FloydMask {
     }
 };
 
+// Pair forces of A atoms per workgroup (A = blockDim.x / 2): the first A
+// threads (whole wavefronts) take the core lists, the other A the shell
+// batches of the same atoms, so twice as many independent gather chains are
+// in flight and no wavefront diverges between the two loops.  The shell
+// thread adds its reweighted sum to the core sum passed through LDS, in the
+// same order as one thread doing both.
 template <bool MIXED, bool ENERGY, int J, int KU>
-__global__ __launch_bounds__(kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf)
+__global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf)
 {
     RB_SYS(xcd_block(blockIdx.x, gridDim.x))
     extern __shared__ uint32_t mask_sm[];
     __shared__ PairCoef pc[kMaxSpecies * kMaxSpecies];
     __shared__ PairCoefF pcf[kMaxSpecies * kMaxSpecies];
+    __shared__ double xch[4][kBlock];  // core F (3) and energy, per atom of the block
     const int S = s.n_species;
     for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
         const PairCoef c = s.pair[t];
@@ -937,8 +944,12 @@ __global__ __launch_bounds__(kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf
     }
     __syncthreads();
 
-    const int i = lb * blockDim.x + threadIdx.x;
+    const int A = blockDim.x >> 1;
+    const bool shell = threadIdx.x >= A;  // uniform per wavefront (A is a multiple of 64)
+    const int ta = shell ? threadIdx.x - A : threadIdx.x;
+    const int i = lb * A + ta;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, Uc = 0.0, Us = 0.0;
+    double Sx = 0.0, Sy = 0.0, Sz = 0.0, Su = 0.0, wgt = 1.0;
     if (i < s.n) {
         const double4 Pi = s.p[i];
         const double xi = Pi.x, yi = Pi.y, zi = Pi.z;
@@ -960,114 +971,128 @@ __global__ __launch_bounds__(kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf
         // loads keep them from evicting the positions that neighbours re-read
         // (a candidate row is re-read by its own lane, so it stays cached).
         constexpr int kU = KU;
-        // core sum, eq. (24)
-        const int nc = min(s.core_cnt[i], s.cap_core);
-        const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
-        for (int k0 = 0; k0 < nc; k0 += kU) {
-            int jj[kU];
-            double X[kU], Y[kU], Z[kU];
-            int T[kU];
+        if (!shell) {
+            // core sum, eq. (24)
+            const int nc = min(s.core_cnt[i], s.cap_core);
+            const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
+            for (int k0 = 0; k0 < nc; k0 += kU) {
+                int jj[kU];
+                double X[kU], Y[kU], Z[kU];
+                int T[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
-                jj[u] = (k0 + u < nc) ? __builtin_nontemporal_load(ctile + (size_t)(k0 + u) * 64) : i;
+                for (int u = 0; u < kU; ++u)
+                    jj[u] = (k0 + u < nc) ? __builtin_nontemporal_load(ctile + (size_t)(k0 + u) * 64) : i;
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const double4 Q = s.p[jj[u]];
-                X[u] = Q.x;
-                Y[u] = Q.y;
-                Z[u] = Q.z;
-                T[u] = (int)Q.w;
-            }
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                if (k0 + u >= nc) break;
-                const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
-                const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
-                const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                if (r2 < s.rc2) {
-                    double uu = 0.0;
-                    const double f = pair_f(T[u], r2, uu);
-                    Fx = fma(f, dx, Fx);
-                    Fy = fma(f, dy, Fy);
-                    Fz = fma(f, dz, Fz);
-                    if (ENERGY) Uc += 0.5 * uu;
+                for (int u = 0; u < kU; ++u) {
+                    const double4 Q = s.p[jj[u]];
+                    X[u] = Q.x;
+                    Y[u] = Q.y;
+                    Z[u] = Q.z;
+                    T[u] = (int)Q.w;
                 }
-            }
-        }
-        // shell batch, eq. (25)
-        const int n = min(s.cand_cnt[i], s.cap_cand);
-        const int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
-        const bool take_all = s.p_r <= 0 || n <= s.p_r;
-        const int cnt = take_all ? n : s.p_r;
-        const double wgt = take_all ? 1.0 : (double)n / (double)s.p_r;
-        FloydMask fm{mask_sm + threadIdx.x, (int)blockDim.x};
-        PhiloxStream st(s.seed, (uint32_t)s.id[i], (uint32_t)s.sc->eval, kTagShell, s.replica);
-        if (!take_all) {
-            // draw the whole batch first, then visit the ranks in ascending
-            // order: the candidate row is swept once, line by line
-            fm.clear(n);
-            for (int k = 0; k < cnt; ++k) fm.step(st, n - s.p_r + k);
-        }
-        int w_cur = 0;  // ascending walk over the set bits of the mask
-        uint32_t m_cur = take_all ? 0u : fm.m[0];
-        double Sx = 0.0, Sy = 0.0, Sz = 0.0, Su = 0.0;
-        for (int k0 = 0; k0 < cnt; k0 += kU) {
-            int jj[kU];
-            double X[kU], Y[kU], Z[kU];
-            int T[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                int e = 0;
-                if (k0 + u < cnt) {
-                    if (take_all) {
-                        e = k0 + u;
-                    } else {
-                        while (m_cur == 0u) m_cur = fm.m[(++w_cur) * fm.stride];
-                        e = w_cur * 32 + __builtin_ctz(m_cur);
-                        m_cur &= m_cur - 1u;
+                for (int u = 0; u < kU; ++u) {
+                    if (k0 + u >= nc) break;
+                    const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
+                    const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
+                    const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 < s.rc2) {
+                        double uu = 0.0;
+                        const double f = pair_f(T[u], r2, uu);
+                        Fx = fma(f, dx, Fx);
+                        Fy = fma(f, dy, Fy);
+                        Fz = fma(f, dz, Fz);
+                        if (ENERGY) Uc += 0.5 * uu;
                     }
                 }
-                jj[u] = (k0 + u < cnt) ? crow[e] : i;
             }
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const double4 Q = s.p[jj[u]];
-                X[u] = Q.x;
-                Y[u] = Q.y;
-                Z[u] = Q.z;
-                T[u] = (int)Q.w;
+        } else {
+            // shell batch, eq. (25)
+            const int n = min(s.cand_cnt[i], s.cap_cand);
+            const int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
+            const bool take_all = s.p_r <= 0 || n <= s.p_r;
+            const int cnt = take_all ? n : s.p_r;
+            wgt = take_all ? 1.0 : (double)n / (double)s.p_r;
+            FloydMask fm{mask_sm + ta, A};
+            PhiloxStream st(s.seed, (uint32_t)s.id[i], (uint32_t)s.sc->eval, kTagShell, s.replica);
+            if (!take_all) {
+                // draw the whole batch first, then visit the ranks in ascending
+                // order: the candidate row is swept once, line by line
+                fm.clear(n);
+                for (int k = 0; k < cnt; ++k) fm.step(st, n - s.p_r + k);
             }
+            int w_cur = 0;  // ascending walk over the set bits of the mask
+            uint32_t m_cur = take_all ? 0u : fm.m[0];
+            for (int k0 = 0; k0 < cnt; k0 += kU) {
+                int jj[kU];
+                double X[kU], Y[kU], Z[kU];
+                int T[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                if (k0 + u >= cnt) break;
-                const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
-                const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
-                const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                if (r2 >= s.rc2 && r2 < s.rs2) {
-                    double uu = 0.0;
-                    const double f = pair_f(T[u], r2, uu);
-                    Sx = fma(f, dx, Sx);
-                    Sy = fma(f, dy, Sy);
-                    Sz = fma(f, dz, Sz);
-                    if (ENERGY) Su += 0.5 * uu;
+                for (int u = 0; u < kU; ++u) {
+                    int e = 0;
+                    if (k0 + u < cnt) {
+                        if (take_all) {
+                            e = k0 + u;
+                        } else {
+                            while (m_cur == 0u) m_cur = fm.m[(++w_cur) * fm.stride];
+                            e = w_cur * 32 + __builtin_ctz(m_cur);
+                            m_cur &= m_cur - 1u;
+                        }
+                    }
+                    jj[u] = (k0 + u < cnt) ? crow[e] : i;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const double4 Q = s.p[jj[u]];
+                    X[u] = Q.x;
+                    Y[u] = Q.y;
+                    Z[u] = Q.z;
+                    T[u] = (int)Q.w;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (k0 + u >= cnt) break;
+                    const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
+                    const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
+                    const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 >= s.rc2 && r2 < s.rs2) {
+                        double uu = 0.0;
+                        const double f = pair_f(T[u], r2, uu);
+                        Sx = fma(f, dx, Sx);
+                        Sy = fma(f, dy, Sy);
+                        Sz = fma(f, dz, Sz);
+                        if (ENERGY) Su += 0.5 * uu;
+                    }
                 }
             }
         }
-        Fx = fma(wgt, Sx, Fx);
-        Fy = fma(wgt, Sy, Fy);
-        Fz = fma(wgt, Sz, Fz);
-        if (ENERGY) Us = wgt * Su;
-        __builtin_nontemporal_store(Fx, s.fsx + i);
-        __builtin_nontemporal_store(Fy, s.fsy + i);
-        __builtin_nontemporal_store(Fz, s.fsz + i);
     }
-    wave_partial(Fx, i, s.n, s.pair_part, kPairPart, 0);
-    wave_partial(Fy, i, s.n, s.pair_part, kPairPart, 1);
-    wave_partial(Fz, i, s.n, s.pair_part, kPairPart, 2);
-    wave_partial(Uc, i, s.n, s.pair_part, kPairPart, 3);
-    wave_partial(Us, i, s.n, s.pair_part, kPairPart, 4);
+    if (!shell) {
+        xch[0][ta] = Fx;
+        xch[1][ta] = Fy;
+        xch[2][ta] = Fz;
+        xch[3][ta] = Uc;
+    }
+    __syncthreads();
+    if (shell) {
+        if (i < s.n) {
+            Fx = fma(wgt, Sx, xch[0][ta]);
+            Fy = fma(wgt, Sy, xch[1][ta]);
+            Fz = fma(wgt, Sz, xch[2][ta]);
+            Uc = xch[3][ta];
+            if (ENERGY) Us = wgt * Su;
+            __builtin_nontemporal_store(Fx, s.fsx + i);
+            __builtin_nontemporal_store(Fy, s.fsy + i);
+            __builtin_nontemporal_store(Fz, s.fsz + i);
+        }
+        wave_partial(Fx, i, s.n, s.pair_part, kPairPart, 0);
+        wave_partial(Fy, i, s.n, s.pair_part, kPairPart, 1);
+        wave_partial(Fz, i, s.n, s.pair_part, kPairPart, 2);
+        wave_partial(Uc, i, s.n, s.pair_part, kPairPart, 3);
+        wave_partial(Us, i, s.n, s.pair_part, kPairPart, 4);
+    }
 }
 
 // Export of the shell ranks drawn by the pair kernel (same selection code).
@@ -1623,10 +1648,10 @@ void launch_ksample(const Plan& P, hipStream_t st)
 template <int KU>
 void launch_pair_ku(const Plan& P, const SogCoef& g, const SogCoefF& gf, bool mixed, bool energy, hipStream_t st)
 {
-    const int bs = P.tune.pair_block;
+    const int bs = P.tune.pair_block;  // atoms per workgroup; twice as many threads
     const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * bs;
     const int nb = P.pair_atoms.blocks;
-#define RB_PAIR(M, E, J) k_pair<M, E, J, KU><<<nb, bs, sm, st>>>(RB_MAP(pair_atoms), g, gf)
+#define RB_PAIR(M, E, J) k_pair<M, E, J, KU><<<nb, 2 * bs, sm, st>>>(RB_MAP(pair_atoms), g, gf)
     if (mixed) {
         if (energy)
             RB_PAIR(true, true, 1);

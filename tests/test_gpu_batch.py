@@ -255,3 +255,74 @@ def test_invalid_tuning_rejected():
     with pytest.raises(R.RbsogError) as e:
         ctx.rbsog_set_tuning(pair_block=96)
     assert e.value.code == -1
+
+
+def _two_ions(base):
+    return dict(name="two_ions", sys=dict(base["sys"]), types=np.array([0, 1], np.int32),
+                pos=np.array([[3.0, 4.0, 5.0], [10.0, 4.5, 5.2]]), vel=np.array([[0.5, 0.0, 0.0], [-0.5, 0.1, 0.0]]),
+                T=0.0)
+
+
+def _empty(base):
+    return dict(name="empty", sys=dict(base["sys"]), types=np.zeros(0, np.int32), pos=np.zeros((0, 3)),
+                vel=np.zeros((0, 3)), T=0.0)
+
+
+def test_batch_with_degenerate_systems():
+    """Degenerate members of a batch, FP64: an empty system, a two-ion system
+    (candidate lists of zero or one entry, structure factors of two charges)
+    and the 512-ion melt; forces and energies at one evaluation and the
+    state after 6 steps with scheduled rebuilds every 3 steps match the
+    oracle of each system."""
+    _say("case: batch of empty + two ions + 512 ions, fp64")
+    base = W.config("nacl_512")
+    cfgs = [_empty(base), _two_ions(base), base, _empty(base)]
+    for c in cfgs:
+        c["sys"] = dict(c["sys"], rebuild_every=3)
+    ctx, offs = _gpu_batch(cfgs, R.FP64)
+    fb, eb = ctx.rbsog_compute_forces(5)
+    fb = fb.cpu().numpy()
+    assert fb.shape == (514, 3)
+    for r, c in enumerate(cfgs):
+        osys = O.System(c["sys"], c["types"], c["pos"], c["vel"])
+        fo, eo = osys.forces(5)
+        sl = slice(offs[r], offs[r + 1])
+        if len(c["types"]) == 0:
+            assert eb[r]["u_total"] == 0.0 and eb[r]["u_kspace"] == 0.0
+            continue
+        assert rel_rms(fb[sl], fo) <= TOL64, r
+        for key in ("u_core", "u_shell", "u_kspace", "u_self"):
+            assert eb[r][key] == pytest.approx(eo[key], rel=1e-11, abs=1e-12), (r, key)
+    ctx.rbsog_compute_forces(0, want_energy=False)
+    eg = ctx.rbsog_step(6)
+    pg, vg, fg, _ = ctx.rbsog_get_state()
+    pg, vg = pg.cpu().numpy(), vg.cpu().numpy()
+    for r, c in enumerate(cfgs):
+        if len(c["types"]) == 0:
+            continue
+        osys = O.System(c["sys"], c["types"], c["pos"], c["vel"])
+        osys.forces(0)
+        eo = osys.vv_steps(6)
+        po, vo, _, _ = osys.state()
+        sl = slice(offs[r], offs[r + 1])
+        L = np.array(c["sys"]["box"])
+        d = pg[sl] - po
+        d -= L * np.rint(d / L)
+        assert np.abs(d).max() < 1e-9, r
+        assert rel_rms(vg[sl], vo) < 1e-9, r
+        assert eg[r]["n_builds"] >= 2
+
+
+def test_empty_single_system():
+    import torch
+    _say("case: empty single system")
+    base = W.config("nacl_512")
+    ctx = R.Context(0)
+    p = R.make_params(base["sys"], R.FP64, n_atoms=0)
+    dev = torch.device("cuda", 0)
+    ctx.rbsog_set_system(p, torch.zeros(0, dtype=torch.int32, device=dev),
+                         torch.zeros((0, 3), dtype=torch.float64, device=dev))
+    f, e = ctx.rbsog_compute_forces(1)
+    assert f.shape == (0, 3) and e["u_total"] == 0.0
+    e = ctx.rbsog_step(3)
+    assert e["kinetic"] == 0.0
