@@ -7,7 +7,8 @@ r_core 5.5 A, r_shell 11 A, skin 1 A, P_R = 30, P_F = 500, lists rebuilt every
 with jitter, Berendsen thermostat at 1150 K with tau = dt.  Both precision forms run:
 FP32-mixed (the reported value) and plain FP64 (reported beside it).
 
-The batched form runs beside it: 64 molten-NaCl replicas of 566..32742 ions
+A 5e6-ion NaCl melt (P_R 20, P_F 1000, mixed) runs after it, with the device
+memory the library holds.  The batched form runs beside it: 64 molten-NaCl replicas of 566..32742 ions
 (600664 in all) in one context, FP32-mixed, launch shapes autotuned, each step
 replayed from a captured HIP graph; its aggregate atom-steps/s is reported
 against the same replicas stepped one after another, each in its own context
@@ -61,6 +62,9 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto"):
     import torch
     from paper_2512_24970_amd import rbsog as R
     dev = torch.device("cuda", 0)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info(dev)[0]
     ctx = R.Context(0)
     prec = R.MIXED if precision == "mixed" else R.FP64
     # the estimator's noise heats an NVE run at this size by several per cent
@@ -87,13 +91,19 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto"):
     t1 = time.perf_counter()
     prof = ctx.rbsog_profile_read()
     ctx.rbsog_profile_enable(False)
+    # device memory held for the system: everything the library allocated
+    # (torch's own cache emptied first)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 1e9
     n = len(cfg["types"])
     dt = t1 - t0
     _log(f"[bench] {precision}: {steps} steps in {dt:.3f} s -> {n * steps / dt:.4g} atom-steps/s")
     ctx.close()
     T = 2 * e1["kinetic"] / ((3 * n - 3) * 8.617333262e-5)
     return {"seconds": dt, "value": n * steps / dt, "ms_per_step": 1e3 * dt / steps, "phases": prof,
-            "energy": e1, "energy_warm": e0, "T_end": T, "force0": f0, "tuning": tuning}
+            "energy": e1, "energy_warm": e0, "T_end": T, "force0": f0, "tuning": tuning,
+            "device_mem_GB": round(mem_gb, 3)}
 
 
 def _batch_inputs(cfgs, dev):
@@ -198,11 +208,11 @@ def kernel_roofline(precision: str, phase: str, ms: float, launches: int, n: int
             "avg_launch_ms": round(ms / launches, 4), "launches": launches, "flops_per_launch": flops}
 
 
-def traffic_from_profiles(kernel: str):
+def traffic_from_profiles(kernel: str, workload: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source (else None)."""
     import hashlib
-    path = os.path.join(HERE, "profiles", "licl_nacl_1m_traffic.md")
+    path = os.path.join(HERE, "profiles", f"{workload}_traffic.md")
     src = os.path.join(HERE, "paper_2512_24970_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
@@ -215,13 +225,14 @@ def traffic_from_profiles(kernel: str):
     return None
 
 
-def roofline(precision: str, res: dict, n: int, sysp: dict) -> dict:
+def roofline(precision: str, res: dict, n: int, sysp: dict, workload: str) -> dict:
     """The dominant kernel (largest time in the timed steps) and the others."""
     phases = {k: v for k, v in res["phases"].items() if k in KERNEL_OF_PHASE and v[1] > 0}
     lines = {k: kernel_roofline(precision, k, v[0], v[1], n, sysp) for k, v in phases.items()}
     top = max(phases, key=lambda k: phases[k][0])
     out = dict(lines[top])
-    out["traffic"] = traffic_from_profiles(out["kernel"] + ("<mixed>" if precision == "mixed" else "<fp64>"))
+    out["traffic"] = traffic_from_profiles(out["kernel"] + ("<mixed>" if precision == "mixed" else "<fp64>"),
+                                           workload)
     if out["traffic"]:
         # the measured HBM bytes against the HBM peak, beside the VALU view
         gbs = out["traffic"] / (out["avg_launch_ms"] * 1e-3) / 1e9
@@ -230,6 +241,9 @@ def roofline(precision: str, res: dict, n: int, sysp: dict) -> dict:
     out["others"] = {lines[k]["kernel"]: {"achieved": lines[k]["achieved"], "frac": lines[k]["frac"],
                                          "avg_launch_ms": lines[k]["avg_launch_ms"]}
                      for k in lines if k != top}
+    # the k-space chain runs on a second stream beside the pair kernel, so
+    # their launch durations overlap and each includes the other's share
+    out["concurrent"] = "k_pair runs beside k_ksample + k_rho (second stream); durations overlap"
     return out
 
 
@@ -285,6 +299,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=20000, help="atoms in the CPU-baseline sample (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--batch", type=int, default=64, help="replicas in the batched-form leg (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=50,
+                    help="timed steps of the 5e6-ion leg (0: skip)")
     ap.add_argument("--tuning", default="auto",
                     help="launch shapes of the single-system runs: auto (autotuned) or "
                          "pair_block,pair_ku,rho_mpl,kf_block")
@@ -330,9 +346,10 @@ def main() -> int:
             "r_shell": cfg["sys"]["r_shell"], "skin": cfg["sys"]["skin"], "p_r": cfg["sys"]["p_r"], "p_f": p_f,
             "rebuild_every": cfg["sys"]["rebuild_every"], "dt_ps": cfg["sys"]["dt"], "form": head,
         },
-        "roofline": roofline(head, r, n, cfg["sys"]),
+        "roofline": roofline(head, r, n, cfg["sys"], args.workload),
         "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
         "tuning": r["tuning"],
+        "device_mem_GB": r["device_mem_GB"],
     }
     line["T_end_K"] = round(r["T_end"], 1)
     if "mixed" in results and "fp64" in results:
@@ -342,10 +359,25 @@ def main() -> int:
         rf = results[f]
         line[f] = {"value": rf["value"], "ms_per_step": rf["ms_per_step"], "T_end_K": round(rf["T_end"], 1),
                    "tuning": rf["tuning"],
-                   "roofline": roofline(f, rf, n, cfg["sys"]),
+                   "roofline": roofline(f, rf, n, cfg["sys"], args.workload),
                    "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in rf["phases"].items()}}
     if args.batch > 0:
         line["batch"] = run_batch(args.batch, args.steps, args.warmup)
+    if args.large_steps > 0:
+        # the 5e6-ion NaCl melt (P_F = 1000), mixed form
+        t = time.perf_counter()
+        big = W.config("nacl_5m")
+        _log(f"[bench] large: N={len(big['types'])} inputs in {time.perf_counter() - t:.1f} s")
+        rl = run_gpu(big, "mixed", args.large_steps, args.warmup, "auto")
+        nb = len(big["types"])
+        line["large"] = {"workload": "nacl_5m", "n_atoms": nb, "p_f": int(big["sys"]["p_f"]),
+                         "p_r": int(big["sys"]["p_r"]), "form": "mixed", "value": rl["value"],
+                         "unit": "atom-steps/s", "steps": args.large_steps, "ms_per_step": rl["ms_per_step"],
+                         "T_end_K": round(rl["T_end"], 1), "tuning": rl["tuning"],
+                         "device_mem_GB": rl["device_mem_GB"],
+                         "roofline": roofline("mixed", rl, nb, big["sys"], "nacl_5m"),
+                         "phases_ms_per_step": {k: round(v[0] / args.large_steps, 4)
+                                                for k, v in rl["phases"].items()}}
     if args.cpu_sample > 0:
         _log(f"[bench] cpu baseline: oracle on {args.cpu_sample} atoms")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)

@@ -115,7 +115,9 @@ rbsog_status rbsog_sog_params(double eps, double r_shell, double* b, double* s, 
                               int32_t* M, double* w, int32_t w_cap);
 
 /* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`
- * (a hipStream_t; NULL = the default stream). */
+ * (a hipStream_t; NULL = the default stream).  Every call's device work is
+ * ordered on that stream: work the library puts on its own second stream is
+ * forked from and joined back to it with events. */
 rbsog_status rbsog_create(rbsog_ctx** out, int hip_device, void* hip_stream);
 rbsog_status rbsog_destroy(rbsog_ctx* ctx);
 const char* rbsog_last_error(const rbsog_ctx* ctx);
@@ -207,13 +209,16 @@ rbsog_status rbsog_use_graphs(rbsog_ctx* ctx, int enable);
 
 /* ---- kernel timing ------------------------------------------------------ */
 
-/* Kernel phases timed with HIP events on the context's stream. */
+/* Kernel phases timed with HIP events on the stream their kernels run on:
+ * the context's stream, or for KSAMPLE and RHO a second stream of the
+ * context on which the k-space chain runs beside the pair kernel (so phase
+ * times can add up to more than the step). */
 typedef enum {
     RBSOG_PHASE_BUILD = 0,     /* cell sort + list build */
     RBSOG_PHASE_KSAMPLE = 1,   /* mode draws of eq. (28) */
     RBSOG_PHASE_PAIR = 2,      /* shell batch + pair forces, eqs. (15), (24)-(25) */
-    RBSOG_PHASE_RHO = 3,       /* structure factors, eq. (22) */
-    RBSOG_PHASE_REDUCE = 4,    /* fixed-order reductions: rho, momentum correction, energies */
+    RBSOG_PHASE_RHO = 3,       /* structure factors, eq. (22), and their fixed-order reduction */
+    RBSOG_PHASE_REDUCE = 4,    /* fixed-order reductions: momentum correction, energies */
     RBSOG_PHASE_KFORCE = 5,    /* k-space force, eq. (29), + closing half kick */
     RBSOG_PHASE_INTEGRATE = 6, /* opening half kick + drift */
     RBSOG_N_PHASES = 7

@@ -118,22 +118,30 @@ struct rbsog_ctx {
         if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
         return e;
     }
-    void begin(int phase)
+    // phases are timed on the stream their kernels run on
+    bool open_aux = false;
+    void begin(int phase, bool on_aux = false)
     {
         if (!profiling) return;
         open_phase = phase;
+        open_aux = on_aux;
         open_a = take_event();
-        (void)hipEventRecord(open_a, stream);
+        (void)hipEventRecord(open_a, on_aux ? aux : stream);
     }
     void end()
     {
         if (!profiling || open_phase < 0) return;
         hipEvent_t b = take_event();
-        (void)hipEventRecord(b, stream);
+        (void)hipEventRecord(b, open_aux ? aux : stream);
         recs.push_back(Rec{open_phase, open_a, b});
         open_phase = -1;
         open_a = nullptr;
     }
+
+    // second stream (default priority) for the k-space chain, which runs
+    // beside the pair kernel; forked from and joined to `stream` by events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     // step graphs, [scheduled rebuild][energies], captured on first use
     bool use_graph = false;
@@ -149,6 +157,12 @@ struct rbsog_ctx {
     ~rbsog_ctx()
     {
         drop_graphs();
+        if (aux) {
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamDestroy(aux);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         for (auto& r : recs) {
             (void)hipEventDestroy(r.a);
             (void)hipEventDestroy(r.b);
@@ -428,25 +442,35 @@ bool any_thermostat(const rbsog_ctx* c)
     return false;
 }
 
+// The k-space chain (mode draws, structure factors and their reduction)
+// reads positions and writes only mode data, the pair kernel reads positions
+// and writes only short-range forces and its partials: the chain runs on the
+// second stream beside the pair kernel, and the first stream waits for it
+// before the sums that need both.
 void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
 {
     const bool ke = energy || (kick && any_thermostat(c));
     const Plan& P = c->plan;
     hipStream_t st = c->stream;
+    hipStream_t ax = c->aux;
     if (P.atoms.blocks <= 0) return;
+    HIP_OK(hipEventRecord(c->ev_fork, st));
+    HIP_OK(hipStreamWaitEvent(ax, c->ev_fork, 0));
     if (P.modes64.blocks > 0) {
-        c->begin(RBSOG_PHASE_KSAMPLE);
-        launch_ksample(P, st);
+        c->begin(RBSOG_PHASE_KSAMPLE, true);
+        launch_ksample(P, ax);
         c->end();
     }
+    c->begin(RBSOG_PHASE_RHO, true);
+    launch_rho(P, c->mixed, ax);
+    launch_rho_finalize(P, ax);
+    c->end();
+    HIP_OK(hipEventRecord(c->ev_join, ax));
     c->begin(RBSOG_PHASE_PAIR);
     launch_pair(P, c->coef, c->mixed, energy, st);
     c->end();
-    c->begin(RBSOG_PHASE_RHO);
-    launch_rho(P, c->mixed, st);
-    c->end();
+    HIP_OK(hipStreamWaitEvent(st, c->ev_join, 0));
     c->begin(RBSOG_PHASE_REDUCE);
-    launch_rho_finalize(P, st);
     launch_finalize(P, st);
     c->end();
     c->begin(RBSOG_PHASE_KFORCE);
@@ -706,6 +730,9 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     for (double w : c->sog.w) wsum += w;
 
     c->drop_graphs();
+    if (!c->aux) HIP_OK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    if (!c->ev_fork) HIP_OK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    if (!c->ev_join) HIP_OK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     c->R = R;
     c->prm = prm;
     c->sel = 0;
