@@ -468,6 +468,7 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     HIP_OK(hipEventRecord(c->ev_join, ax));
     c->begin(RBSOG_PHASE_PAIR);
     launch_pair(P, c->coef, c->mixed, energy, st);
+    HIP_OK(hipGetLastError());  // a launch the device refuses (e.g. LDS size) must not pass silently
     c->end();
     HIP_OK(hipStreamWaitEvent(st, c->ev_join, 0));
     c->begin(RBSOG_PHASE_REDUCE);
@@ -536,12 +537,15 @@ void launch_step(rbsog_ctx* c, bool scheduled, bool energy)
     HIP_OK(hipGraphLaunch(g, c->stream));
 }
 
+// Event time of `reps` runs of f, or infinity if the launch is refused.
 double time_ms(rbsog_ctx* c, int reps, const std::function<void()>& f)
 {
+    (void)hipGetLastError();
+    f();  // warm
+    if (hipGetLastError() != hipSuccess) return 1e300;
     hipEvent_t a = nullptr, b = nullptr;
     HIP_OK(hipEventCreate(&a));
     HIP_OK(hipEventCreate(&b));
-    f();  // warm
     HIP_OK(hipEventRecord(a, c->stream));
     for (int r = 0; r < reps; ++r) f();
     HIP_OK(hipEventRecord(b, c->stream));
