@@ -22,6 +22,7 @@ MAXS = 8
 MAXM = 511
 TAG_SHELL = 2
 TAG_KMODE = 3
+TAG_SHELL_BUILD = 5
 
 
 def build(force: bool = True) -> str:
@@ -46,6 +47,7 @@ class Params(C.Structure):
         ("rho", C.c_double * (MAXS * MAXS)), ("C", C.c_double * (MAXS * MAXS)),
         ("D", C.c_double * (MAXS * MAXS)),
         ("t_target", C.c_double), ("tau_t", C.c_double),
+        ("shell_stored", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -100,6 +102,7 @@ def lib():
             "orc_kforce_atoms": (None, [C.c_void_p, C.c_int32, i32p, dp, C.c_double, C.c_int32, i32p, dp]),
             "orc_set_threads": (None, [C.c_int]),
             "orc_get_threads": (C.c_int, []),
+            "orc_n_builds": (C.c_int64, [C.c_void_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -164,6 +167,7 @@ def make_params(sysp: dict) -> Params:
     p.sog_eps = float(sysp.get("sog_eps", 1e-5))
     p.t_target = float(sysp.get("t_target", 0.0))
     p.tau_t = float(sysp.get("tau_t", 0.0))
+    p.shell_stored = 1 if sysp.get("shell_stored", False) else 0
     for i in range(S):
         p.q[i] = float(sp["q"][i])
         p.mass[i] = float(sp["mass"][i])
@@ -247,6 +251,9 @@ class System:
     def _ensure_lists(self):
         if not self._lists:
             self.build_lists()
+
+    def n_builds(self) -> int:
+        return int(lib().orc_n_builds(self._h))
 
     def list_counts(self):
         self._ensure_lists()

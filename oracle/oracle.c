@@ -449,6 +449,7 @@ struct orc_ctx {
     double* vel;  /* [n][3] */
     double* frc;  /* [n][3] last force */
     uint64_t eval;
+    uint64_t n_builds; /* list builds so far */
     /* lists */
     int32_t* core_off;
     int32_t* core;
@@ -637,8 +638,11 @@ int orc_build_lists(orc_ctx* c)
     free(c->ref);
     c->ref = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
     if (n > 0) memcpy(c->ref, c->pos, sizeof(double) * 3 * n);
+    c->n_builds += 1;
     return 0;
 }
+
+int64_t orc_n_builds(const orc_ctx* c) { return (int64_t)c->n_builds; }
 
 int orc_list_counts(const orc_ctx* c, int32_t* n_core, int32_t* n_cand)
 {
@@ -661,8 +665,12 @@ int orc_list_atom(const orc_ctx* c, int32_t i, int32_t* core, int32_t* cand)
 /* Shell batch (eq. 25): P_R distinct ranks out of n candidates by Floyd's
  * algorithm (Bentley & Floyd, CACM 30(9), 1987): for j = n-P_R .. n-1 draw
  * t uniform in [0, j]; take t unless already taken, else take j.  Ranks are
- * returned ascending.  n <= P_R (or P_R <= 0) takes every rank. */
-static int shell_ranks(const orc_params* p, uint32_t atom_index, int n, uint64_t eval, int32_t* ranks)
+ * returned ascending.  n <= P_R (or P_R <= 0) takes every rank.  The stream
+ * is (atom, ctr1, tag): ctr1 = eval with TAG_SHELL for a fresh batch per
+ * evaluation, ctr1 = build number with TAG_SHELL_BUILD for a batch kept
+ * from one list build to the next. */
+static int shell_ranks(const orc_params* p, uint32_t atom_index, int n, uint32_t ctr1, uint32_t tag,
+                       int32_t* ranks)
 {
     if (p->p_r <= 0 || n <= p->p_r) {
         for (int t = 0; t < n; ++t) ranks[t] = t;
@@ -670,7 +678,7 @@ static int shell_ranks(const orc_params* p, uint32_t atom_index, int n, uint64_t
     }
     unsigned char* taken = (unsigned char*)calloc(n, 1);
     orc_stream s;
-    stream_init(&s, p->seed, atom_index, (uint32_t)eval, ORC_TAG_SHELL, p->replica);
+    stream_init(&s, p->seed, atom_index, ctr1, tag, p->replica);
     for (int j = n - p->p_r; j < n; ++j) {
         uint32_t t = stream_bounded(&s, (uint32_t)(j + 1));
         if (taken[t])
@@ -685,11 +693,27 @@ static int shell_ranks(const orc_params* p, uint32_t atom_index, int n, uint64_t
     return k;
 }
 
+/* Stream of the shell batch used at evaluation `eval`: per evaluation, or,
+ * with shell_stored, the one of the last list build (number n_builds - 1; 0
+ * before any build, the number the first build will take). */
+static void shell_stream(const orc_ctx* c, uint64_t eval, uint32_t* ctr1, uint32_t* tag)
+{
+    if (c->p.shell_stored) {
+        *ctr1 = (uint32_t)(c->n_builds > 0 ? c->n_builds - 1 : 0);
+        *tag = ORC_TAG_SHELL_BUILD;
+    } else {
+        *ctr1 = (uint32_t)eval;
+        *tag = ORC_TAG_SHELL;
+    }
+}
+
 int orc_shell_ranks(const orc_ctx* c, int32_t i, uint64_t eval, int32_t* ranks)
 {
     if (!c->cand_off || i < 0 || i >= c->n) return -1;
     int n = c->cand_off[i + 1] - c->cand_off[i];
-    return shell_ranks(&c->p, (uint32_t)i, n, eval, ranks);
+    uint32_t ctr1, tag;
+    shell_stream(c, eval, &ctr1, &tag);
+    return shell_ranks(&c->p, (uint32_t)i, n, ctr1, tag, ranks);
 }
 
 /* Pair force scalar f (F_i += f * r_ij) of eq. (15) with k_e on the Coulomb
@@ -746,7 +770,9 @@ static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32
         Uc += 0.5 * u;
     }
     int32_t* ranks = (int32_t*)malloc(sizeof(int32_t) * (nk > 0 ? nk : 1));
-    int nr = shell_ranks(p, (uint32_t)i, nk, eval, ranks);
+    uint32_t ctr1, tag;
+    shell_stream(c, eval, &ctr1, &tag);
+    int nr = shell_ranks(p, (uint32_t)i, nk, ctr1, tag, ranks);
     double wgt = (p->p_r <= 0 || nk <= p->p_r) ? 1.0 : (double)nk / (double)p->p_r;
     double Fs[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < nr; ++a) {

@@ -31,6 +31,7 @@ extern "C" {
 /* Philox stream tags (third counter word, low byte). */
 #define ORC_TAG_SHELL 2u
 #define ORC_TAG_KMODE 3u
+#define ORC_TAG_SHELL_BUILD 5u  /* shell batch drawn once per list build */
 
 typedef struct {
     int32_t n_species;
@@ -57,6 +58,13 @@ typedef struct {
     double D[ORC_MAXS * ORC_MAXS];
     double t_target;        /* K; Berendsen thermostat when t_target > 0 and tau_t > 0 */
     double tau_t;           /* ps */
+    int32_t shell_stored;   /* 0: fresh shell batch every force evaluation,
+                               stream (atom, eval, TAG_SHELL); 1: one batch per
+                               list build, kept until the next build, stream
+                               (atom, build number, TAG_SHELL_BUILD) with builds
+                               counted from 0 (Section 2.4: O(core + P_R) list
+                               entries per atom).  Needs p_r > 0. */
+    int32_t pad_;
 } orc_params;
 
 typedef struct {
@@ -113,8 +121,12 @@ int orc_build_lists(orc_ctx* c);
 int orc_list_counts(const orc_ctx* c, int32_t* n_core, int32_t* n_cand);
 int orc_list_atom(const orc_ctx* c, int32_t i, int32_t* core, int32_t* cand);
 /* Shell batch of atom i for evaluation `eval`: ranks into the candidate list,
- * ascending.  Returns the number of ranks (min(P_R, n_i), or n_i if P_R <= 0). */
+ * ascending.  Returns the number of ranks (min(P_R, n_i), or n_i if P_R <= 0).
+ * With shell_stored the batch is the one drawn for the last list build and
+ * `eval` is not used. */
 int orc_shell_ranks(const orc_ctx* c, int32_t i, uint64_t eval, int32_t* ranks);
+/* List builds since the system was created (the first build is number 0). */
+int64_t orc_n_builds(const orc_ctx* c);
 /* Force on i from j (d = r_i - r_j, minimum image) of eq. (15) with k_e;
  * returns the pair energy q_i q_j k_e N(r) + B_BMH(r). */
 double orc_pair_force(const orc_params* p, int32_t ti, int32_t tj, const double d[3], double f[3]);

@@ -80,14 +80,12 @@ def test_lemire_rejects_exactly_the_biased_words():
     assert abs(rej / len(words) - thr / 2**32) < 0.01
 
 
-def _floyd_subsets(n, k, trials):
-    """Shell ranks drawn by the oracle for a synthetic atom with n candidates."""
+def _floyd_subsets(n, k, trials, stored=False):
+    """Shell ranks drawn by the oracle for a synthetic atom with n candidates:
+    one draw per evaluation index, or (stored) one per list build."""
     sysp = W.config("nacl_small")["sys"]
-    sysp = dict(sysp, p_r=k)
-    p = O.make_params(sysp)
-    # a system whose atom 0 has exactly n shell candidates is awkward to make;
-    # drive the sampler through a 2-atom context instead: reuse shell ranks of
-    # atom 0 by building an explicit geometry.
+    sysp = dict(sysp, p_r=k, shell_stored=stored)
+    # atom 0 at the centre, n atoms on a ring of radius 7 inside its shell
     box = sysp["box"][0]
     pos = [[box / 2, box / 2, box / 2]]
     for t in range(n):
@@ -98,18 +96,20 @@ def _floyd_subsets(n, k, trials):
     s = O.System(sysp, types, pos)
     counts = {}
     for ev in range(trials):
-        r = tuple(int(x) for x in s.shell_ranks(0, ev))
+        if stored:
+            s.build_lists()
+        r = tuple(int(x) for x in s.shell_ranks(0, 0 if stored else ev))
         counts[r] = counts.get(r, 0) + 1
     s.close()
-    del p
     return counts
 
 
-def test_floyd_subsets_uniform():
+@pytest.mark.parametrize("stored", [False, True])
+def test_floyd_subsets_uniform(stored):
     """Floyd's algorithm gives every k-subset of the n ranks equal probability
-    (chi-square over all C(n, k) subsets)."""
+    (chi-square over all C(n, k) subsets), per evaluation or per list build."""
     n, k, trials = 7, 3, 14000
-    counts = _floyd_subsets(n, k, trials)
+    counts = _floyd_subsets(n, k, trials, stored)
     assert all(len(s) == k and len(set(s)) == k for s in counts)
     nsub = math.comb(n, k)
     assert len(counts) == nsub
@@ -414,6 +414,57 @@ def test_rbl_shell_force_in_oracle_uses_the_batch():
     want = fcore + len(cand) / p.p_r * fpop[r].sum(0)
     f, _, _ = s.forces_short(ev)
     assert np.allclose(f[i], want, rtol=1e-12, atol=1e-13)
+
+
+def test_stored_batch_fixed_between_builds():
+    """Memory form of the list (Section 2.4: O(core + P_R) entries per atom):
+    the shell batch is drawn at the list build and kept, so the evaluation
+    index does not change it and the short-range force at fixed positions is
+    the same for every evaluation until the next build, which draws anew."""
+    cfg = W.config("nacl_512")
+    s = O.System(dict(cfg["sys"], shell_stored=True), cfg["types"], cfg["pos"])
+    s.build_lists()
+    assert s.n_builds() == 1
+    r = [s.shell_ranks(i, 3) for i in range(0, 512, 37)]
+    assert all(np.array_equal(a, s.shell_ranks(i, 1234)) for a, i in zip(r, range(0, 512, 37)))
+    f1, uc1, us1 = s.forces_short(3)
+    f2, uc2, us2 = s.forces_short(77)
+    assert np.array_equal(f1, f2) and us1 == us2 and uc1 == uc2
+    s.build_lists()
+    r2 = [s.shell_ranks(i, 3) for i in range(0, 512, 37)]
+    assert sum(not np.array_equal(a, b) for a, b in zip(r, r2)) >= len(r) - 1
+    f3, _, us3 = s.forces_short(3)
+    assert not np.array_equal(f1, f3) and us3 != us1
+    # the per-evaluation form draws a new batch at every evaluation
+    e = O.System(cfg["sys"], cfg["types"], cfg["pos"])
+    g1, _, _ = e.forces_short(3)
+    g2, _, _ = e.forces_short(77)
+    assert not np.array_equal(g1, g2)
+
+
+def test_stored_shell_estimator_unbiased_with_exact_variance():
+    """Over list builds at fixed positions the stored batch is a fresh uniform
+    P_R-subset each time: the estimator of eq. (25) averages to the full shell
+    sum with the finite-population variance, as the per-evaluation form."""
+    cfg = W.config("nacl_512")
+    s = O.System(dict(cfg["sys"], shell_stored=True), cfg["types"], cfg["pos"])
+    p = s.params
+    i = 11
+    core, cand = s.lists_of(i)
+    fpop = _shell_population(s, p, i, cand)
+    n, P = len(cand), p.p_r
+    exact = fpop.sum(0)
+    var_exact = (n / P) ** 2 * P * (n - P) / (n - 1) * fpop.var(0)
+    K = 3000
+    est = np.zeros((K, 3))
+    for b in range(K):
+        s.build_lists()
+        r = s.shell_ranks(i, 0)
+        est[b] = n / P * fpop[r].sum(0)
+    mean = est.mean(0)
+    se = np.sqrt(var_exact / K)
+    assert np.all(np.abs(mean - exact) < 5 * se)
+    assert np.allclose(est.var(0), var_exact, rtol=0.15)
 
 
 def test_rbsog_estimator_unbiased():
