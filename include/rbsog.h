@@ -54,6 +54,21 @@ typedef enum {
 
 typedef enum { RBSOG_FP64 = 0, RBSOG_MIXED = 1 } rbsog_precision;
 
+/* rbsog_params.flags bits.
+ * RBSOG_FLAG_SHELL_STORED: the memory form of the random batch list
+ *   (Section 2.4 bounds the per-atom list at O(core + P_R) entries).  The
+ *   shell batch of each atom (eq. 25) is drawn when the lists are built and
+ *   kept until the next build, instead of being drawn afresh at every force
+ *   evaluation: Floyd's selection on the Philox stream (atom id, build
+ *   number, tag 5, replica), builds numbered from 0 since the system was set
+ *   (a build that overflowed and is redone keeps its number).  The library
+ *   then keeps per atom the core list and P_R batch entries; candidate rows
+ *   exist only during the build, one chunk of cells at a time (see
+ *   rbsog_set_list_chunks).  Each evaluation still masks the batch to
+ *   r_core <= r < r_shell at the current positions and weights it by
+ *   N_shell/P_R (N_shell = candidate count at the build).  Needs p_r >= 1. */
+#define RBSOG_FLAG_SHELL_STORED 1u
+
 typedef struct {
     double q;    /* charge, e */
     double mass; /* amu */
@@ -83,7 +98,7 @@ typedef struct {
     int32_t precision;     /* rbsog_precision */
     uint64_t seed;         /* Philox key */
     uint32_t replica;      /* Philox stream id of this system */
-    uint32_t flags;        /* reserved, 0 */
+    uint32_t flags;        /* RBSOG_FLAG_* bits (others must be 0); equal across a batch */
     double coulomb_k;      /* e^2/(4 pi eps0) in eV*Angstrom; <= 0 means 14.399645478 */
     double t_target;       /* K; with tau_t > 0 a Berendsen thermostat rescales v at the start of
                               each step by sqrt(1 + dt/tau_t (t_target/T - 1)), T from 3N-3
@@ -182,6 +197,14 @@ rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* f
 
 /* ---- launch shapes and step graphs -------------------------------------- */
 
+/* Memory form (RBSOG_FLAG_SHELL_STORED): build the lists in `chunks`
+ * launches over consecutive ranges of cells (1..64, default 8; a system
+ * with fewer cells uses one chunk per cell), so the candidate rows exist for
+ * about 1/chunks of the atoms at a time.  No choice changes a result bit.
+ * Applies to the systems set by later rbsog_set_system / rbsog_set_batch
+ * calls.  Needs no GPU work. */
+rbsog_status rbsog_set_list_chunks(rbsog_ctx* ctx, int32_t chunks);
+
 /* Launch shapes of the hot kernels.  No choice changes a result bit: partial
  * sums are taken per 64-atom wavefront and every structure factor is summed
  * over the atoms in the same order whatever the shape. */
@@ -241,12 +264,19 @@ rbsog_status rbsog_get_list_counts(rbsog_ctx* ctx, int32_t* n_core, int32_t* n_c
  * canonical order the shell ranks refer to: by cell (grid of
  * n_c = 2 floor(L/(r_shell+skin)) cells per axis, one where
  * floor(L/(r_shell+skin)) is below 3; cell index floor(x n_c/L) with x
- * fastest), then by id. */
+ * fastest), then by id.  With RBSOG_FLAG_SHELL_STORED the candidate lists
+ * are not kept: cand must be NULL (else RBSOG_E_STATE). */
 rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_t* cand);
 /* Shell batch ranks (indices into the ordered candidate list, ascending)
  * of every atom for evaluation `eval`: ranks[N][P_R]; unused slots are -1.
- * n_ranks[N] gets min(P_R, n_cand). */
+ * n_ranks[N] gets min(P_R, n_cand).  Not available with
+ * RBSOG_FLAG_SHELL_STORED (RBSOG_E_STATE). */
 rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ranks, int32_t* ranks);
+/* With RBSOG_FLAG_SHELL_STORED (else RBSOG_E_STATE): the batch drawn at the
+ * last list build as atom ids in ascending rank order, ids[N][P_R] (-1 past
+ * min(P_R, n_cand)), and the candidate count N_shell of each atom at that
+ * build, n_cand[N].  Either may be NULL. */
+rbsog_status rbsog_get_shell_batch(rbsog_ctx* ctx, int32_t* n_cand, int32_t* ids);
 /* The P_F modes m[P_F][3] drawn for evaluation `eval` and S of eq. (28). */
 rbsog_status rbsog_get_kmodes(rbsog_ctx* ctx, uint64_t eval, int32_t* m, double* S);
 /* Structure factors rho[P_F][2] (eq. 22) of the last force evaluation. */

@@ -93,7 +93,11 @@ struct rbsog_ctx {
 
     // device memory
     DBuf d_sys, d_kd, d_maps;
-    DBuf atoms, sortbuf, cells, lists_core, lists_cand, counts, pair_tab, scalars;
+    DBuf atoms, sortbuf, cells, lists_core, lists_cand, lists_bat, counts, pair_tab, scalars;
+    // memory form of the list: build chunks asked for, and the headroom of the
+    // candidate scratch over a chunk's expected atom count
+    int list_chunks = 8;
+    double row_slack = 1.25;
     DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, kin_part, export_tmp, snap;
 
     // phase timing
@@ -223,6 +227,8 @@ void validate(const rbsog_params* p)
     require(p->precision == RBSOG_FP64 || p->precision == RBSOG_MIXED, RBSOG_E_ARG, "unknown precision");
     require(!(p->t_target > 0.0 && p->tau_t > 0.0) || p->tau_t >= p->dt, RBSOG_E_ARG, "tau_t < dt");
     require(!(p->t_target > 0.0 && p->tau_t > 0.0) || p->n_atoms >= 2, RBSOG_E_ARG, "thermostat needs 2+ atoms");
+    require((p->flags & ~(uint32_t)RBSOG_FLAG_SHELL_STORED) == 0, RBSOG_E_ARG, "unknown flag");
+    require(!(p->flags & RBSOG_FLAG_SHELL_STORED) || p->p_r >= 1, RBSOG_E_ARG, "a stored shell batch needs p_r >= 1");
     for (int a = 0; a < 3; ++a) {
         require(std::isfinite(p->box[a]) && p->box[a] > 0.0, RBSOG_E_ARG, "box must be positive");
         require(p->box[a] >= 2.0 * (p->r_shell + p->skin), RBSOG_E_BOX,
@@ -247,7 +253,7 @@ void require_shared(const rbsog_params& a, const rbsog_params& b)
 {
     bool same = a.n_species == b.n_species && a.r_core == b.r_core && a.r_shell == b.r_shell &&
                 a.skin == b.skin && a.sog_eps == b.sog_eps && a.dt == b.dt && a.rebuild_every == b.rebuild_every &&
-                a.precision == b.precision && a.coulomb_k == b.coulomb_k;
+                a.precision == b.precision && a.coulomb_k == b.coulomb_k && a.flags == b.flags;
     for (int i = 0; same && i < a.n_species; ++i) {
         same = a.species[i].q == b.species[i].q && a.species[i].mass == b.species[i].mass;
         for (int j = 0; same && j < a.n_species; ++j) {
@@ -258,7 +264,7 @@ void require_shared(const rbsog_params& a, const rbsog_params& b)
     }
     require(same, RBSOG_E_ARG,
             "systems of a batch must share species, pair table, radii, skin, sog_eps, dt, rebuild_every, "
-            "precision and coulomb_k");
+            "precision, coulomb_k and flags");
 }
 
 // Device copies of the system records, after a host-side change.
@@ -289,14 +295,18 @@ Plan one(const rbsog_ctx* c, int r)
     P.modes64.blocks = (s.n > 0 && k.sampled) ? blocks_for(k.n_modes, 64) : 0;
     P.rho.blocks = (s.n > 0 && k.n_modes > 0) ? k.n_chunks * blocks_for(k.n_modes, 64 * P.tune.rho_mpl) : 0;
     P.modes1.blocks = s.n > 0 ? k.n_modes : 0;
+    P.rows64.blocks = (s.n > 0 && s.shell_stored) ? blocks_for(s.cand_rows, 64) : 0;
     P.list_mode = c->plan.list_mode;
+    P.stored = c->plan.stored;
+    P.n_chunks = c->plan.n_chunks;
     P.cap_core = c->plan.cap_core;
     P.cap_cand = c->plan.cap_cand;
     return P;
 }
 
-// Block maps of the batch launches (none for a single system).  Called again
-// whenever the tuning changes the shapes.
+// Block maps of the batch launches (none for a single system, except the
+// chunks of a memory-form build).  Called again whenever the tuning or the
+// list plan changes the shapes.
 void plan_launches(rbsog_ctx* c)
 {
     HIP_OK(hipStreamSynchronize(c->stream));  // the old maps may still be in use
@@ -306,28 +316,41 @@ void plan_launches(rbsog_ctx* c)
     P.kd = c->d_kd.as<KDev>();
     P.sc = c->scalars.as<DeviceScalars>();
     P.R = c->R;
-    constexpr int kShapes = 8;
-    Shape* dst[kShapes] = {&P.atoms, &P.pair_atoms, &P.kf_atoms, &P.cells, &P.atom1, &P.modes64, &P.rho, &P.modes1};
-    if (c->R == 1) {
-        const Plan o = one(c, 0);
-        const Shape* sh[kShapes] = {&o.atoms, &o.pair_atoms, &o.kf_atoms, &o.cells, &o.atom1, &o.modes64, &o.rho, &o.modes1};
-        for (int q = 0; q < kShapes; ++q) *dst[q] = *sh[q];
-        return;
-    }
-    std::vector<int2> m[kShapes];
+    constexpr int kShapes = 9;
+    Shape* dst[kShapes] = {&P.atoms, &P.pair_atoms, &P.kf_atoms, &P.cells, &P.atom1,
+                           &P.modes64, &P.rho, &P.modes1, &P.rows64};
+    std::vector<std::vector<int2>> m(kShapes + kMaxListChunks);
+    const bool maps = c->R > 1;
     for (int r = 0; r < c->R; ++r) {
         const Plan o = one(c, r);
-        const Shape* sh[kShapes] = {&o.atoms, &o.pair_atoms, &o.kf_atoms, &o.cells, &o.atom1, &o.modes64, &o.rho, &o.modes1};
-        for (int q = 0; q < kShapes; ++q)
-            for (int b = 0; b < sh[q]->blocks; ++b) m[q].push_back(make_int2(r, b));
+        const Shape* sh[kShapes] = {&o.atoms, &o.pair_atoms, &o.kf_atoms, &o.cells, &o.atom1,
+                                    &o.modes64, &o.rho, &o.modes1, &o.rows64};
+        for (int q = 0; q < kShapes; ++q) {
+            if (maps)
+                for (int b = 0; b < sh[q]->blocks; ++b) m[q].push_back(make_int2(r, b));
+            else
+                *dst[q] = *sh[q];
+        }
+        // cells of each build chunk, the split the kernels compute
+        const DevSys& s = c->hs[r];
+        if (P.stored && o.cells.blocks > 0)
+            for (int k = 0; k < s.n_chunks; ++k) {
+                const int c0 = (int)(((long long)k * s.ncell) / s.n_chunks);
+                const int c1 = (int)(((long long)(k + 1) * s.ncell) / s.n_chunks);
+                for (int cc = c0; cc < c1; ++cc) m[kShapes + k].push_back(make_int2(r, cc));
+            }
     }
+    for (int k = 0; k < kMaxListChunks; ++k) P.cell_chunk[k] = Shape{};
     size_t total = 0;
     for (auto& v : m) total += v.size();
-    c->d_maps.alloc(sizeof(int2) * std::max<size_t>(1, total));
+    if (total == 0) return;
+    c->d_maps.alloc(sizeof(int2) * total);
     int2* d = c->d_maps.as<int2>();
-    for (int q = 0; q < kShapes; ++q) {
-        dst[q]->blocks = (int)m[q].size();
-        dst[q]->map = d;
+    for (int q = 0; q < kShapes + kMaxListChunks; ++q) {
+        if (q < kShapes && !maps) continue;
+        Shape& sh = q < kShapes ? *dst[q] : P.cell_chunk[q - kShapes];
+        sh.blocks = (int)m[q].size();
+        sh.map = d;
         if (!m[q].empty()) HIP_OK(hipMemcpy(d, m[q].data(), sizeof(int2) * m[q].size(), hipMemcpyHostToDevice));
         d += m[q].size();
     }
@@ -338,16 +361,63 @@ void plan_lists(rbsog_ctx* c, int cap_core, int cap_cand)
     c->drop_graphs();
     c->plan.cap_core = cap_core;
     c->plan.cap_cand = cap_cand;
+    const bool stored = c->R > 0 && c->hs[0].shell_stored;
+    // the memory form keeps candidate rows for one chunk of cells at a time
+    // (the per-atom fallback kernel needs them all); otherwise one per atom
+    const int K = (stored && c->plan.list_mode != 2) ? std::max(1, std::min(c->list_chunks, kMaxListChunks)) : 1;
+    c->plan.stored = stored;
+    c->plan.n_chunks = K;
+    size_t bat_all = 0;
+    std::vector<int> rows(c->R);
+    for (int r = 0; r < c->R; ++r) {
+        DevSys& s = c->hs[r];
+        const int npad = round_up(std::max(s.n, 1), 64);
+        s.n_chunks = std::max(1, std::min(K, s.ncell));
+        if (s.n_chunks == 1) {
+            rows[r] = npad;
+        } else {
+            // most cells in one chunk, times the mean atoms per cell, with headroom
+            const int cells_max = (s.ncell + s.n_chunks - 1) / s.n_chunks;
+            const double expect = (double)s.n * cells_max / s.ncell;
+            rows[r] = std::min(npad, round_up((int)std::ceil(expect * c->row_slack) + 64, 64));
+        }
+        bat_all += stored ? (size_t)npad * s.p_r : 0;
+    }
     const size_t slots = (size_t)std::max(c->n_slots, 64);
     c->lists_core.alloc(sizeof(int32_t) * slots * cap_core);
-    c->lists_cand.alloc(sizeof(int32_t) * slots * cap_cand);
+    size_t cand_rows_total = 0;
+    if (stored)
+        for (int r = 0; r < c->R; ++r) cand_rows_total += (size_t)rows[r];
+    else
+        cand_rows_total = slots;
+    c->lists_cand.alloc(sizeof(int32_t) * std::max<size_t>(cand_rows_total, 1) * cap_cand);
+    if (stored)
+        c->lists_bat.alloc(sizeof(int32_t) * std::max<size_t>(bat_all, 1));
+    else
+        c->lists_bat.release();
+    // every list entry holds an atom index from the start: a kernel that runs
+    // after a build that overflowed (and is discarded) reads only indices
+    for (DBuf* b : {&c->lists_core, &c->lists_cand, &c->lists_bat})
+        if (b->p) HIP_OK(hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+    size_t row_off = 0, bat_off = 0;
     for (int r = 0; r < c->R; ++r) {
         DevSys& s = c->hs[r];
         s.cap_core = cap_core;
         s.cap_cand = cap_cand;
         // slot offsets are multiples of 64: whole core-list tiles per system
         s.core_idx = c->lists_core.as<int32_t>() + (size_t)c->slot_off[r] * cap_core;
-        s.cand_idx = c->lists_cand.as<int32_t>() + (size_t)c->slot_off[r] * cap_cand;
+        if (stored) {
+            s.cand_rows = rows[r];
+            s.cand_idx = c->lists_cand.as<int32_t>() + row_off * cap_cand;
+            row_off += (size_t)rows[r];
+            s.bat_idx = c->lists_bat.as<int32_t>() + bat_off;
+            bat_off += (size_t)round_up(std::max(s.n, 1), 64) * s.p_r;
+        } else {
+            s.n_chunks = 1;
+            s.cand_rows = round_up(std::max(s.n, 1), 64);
+            s.cand_idx = c->lists_cand.as<int32_t>() + (size_t)c->slot_off[r] * cap_cand;
+            s.bat_idx = nullptr;
+        }
     }
     upload_sys(c);
 }
@@ -401,36 +471,39 @@ void snapshot(rbsog_ctx* c, bool save)
     }
 }
 
-// Grow list capacities from the true counts of the last build.
-void grow_lists(rbsog_ctx* c)
+// After a build that overflowed: grow what overflowed (bit 1: list
+// capacities, from the true counts of the build; bit 4: the list kernel's
+// stencil; bit 8: the candidate scratch of a memory-form chunk) and plan the
+// lists again.  Bit 2 (a cell above the in-cell sort's capacity) is fatal.
+void grow_after_overflow(rbsog_ctx* c, int o)
 {
-    int mc = 0, mk = 0;
-    for (const auto& h : read_scalars(c)) {
-        mc = std::max(mc, h.max_core);
-        mk = std::max(mk, h.max_cand);
+    require((o & 2) == 0, RBSOG_E_CAPACITY, "a cell holds more than 2048 atoms");
+    int cap_core = c->plan.cap_core, cap_cand = c->plan.cap_cand;
+    if (o & 1) {
+        int mc = 0, mk = 0;
+        for (const auto& h : read_scalars(c)) {
+            mc = std::max(mc, h.max_core);
+            mk = std::max(mk, h.max_cand);
+        }
+        cap_core = std::max(cap_core, round_up(mc + mc / 4 + 8, 32));
+        cap_cand = std::max(cap_cand, round_up(mk + mk / 4 + 8, 32));
+        require(cap_cand <= 4096 && cap_core <= 4096, RBSOG_E_CAPACITY, "neighbour list capacity above 4096");
     }
-    const int cap_core = std::max(c->plan.cap_core, round_up(mc + mc / 4 + 8, 32));
-    const int cap_cand = std::max(c->plan.cap_cand, round_up(mk + mk / 4 + 8, 32));
-    require(cap_cand <= 4096 && cap_core <= 4096, RBSOG_E_CAPACITY, "neighbour list capacity above 4096");
+    if (o & 4) c->plan.list_mode = std::min(2, c->plan.list_mode + 1);
+    if (o & 8) c->row_slack *= 2.0;
     plan_lists(c, cap_core, cap_cand);
+    plan_launches(c);
 }
 
-// Build; if a list or cell capacity overflowed, grow the lists and build again.
+// Build; if a list or cell capacity overflowed, grow it and build again.
 void build_checked(rbsog_ctx* c)
 {
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    for (int attempt = 0; attempt < 6; ++attempt) {
         launch_clear_flags(c->plan, c->stream);
         enqueue_build(c, false);
         const int o = any_overflow(read_scalars(c));
         if (o == 0) return;
-        if (o & 2) throw Error(RBSOG_E_CAPACITY, "a cell holds more than 2048 atoms");
-        if (o & 4) {
-            // a cell's stencil did not fit in LDS: larger stencil, then per-atom lists
-            c->plan.list_mode = std::min(2, c->plan.list_mode + 1);
-            c->drop_graphs();
-            continue;
-        }
-        grow_lists(c);
+        grow_after_overflow(c, o);
     }
     throw Error(RBSOG_E_CAPACITY, "list capacity did not converge");
 }
@@ -655,6 +728,8 @@ void init_devsys(const rbsog_params& p, int n, DevSys& s)
     s.t_target = thermo ? p.t_target : 0.0;
     s.dof_kb = (3.0 * n - 3.0) * kBoltzmann;
     s.p_r = p.p_r;
+    s.shell_stored = (p.flags & RBSOG_FLAG_SHELL_STORED) ? 1 : 0;
+    s.n_chunks = 1;
     s.replica = p.replica;
     s.seed = p.seed;
 }
@@ -740,6 +815,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->R = R;
     c->prm = prm;
     c->sel = 0;
+    c->row_slack = 1.25;
     c->plan.tune = Tuning{};
     c->slot_off.assign(slot_off.begin(), slot_off.end() - 1);
     c->n_slots = slot_off[R];
@@ -1216,12 +1292,7 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
                 return;
             }
             require(attempt < 4 && (o & 2) == 0, RBSOG_E_CAPACITY, "list capacity exceeded in the step loop");
-            if (o & 4) {
-                ctx->plan.list_mode = std::min(2, ctx->plan.list_mode + 1);
-                ctx->drop_graphs();
-            } else {
-                grow_lists(ctx);
-            }
+            grow_after_overflow(ctx, o);
             snapshot(ctx, false);
             build_checked(ctx);
             launch_set_eval(ctx->plan, ctx->eval, ctx->stream);
@@ -1318,8 +1389,8 @@ rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_
         HIP_OK(hipMemcpy(&t, s.inv + i, sizeof(int32_t), hipMemcpyDeviceToHost));
         HIP_OK(hipMemcpy(&nc, s.core_cnt + t, sizeof(int32_t), hipMemcpyDeviceToHost));
         HIP_OK(hipMemcpy(&nk, s.cand_cnt + t, sizeof(int32_t), hipMemcpyDeviceToHost));
-        nc = std::min(nc, s.cap_core);
-        nk = std::min(nk, s.cap_cand);
+        nc = std::min(nc, s.cap_core - 1);
+        nk = std::min(nk, s.cap_cand - 1);
         if (core) {
             std::vector<int32_t> tile((size_t)s.cap_core * 64);
             const int32_t* src = s.core_idx + (size_t)(t >> 6) * s.cap_core * 64;
@@ -1329,6 +1400,8 @@ rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_
             std::sort(ids.begin(), ids.end());
             std::copy(ids.begin(), ids.end(), core);
         }
+        require(!(cand && s.shell_stored), RBSOG_E_STATE,
+                "the stored-batch form keeps no candidate lists after the build");
         if (cand) {
             std::vector<int32_t> row(std::max(nk, 1));
             if (nk > 0)
@@ -1344,6 +1417,7 @@ rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ran
     return guarded(ctx, [&] {
         need_system(ctx);
         const DevSys& s = ctx->hs[ctx->sel];
+        require(!s.shell_stored, RBSOG_E_STATE, "a stored shell batch is exported by rbsog_get_shell_batch");
         const Plan P1 = one(ctx, ctx->sel);
         const int P = std::max(s.p_r, 1);
         DBuf out;
@@ -1367,6 +1441,35 @@ rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ran
                 for (int q = 0; q < P; ++q) ranks[(size_t)u * P + q] = q < hc[u] ? row[q] : -1;
             }
         }
+    });
+}
+
+rbsog_status rbsog_get_shell_batch(rbsog_ctx* ctx, int32_t* n_cand, int32_t* ids)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        const DevSys& s = ctx->hs[ctx->sel];
+        require(s.shell_stored, RBSOG_E_STATE, "no stored shell batch (RBSOG_FLAG_SHELL_STORED is off)");
+        const Plan P1 = one(ctx, ctx->sel);
+        const int P = s.p_r;
+        DBuf out;
+        out.alloc(sizeof(int32_t) * ((size_t)s.n * P + s.n + 1));
+        int32_t* d = out.as<int32_t>();
+        int32_t* cnt = d + (size_t)s.n * P;
+        launch_batch_ids(P1, d, cnt, ctx->stream);
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        if (s.n > 0) {
+            if (ids) HIP_OK(hipMemcpy(ids, d, sizeof(int32_t) * (size_t)s.n * P, hipMemcpyDeviceToHost));
+            if (n_cand) HIP_OK(hipMemcpy(n_cand, cnt, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost));
+        }
+    });
+}
+
+rbsog_status rbsog_set_list_chunks(rbsog_ctx* ctx, int32_t chunks)
+{
+    return guarded(ctx, [&] {
+        require(chunks >= 1 && chunks <= kMaxListChunks, RBSOG_E_ARG, "chunks out of range (1..64)");
+        ctx->list_chunks = chunks;  // used by the next rbsog_set_system / rbsog_set_batch
     });
 }
 

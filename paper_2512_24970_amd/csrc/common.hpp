@@ -15,6 +15,8 @@ constexpr int kTableBits = 10;    // sincos table: e^{2 pi i j / 1024}
 constexpr int kTableSize = 1 << kTableBits;
 constexpr uint32_t kTagShell = 2u;
 constexpr uint32_t kTagKmode = 3u;
+constexpr uint32_t kTagShellBuild = 5u;  // shell batch drawn once per list build
+constexpr int kMaxListChunks = 64;      // launches a list build may be cut into
 constexpr double kPi = 3.14159265358979323846;
 // 1 eV/(Angstrom*amu) in Angstrom/ps^2
 constexpr double kAccUnit = 9648.533212331;

@@ -50,7 +50,7 @@ __device__ inline DevSys global_view(DevSys s)
     s.slot_of = glob(s.slot_of), s.order = glob(s.order);
     s.cell_count = glob(s.cell_count), s.cell_start = glob(s.cell_start);
     s.core_cnt = glob(s.core_cnt), s.core_idx = glob(s.core_idx);
-    s.cand_cnt = glob(s.cand_cnt), s.cand_idx = glob(s.cand_idx);
+    s.cand_cnt = glob(s.cand_cnt), s.cand_idx = glob(s.cand_idx), s.bat_idx = glob(s.bat_idx);
     s.pair = glob(s.pair), s.sc = glob(s.sc), s.spc = glob(s.spc);
     s.pair_part = glob(s.pair_part), s.kin_part = glob(s.kin_part);
     return s;
@@ -160,7 +160,8 @@ __global__ void k_bump_eval(DeviceScalars* sc, int R)
 {
     for (int r = threadIdx.x; r < R; r += blockDim.x) sc[r].eval += 1;
 }
-// Closes a build: lower the flag, restart the displacement tracking.
+// Closes a build: lower the flag, restart the displacement tracking.  A
+// build that overflowed is discarded and built again, so it takes no number.
 __global__ void k_build_done(const DevSys* __restrict__ sys, int R, int gate)
 {
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
@@ -168,7 +169,7 @@ __global__ void k_build_done(const DevSys* __restrict__ sys, int R, int gate)
         if (gate && sc->rebuild == 0) continue;
         sc->rebuild = 0;
         sc->max_disp2 = 0.0;
-        sc->n_builds += 1;
+        if (sc->overflow == 0) sc->n_builds += 1;
     }
 }
 __global__ void k_clear_flags(DeviceScalars* sc, int R)
@@ -350,6 +351,11 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
 {
     RB_SYS(blockIdx.x)
     RB_GATE
+    if (s.n_chunks != 1) {
+        // candidate rows are per atom here: the host plans one chunk
+        if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 8);
+        return;
+    }
     extern __shared__ long long lsm64[];
     const int capP2 = [&] {
         int p = 1;
@@ -415,14 +421,15 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
     if (lane == 0) {
         s.core_cnt[i] = ncore;
         s.cand_cnt[i] = ncand;
-        if (ncore > s.cap_core || ncand > s.cap_cand) {
+        // usable capacity cap - 1, as in the per-cell kernel
+        if (ncore >= s.cap_core || ncand >= s.cap_cand) {
             atomicOr(&s.sc->overflow, 1);
-            atomicMax(&s.sc->max_core, ncore);
-            atomicMax(&s.sc->max_cand, ncand);
+            atomicMax(&s.sc->max_core, ncore + 1);
+            atomicMax(&s.sc->max_cand, ncand + 1);
         }
     }
-    const int nk = min(ncand, s.cap_cand);
-    const int nc = min(ncore, s.cap_core);
+    const int nk = min(ncand, s.cap_cand - 1);
+    const int nc = min(ncore, s.cap_core - 1);
     int P = 1;
     while (P < nk) P <<= 1;
     for (int t = nk + lane; t < P; t += 64) {
@@ -477,11 +484,24 @@ __device__ inline int mbcnt64(uint64_t m)
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// First atom of build chunk `chunk` (cells [chunk ncell / K, (chunk+1) ncell / K)).
+__device__ inline int chunk_first_atom(const DevSys& s, int chunk)
+{
+    return s.cell_start[(int)(((long long)chunk * s.ncell) / s.n_chunks)];
+}
+
 template <int CAP>
-__global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
+__global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, int chunk)
 {
     RB_SYS(xcd_block(blockIdx.x, gridDim.x))
     RB_GATE
+    if (chunk >= s.n_chunks) return;
+    // candidate rows of this chunk's atoms start at its first atom
+    const int row0 = chunk_first_atom(s, chunk);
+    if (chunk_first_atom(s, chunk + 1) - row0 > s.cand_rows) {
+        if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 8);
+        return;
+    }
     __shared__ int32_t val[CAP];
     __shared__ double px[CAP];
     __shared__ double py[CAP];
@@ -737,8 +757,10 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate)
             yu[u] = py[a];
             zu[u] = pz[a];
             iu[u] = here ? __builtin_amdgcn_readfirstlane(val[a]) : -1;
-            const int ii = here ? iu[u] : 0;
-            crow[u] = s.cand_idx + (size_t)ii * s.cap_cand;
+            // a missing atom sweeps into the rows of the unit's first atom,
+            // where its misses land on the unused last entry
+            const int ii = here ? iu[u] : __builtin_amdgcn_readfirstlane(val[a0]);
+            crow[u] = s.cand_idx + (size_t)(ii - row0) * s.cap_cand;
             ccol[u] = s.core_idx + (size_t)(ii >> 6) * s.cap_core * 64 + (ii & 63);
             ncore[u] = 0;
             ncand[u] = 0;
@@ -973,7 +995,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
         constexpr int kU = KU;
         if (!shell) {
             // core sum, eq. (24)
-            const int nc = min(s.core_cnt[i], s.cap_core);
+            const int nc = min(s.core_cnt[i], s.cap_core - 1);
             const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
             for (int k0 = 0; k0 < nc; k0 += kU) {
                 int jj[kU];
@@ -1007,9 +1029,49 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     }
                 }
             }
+        } else if (s.shell_stored) {
+            // shell batch of eq. (25) drawn at the list build: a tile row per
+            // atom, read coalesced like the core list
+            const int n = min(s.cand_cnt[i], s.cap_cand - 1);
+            const bool take_all = n <= s.p_r;
+            const int cnt = take_all ? n : s.p_r;
+            wgt = take_all ? 1.0 : (double)n / (double)s.p_r;
+            const int32_t* btile = s.bat_idx + (size_t)(i >> 6) * s.p_r * 64 + (i & 63);
+            for (int k0 = 0; k0 < cnt; k0 += kU) {
+                int jj[kU];
+                double X[kU], Y[kU], Z[kU];
+                int T[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    jj[u] = (k0 + u < cnt) ? __builtin_nontemporal_load(btile + (size_t)(k0 + u) * 64) : i;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const double4 Q = s.p[jj[u]];
+                    X[u] = Q.x;
+                    Y[u] = Q.y;
+                    Z[u] = Q.z;
+                    T[u] = (int)Q.w;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (k0 + u >= cnt) break;
+                    const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
+                    const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
+                    const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 >= s.rc2 && r2 < s.rs2) {
+                        double uu = 0.0;
+                        const double f = pair_f(T[u], r2, uu);
+                        Sx = fma(f, dx, Sx);
+                        Sy = fma(f, dy, Sy);
+                        Sz = fma(f, dz, Sz);
+                        if (ENERGY) Su += 0.5 * uu;
+                    }
+                }
+            }
         } else {
             // shell batch, eq. (25)
-            const int n = min(s.cand_cnt[i], s.cap_cand);
+            const int n = min(s.cand_cnt[i], s.cap_cand - 1);
             const int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
             const bool take_all = s.p_r <= 0 || n <= s.p_r;
             const int cnt = take_all ? n : s.p_r;
@@ -1102,7 +1164,7 @@ __global__ __launch_bounds__(kBlock) void k_shell_ranks(RB_ARGS, int32_t* out, i
     extern __shared__ uint32_t mask_sm[];
     const int i = lb * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
-    const int n = min(s.cand_cnt[i], s.cap_cand);
+    const int n = min(s.cand_cnt[i], s.cap_cand - 1);
     const int P = s.p_r;
     const int uid = s.id[i];
     int32_t* o = out + (size_t)uid * (P > 0 ? P : 1);
@@ -1116,6 +1178,59 @@ __global__ __launch_bounds__(kBlock) void k_shell_ranks(RB_ARGS, int32_t* out, i
     fm.clear(n);
     for (int k = 0; k < P; ++k) o[k] = fm.step(st, n - P + k);
     n_out[uid] = P;
+}
+
+// Memory form of the list: the shell batch of each atom of build chunk
+// `chunk`, drawn once at the build (Floyd's selection as in the pair kernel,
+// on the stream (id, build number, kTagShellBuild)) from its candidate row,
+// stored in ascending rank order as atom indices in the atom's tile row.
+__global__ __launch_bounds__(64) void k_select(RB_ARGS, int gate, int chunk)
+{
+    RB_SYS(blockIdx.x)
+    RB_GATE
+    extern __shared__ uint32_t mask_sm[];
+    if (chunk >= s.n_chunks) return;
+    const int row0 = chunk_first_atom(s, chunk);
+    const int row1 = chunk_first_atom(s, chunk + 1);
+    const int t = lb * 64 + threadIdx.x;
+    const int a = row0 + t;
+    // rows of a chunk that did not fit were not built (the host builds again)
+    if (row1 - row0 > s.cand_rows || t >= s.cand_rows || a >= row1) return;
+    const int n = min(s.cand_cnt[a], s.cap_cand - 1);
+    const int P = s.p_r;
+    const int32_t* crow = s.cand_idx + (size_t)t * s.cap_cand;
+    int32_t* btile = s.bat_idx + (size_t)(a >> 6) * P * 64 + (a & 63);
+    if (n <= P) {
+        for (int k = 0; k < n; ++k) btile[(size_t)k * 64] = crow[k];
+        return;
+    }
+    FloydMask fm{mask_sm + threadIdx.x, 64};
+    PhiloxStream st(s.seed, (uint32_t)s.id[a], (uint32_t)s.sc->n_builds, kTagShellBuild, s.replica);
+    fm.clear(n);
+    for (int k = 0; k < P; ++k) fm.step(st, n - P + k);
+    int w = 0;
+    uint32_t m = fm.m[0];
+    for (int k = 0; k < P; ++k) {
+        while (m == 0u) m = fm.m[(++w) * fm.stride];
+        const int e = w * 32 + __builtin_ctz(m);
+        m &= m - 1u;
+        btile[(size_t)k * 64] = crow[e];
+    }
+}
+
+// Export of the stored batch as atom ids (ascending rank order).
+__global__ __launch_bounds__(kBlock) void k_batch_ids(RB_ARGS, int32_t* out, int32_t* n_out)
+{
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const int n = min(s.cand_cnt[i], s.cap_cand - 1);
+    const int P = s.p_r;
+    const int cnt = min(n, P);
+    const int uid = s.id[i];
+    const int32_t* btile = s.bat_idx + (size_t)(i >> 6) * P * 64 + (i & 63);
+    for (int k = 0; k < P; ++k) out[(size_t)uid * P + k] = k < cnt ? s.id[btile[(size_t)k * 64]] : -1;
+    n_out[uid] = n;
 }
 
 // ---------------------------------------------------------------- k-space
@@ -1627,15 +1742,23 @@ void launch_build(const Plan& P, bool gate, hipStream_t st)
     k_scatter<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), g);
     k_cell_sort<<<P.cells.blocks, kBlock, 0, st>>>(RB_MAP(cells), g);
     k_gather<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), g);
-    if (P.list_mode == 0) {
-        k_lists_cell<2048><<<P.cells.blocks, kListBlock, 0, st>>>(RB_MAP(cells), g);
-    } else if (P.list_mode == 1) {
-        k_lists_cell<4096><<<P.cells.blocks, kListBlock, 0, st>>>(RB_MAP(cells), g);
-    } else {
-        int capP2 = 1;
-        while (capP2 < P.cap_cand) capP2 <<= 1;
-        const size_t sm = sizeof(long long) * (size_t)capP2 + sizeof(int32_t) * ((size_t)capP2 + P.cap_core);
-        k_lists<<<P.atom1.blocks, 64, sm, st>>>(RB_MAP(atom1), g);
+    // the memory form builds chunk by chunk: candidate rows of one chunk of
+    // cells, then the batch draw from them, in the same scratch rows
+    const int K = P.stored ? P.n_chunks : 1;
+    const size_t sm_sel = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * 64;
+    for (int k = 0; k < K; ++k) {
+        const Shape& cs = P.stored ? P.cell_chunk[k] : P.cells;
+        if (P.list_mode == 0) {
+            if (cs.blocks > 0) k_lists_cell<2048><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
+        } else if (P.list_mode == 1) {
+            if (cs.blocks > 0) k_lists_cell<4096><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
+        } else {
+            int capP2 = 1;
+            while (capP2 < P.cap_cand) capP2 <<= 1;
+            const size_t sm = sizeof(long long) * (size_t)capP2 + sizeof(int32_t) * ((size_t)capP2 + P.cap_core);
+            k_lists<<<P.atom1.blocks, 64, sm, st>>>(RB_MAP(atom1), g);
+        }
+        if (P.stored && P.rows64.blocks > 0) k_select<<<P.rows64.blocks, 64, sm_sel, st>>>(RB_MAP(rows64), g, k);
     }
     k_build_done<<<1, 64, 0, st>>>(P.sys, P.R, g);
 }
@@ -1649,7 +1772,8 @@ template <int KU>
 void launch_pair_ku(const Plan& P, const SogCoef& g, const SogCoefF& gf, bool mixed, bool energy, hipStream_t st)
 {
     const int bs = P.tune.pair_block;  // atoms per workgroup; twice as many threads
-    const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * bs;
+    // Floyd masks of the per-evaluation batch draw (none for a stored batch)
+    const size_t sm = P.stored ? 0 : sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * bs;
     const int nb = P.pair_atoms.blocks;
 #define RB_PAIR(M, E, J) k_pair<M, E, J, KU><<<nb, 2 * bs, sm, st>>>(RB_MAP(pair_atoms), g, gf)
     if (mixed) {
@@ -1764,6 +1888,11 @@ void launch_shell_ranks(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t
 {
     const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * kBlock;
     if (P.atoms.blocks > 0) k_shell_ranks<<<P.atoms.blocks, kBlock, sm, st>>>(RB_MAP(atoms), out, n_out);
+}
+
+void launch_batch_ids(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st)
+{
+    if (P.atoms.blocks > 0) k_batch_ids<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), out, n_out);
 }
 
 void launch_from_user(const Plan& P, const int32_t* type, const double* pos, const double* vel, hipStream_t st)

@@ -45,6 +45,13 @@ struct DevSys {
     double dof_kb;         // (3N - 3) k_B
     int p_r;
     int cap_core, cap_cand;
+    // Memory form of the list (shell_stored): the shell batch is drawn at the
+    // build into bat_idx and kept; candidate rows are build scratch for one
+    // chunk of cells at a time (n_chunks chunks, cand_rows rows).  Otherwise
+    // n_chunks = 1 and cand_idx holds a row per atom.
+    int shell_stored;
+    int n_chunks;
+    int cand_rows;
     uint32_t replica;
     uint64_t seed;
     const struct SpeciesDev* spc;  // per-species constants (shared by a batch)
@@ -64,6 +71,7 @@ struct DevSys {
     int32_t *cell_count, *cell_start;
     // lists
     int32_t *core_cnt, *core_idx, *cand_cnt, *cand_idx;
+    int32_t* bat_idx;      // [ceil(n/64)][p_r][64] stored shell batch (sorted atom indices)
     // pair coefficients [S*S]
     const PairCoef* pair;
     DeviceScalars* sc;
@@ -121,11 +129,15 @@ struct Plan {
     Shape pair_atoms;  // tune.pair_block-atom blocks (pair kernel)
     Shape kf_atoms;    // tune.kf_block-atom blocks (k-space force kernel)
     Shape cells;    // one block per cell
+    Shape cell_chunk[kMaxListChunks];  // the cells of each build chunk (memory form)
+    Shape rows64;   // 64-row blocks over each system's candidate rows (batch draw)
     Shape atom1;    // one block per atom (per-atom list kernel)
     Shape modes64;  // 64-mode blocks of the systems that draw modes
     Shape rho;      // rho blocks: local block = mode tile * n_chunks + chunk (tiles of 64 rho_mpl modes)
     Shape modes1;   // one block per mode
     int list_mode = 0;  // 0/1: per-cell list kernel with a 2048/4096-atom stencil, 2: per-atom kernel
+    bool stored = false;  // memory form: batch drawn at the build
+    int n_chunks = 1;     // build chunks (1 unless stored)
     int cap_core = 0, cap_cand = 0;
     Tuning tune;
 };
@@ -163,6 +175,9 @@ void launch_pos_to_user(const Plan& P, double* out, hipStream_t st);
 void launch_kspace_part(const Plan& P, double* out, hipStream_t st);
 // shell ranks of one system (P.R == 1) into out[n][P_R], n_out[n] by atom id
 void launch_shell_ranks(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st);
+// stored shell batch of one system (P.R == 1) as atom ids into out[n][P_R]
+// (-1 past the batch) and candidate counts into n_out[n], by atom id
+void launch_batch_ids(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st);
 void launch_from_user(const Plan& P, const int32_t* type, const double* pos, const double* vel, hipStream_t st);
 
 }  // namespace rbsog

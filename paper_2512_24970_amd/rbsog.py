@@ -19,6 +19,7 @@ MAX_SPECIES = 8
 MAX_SOG = 512
 FP64 = 0
 MIXED = 1
+FLAG_SHELL_STORED = 1  # shell batch drawn at the list build and kept (memory form)
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_OOM", -5: "E_LIST_STALE",
           -6: "E_NONNEUTRAL", -7: "E_BOX", -8: "E_NONFINITE", -9: "E_CAPACITY"}
@@ -94,6 +95,8 @@ ABI = {
     "rbsog_get_list_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbsog_get_lists_of": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "rbsog_get_shell_ranks": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "rbsog_get_shell_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rbsog_set_list_chunks": (C.c_int, [C.c_void_p, C.c_int32]),
     "rbsog_get_kmodes": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_double)]),
     "rbsog_get_rho": (C.c_int, [C.c_void_p, C.c_void_p]),
     "rbsog_get_sog": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -152,7 +155,7 @@ def make_params(sysp: dict, precision: int = FP64, n_atoms: int | None = None) -
     p.precision = int(precision)
     p.seed = int(sysp["seed"])
     p.replica = int(sysp.get("replica", 0))
-    p.flags = 0
+    p.flags = FLAG_SHELL_STORED if sysp.get("shell_stored", False) else 0
     p.coulomb_k = float(sysp["coulomb_k"])
     p.t_target = float(sysp.get("t_target", 0.0))
     p.tau_t = float(sysp.get("tau_t", 0.0))
@@ -279,6 +282,9 @@ class Context:
     def rbsog_use_graphs(self, on: bool = True):
         self._check(lib().rbsog_use_graphs(self._h, 1 if on else 0), "rbsog_use_graphs")
 
+    def rbsog_set_list_chunks(self, chunks: int):
+        self._check(lib().rbsog_set_list_chunks(self._h, chunks), "rbsog_set_list_chunks")
+
     def _order_outputs(self):
         """Device outputs are written on the context's stream: make torch's
         current stream wait for them when the two differ."""
@@ -349,11 +355,13 @@ class Context:
         self._check(lib().rbsog_get_list_counts(self._h, _np_ptr(nc), _np_ptr(nk)), "rbsog_get_list_counts")
         return nc, nk
 
-    def rbsog_get_lists_of(self, i: int, n_core: int, n_cand: int):
+    def rbsog_get_lists_of(self, i: int, n_core: int, n_cand: int | None):
+        """Core and candidate lists of atom i; n_cand None asks for no candidates."""
         core = np.zeros(max(n_core, 1), np.int32)
-        cand = np.zeros(max(n_cand, 1), np.int32)
-        self._check(lib().rbsog_get_lists_of(self._h, i, _np_ptr(core), _np_ptr(cand)), "rbsog_get_lists_of")
-        return core[:n_core], cand[:n_cand]
+        cand = None if n_cand is None else np.zeros(max(n_cand, 1), np.int32)
+        self._check(lib().rbsog_get_lists_of(self._h, i, _np_ptr(core), None if cand is None else _np_ptr(cand)),
+                    "rbsog_get_lists_of")
+        return core[:n_core], None if cand is None else cand[:n_cand]
 
     def rbsog_get_shell_ranks(self, ev: int):
         P = max(self.params_list[self.sel].p_r, 1)
@@ -361,6 +369,13 @@ class Context:
         r = np.zeros((self._sel_n, P), np.int32)
         self._check(lib().rbsog_get_shell_ranks(self._h, ev, _np_ptr(nr), _np_ptr(r)), "rbsog_get_shell_ranks")
         return nr, r
+
+    def rbsog_get_shell_batch(self):
+        P = max(self.params_list[self.sel].p_r, 1)
+        nk = np.zeros(self._sel_n, np.int32)
+        ids = np.zeros((self._sel_n, P), np.int32)
+        self._check(lib().rbsog_get_shell_batch(self._h, _np_ptr(nk), _np_ptr(ids)), "rbsog_get_shell_batch")
+        return nk, ids
 
     def rbsog_get_kmodes(self, ev: int):
         p_f = self.params_list[self.sel].p_f
