@@ -301,6 +301,9 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=64, help="replicas in the batched-form leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=50,
                     help="timed steps of the 5e6-ion leg (0: skip)")
+    ap.add_argument("--stored", type=int, default=1,
+                    help="1: also time the memory form of the list (shell batch drawn at the build) "
+                         "on the 1e6-ion workload and, with --large-steps, on the 5e6-ion melt")
     ap.add_argument("--tuning", default="auto",
                     help="launch shapes of the single-system runs: auto (autotuned) or "
                          "pair_block,pair_ku,rho_mpl,kf_block")
@@ -378,6 +381,21 @@ def main() -> int:
                          "roofline": roofline("mixed", rl, nb, big["sys"], "nacl_5m"),
                          "phases_ms_per_step": {k: round(v[0] / args.large_steps, 4)
                                                 for k, v in rl["phases"].items()}}
+    if args.stored:
+        # memory form of the random batch list: the shell batch is drawn at the
+        # list build and kept until the next one (P_R entries per atom)
+        def stored_leg(c, steps, wl):
+            cs = dict(c, sys=dict(c["sys"], shell_stored=True))
+            rs = run_gpu(cs, "mixed", steps, args.warmup, "auto")
+            nn = len(c["types"])
+            return {"workload": wl, "n_atoms": nn, "form": "mixed", "value": rs["value"], "unit": "atom-steps/s",
+                    "steps": steps, "ms_per_step": rs["ms_per_step"], "T_end_K": round(rs["T_end"], 1),
+                    "tuning": rs["tuning"], "device_mem_GB": rs["device_mem_GB"],
+                    "roofline": roofline("mixed", rs, nn, c["sys"], wl + "_stored"),
+                    "phases_ms_per_step": {k: round(v[0] / steps, 4) for k, v in rs["phases"].items()}}
+        line["stored"] = stored_leg(cfg, args.steps, args.workload)
+        if args.large_steps > 0:
+            line["stored"]["large"] = stored_leg(big, args.large_steps, "nacl_5m")
     if args.cpu_sample > 0:
         _log(f"[bench] cpu baseline: oracle on {args.cpu_sample} atoms")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
