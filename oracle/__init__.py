@@ -23,6 +23,8 @@ MAXM = 511
 TAG_SHELL = 2
 TAG_KMODE = 3
 TAG_SHELL_BUILD = 5
+TAG_LANGEVIN = 6
+THERMOSTATS = {"berendsen": 0, "nose_hoover": 1, "langevin": 2}
 
 
 def build(force: bool = True) -> str:
@@ -47,19 +49,19 @@ class Params(C.Structure):
         ("rho", C.c_double * (MAXS * MAXS)), ("C", C.c_double * (MAXS * MAXS)),
         ("D", C.c_double * (MAXS * MAXS)),
         ("t_target", C.c_double), ("tau_t", C.c_double),
-        ("shell_stored", C.c_int32), ("pad_", C.c_int32),
+        ("shell_stored", C.c_int32), ("thermostat", C.c_int32),
     ]
 
 
 class Energy(C.Structure):
     _fields_ = [("u_core", C.c_double), ("u_shell", C.c_double), ("u_kspace", C.c_double),
                 ("u_self", C.c_double), ("u_total", C.c_double), ("kinetic", C.c_double),
-                ("p_corr", C.c_double * 3)]
+                ("p_corr", C.c_double * 3), ("e_thermostat", C.c_double)]
 
     def as_dict(self) -> dict:
         return {"u_core": self.u_core, "u_shell": self.u_shell, "u_kspace": self.u_kspace,
                 "u_self": self.u_self, "u_total": self.u_total, "kinetic": self.kinetic,
-                "p_corr": list(self.p_corr)}
+                "p_corr": list(self.p_corr), "e_thermostat": self.e_thermostat}
 
 
 _lib = None
@@ -168,6 +170,7 @@ def make_params(sysp: dict) -> Params:
     p.t_target = float(sysp.get("t_target", 0.0))
     p.tau_t = float(sysp.get("tau_t", 0.0))
     p.shell_stored = 1 if sysp.get("shell_stored", False) else 0
+    p.thermostat = THERMOSTATS[sysp.get("thermostat", "berendsen")]
     for i in range(S):
         p.q[i] = float(sp["q"][i])
         p.mass[i] = float(sp["mass"][i])

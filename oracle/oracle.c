@@ -450,6 +450,7 @@ struct orc_ctx {
     double* frc;  /* [n][3] last force */
     uint64_t eval;
     uint64_t n_builds; /* list builds so far */
+    double nh_x, nh_v; /* Nose-Hoover variable xi and its velocity */
     /* lists */
     int32_t* core_off;
     int32_t* core;
@@ -1036,10 +1037,51 @@ int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
     return 0;
 }
 
+#define ORC_KB 8.617333262e-5 /* eV/K */
+
+/* Nose-Hoover half step (Trotter splitting of the NVT equations of motion
+ * with one thermostat variable; Martyna, Tuckerman & Klein, Mol. Phys. 87,
+ * 1117 (1996), chain of length one): with G = (2K - g k_B T0)/Q,
+ * v_xi += G dt/4; v *= exp(-v_xi dt/2) (K scaled alike); xi += v_xi dt/2;
+ * v_xi += G dt/4 with the new K.  g = 3N - 3, Q = g k_B T0 tau^2. */
+static void nh_half(orc_ctx* c, double gkt, double Q, double dt)
+{
+    double K = kinetic(c);
+    c->nh_v += 0.25 * dt * (2.0 * K - gkt) / Q;
+    double s = exp(-0.5 * dt * c->nh_v);
+    for (int i = 0; i < 3 * c->n; ++i) c->vel[i] *= s;
+    K *= s * s;
+    c->nh_x += 0.5 * dt * c->nh_v;
+    c->nh_v += 0.25 * dt * (2.0 * K - gkt) / Q;
+}
+
+/* Three standard normals for the Langevin step of atom i at step `step`:
+ * Box-Muller on four 53-bit uniforms of the stream (i, step, TAG_LANGEVIN):
+ * r = sqrt(-2 ln(1 - u1)), z0 = r cos(2 pi u2), z1 = r sin(2 pi u2), then
+ * z2 = sqrt(-2 ln(1 - u3)) cos(2 pi u4). */
+static void langevin_normals(const orc_params* p, uint32_t i, uint32_t step, double z[3])
+{
+    orc_stream s;
+    stream_init(&s, p->seed, i, step, ORC_TAG_LANGEVIN, p->replica);
+    double u1 = stream_uniform(&s), u2 = stream_uniform(&s);
+    double u3 = stream_uniform(&s), u4 = stream_uniform(&s);
+    double r = sqrt(-2.0 * log(1.0 - u1));
+    z[0] = r * cos(2.0 * ORC_PI * u2);
+    z[1] = r * sin(2.0 * ORC_PI * u2);
+    z[2] = sqrt(-2.0 * log(1.0 - u3)) * cos(2.0 * ORC_PI * u4);
+}
+
 /* Velocity Verlet: v += dt/2 F/m; r += dt v (wrapped); lists rebuilt when the
  * step number is a multiple of rebuild_every or when some atom has moved more
  * than skin/2 since the last build; F at eval index = step number;
- * v += dt/2 F/m. */
+ * v += dt/2 F/m.  Thermostats (t_target > 0 and tau_t > 0):
+ *  Berendsen: v *= sqrt(1 + (dt/tau)(T0/T - 1)) at the start of each step,
+ *    T from the current kinetic energy and 3N - 3 degrees of freedom;
+ *  Nose-Hoover: a half step of nh_half before the first kick and after the
+ *    second;
+ *  Langevin (BAOAB; Leimkuhler & Matthews, AMRX 2013): the drift becomes
+ *    r += dt/2 v; v = c1 v + c2 z; r += dt/2 v with c1 = exp(-dt/tau),
+ *    c2 = sqrt((1 - c1^2) k_B T0 / m), z standard normals. */
 int orc_vv_steps(orc_ctx* c, int32_t n_steps, orc_energy* e_last)
 {
     int n = c->n;
@@ -1049,26 +1091,44 @@ int orc_vv_steps(orc_ctx* c, int32_t n_steps, orc_energy* e_last)
     orc_energy e;
     memset(&e, 0, sizeof(e));
     int thermo = p->t_target > 0.0 && p->tau_t > 0.0 && n > 1;
+    int kind = thermo ? p->thermostat : -1;
+    double gkt = (3.0 * n - 3.0) * ORC_KB * p->t_target;
+    double Q = gkt * p->tau_t * p->tau_t;
+    double c1 = exp(-p->dt / p->tau_t);
     for (int k = 0; k < n_steps; ++k) {
         uint64_t step = c->eval + 1;
-        /* Berendsen (weak coupling): v *= sqrt(1 + (dt/tau)(T0/T - 1)), with
-         * T from the current kinetic energy and 3N - 3 degrees of freedom */
         double lam = 1.0;
-        if (thermo) {
+        if (kind == ORC_THERMO_BERENDSEN) {
             double ke = kinetic(c);
             if (ke > 0.0) {
-                double T = 2.0 * ke / ((3.0 * n - 3.0) * 8.617333262e-5);
+                double T = 2.0 * ke / ((3.0 * n - 3.0) * ORC_KB);
                 double l2 = 1.0 + p->dt / p->tau_t * (p->t_target / T - 1.0);
                 lam = l2 > 0.0 ? sqrt(l2) : 0.0;
             }
+        } else if (kind == ORC_THERMO_NOSE_HOOVER) {
+            nh_half(c, gkt, Q, p->dt);
         }
         for (int i = 0; i < n; ++i) {
             double a = 0.5 * p->dt * ORC_ACC / p->mass[c->type[i]];
-            for (int x = 0; x < 3; ++x) {
-                c->vel[3 * i + x] = lam * c->vel[3 * i + x] + a * c->frc[3 * i + x];
-                c->pos[3 * i + x] += p->dt * c->vel[3 * i + x];
+            double* v = c->vel + 3 * i;
+            double* x = c->pos + 3 * i;
+            if (kind == ORC_THERMO_LANGEVIN) {
+                double z[3];
+                langevin_normals(p, (uint32_t)i, (uint32_t)step, z);
+                double c2 = sqrt((1.0 - c1 * c1) * ORC_KB * p->t_target * ORC_ACC / p->mass[c->type[i]]);
+                for (int d = 0; d < 3; ++d) {
+                    v[d] = v[d] + a * c->frc[3 * i + d];
+                    x[d] += 0.5 * p->dt * v[d];
+                    v[d] = c1 * v[d] + c2 * z[d];
+                    x[d] += 0.5 * p->dt * v[d];
+                }
+            } else {
+                for (int d = 0; d < 3; ++d) {
+                    v[d] = lam * v[d] + a * c->frc[3 * i + d];
+                    x[d] += p->dt * v[d];
+                }
             }
-            wrap(p, c->pos + 3 * i);
+            wrap(p, x);
         }
         int every = p->rebuild_every > 0 ? p->rebuild_every : 1;
         int moved = 0;
@@ -1084,9 +1144,11 @@ int orc_vv_steps(orc_ctx* c, int32_t n_steps, orc_energy* e_last)
             double a = 0.5 * p->dt * ORC_ACC / p->mass[c->type[i]];
             for (int x = 0; x < 3; ++x) c->vel[3 * i + x] += a * f[3 * i + x];
         }
+        if (kind == ORC_THERMO_NOSE_HOOVER) nh_half(c, gkt, Q, p->dt);
     }
     e.kinetic = kinetic(c);
     e.u_total = e.u_core + e.u_shell + e.u_kspace - e.u_self;
+    e.e_thermostat = kind == ORC_THERMO_NOSE_HOOVER ? 0.5 * Q * c->nh_v * c->nh_v + gkt * c->nh_x : 0.0;
     if (e_last) *e_last = e;
     free(f);
     return (int)c->eval;

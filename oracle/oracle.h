@@ -32,6 +32,12 @@ extern "C" {
 #define ORC_TAG_SHELL 2u
 #define ORC_TAG_KMODE 3u
 #define ORC_TAG_SHELL_BUILD 5u  /* shell batch drawn once per list build */
+#define ORC_TAG_LANGEVIN 6u     /* Langevin noise: counter word 1 = step number */
+
+/* Thermostats (active when t_target > 0 and tau_t > 0). */
+#define ORC_THERMO_BERENDSEN 0    /* v <- lambda v at the start of each step */
+#define ORC_THERMO_NOSE_HOOVER 1  /* one Nose-Hoover variable, Trotter half steps around the step */
+#define ORC_THERMO_LANGEVIN 2     /* BAOAB splitting, friction 1/tau_t */
 
 typedef struct {
     int32_t n_species;
@@ -64,12 +70,13 @@ typedef struct {
                                (atom, build number, TAG_SHELL_BUILD) with builds
                                counted from 0 (Section 2.4: O(core + P_R) list
                                entries per atom).  Needs p_r > 0. */
-    int32_t pad_;
+    int32_t thermostat;     /* ORC_THERMO_* */
 } orc_params;
 
 typedef struct {
     double u_core, u_shell, u_kspace, u_self, u_total, kinetic;
     double p_corr[3];       /* momentum correction that was subtracted, eq. (26) */
+    double e_thermostat;    /* Nose-Hoover: Q v_xi^2 / 2 + g k_B T0 xi (else 0) */
 } orc_energy;
 
 /* ---- Philox4x32-10 (Salmon et al., SC'11).  Pinned: published test vectors. */

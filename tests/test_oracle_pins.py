@@ -589,3 +589,115 @@ def test_berendsen_thermostat_holds_temperature():
         temps[label] = 2 * e["kinetic"] / ((3 * n - 3) * W.KB)
     assert abs(temps["nvt"] - T0) / T0 < 0.05
     assert temps["nve"] > temps["nvt"]
+
+
+# --------------------------------------------------------------------------- thermostats
+def _free_particles(n=4096, box=50.4, T=1200.0, tau=0.01):
+    """Ions with every interaction switched off (zero charges, A = C = D = 0):
+    the Langevin step reduces to an Ornstein-Uhlenbeck update of v."""
+    cfg = W.config("nacl_32768", n=n, box=box, T=T)
+    sp = dict(cfg["sys"]["species"])
+    S = len(sp["q"])
+    sp["q"] = [0.0] * S
+    for key in ("A", "C", "D"):
+        sp[key] = [[0.0] * S for _ in range(S)]
+    sysp = dict(cfg["sys"], species=sp, t_target=T, tau_t=tau, thermostat="langevin")
+    return cfg, sysp
+
+
+def test_langevin_step_is_the_ou_update_on_free_particles():
+    """BAOAB with no force: x1 = x0 + dt/2 (v0 + v1) and v1 = c1 v0 + c2 z with
+    c1 = exp(-dt/tau), c2 = sqrt((1 - c1^2) k_B T0 / m); the recovered z are
+    independent standard normals (Kolmogorov-Smirnov), i.e. the friction and
+    the noise satisfy fluctuation-dissipation at T0."""
+    cfg, sysp = _free_particles()
+    s = O.System(sysp, cfg["types"], cfg["pos"], cfg["vel"])
+    s.forces(0)
+    x0, v0, _, _ = s.state()
+    s.vv_steps(1)
+    x1, v1, f1, _ = s.state()
+    assert np.abs(f1).max() == 0.0
+    dt, tau, T = sysp["dt"], sysp["tau_t"], sysp["t_target"]
+    L = np.array(sysp["box"])
+    d = x1 - x0 - 0.5 * dt * (v0 + v1)
+    d -= L * np.rint(d / L)
+    assert np.abs(d).max() < 1e-12
+    c1 = math.exp(-dt / tau)
+    m = np.array(cfg["sys"]["species"]["mass"])[cfg["types"]][:, None]
+    c2 = np.sqrt((1 - c1 * c1) * W.KB * T * 9648.533212331 / m)
+    z = ((v1 - c1 * v0) / c2).ravel()
+    assert abs(z.mean()) < 4 / math.sqrt(len(z))
+    assert abs(z.var() - 1.0) < 0.05
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    zz = ((v1 - c1 * v0) / c2)
+    assert abs(np.corrcoef(zz[:, 0], zz[:, 1])[0, 1]) < 0.05
+
+
+def test_langevin_free_particles_stationary_and_decorrelating():
+    """From Maxwell-Boltzmann velocities at T0 the OU process stays at T0
+    (equipartition per component) and <v_n . v_0> / <v_0 . v_0> = c1^n."""
+    cfg, sysp = _free_particles()
+    n = len(cfg["types"])
+    s = O.System(sysp, cfg["types"], cfg["pos"], cfg["vel"])
+    s.forces(0)
+    _, v0, _, _ = s.state()
+    e = s.vv_steps(8)
+    _, v8, _, _ = s.state()
+    T = 2 * e["kinetic"] / ((3 * n - 3) * W.KB)
+    assert abs(T - sysp["t_target"]) / sysp["t_target"] < 5 * math.sqrt(2 / (3 * n))
+    c1 = math.exp(-sysp["dt"] / sysp["tau_t"])
+    m = np.array(cfg["sys"]["species"]["mass"])[cfg["types"]]
+    r = (m * (v8 * v0).sum(1)).sum() / (m * (v0 * v0).sum(1)).sum()
+    assert abs(r - c1 ** 8) < 0.03
+
+
+def test_nose_hoover_conserves_extended_energy():
+    """Deterministic force (P_R, P_F off), Nose-Hoover toward T0 = 1000 K from
+    a 1200 K melt: the energy E = U + K changes as the thermostat works, while
+    the extended energy H = E + Q v_xi^2/2 + g k_B T0 xi stays flat (to the
+    drift of plain velocity Verlet with this force)."""
+    cfg = W.config("nacl_small")
+    sysp = dict(_deterministic(cfg), t_target=1000.0, tau_t=0.02, thermostat="nose_hoover")
+    s = O.System(sysp, cfg["types"], cfg["pos"], cfg["vel"])
+    _, e0 = s.forces(0)
+    H0 = e0["u_total"] + e0["kinetic"]
+    E, H = [], []
+    for _ in range(6):
+        e = s.vv_steps(20)
+        E.append(e["u_total"] + e["kinetic"])
+        H.append(e["u_total"] + e["kinetic"] + e["e_thermostat"])
+    drift = max(abs(h - H0) for h in H)
+    change = max(abs(x - H0) for x in E)
+    assert drift / e0["kinetic"] < 2e-4
+    assert change > 20 * drift
+
+
+def test_nose_hoover_with_huge_mass_is_plain_verlet():
+    """Q -> infinity (tau = 1e6 ps) leaves v_xi at ~0: the trajectory equals
+    the thermostat-free one."""
+    cfg = W.config("nacl_small")
+    out = []
+    for over in ({}, dict(t_target=1000.0, tau_t=1e6, thermostat="nose_hoover")):
+        s = O.System(dict(cfg["sys"], **over), cfg["types"], cfg["pos"], cfg["vel"])
+        s.forces(0)
+        s.vv_steps(15)
+        out.append(s.state())
+    assert np.abs(out[0][0] - out[1][0]).max() < 1e-9
+    assert np.abs(out[0][1] - out[1][1]).max() < 1e-9
+
+
+@pytest.mark.parametrize("kind,tau", [("nose_hoover", 0.02), ("langevin", 0.02)])
+def test_thermostats_hold_the_melt_at_t0(kind, tau):
+    """With the random-batch force on (which heats an NVE run), both
+    thermostats keep the time-averaged temperature near T0."""
+    cfg = W.config("nacl_small")
+    n = len(cfg["types"])
+    T0 = 1200.0
+    s = O.System(dict(cfg["sys"], t_target=T0, tau_t=tau, thermostat=kind), cfg["types"], cfg["pos"], cfg["vel"])
+    s.forces(0)
+    s.vv_steps(100)
+    Ts = []
+    for _ in range(100):
+        e = s.vv_steps(1)
+        Ts.append(2 * e["kinetic"] / ((3 * n - 3) * W.KB))
+    assert abs(np.mean(Ts) - T0) / T0 < 0.06
