@@ -100,11 +100,30 @@ typedef struct {
     uint32_t replica;      /* Philox stream id of this system */
     uint32_t flags;        /* RBSOG_FLAG_* bits (others must be 0); equal across a batch */
     double coulomb_k;      /* e^2/(4 pi eps0) in eV*Angstrom; <= 0 means 14.399645478 */
-    double t_target;       /* K; with tau_t > 0 a Berendsen thermostat rescales v at the start of
-                              each step by sqrt(1 + dt/tau_t (t_target/T - 1)), T from 3N-3
-                              degrees of freedom; <= 0 = NVE */
-    double tau_t;          /* ps; tau_t = dt rescales to t_target exactly every step */
+    double t_target;       /* K; a thermostat acts when t_target > 0 and tau_t > 0, else NVE */
+    double tau_t;          /* ps; coupling time of the thermostat (see `thermostat`) */
+    int32_t thermostat;    /* RBSOG_THERMO_*; systems of a batch may differ */
+    int32_t reserved;      /* 0 */
 } rbsog_params;
+
+/* Thermostats (rbsog_params.thermostat), with T from the kinetic energy and
+ * g = 3N - 3 degrees of freedom.  The paper's runs are NVT (Section 3) and
+ * its trajectory estimate (Theorem 2.3) is stated for Langevin dynamics;
+ * it prints neither integrator, so these are the textbook forms.
+ * BERENDSEN: v <- lambda v at the start of each step, lambda^2 =
+ *   1 + (dt/tau_t)(t_target/T - 1); tau_t = dt rescales to t_target exactly.
+ * NOSE_HOOVER: one thermostat variable xi with mass Q = g k_B t_target
+ *   tau_t^2, advanced by Trotter half steps before the opening kick and
+ *   after the closing kick (Martyna, Tuckerman, Klein 1996); the conserved
+ *   extended energy is u_total + kinetic + e_thermostat.
+ * LANGEVIN: BAOAB splitting (Leimkuhler, Matthews 2013), friction 1/tau_t:
+ *   the drift becomes r += dt/2 v; v = c1 v + c2 z; r += dt/2 v with
+ *   c1 = exp(-dt/tau_t), c2 = sqrt((1 - c1^2) k_B t_target / m) and z three
+ *   standard normals per atom by Box-Muller from four 53-bit uniforms of the
+ *   Philox stream (atom id, step number, tag 6, replica). */
+#define RBSOG_THERMO_BERENDSEN 0
+#define RBSOG_THERMO_NOSE_HOOVER 1
+#define RBSOG_THERMO_LANGEVIN 2
 
 typedef struct {
     double u_core;    /* core-list energy, sum over r < r_core of N + B_BMH (eqs. 13-14, 24) */
@@ -116,6 +135,7 @@ typedef struct {
     double p_corr[3]; /* momentum correction F_corr of eq. (26) that was subtracted */
     double max_disp;  /* largest displacement since the last list build */
     int64_t n_builds; /* list builds since the system was set */
+    double e_thermostat; /* Nose-Hoover: Q v_xi^2 / 2 + g k_B t_target xi; else 0 */
 } rbsog_energy;
 
 /* Library version string. */

@@ -228,6 +228,9 @@ void validate(const rbsog_params* p)
     require(!(p->t_target > 0.0 && p->tau_t > 0.0) || p->tau_t >= p->dt, RBSOG_E_ARG, "tau_t < dt");
     require(!(p->t_target > 0.0 && p->tau_t > 0.0) || p->n_atoms >= 2, RBSOG_E_ARG, "thermostat needs 2+ atoms");
     require((p->flags & ~(uint32_t)RBSOG_FLAG_SHELL_STORED) == 0, RBSOG_E_ARG, "unknown flag");
+    require(p->thermostat == RBSOG_THERMO_BERENDSEN || p->thermostat == RBSOG_THERMO_NOSE_HOOVER ||
+                p->thermostat == RBSOG_THERMO_LANGEVIN,
+            RBSOG_E_ARG, "unknown thermostat");
     require(!(p->flags & RBSOG_FLAG_SHELL_STORED) || p->p_r >= 1, RBSOG_E_ARG, "a stored shell batch needs p_r >= 1");
     for (int a = 0; a < 3; ++a) {
         require(std::isfinite(p->box[a]) && p->box[a] > 0.0, RBSOG_E_ARG, "box must be positive");
@@ -508,10 +511,12 @@ void build_checked(rbsog_ctx* c)
     throw Error(RBSOG_E_CAPACITY, "list capacity did not converge");
 }
 
+// A thermostat that needs the kinetic energy every step (Berendsen,
+// Nose-Hoover; Langevin acts atom by atom).
 bool any_thermostat(const rbsog_ctx* c)
 {
     for (const auto& s : c->hs)
-        if (s.thermo_c > 0.0) return true;
+        if (s.thermo_c > 0.0 && s.thermostat != RBSOG_THERMO_LANGEVIN) return true;
     return false;
 }
 
@@ -550,7 +555,7 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     c->begin(RBSOG_PHASE_KFORCE);
     launch_kforce(P, c->mixed, kick, ke, st);
     c->end();
-    if (ke) launch_kinetic_finalize(P, st);
+    if (ke) launch_kinetic_finalize(P, kick, st);
 }
 
 void fill_energy(rbsog_ctx* c, const std::vector<DeviceScalars>& hv, rbsog_energy* e)
@@ -566,6 +571,10 @@ void fill_energy(rbsog_ctx* c, const std::vector<DeviceScalars>& hv, rbsog_energ
         for (int a = 0; a < 3; ++a) e[r].p_corr[a] = h.p_corr[a];
         e[r].max_disp = std::sqrt(h.max_disp2);
         e[r].n_builds = h.n_builds;
+        const DevSys& s = c->hs[r];
+        e[r].e_thermostat = (s.thermo_c > 0.0 && s.thermostat == RBSOG_THERMO_NOSE_HOOVER)
+                                ? 0.5 * s.nh_q * h.nh_v * h.nh_v + s.dof_kb * s.t_target * h.nh_x
+                                : 0.0;
     }
 }
 
@@ -580,7 +589,7 @@ void check_flags(const std::vector<DeviceScalars>& h)
 void enqueue_step(rbsog_ctx* c, bool scheduled, bool energy)
 {
     c->begin(RBSOG_PHASE_INTEGRATE);
-    launch_bump_eval(c->plan, c->stream);
+    launch_step_begin(c->plan, c->stream);
     launch_kick_drift(c->plan, scheduled, c->stream);
     c->end();
     enqueue_build(c, true);
@@ -727,6 +736,13 @@ void init_devsys(const rbsog_params& p, int n, DevSys& s)
     s.thermo_c = thermo ? p.dt / p.tau_t : 0.0;
     s.t_target = thermo ? p.t_target : 0.0;
     s.dof_kb = (3.0 * n - 3.0) * kBoltzmann;
+    s.thermostat = p.thermostat;
+    if (thermo) {
+        s.nh_q = s.dof_kb * p.t_target * p.tau_t * p.tau_t;
+        s.lv_c1 = std::exp(-p.dt / p.tau_t);
+        for (int t = 0; t < p.n_species; ++t)
+            s.lv_c2[t] = std::sqrt((1.0 - s.lv_c1 * s.lv_c1) * kBoltzmann * p.t_target * kAccUnit / p.species[t].mass);
+    }
     s.p_r = p.p_r;
     s.shell_stored = (p.flags & RBSOG_FLAG_SHELL_STORED) ? 1 : 0;
     s.n_chunks = 1;
@@ -849,6 +865,12 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
     c->scalars.alloc(sizeof(DeviceScalars) * R);
     HIP_OK(hipMemsetAsync(c->scalars.p, 0, sizeof(DeviceScalars) * R, c->stream));
+    {
+        Plan p1;
+        p1.sc = c->scalars.as<DeviceScalars>();
+        p1.R = R;
+        launch_init_scalars(p1, c->stream);
+    }
     {
         double4* P = c->atoms.as<double4>();
         double* d = reinterpret_cast<double*>(P + N);
@@ -1271,7 +1293,7 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
         if (any_thermostat(ctx)) {
             // velocity factor of the first step from the current velocities
             launch_kinetic(ctx->plan, ctx->stream);
-            launch_kinetic_finalize(ctx->plan, ctx->stream);
+            launch_kinetic_finalize(ctx->plan, false, ctx->stream);
         }
         const int every = ctx->prm[0].rebuild_every;
         // a list overflow inside the loop restarts the call from a snapshot
@@ -1298,7 +1320,7 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
             launch_set_eval(ctx->plan, ctx->eval, ctx->stream);
             if (any_thermostat(ctx)) {
                 launch_kinetic(ctx->plan, ctx->stream);
-                launch_kinetic_finalize(ctx->plan, ctx->stream);
+                launch_kinetic_finalize(ctx->plan, false, ctx->stream);
             }
         }
     });

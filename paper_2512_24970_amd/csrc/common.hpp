@@ -16,6 +16,9 @@ constexpr int kTableSize = 1 << kTableBits;
 constexpr uint32_t kTagShell = 2u;
 constexpr uint32_t kTagKmode = 3u;
 constexpr uint32_t kTagShellBuild = 5u;  // shell batch drawn once per list build
+constexpr uint32_t kTagLangevin = 6u;    // Langevin noise, counter word 1 = step number
+// thermostat kinds (rbsog_params.thermostat)
+constexpr int kThermoBerendsen = 0, kThermoNoseHoover = 1, kThermoLangevin = 2;
 constexpr int kMaxListChunks = 64;      // launches a list build may be cut into
 constexpr double kPi = 3.14159265358979323846;
 // 1 eV/(Angstrom*amu) in Angstrom/ps^2
@@ -135,6 +138,8 @@ struct DeviceScalars {
     int32_t max_core;     // largest core / candidate list seen (true sizes)
     int32_t max_cand;
     double vscale;        // thermostat velocity factor for the next step
+    double nh_x, nh_v;    // Nose-Hoover variable and its velocity
+    double vpend;         // factor the stored velocities still owe (Nose-Hoover half step at a step's end)
 };
 
 }  // namespace rbsog

@@ -156,9 +156,47 @@ __global__ void k_set_eval(DeviceScalars* sc, int R, uint64_t eval)
 {
     for (int r = threadIdx.x; r < R; r += blockDim.x) sc[r].eval = eval;
 }
-__global__ void k_bump_eval(DeviceScalars* sc, int R)
+// Nose-Hoover half step on the thermostat variables (Trotter splitting,
+// one variable): from the kinetic energy K of the velocities it acts on,
+// returns the velocity factor and leaves K scaled by its square.
+__device__ inline double nh_half(const DevSys& s, DeviceScalars* sc, double& K)
 {
-    for (int r = threadIdx.x; r < R; r += blockDim.x) sc[r].eval += 1;
+    const double gkt = s.dof_kb * s.t_target;
+    double v = sc->nh_v + 0.25 * s.dt * (2.0 * K - gkt) / s.nh_q;
+    const double f = exp(-0.5 * s.dt * v);
+    K = K * (f * f);
+    sc->nh_x += 0.5 * s.dt * v;
+    sc->nh_v = v + 0.25 * s.dt * (2.0 * K - gkt) / s.nh_q;
+    return f;
+}
+
+__device__ inline bool is_nh(const DevSys& s) { return s.thermo_c > 0.0 && s.thermostat == kThermoNoseHoover; }
+
+// Start of a step: the Philox counter moves on; Nose-Hoover takes its
+// opening half step from the kinetic energy at the end of the last one and
+// hands the opening kick the product of both pending velocity factors.
+__global__ void k_step_begin(const DevSys* __restrict__ sys, int R)
+{
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        const DevSys s = global_view(sys[r]);
+        DeviceScalars* sc = s.sc;
+        sc->eval += 1;
+        if (is_nh(s)) {
+            double K = sc->kinetic;
+            const double f = nh_half(s, sc, K);
+            sc->kinetic = K;
+            sc->vscale = sc->vpend * f;
+            sc->vpend = 1.0;
+        }
+    }
+}
+
+__global__ void k_init_scalars(DeviceScalars* sc, int R)
+{
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        sc[r].vscale = 1.0;
+        sc[r].vpend = 1.0;
+    }
 }
 // Closes a build: lower the flag, restart the displacement tracking.  A
 // build that overflowed is discarded and built again, so it takes no number.
@@ -1566,7 +1604,7 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
     if (ENERGY) wave_partial(ke, i, s.n, s.kin_part, 1, 0);
 }
 
-__global__ __launch_bounds__(1024) void k_kinetic_finalize(const DevSys* __restrict__ sys)
+__global__ __launch_bounds__(1024) void k_kinetic_finalize(const DevSys* __restrict__ sys, int step_end)
 {
     const DevSys s = global_view(sys[blockIdx.x]);
     const double* part = s.kin_part;
@@ -1577,15 +1615,27 @@ __global__ __launch_bounds__(1024) void k_kinetic_finalize(const DevSys* __restr
     const double t = block_sum(v, red);
     if (threadIdx.x == 0) {
         const double ke = t / kAccUnit;
-        s.sc->kinetic = ke;
-        double f = 1.0;
-        if (s.thermo_c > 0.0 && ke > 0.0) {
-            // Berendsen: lambda^2 = 1 + (dt/tau)(T0/T - 1)
-            const double T = 2.0 * ke / s.dof_kb;
-            const double l2 = 1.0 + s.thermo_c * (s.t_target / T - 1.0);
-            f = l2 > 0.0 ? sqrt(l2) : 0.0;
+        if (is_nh(s)) {
+            if (step_end) {
+                // closing half step; the velocities owe its factor until the
+                // next opening kick (exports apply it)
+                double K = ke;
+                s.sc->vpend = nh_half(s, s.sc, K);
+                s.sc->kinetic = K;
+            } else {
+                s.sc->kinetic = ke * (s.sc->vpend * s.sc->vpend);
+            }
+        } else {
+            s.sc->kinetic = ke;
+            double f = 1.0;
+            if (s.thermo_c > 0.0 && s.thermostat == kThermoBerendsen && ke > 0.0) {
+                // Berendsen: lambda^2 = 1 + (dt/tau)(T0/T - 1)
+                const double T = 2.0 * ke / s.dof_kb;
+                const double l2 = 1.0 + s.thermo_c * (s.t_target / T - 1.0);
+                f = l2 > 0.0 ? sqrt(l2) : 0.0;
+            }
+            s.sc->vscale = f;
         }
-        s.sc->vscale = f;
     }
 }
 
@@ -1611,20 +1661,45 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
     __shared__ double red[4];
     const int i = lb * blockDim.x + threadIdx.x;
     double d2 = 0.0;
-    const double lam = s.thermo_c > 0.0 ? s.sc->vscale : 1.0;
+    const bool langevin = s.thermo_c > 0.0 && s.thermostat == kThermoLangevin;
+    const double lam = (s.thermo_c > 0.0 && !langevin) ? s.sc->vscale : 1.0;
     if (i < s.n) {
         const int ti = s.type[i];
         const double a = 0.5 * s.dt * s.spc->inv_mass_acc[ti];
-        const double vx = lam * s.vx[i] + a * s.fx[i];
-        const double vy = lam * s.vy[i] + a * s.fy[i];
-        const double vz = lam * s.vz[i] + a * s.fz[i];
+        double vx = lam * s.vx[i] + a * s.fx[i];
+        double vy = lam * s.vy[i] + a * s.fy[i];
+        double vz = lam * s.vz[i] + a * s.fz[i];
+        const double4 P = s.p[i];
+        double px, py, pz;
+        if (langevin) {
+            // BAOAB: half drift, Ornstein-Uhlenbeck velocity update with
+            // Box-Muller normals of the stream (id, step, kTagLangevin), half drift
+            PhiloxStream st(s.seed, (uint32_t)s.id[i], (uint32_t)s.sc->eval, kTagLangevin, s.replica);
+            const double u1 = st.uniform(), u2 = st.uniform(), u3 = st.uniform(), u4 = st.uniform();
+            const double r = sqrt(-2.0 * log(1.0 - u1));
+            const double z0 = r * cos(2.0 * kPi * u2), z1 = r * sin(2.0 * kPi * u2);
+            const double z2 = sqrt(-2.0 * log(1.0 - u3)) * cos(2.0 * kPi * u4);
+            const double h = 0.5 * s.dt, c1 = s.lv_c1, c2 = s.lv_c2[ti];
+            px = P.x + h * vx;
+            py = P.y + h * vy;
+            pz = P.z + h * vz;
+            vx = c1 * vx + c2 * z0;
+            vy = c1 * vy + c2 * z1;
+            vz = c1 * vz + c2 * z2;
+            px = px + h * vx;
+            py = py + h * vy;
+            pz = pz + h * vz;
+        } else {
+            px = P.x + s.dt * vx;
+            py = P.y + s.dt * vy;
+            pz = P.z + s.dt * vz;
+        }
         s.vx[i] = vx;
         s.vy[i] = vy;
         s.vz[i] = vz;
-        const double4 P = s.p[i];
-        const double x = wrap_coord(P.x + s.dt * vx, s.L[0], s.invL[0]);
-        const double y = wrap_coord(P.y + s.dt * vy, s.L[1], s.invL[1]);
-        const double z = wrap_coord(P.z + s.dt * vz, s.L[2], s.invL[2]);
+        const double x = wrap_coord(px, s.L[0], s.invL[0]);
+        const double y = wrap_coord(py, s.L[1], s.invL[1]);
+        const double z = wrap_coord(pz, s.L[2], s.invL[2]);
         s.p[i] = make_double4(x, y, z, P.w);
         const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
         const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
@@ -1656,9 +1731,11 @@ __global__ void k_to_user3(RB_ARGS, int field, double* out)
     const double* ay = field == 0 ? s.fy : (field == 1 ? s.fsy : s.vy);
     const double* az = field == 0 ? s.fz : (field == 1 ? s.fsz : s.vz);
     const size_t u = ((size_t)s.user_off + s.id[i]) * 3;
-    out[u] = ax[i];
-    out[u + 1] = ay[i];
-    out[u + 2] = az[i];
+    // velocities may still owe a Nose-Hoover factor (applied at the next kick)
+    const double f = field == 2 ? s.sc->vpend : 1.0;
+    out[u] = f * ax[i];
+    out[u + 1] = f * ay[i];
+    out[u + 2] = f * az[i];
 }
 
 __global__ void k_pos_to_user(RB_ARGS, double* out)
@@ -1728,7 +1805,8 @@ SogCoefF to_f32(const SogCoef& g)
 
 // ---------------------------------------------------------------- launchers
 void launch_set_eval(const Plan& P, uint64_t eval, hipStream_t st) { k_set_eval<<<1, 64, 0, st>>>(P.sc, P.R, eval); }
-void launch_bump_eval(const Plan& P, hipStream_t st) { k_bump_eval<<<1, 64, 0, st>>>(P.sc, P.R); }
+void launch_step_begin(const Plan& P, hipStream_t st) { k_step_begin<<<1, 64, 0, st>>>(P.sys, P.R); }
+void launch_init_scalars(const Plan& P, hipStream_t st) { k_init_scalars<<<1, 64, 0, st>>>(P.sc, P.R); }
 void launch_clear_flags(const Plan& P, hipStream_t st) { k_clear_flags<<<1, 64, 0, st>>>(P.sc, P.R); }
 
 #define RB_MAP(shape) P.sys, P.shape.map
@@ -1854,9 +1932,9 @@ void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_
 #undef RB_KF
 }
 
-void launch_kinetic_finalize(const Plan& P, hipStream_t st)
+void launch_kinetic_finalize(const Plan& P, bool step_end, hipStream_t st)
 {
-    if (P.R > 0) k_kinetic_finalize<<<P.R, 1024, 0, st>>>(P.sys);
+    if (P.R > 0) k_kinetic_finalize<<<P.R, 1024, 0, st>>>(P.sys, step_end ? 1 : 0);
 }
 
 void launch_kinetic(const Plan& P, hipStream_t st)

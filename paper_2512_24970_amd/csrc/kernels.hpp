@@ -43,6 +43,10 @@ struct DevSys {
     double thermo_c;       // dt / tau_t (0: no thermostat)
     double t_target;
     double dof_kb;         // (3N - 3) k_B
+    int thermostat;        // kThermo* (meaningful when thermo_c > 0)
+    double nh_q;           // Nose-Hoover mass g k_B T0 tau^2
+    double lv_c1;          // Langevin exp(-dt / tau)
+    double lv_c2[kMaxSpecies];  // Langevin sqrt((1 - c1^2) k_B T0 / m) per species, A/ps
     int p_r;
     int cap_core, cap_cand;
     // Memory form of the list (shell_stored): the shell batch is drawn at the
@@ -143,7 +147,10 @@ struct Plan {
 };
 
 void launch_set_eval(const Plan& P, uint64_t eval, hipStream_t st);
-void launch_bump_eval(const Plan& P, hipStream_t st);
+// start of a step: eval index + 1, and the opening Nose-Hoover half step
+void launch_step_begin(const Plan& P, hipStream_t st);
+// scalars that start at 1 (velocity factors), after the scalars are zeroed
+void launch_init_scalars(const Plan& P, hipStream_t st);
 void launch_clear_flags(const Plan& P, hipStream_t st);
 
 // cell sort + lists; with gate the kernels of a system run only when its
@@ -158,8 +165,10 @@ void launch_rho_finalize(const Plan& P, hipStream_t st);
 void launch_finalize(const Plan& P, hipStream_t st);
 void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st);
 // kinetic energy from the partials; with a thermostat also the velocity
-// factor of the next step
-void launch_kinetic_finalize(const Plan& P, hipStream_t st);
+// factor of the next step.  step_end: the partials are those of a step's
+// closing kick (the Nose-Hoover closing half step is taken), else a
+// measurement of the current velocities
+void launch_kinetic_finalize(const Plan& P, bool step_end, hipStream_t st);
 // kinetic-energy partials of the current velocities
 void launch_kinetic(const Plan& P, hipStream_t st);
 

@@ -20,6 +20,7 @@ MAX_SOG = 512
 FP64 = 0
 MIXED = 1
 FLAG_SHELL_STORED = 1  # shell batch drawn at the list build and kept (memory form)
+THERMOSTATS = {"berendsen": 0, "nose_hoover": 1, "langevin": 2}
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_OOM", -5: "E_LIST_STALE",
           -6: "E_NONNEUTRAL", -7: "E_BOX", -8: "E_NONFINITE", -9: "E_CAPACITY"}
@@ -48,7 +49,7 @@ class Params(C.Structure):
         ("p_r", C.c_int32), ("p_f", C.c_int32), ("sog_eps", C.c_double), ("dt", C.c_double),
         ("rebuild_every", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
         ("replica", C.c_uint32), ("flags", C.c_uint32), ("coulomb_k", C.c_double),
-        ("t_target", C.c_double), ("tau_t", C.c_double),
+        ("t_target", C.c_double), ("tau_t", C.c_double), ("thermostat", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -62,7 +63,8 @@ class Tuning(C.Structure):
 class Energy(C.Structure):
     _fields_ = [("u_core", C.c_double), ("u_shell", C.c_double), ("u_kspace", C.c_double),
                 ("u_self", C.c_double), ("u_total", C.c_double), ("kinetic", C.c_double),
-                ("p_corr", C.c_double * 3), ("max_disp", C.c_double), ("n_builds", C.c_int64)]
+                ("p_corr", C.c_double * 3), ("max_disp", C.c_double), ("n_builds", C.c_int64),
+                ("e_thermostat", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: (list(getattr(self, k)) if k == "p_corr" else getattr(self, k)) for k, _ in self._fields_}
@@ -159,6 +161,7 @@ def make_params(sysp: dict, precision: int = FP64, n_atoms: int | None = None) -
     p.coulomb_k = float(sysp["coulomb_k"])
     p.t_target = float(sysp.get("t_target", 0.0))
     p.tau_t = float(sysp.get("tau_t", 0.0))
+    p.thermostat = THERMOSTATS[sysp.get("thermostat", "berendsen")]
     return p
 
 
