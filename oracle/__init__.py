@@ -56,12 +56,12 @@ class Params(C.Structure):
 class Energy(C.Structure):
     _fields_ = [("u_core", C.c_double), ("u_shell", C.c_double), ("u_kspace", C.c_double),
                 ("u_self", C.c_double), ("u_total", C.c_double), ("kinetic", C.c_double),
-                ("p_corr", C.c_double * 3), ("e_thermostat", C.c_double)]
+                ("p_corr", C.c_double * 3), ("e_thermostat", C.c_double), ("virial", C.c_double * 6)]
 
     def as_dict(self) -> dict:
         return {"u_core": self.u_core, "u_shell": self.u_shell, "u_kspace": self.u_kspace,
                 "u_self": self.u_self, "u_total": self.u_total, "kinetic": self.kinetic,
-                "p_corr": list(self.p_corr), "e_thermostat": self.e_thermostat}
+                "p_corr": list(self.p_corr), "e_thermostat": self.e_thermostat, "virial": list(self.virial)}
 
 
 _lib = None
@@ -85,6 +85,7 @@ def lib():
             "orc_far": (C.c_double, [P(Params), C.c_double]),
             "orc_near": (C.c_double, [P(Params), C.c_double]),
             "orc_far_hat": (C.c_double, [P(Params), C.c_double]),
+            "orc_far_hat_g": (C.c_double, [P(Params), C.c_double]),
             "orc_kspace_S": (C.c_double, [P(Params)]),
             "orc_kmodes": (C.c_int, [P(Params), C.c_uint64, i32p, dp]),
             "orc_create": (C.c_void_p, [P(Params), C.c_int32, i32p, dp, dp]),
@@ -95,8 +96,8 @@ def lib():
             "orc_shell_ranks": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint64, i32p]),
             "orc_pair_force": (C.c_double, [P(Params), C.c_int32, C.c_int32, dp, dp]),
             "orc_forces": (C.c_int, [C.c_void_p, C.c_uint64, dp, P(Energy)]),
-            "orc_forces_short": (C.c_int, [C.c_void_p, C.c_uint64, dp, dp, dp]),
-            "orc_forces_kspace": (C.c_int, [C.c_void_p, C.c_uint64, dp, dp]),
+            "orc_forces_short": (C.c_int, [C.c_void_p, C.c_uint64, dp, dp, dp, dp]),
+            "orc_forces_kspace": (C.c_int, [C.c_void_p, C.c_uint64, dp, dp, dp]),
             "orc_rho": (None, [C.c_void_p, C.c_int32, i32p, dp]),
             "orc_vv_steps": (C.c_int, [C.c_void_p, C.c_int32, P(Energy)]),
             "orc_get_state": (None, [C.c_void_p, dp, dp, dp, P(C.c_uint64)]),
@@ -203,6 +204,11 @@ def far_hat(p: Params, k: float) -> float:
     return lib().orc_far_hat(C.byref(p), k)
 
 
+def far_hat_g(p: Params, k: float) -> float:
+    """-dF^/dk / k."""
+    return lib().orc_far_hat_g(C.byref(p), k)
+
+
 def pair_force(p: Params, ti: int, tj: int, d) -> tuple:
     """Force on i from j for displacement d = r_i - r_j, and the pair energy."""
     dd = np.ascontiguousarray(d, dtype=np.float64)
@@ -290,13 +296,25 @@ class System:
         self._ensure_lists()
         f = np.zeros((self.n, 3))
         uc, us = C.c_double(0), C.c_double(0)
-        lib().orc_forces_short(self._h, ev, _ptr(f, C.c_double), C.byref(uc), C.byref(us))
+        lib().orc_forces_short(self._h, ev, _ptr(f, C.c_double), C.byref(uc), C.byref(us), None)
         return f, uc.value, us.value
+
+    def virial_parts(self, ev: int):
+        """Virial W[6] (xx, yy, zz, xy, xz, yz) of the short-range and of the
+        k-space estimator at evaluation ev."""
+        self._ensure_lists()
+        f = np.zeros((self.n, 3))
+        uc, us, uk = C.c_double(0), C.c_double(0), C.c_double(0)
+        ws = np.zeros(6)
+        wk = np.zeros(6)
+        lib().orc_forces_short(self._h, ev, _ptr(f, C.c_double), C.byref(uc), C.byref(us), _ptr(ws, C.c_double))
+        lib().orc_forces_kspace(self._h, ev, _ptr(f, C.c_double), C.byref(uk), _ptr(wk, C.c_double))
+        return ws, wk
 
     def forces_kspace(self, ev: int):
         f = np.zeros((self.n, 3))
         uk = C.c_double(0)
-        lib().orc_forces_kspace(self._h, ev, _ptr(f, C.c_double), C.byref(uk))
+        lib().orc_forces_kspace(self._h, ev, _ptr(f, C.c_double), C.byref(uk), None)
         return f, uk.value
 
     def rho(self, m: np.ndarray) -> np.ndarray:

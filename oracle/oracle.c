@@ -291,6 +291,29 @@ double orc_far_hat(const orc_params* p, double k)
     return acc;
 }
 
+double orc_far_hat_g(const orc_params* p, double k)
+{
+    double acc = 0.0;
+    for (int m = 0; m <= p->M; ++m) {
+        double sg = sigma_m(p, m);
+        acc += pow(2.0 * ORC_PI, 1.5) * p->w[m] * sg * sg * sg * sg * sg * exp(-sg * sg * k * k / 2.0);
+    }
+    return acc;
+}
+
+/* Adds (k_e/2) e (delta_ab - g k_a k_b) to W[6] (xx, yy, zz, xy, xz, yz):
+ * the strain derivative of one mode's energy (k_e/2) coef |rho|^2, with the
+ * mode's k shrinking as the box grows (dk_a/de_ab = -k_b). */
+static void mode_virial(double ke_half_e, double g, const double k[3], double W[6])
+{
+    W[0] += ke_half_e * (1.0 - g * k[0] * k[0]);
+    W[1] += ke_half_e * (1.0 - g * k[1] * k[1]);
+    W[2] += ke_half_e * (1.0 - g * k[2] * k[2]);
+    W[3] -= ke_half_e * g * k[0] * k[1];
+    W[4] -= ke_half_e * g * k[0] * k[2];
+    W[5] -= ke_half_e * g * k[1] * k[2];
+}
+
 /* ======================================================================
  * Importance sampling of eq. (28): P(k) = k^2 F^(k) / S.
  *
@@ -751,9 +774,22 @@ double orc_pair_force(const orc_params* p, int32_t ti, int32_t tj, const double 
 
 /* Short-range force on atom i from its lists: core sum (eq. 24) plus the
  * reweighted shell batch (eq. 25).  No momentum correction. */
-static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32_t* core, int nc,
-                       const int32_t* cand, int nk, uint64_t eval, double f_out[3], double* uc, double* us)
+/* 1/2 r_ij (x) F_ij of one pair, F_ij = f r_ij the force on i from j. */
+static void pair_virial(double f, const double d[3], double W[6])
 {
+    W[0] += 0.5 * f * d[0] * d[0];
+    W[1] += 0.5 * f * d[1] * d[1];
+    W[2] += 0.5 * f * d[2] * d[2];
+    W[3] += 0.5 * f * d[0] * d[1];
+    W[4] += 0.5 * f * d[0] * d[2];
+    W[5] += 0.5 * f * d[1] * d[2];
+}
+
+static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32_t* core, int nc,
+                       const int32_t* cand, int nk, uint64_t eval, double f_out[3], double* uc, double* us,
+                       double w_out[6])
+{
+    double Wc[6] = {0, 0, 0, 0, 0, 0}, Ws[6] = {0, 0, 0, 0, 0, 0};
     double rc2 = p->r_core * p->r_core;
     double rs2 = p->r_shell * p->r_shell;
     double F[3] = {0.0, 0.0, 0.0};
@@ -769,6 +805,7 @@ static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32
         double f = pair_scalar(p, ti, c->type[j], r2, &u);
         for (int x = 0; x < 3; ++x) F[x] += f * d[x];
         Uc += 0.5 * u;
+        pair_virial(f, d, Wc);
     }
     int32_t* ranks = (int32_t*)malloc(sizeof(int32_t) * (nk > 0 ? nk : 1));
     uint32_t ctr1, tag;
@@ -786,33 +823,44 @@ static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32
         double f = pair_scalar(p, ti, c->type[j], r2, &u);
         for (int x = 0; x < 3; ++x) Fs[x] += f * d[x];
         Us += 0.5 * u;
+        pair_virial(f, d, Ws);
     }
     free(ranks);
     for (int x = 0; x < 3; ++x) f_out[x] = F[x] + wgt * Fs[x];
     *uc = Uc;
     *us = wgt * Us;
+    if (w_out)
+        for (int a = 0; a < 6; ++a) w_out[a] = Wc[a] + wgt * Ws[a];
 }
 
-int orc_forces_short(orc_ctx* c, uint64_t eval, double* force, double* u_core, double* u_shell)
+int orc_forces_short(orc_ctx* c, uint64_t eval, double* force, double* u_core, double* u_shell,
+                     double* virial)
 {
     if (!c->core_off) orc_build_lists(c);
     const orc_params* p = &c->p;
     int n = c->n;
     double* uc = (double*)calloc(n > 0 ? n : 1, sizeof(double));
     double* us = (double*)calloc(n > 0 ? n : 1, sizeof(double));
+    double* wv = (double*)calloc(6 * (n > 0 ? n : 1), sizeof(double));
 #pragma omp parallel for schedule(dynamic, 16) num_threads(ORC_NT)
     for (int i = 0; i < n; ++i) {
         short_atom(p, c, i, c->core + c->core_off[i], c->core_off[i + 1] - c->core_off[i],
                    c->cand + c->cand_off[i], c->cand_off[i + 1] - c->cand_off[i], eval, force + 3 * i, uc + i,
-                   us + i);
+                   us + i, wv + 6 * i);
     }
     double Uc = 0.0, Us = 0.0;
     for (int i = 0; i < n; ++i) {
         Uc += uc[i];
         Us += us[i];
     }
+    if (virial) {
+        for (int a = 0; a < 6; ++a) virial[a] = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < 6; ++a) virial[a] += wv[6 * i + a];
+    }
     free(uc);
     free(us);
+    free(wv);
     if (u_core) *u_core = Uc;
     if (u_shell) *u_shell = Us;
     return 0;
@@ -835,7 +883,7 @@ int orc_forces_short_atoms(const orc_ctx* c, uint64_t eval, int32_t n_sel, const
         int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (nk + 1));
         scan_atom(c, i, core, &nc, cand, &nk, 0);
         double uc, us;
-        short_atom(p, c, i, core, nc, cand, nk, eval, force + 3 * a, &uc, &us);
+        short_atom(p, c, i, core, nc, cand, nk, eval, force + 3 * a, &uc, &us, NULL);
         free(core);
         free(cand);
     }
@@ -894,7 +942,7 @@ static double box_volume(const orc_params* p) { return p->box[0] * p->box[1] * p
 
 /* Full k-sum of eq. (23) over every k != 0 whose narrowest-Gaussian factor
  * exp(-s^2 k^2 / 2) is at least e^-45. */
-static int kspace_full(orc_ctx* c, double* force, double* u_k)
+static int kspace_full(orc_ctx* c, double* force, double* u_k, double* virial)
 {
     const orc_params* p = &c->p;
     int nmax[3];
@@ -933,6 +981,17 @@ static int kspace_full(orc_ctx* c, double* force, double* u_k)
     double U = 0.0;
     for (long t = 0; t < cnt; ++t) U += fh[t] * (rho[2 * t] * rho[2 * t] + rho[2 * t + 1] * rho[2 * t + 1]) / (2.0 * V);
     *u_k = p->coulomb_k * U;
+    if (virial) {
+        /* W_ab = sum_k (k_e |rho|^2 / 2V) (F^ delta_ab - G k_a k_b) */
+        for (int a = 0; a < 6; ++a) virial[a] = 0.0;
+        for (long t = 0; t < cnt; ++t) {
+            double k[3];
+            for (int a = 0; a < 3; ++a) k[a] = 2.0 * ORC_PI * (double)m[3 * t + a] / p->box[a];
+            double kk = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+            double e = fh[t] * (rho[2 * t] * rho[2 * t] + rho[2 * t + 1] * rho[2 * t + 1]) / V;
+            mode_virial(0.5 * p->coulomb_k * e, orc_far_hat_g(p, kk) / fh[t], k, virial);
+        }
+    }
     /* eq. (23): F_i = -sum_k (q_i k / V) F^(k) Im(e^{-ik.r_i} rho(k)) */
 #pragma omp parallel for schedule(static) num_threads(ORC_NT)
     for (int i = 0; i < c->n; ++i) {
@@ -954,10 +1013,10 @@ static int kspace_full(orc_ctx* c, double* force, double* u_k)
     return 0;
 }
 
-int orc_forces_kspace(orc_ctx* c, uint64_t eval, double* force, double* u_k)
+int orc_forces_kspace(orc_ctx* c, uint64_t eval, double* force, double* u_k, double* virial)
 {
     const orc_params* p = &c->p;
-    if (p->p_f <= 0) return kspace_full(c, force, u_k);
+    if (p->p_f <= 0) return kspace_full(c, force, u_k, virial);
     if (!c->have_kt) {
         ktab_build(p, &c->kt);
         c->have_kt = 1;
@@ -981,6 +1040,19 @@ int orc_forces_kspace(orc_ctx* c, uint64_t eval, double* force, double* u_k)
         U += (rho[2 * q] * rho[2 * q] + rho[2 * q + 1] * rho[2 * q + 1]) / k2;
     }
     *u_k = p->coulomb_k * S / (2.0 * V * (double)P) * U;
+    if (virial) {
+        /* importance-sampled estimator of the full-sum virial: each mode's
+         * term divided by P_F P(k) = P_F k^2 F^(k) / S */
+        for (int a = 0; a < 6; ++a) virial[a] = 0.0;
+        for (int q = 0; q < P; ++q) {
+            double k[3];
+            for (int a = 0; a < 3; ++a) k[a] = 2.0 * ORC_PI * (double)m[3 * q + a] / p->box[a];
+            double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            double kk = sqrt(k2);
+            double e = S / ((double)P * V * k2) * (rho[2 * q] * rho[2 * q] + rho[2 * q + 1] * rho[2 * q + 1]);
+            mode_virial(0.5 * p->coulomb_k * e, orc_far_hat_g(p, kk) / orc_far_hat(p, kk), k, virial);
+        }
+    }
     free(m);
     free(rho);
     return 0;
@@ -1011,8 +1083,8 @@ int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
 {
     int n = c->n;
     double* fk = (double*)calloc(3 * (n > 0 ? n : 1), sizeof(double));
-    double uc = 0.0, us = 0.0, uk = 0.0;
-    orc_forces_short(c, eval, force, &uc, &us);
+    double uc = 0.0, us = 0.0, uk = 0.0, ws[6], wk[6] = {0, 0, 0, 0, 0, 0};
+    orc_forces_short(c, eval, force, &uc, &us, ws);
     /* eq. (26)-(27): subtract the mean short-range force */
     double corr[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < n; ++i)
@@ -1020,7 +1092,7 @@ int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
     for (int a = 0; a < 3; ++a) corr[a] = n > 0 ? corr[a] / n : 0.0;
     for (int i = 0; i < n; ++i)
         for (int a = 0; a < 3; ++a) force[3 * i + a] -= corr[a];
-    if (n > 0) orc_forces_kspace(c, eval, fk, &uk);
+    if (n > 0) orc_forces_kspace(c, eval, fk, &uk, wk);
     for (int i = 0; i < 3 * n; ++i) force[i] += fk[i];
     free(fk);
     memcpy(c->frc, force, sizeof(double) * 3 * n);
@@ -1033,6 +1105,7 @@ int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
         e->u_total = uc + us + uk - e->u_self;
         e->kinetic = kinetic(c);
         for (int a = 0; a < 3; ++a) e->p_corr[a] = corr[a];
+        for (int a = 0; a < 6; ++a) e->virial[a] = ws[a] + wk[a];
     }
     return 0;
 }

@@ -77,6 +77,9 @@ typedef struct {
     double u_core, u_shell, u_kspace, u_self, u_total, kinetic;
     double p_corr[3];       /* momentum correction that was subtracted, eq. (26) */
     double e_thermostat;    /* Nose-Hoover: Q v_xi^2 / 2 + g k_B T0 xi (else 0) */
+    double virial[6];       /* W_ab = -dU/de_ab (xx, yy, zz, xy, xz, yz), eV; pressure
+                               tensor V P_ab = sum m v_a v_b + W_ab.  Excludes the
+                               momentum correction (a uniform force of zero mean). */
 } orc_energy;
 
 /* ---- Philox4x32-10 (Salmon et al., SC'11).  Pinned: published test vectors. */
@@ -140,8 +143,17 @@ double orc_pair_force(const orc_params* p, int32_t ti, int32_t tj, const double 
 /* Full IRBSOG force on every atom (eqs. 15, 24-27, 29).  force[N][3]. */
 int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e);
 /* Parts of the above: short range (before the momentum correction) and k-space. */
-int orc_forces_short(orc_ctx* c, uint64_t eval, double* force, double* u_core, double* u_shell);
-int orc_forces_kspace(orc_ctx* c, uint64_t eval, double* force, double* u_k);
+/* virial (may be NULL): W[6] of the short-range estimator, 1/2 sum_i sum_j
+ * r_ij (x) F_ij over the core pairs plus N_shell/P_R times the same over the
+ * batch (eqs. 24-25). */
+int orc_forces_short(orc_ctx* c, uint64_t eval, double* force, double* u_core, double* u_shell,
+                     double* virial);
+/* virial (may be NULL): W[6] of the k-space part, sum over modes of
+ * (k_e/2) e_k (delta_ab - g(k) k_a k_b) with e_k |rho|^2 times the mode's
+ * coefficient (eq. 23 or 29) and g(k) = G(k)/F^(k), G = -F^'(k)/k. */
+int orc_forces_kspace(orc_ctx* c, uint64_t eval, double* force, double* u_k, double* virial);
+/* G(k) = -dF^/dk / k = sum_m (2 pi)^{3/2} w_m sigma_m^5 exp(-sigma_m^2 k^2 / 2). */
+double orc_far_hat_g(const orc_params* p, double k);
 /* Structure factors rho(k) (eq. 22) for the given integer modes. */
 void orc_rho(const orc_ctx* c, int32_t n_modes, const int32_t* m, double* rho /*[n][2]*/);
 /* Velocity-Verlet steps; lists are rebuilt when the step number is a multiple

@@ -701,3 +701,129 @@ def test_thermostats_hold_the_melt_at_t0(kind, tau):
         e = s.vv_steps(1)
         Ts.append(2 * e["kinetic"] / ((3 * n - 3) * W.KB))
     assert abs(np.mean(Ts) - T0) / T0 < 0.06
+
+
+# --------------------------------------------------------------------------- virial
+def test_far_hat_g_is_minus_derivative_over_k():
+    """G(k) = -F^'(k)/k, by central differences of eq. (21)."""
+    p, _ = _p()
+    for k in (0.05, 0.3, 0.8, 1.5):
+        h = 1e-5
+        d = (O.far_hat(p, k + h) - O.far_hat(p, k - h)) / (2 * h)
+        assert O.far_hat_g(p, k) == pytest.approx(-d / k, rel=1e-7)
+
+
+def _strained_energy(cfg, sysp, axis, eps):
+    pos = np.array(cfg["pos"], dtype=float)
+    pos[:, axis] *= 1.0 + eps
+    box = list(sysp["box"])
+    box[axis] *= 1.0 + eps
+    s = O.System(dict(sysp, box=box), cfg["types"], pos, cfg["vel"])
+    _, e = s.forces(0)
+    s.close()
+    return e["u_total"]
+
+
+def _pair_distances(cfg, box):
+    pos = np.array(cfg["pos"], dtype=float)
+    L = np.array(box)
+    d = pos[:, None, :] - pos[None, :, :]
+    d -= L * np.rint(d / L)
+    r = np.sqrt((d ** 2).sum(-1))
+    return r[np.triu_indices(len(pos), 1)]
+
+
+@pytest.mark.parametrize("coulomb_only", [True, False])
+def test_virial_diagonal_is_minus_axial_strain_derivative(coulomb_only):
+    """W_aa = -dU/de_aa: stretch positions and box along one axis and
+    difference the energy (deterministic force: every shell candidate, full
+    k-sum).  With the BMH terms on, the strain moves no pair across their
+    unshifted cut at r_shell (checked)."""
+    cfg = W.config("nacl_small")
+    sysp = _deterministic(cfg, coulomb_only=coulomb_only)
+    eps = 1e-7
+    r = _pair_distances(cfg, sysp["box"])
+    assert np.abs(r - sysp["r_shell"]).min() > 1e3 * eps * max(sysp["box"])
+    s = O.System(sysp, cfg["types"], cfg["pos"], cfg["vel"])
+    _, e = s.forces(0)
+    vir = e["virial"]
+    for a in range(3):
+        fd = -(_strained_energy(cfg, sysp, a, eps) - _strained_energy(cfg, sysp, a, -eps)) / (2 * eps)
+        assert vir[a] == pytest.approx(fd, rel=2e-5, abs=2e-4), a
+
+
+def test_virial_rotates_as_a_tensor():
+    """A quarter turn about z maps the cubic box onto itself: the virial of
+    the turned configuration is R W R^T (diagonal entries swap, xy and xz
+    change sign or place) — pins the off-diagonal entries."""
+    cfg = W.config("nacl_small")
+    sysp = _deterministic(cfg)
+    L = sysp["box"][0]
+    pos = np.array(cfg["pos"], dtype=float)
+    turned = np.stack([pos[:, 1], (L - pos[:, 0]) % L, pos[:, 2]], axis=1)
+    vel = np.array(cfg["vel"], dtype=float)
+    vir = O.System(sysp, cfg["types"], pos, vel).forces(0)[1]["virial"]
+    Wt = O.System(sysp, cfg["types"], turned, vel).forces(0)[1]["virial"]
+    xx, yy, zz, xy, xz, yz = vir
+    want = [yy, xx, zz, -xy, yz, -xz]
+    scale = max(abs(v) for v in vir)
+    assert np.allclose(Wt, want, rtol=0, atol=1e-9 * scale)
+    assert abs(xy) > 1e-3 * scale and abs(xz) > 1e-3 * scale
+
+
+def test_virial_estimators_unbiased():
+    """Over independent shell batches and mode batches the short-range and
+    k-space virial estimators average to the deterministic values (every
+    candidate; full k-sum of eq. (23)) at the same positions."""
+    cfg = W.config("nacl_small")
+    det = O.System(_deterministic(cfg), cfg["types"], cfg["pos"], cfg["vel"])
+    ws_exact, wk_exact = det.virial_parts(0)
+    s = O.System(cfg["sys"], cfg["types"], cfg["pos"], cfg["vel"])
+    K = 1500
+    ws = np.zeros((K, 6))
+    wk = np.zeros((K, 6))
+    for ev in range(K):
+        ws[ev], wk[ev] = s.virial_parts(ev)
+    for est, exact in ((ws, ws_exact), (wk, wk_exact)):
+        se = est.std(0) / math.sqrt(K)
+        assert np.all(np.abs(est.mean(0) - exact) < 5 * se + 1e-12), (est.mean(0), exact, se)
+
+
+@pytest.mark.parametrize("plane", [(0, 1), (0, 2), (1, 2)])
+def test_virial_off_diagonal_from_a_rotated_supercell(plane):
+    """A cubic periodic system is also periodic on the lattice spanned by
+    L(e_a + e_b), L(e_b - e_a) and L e_c, which is orthorhombic in a frame
+    turned by 45 degrees in the (a, b) plane.  The oracle's virial of that
+    2N-atom supercell, computed from scratch in the turned frame, must be
+    2 R W R^T; its (a, a) entry fixes W_ab = (W_aa + W_bb)/2 - W'_aa/2,
+    sign included, and its energy is 2U."""
+    a, b = plane
+    c3 = 3 - a - b
+    cfg = W.config("nacl_small")
+    sysp = _deterministic(cfg)
+    L = sysp["box"][0]
+    pos = np.array(cfg["pos"], dtype=float)
+    vel = np.array(cfg["vel"], dtype=float)
+    s = O.System(sysp, cfg["types"], pos, vel)
+    _, e = s.forces(0)
+    vir = dict(zip(["00", "11", "22", "01", "02", "12"], e["virial"]))
+    shift = np.zeros(3)
+    shift[a] = L
+    big = np.concatenate([pos, pos + shift])
+    cs = 1 / math.sqrt(2)
+    turned = big.copy()
+    turned[:, a] = cs * big[:, a] - cs * big[:, b]
+    turned[:, b] = cs * big[:, a] + cs * big[:, b]
+    box = [0.0, 0.0, 0.0]
+    box[a] = box[b] = math.sqrt(2) * L
+    box[c3] = L
+    turned = np.mod(turned, np.array(box))
+    s2 = O.System(dict(sysp, box=box), np.concatenate([cfg["types"], cfg["types"]]), turned,
+                  np.concatenate([vel, vel]))
+    _, e2 = s2.forces(0)
+    assert e2["u_total"] == pytest.approx(2 * e["u_total"], rel=1e-10)
+    w_ab = vir[f"{a}{b}"]
+    w_aa2 = e2["virial"][a]
+    assert w_aa2 / 2 == pytest.approx((vir[f"{a}{a}"] + vir[f"{b}{b}"]) / 2 - w_ab,
+                                      rel=1e-8, abs=1e-8 * abs(vir["00"]))
+    assert abs(w_ab) > 1e-4 * abs(vir["00"])
