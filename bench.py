@@ -58,7 +58,8 @@ def _log(msg: str) -> None:
 TUNING_KEYS = ("pair_block", "pair_ku", "rho_mpl", "kf_block")
 
 
-def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto"):
+def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto", thermostat: str = "berendsen",
+            tau: float | None = None):
     import torch
     from paper_2512_24970_amd import rbsog as R
     dev = torch.device("cuda", 0)
@@ -69,7 +70,8 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto"):
     prec = R.MIXED if precision == "mixed" else R.FP64
     # the estimator's noise heats an NVE run at this size by several per cent
     # per step; the paper runs NVT, here a Berendsen thermostat with tau = dt
-    sysp = dict(cfg["sys"], t_target=cfg["T"], tau_t=cfg["sys"]["dt"])
+    sysp = dict(cfg["sys"], t_target=cfg["T"], tau_t=cfg["sys"]["dt"] if tau is None else tau,
+                thermostat=thermostat)
     p = R.make_params(sysp, prec, n_atoms=len(cfg["types"]))
     ctx.rbsog_set_system(p, torch.as_tensor(cfg["types"], device=dev), torch.as_tensor(cfg["pos"], device=dev),
                          torch.as_tensor(cfg["vel"], device=dev))
@@ -304,6 +306,8 @@ def main() -> int:
     ap.add_argument("--stored", type=int, default=1,
                     help="1: also time the memory form of the list (shell batch drawn at the build) "
                          "on the 1e6-ion workload and, with --large-steps, on the 5e6-ion melt")
+    ap.add_argument("--thermo-steps", type=int, default=30,
+                    help="timed steps of the Nose-Hoover and Langevin legs on the main workload (0: skip)")
     ap.add_argument("--tuning", default="auto",
                     help="launch shapes of the single-system runs: auto (autotuned) or "
                          "pair_block,pair_ku,rho_mpl,kf_block")
@@ -396,6 +400,15 @@ def main() -> int:
         line["stored"] = stored_leg(cfg, args.steps, args.workload)
         if args.large_steps > 0:
             line["stored"]["large"] = stored_leg(big, args.large_steps, "nacl_5m")
+    if args.thermo_steps > 0:
+        # the other thermostats on the main workload (mixed form), tau = 10 fs
+        line["thermostats"] = {}
+        for kind in ("nose_hoover", "langevin"):
+            rt = run_gpu(cfg, "mixed", args.thermo_steps, args.warmup, "auto", kind, 0.01)
+            line["thermostats"][kind] = {"tau_ps": 0.01, "value": rt["value"], "ms_per_step": rt["ms_per_step"],
+                                         "steps": args.thermo_steps, "T_end_K": round(rt["T_end"], 1),
+                                         "phases_ms_per_step": {k: round(v[0] / args.thermo_steps, 4)
+                                                                for k, v in rt["phases"].items()}}
     if args.cpu_sample > 0:
         _log(f"[bench] cpu baseline: oracle on {args.cpu_sample} atoms")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)

@@ -136,6 +136,14 @@ typedef struct {
     double max_disp;  /* largest displacement since the last list build */
     int64_t n_builds; /* list builds since the system was set */
     double e_thermostat; /* Nose-Hoover: Q v_xi^2 / 2 + g k_B t_target xi; else 0 */
+    double virial[6];    /* W_ab = -dU/de_ab (xx, yy, zz, xy, xz, yz), eV, with positions and box
+                            strained together: half the sum of r_ij (x) F_ij over core pairs plus
+                            N_shell/P_R times the same over the shell batch (eqs. 24-25), and per
+                            k-space mode (k_e/2) e_k (delta_ab - g(k) k_a k_b) with e_k the mode's
+                            energy weight (eq. 23 or 29) and g = -F^'(k)/(k F^(k)) (eq. 21), so the
+                            sampled form is unbiased for the full sum.  The momentum correction
+                            (eq. 26) is not included.  Pressure tensor: P_ab V = sum_i m v_a v_b
+                            + W_ab. */
 } rbsog_energy;
 
 /* Library version string. */

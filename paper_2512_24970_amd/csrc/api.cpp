@@ -98,7 +98,7 @@ struct rbsog_ctx {
     // candidate scratch over a chunk's expected atom count
     int list_chunks = 8;
     double row_slack = 1.25;
-    DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, kin_part, export_tmp, snap;
+    DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, kin_part, export_tmp, snap, sogk;
 
     // phase timing
     bool profiling = false;
@@ -550,7 +550,7 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     c->end();
     HIP_OK(hipStreamWaitEvent(st, c->ev_join, 0));
     c->begin(RBSOG_PHASE_REDUCE);
-    launch_finalize(P, st);
+    launch_finalize(P, energy, st);
     c->end();
     c->begin(RBSOG_PHASE_KFORCE);
     launch_kforce(P, c->mixed, kick, ke, st);
@@ -571,6 +571,7 @@ void fill_energy(rbsog_ctx* c, const std::vector<DeviceScalars>& hv, rbsog_energ
         for (int a = 0; a < 3; ++a) e[r].p_corr[a] = h.p_corr[a];
         e[r].max_disp = std::sqrt(h.max_disp2);
         e[r].n_builds = h.n_builds;
+        for (int a = 0; a < 6; ++a) e[r].virial[a] = h.virial[a];
         const DevSys& s = c->hs[r];
         e[r].e_thermostat = (s.thermo_c > 0.0 && s.thermostat == RBSOG_THERMO_NOSE_HOOVER)
                                 ? 0.5 * s.nh_q * h.nh_v * h.nh_v + s.dof_kb * s.t_target * h.nh_x
@@ -681,7 +682,7 @@ void autotune(rbsog_ctx* c, int reps)
     }
     try_shape(best);
     launch_rho_finalize(c->plan, st);
-    launch_finalize(c->plan, st);
+    launch_finalize(c->plan, false, st);
     tb = 1e300;
     for (int bs : {64, 128, 256}) {
         Tuning t = best;
@@ -862,6 +863,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     size_t n_waves = 0;
     for (const auto& s : c->hs) n_waves += blocks_for(s.n, 64);
     c->pair_part.alloc(sizeof(double) * kPairPart * std::max<size_t>(1, n_waves));
+    HIP_OK(hipMemsetAsync(c->pair_part.p, 0, c->pair_part.bytes, c->stream));
     c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
     c->scalars.alloc(sizeof(DeviceScalars) * R);
     HIP_OK(hipMemsetAsync(c->scalars.p, 0, sizeof(DeviceScalars) * R, c->stream));
@@ -975,6 +977,13 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     }
     c->ktab.alloc(sizeof(double) * table.size());
     HIP_OK(hipMemcpy(c->ktab.p, table.data(), sizeof(double) * table.size(), hipMemcpyHostToDevice));
+    // terms of F^(k) for the k-space virial (shared)
+    std::vector<double> sog_c, sog_s2;
+    sog_kspace_terms(c->sog, &sog_c, &sog_s2);
+    c->sogk.alloc(sizeof(double) * 2 * sog_c.size());
+    HIP_OK(hipMemcpy(c->sogk.p, sog_c.data(), sizeof(double) * sog_c.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->sogk.as<double>() + sog_c.size(), sog_s2.data(), sizeof(double) * sog_s2.size(),
+                     hipMemcpyHostToDevice));
     std::vector<std::vector<int32_t>> em(R);
     std::vector<std::vector<double>> ecoef(R);
     size_t cdf_doubles = 0, cdf_ints = 0, n_modes_all = 0, rho_part_all = 0;
@@ -983,6 +992,9 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
         KDev& k = c->hk[r];
         k = KDev{};
         k.table = c->ktab.as<double>();
+        k.n_sog = (int)sog_c.size();
+        k.sog_c = c->sogk.as<double>();
+        k.sog_s2 = c->sogk.as<double>() + sog_c.size();
         const double V = p.box[0] * p.box[1] * p.box[2];
         if (p.p_f > 0) {
             build_ktables(c->sog, p.box, &c->kt[r]);

@@ -140,6 +140,7 @@ struct DeviceScalars {
     double vscale;        // thermostat velocity factor for the next step
     double nh_x, nh_v;    // Nose-Hoover variable and its velocity
     double vpend;         // factor the stored velocities still owe (Nose-Hoover half step at a step's end)
+    double virial[6];     // W_ab of the last evaluation with energies (xx, yy, zz, xy, xz, yz)
 };
 
 }  // namespace rbsog

@@ -63,6 +63,7 @@ __device__ inline KDev global_view(KDev k)
     k.g0cdf = glob(k.g0cdf), k.g2cdf = glob(k.g2cdf), k.comp_cdf = glob(k.comp_cdf);
     k.m = glob(k.m), k.modes = glob(k.modes);
     k.rho_part = glob(k.rho_part), k.rho = glob(k.rho);
+    k.sog_c = glob(k.sog_c), k.sog_s2 = glob(k.sog_s2);
     return k;
 }
 
@@ -982,6 +983,27 @@ struct FloydMask {
     }
 };
 
+// Adds one pair's force f r_ij to F and, with energies, half its energy to
+// U and half of r_ij (x) f r_ij to the virial W (xx, yy, zz, xy, xz, yz).
+template <bool ENERGY>
+__device__ inline void add_pair(double f, double uu, double dx, double dy, double dz, double& Fx, double& Fy,
+                                double& Fz, double& U, double* W)
+{
+    Fx = fma(f, dx, Fx);
+    Fy = fma(f, dy, Fy);
+    Fz = fma(f, dz, Fz);
+    if (ENERGY) {
+        U += 0.5 * uu;
+        const double hx = 0.5 * f * dx, hy = 0.5 * f * dy;
+        W[0] = fma(hx, dx, W[0]);
+        W[1] = fma(hy, dy, W[1]);
+        W[2] = fma(0.5 * f * dz, dz, W[2]);
+        W[3] = fma(hx, dy, W[3]);
+        W[4] = fma(hx, dz, W[4]);
+        W[5] = fma(hy, dz, W[5]);
+    }
+}
+
 // Pair forces of A atoms per workgroup (A = blockDim.x / 2): the first A
 // threads (whole wavefronts) take the core lists, the other A the shell
 // batches of the same atoms, so twice as many independent gather chains are
@@ -995,7 +1017,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
     extern __shared__ uint32_t mask_sm[];
     __shared__ PairCoef pc[kMaxSpecies * kMaxSpecies];
     __shared__ PairCoefF pcf[kMaxSpecies * kMaxSpecies];
-    __shared__ double xch[4][kBlock];  // core F (3) and energy, per atom of the block
+    __shared__ double xch[ENERGY ? 10 : 4][kBlock];  // core F (3), energy and virial (6), per atom
     const int S = s.n_species;
     for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
         const PairCoef c = s.pair[t];
@@ -1010,6 +1032,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
     const int i = lb * A + ta;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, Uc = 0.0, Us = 0.0;
     double Sx = 0.0, Sy = 0.0, Sz = 0.0, Su = 0.0, wgt = 1.0;
+    double Wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // this lane's virial (core or shell sum)
     if (i < s.n) {
         const double4 Pi = s.p[i];
         const double xi = Pi.x, yi = Pi.y, zi = Pi.z;
@@ -1060,10 +1083,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     if (r2 < s.rc2) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
-                        Fx = fma(f, dx, Fx);
-                        Fy = fma(f, dy, Fy);
-                        Fz = fma(f, dz, Fz);
-                        if (ENERGY) Uc += 0.5 * uu;
+                        add_pair<ENERGY>(f, uu, dx, dy, dz, Fx, Fy, Fz, Uc, Wv);
                     }
                 }
             }
@@ -1100,10 +1120,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     if (r2 >= s.rc2 && r2 < s.rs2) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
-                        Sx = fma(f, dx, Sx);
-                        Sy = fma(f, dy, Sy);
-                        Sz = fma(f, dz, Sz);
-                        if (ENERGY) Su += 0.5 * uu;
+                        add_pair<ENERGY>(f, uu, dx, dy, dz, Sx, Sy, Sz, Su, Wv);
                     }
                 }
             }
@@ -1160,10 +1177,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     if (r2 >= s.rc2 && r2 < s.rs2) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
-                        Sx = fma(f, dx, Sx);
-                        Sy = fma(f, dy, Sy);
-                        Sz = fma(f, dz, Sz);
-                        if (ENERGY) Su += 0.5 * uu;
+                        add_pair<ENERGY>(f, uu, dx, dy, dz, Sx, Sy, Sz, Su, Wv);
                     }
                 }
             }
@@ -1174,6 +1188,8 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
         xch[1][ta] = Fy;
         xch[2][ta] = Fz;
         xch[3][ta] = Uc;
+        if (ENERGY)
+            for (int c = 0; c < 6; ++c) xch[4 + c][ta] = Wv[c];
     }
     __syncthreads();
     if (shell) {
@@ -1182,7 +1198,10 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
             Fy = fma(wgt, Sy, xch[1][ta]);
             Fz = fma(wgt, Sz, xch[2][ta]);
             Uc = xch[3][ta];
-            if (ENERGY) Us = wgt * Su;
+            if (ENERGY) {
+                Us = wgt * Su;
+                for (int c = 0; c < 6; ++c) Wv[c] = fma(wgt, Wv[c], xch[4 + c][ta]);
+            }
             __builtin_nontemporal_store(Fx, s.fsx + i);
             __builtin_nontemporal_store(Fy, s.fsy + i);
             __builtin_nontemporal_store(Fz, s.fsz + i);
@@ -1192,6 +1211,8 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
         wave_partial(Fz, i, s.n, s.pair_part, kPairPart, 2);
         wave_partial(Uc, i, s.n, s.pair_part, kPairPart, 3);
         wave_partial(Us, i, s.n, s.pair_part, kPairPart, 4);
+        if (ENERGY)
+            for (int c = 0; c < 6; ++c) wave_partial(Wv[c], i, s.n, s.pair_part, kPairPart, 5 + c);
     }
 }
 
@@ -1503,22 +1524,55 @@ __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __rest
 
 // Momentum correction (eq. 26) and energy sums; one 1024-thread block per
 // system.
-__global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sys, const KDev* __restrict__ kd)
+// Sum of F^(k) terms at k^2 (value and -F^'(k)/k) for the mode virial.
+__device__ inline double mode_g(const KDev& k, double k2)
+{
+    double F = 0.0, G = 0.0;
+    for (int m = 0; m < k.n_sog; ++m) {
+        const double e = k.sog_c[m] * exp(-0.5 * k.sog_s2[m] * k2);
+        F += e;
+        G = fma(e, k.sog_s2[m], G);
+    }
+    return F > 0.0 ? G / F : 0.0;
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sys, const KDev* __restrict__ kd,
+                                                   int energy)
 {
     const DevSys s = global_view(sys[blockIdx.x]);
     const KDev k = global_view(kd[blockIdx.x]);
     const double* part = s.pair_part;
     const int nb = (s.n + 63) / 64;  // wavefront partials
+    const int nc = energy ? kPairPart : 5;
     __shared__ double red[16];
-    double v[kPairPart] = {0, 0, 0, 0, 0};
+    double v[kPairPart];
+    for (int c = 0; c < kPairPart; ++c) v[c] = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x)
-        for (int c = 0; c < kPairPart; ++c) v[c] += part[(size_t)b * kPairPart + c];
+        for (int c = 0; c < nc; ++c) v[c] += part[(size_t)b * kPairPart + c];
     double ue = 0.0;
+    double wk[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int nm = s.n > 0 ? k.n_modes : 0;  // an empty system sums no modes
-    for (int p = threadIdx.x; p < nm; p += blockDim.x) ue += k.modes[p].e;
+    for (int p = threadIdx.x; p < nm; p += blockDim.x) {
+        const ModeRec r = k.modes[p];
+        ue += r.e;
+        if (energy) {
+            // strain derivative of the mode's energy: e (delta_ab - g k_a k_b)
+            const double kx = s.two_pi_L[0] * r.mx, ky = s.two_pi_L[1] * r.my, kz = s.two_pi_L[2] * r.mz;
+            const double eg = r.e * mode_g(k, (kx * kx + ky * ky) + kz * kz);
+            wk[0] += r.e - eg * kx * kx;
+            wk[1] += r.e - eg * ky * ky;
+            wk[2] += r.e - eg * kz * kz;
+            wk[3] -= eg * kx * ky;
+            wk[4] -= eg * kx * kz;
+            wk[5] -= eg * ky * kz;
+        }
+    }
     double tot[kPairPart];
-    for (int c = 0; c < kPairPart; ++c) tot[c] = block_sum(v[c], red);
+    for (int c = 0; c < nc; ++c) tot[c] = block_sum(v[c], red);
     const double ut = block_sum(ue, red);
+    double wt[6];
+    if (energy)
+        for (int c = 0; c < 6; ++c) wt[c] = block_sum(wk[c], red);
     if (threadIdx.x == 0) {
         DeviceScalars* sc = s.sc;
         const double inv_n = s.n > 0 ? 1.0 / (double)s.n : 0.0;
@@ -1528,6 +1582,8 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
         sc->u_core = tot[3];
         sc->u_shell = tot[4];
         sc->u_kspace = 0.5 * s.coulomb_k * ut;
+        if (energy)
+            for (int c = 0; c < 6; ++c) sc->virial[c] = tot[5 + c] + 0.5 * s.coulomb_k * wt[c];
     }
 }
 
@@ -1905,9 +1961,9 @@ void launch_rho_finalize(const Plan& P, hipStream_t st)
     if (P.modes1.blocks > 0) k_rho_finalize<<<P.modes1.blocks, 64, 0, st>>>(RB_MAP(modes1), P.kd);
 }
 
-void launch_finalize(const Plan& P, hipStream_t st)
+void launch_finalize(const Plan& P, bool energy, hipStream_t st)
 {
-    if (P.R > 0) k_finalize<<<P.R, 1024, 0, st>>>(P.sys, P.kd);
+    if (P.R > 0) k_finalize<<<P.R, 1024, 0, st>>>(P.sys, P.kd, energy ? 1 : 0);
 }
 
 void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st)

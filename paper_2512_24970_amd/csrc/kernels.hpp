@@ -102,10 +102,14 @@ struct KDev {
     double* rho_part;     // [n_chunks][n_modes_pad][2]
     int n_modes_pad;
     double* rho;          // [n_modes][2]
+    int n_sog;            // terms of F^(k): c[m] exp(-s2[m] k^2 / 2), m < n_sog
+    const double* sog_c;
+    const double* sog_s2;
 };
 
-// Per-wavefront partial sums written by the pair kernel: F (3), u_core, u_shell.
-constexpr int kPairPart = 5;
+// Per-wavefront partial sums written by the pair kernel: F (3), u_core,
+// u_shell, and (evaluations with energies) the virial W (6).
+constexpr int kPairPart = 11;
 
 // The grid of one launch over a batch: block b works on local block map[b].y
 // of system map[b].x.  A null map means one system (system 0, local block b).
@@ -162,7 +166,8 @@ void launch_ksample(const Plan& P, hipStream_t st);
 void launch_pair(const Plan& P, const SogCoef& sog, bool mixed, bool energy, hipStream_t st);
 void launch_rho(const Plan& P, bool mixed, hipStream_t st);
 void launch_rho_finalize(const Plan& P, hipStream_t st);
-void launch_finalize(const Plan& P, hipStream_t st);
+// momentum correction and energies; with `energy` also the virial
+void launch_finalize(const Plan& P, bool energy, hipStream_t st);
 void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st);
 // kinetic energy from the partials; with a thermostat also the velocity
 // factor of the next step.  step_end: the partials are those of a step's

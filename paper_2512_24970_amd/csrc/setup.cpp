@@ -237,6 +237,17 @@ double far_hat(const SogSplit& sp, double k)
     return acc;
 }
 
+void sog_kspace_terms(const SogSplit& sp, std::vector<double>* c, std::vector<double>* s2)
+{
+    c->assign(sp.M + 1, 0.0);
+    s2->assign(sp.M + 1, 0.0);
+    for (int m = 0; m <= sp.M; ++m) {
+        const double sg = sp.s * std::pow(sp.b, (double)m);
+        (*c)[m] = std::pow(2.0 * kPi, 1.5) * sp.w[m] * sg * sg * sg;
+        (*s2)[m] = sg * sg;
+    }
+}
+
 void enumerate_modes(const SogSplit& sp, const double box[3], std::vector<int32_t>* m, std::vector<double>* coef)
 {
     m->clear();

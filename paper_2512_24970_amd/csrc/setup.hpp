@@ -42,5 +42,8 @@ void enumerate_modes(const SogSplit& sp, const double box[3], std::vector<int32_
 
 // F^(k) of eq. (21).
 double far_hat(const SogSplit& sp, double k);
+// Terms of F^ for the device: F^(k) = sum_m c[m] exp(-s2[m] k^2 / 2) with
+// c_m = (2 pi)^{3/2} w_m sigma_m^3 and s2_m = sigma_m^2, m = 0..M.
+void sog_kspace_terms(const SogSplit& sp, std::vector<double>* c, std::vector<double>* s2);
 
 }  // namespace rbsog
