@@ -303,6 +303,8 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=64, help="replicas in the batched-form leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=50,
                     help="timed steps of the 5e6-ion leg (0: skip)")
+    ap.add_argument("--shell-stored", type=int, default=0,
+                    help="1: the main legs use the memory form of the list (shell batch drawn at the build)")
     ap.add_argument("--stored", type=int, default=1,
                     help="1: also time the memory form of the list (shell batch drawn at the build) "
                          "on the 1e6-ion workload and, with --large-steps, on the 5e6-ion melt")
@@ -325,6 +327,9 @@ def main() -> int:
     from paper_2512_24970_amd import workloads as W
     t = time.perf_counter()
     cfg = W.config(args.workload)
+    if args.shell_stored:
+        cfg = dict(cfg, sys=dict(cfg["sys"], shell_stored=True))
+    wl_key = args.workload + ("_stored" if args.shell_stored else "")
     n = len(cfg["types"])
     _log(f"[bench] workload {args.workload}: N={n} inputs in {time.perf_counter() - t:.1f} s")
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
@@ -352,8 +357,9 @@ def main() -> int:
             "species": cfg["sys"]["species"]["names"], "r_core": cfg["sys"]["r_core"],
             "r_shell": cfg["sys"]["r_shell"], "skin": cfg["sys"]["skin"], "p_r": cfg["sys"]["p_r"], "p_f": p_f,
             "rebuild_every": cfg["sys"]["rebuild_every"], "dt_ps": cfg["sys"]["dt"], "form": head,
+            "shell_batch": "stored at the list build" if args.shell_stored else "drawn every evaluation",
         },
-        "roofline": roofline(head, r, n, cfg["sys"], args.workload),
+        "roofline": roofline(head, r, n, cfg["sys"], wl_key),
         "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
         "tuning": r["tuning"],
         "device_mem_GB": r["device_mem_GB"],
@@ -366,7 +372,7 @@ def main() -> int:
         rf = results[f]
         line[f] = {"value": rf["value"], "ms_per_step": rf["ms_per_step"], "T_end_K": round(rf["T_end"], 1),
                    "tuning": rf["tuning"],
-                   "roofline": roofline(f, rf, n, cfg["sys"], args.workload),
+                   "roofline": roofline(f, rf, n, cfg["sys"], wl_key),
                    "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in rf["phases"].items()}}
     if args.batch > 0:
         line["batch"] = run_batch(args.batch, args.steps, args.warmup)

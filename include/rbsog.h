@@ -157,6 +157,18 @@ const char* rbsog_version(void);
 rbsog_status rbsog_sog_params(double eps, double r_shell, double* b, double* s, double* x_c,
                               int32_t* M, double* w, int32_t w_cap);
 
+/* FP32 near-field table the mixed form evaluates the SOG Coulomb kernels
+ * from (Section 2.4: near field by table lookup indexed by the bits of
+ * r^2), for the split of (eps, r_shell): binades of s = r^2 from 2^e0 up to
+ * past r_shell^2, 64 intervals each (interval index = exponent and six
+ * leading mantissa bits of s), *n_intervals in all; per interval eight
+ * floats, the cubic Hermite coefficients (ascending powers of t = s - the
+ * interval's start) of CF(s) = -N'(r)/r and of CU(s) = N(r) (eqs. 8, 14-15;
+ * pair force k_e q_i q_j CF r_ij, energy k_e q_i q_j CU).  coef may be NULL;
+ * otherwise it must hold cap >= 8 * n_intervals floats.  Needs no GPU. */
+rbsog_status rbsog_near_table(double eps, double r_shell, float* coef, int32_t cap, int32_t* e0,
+                              int32_t* n_intervals);
+
 /* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the default stream).  Every call's device work is
  * ordered on that stream: work the library puts on its own second stream is

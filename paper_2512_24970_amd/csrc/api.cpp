@@ -98,7 +98,7 @@ struct rbsog_ctx {
     // candidate scratch over a chunk's expected atom count
     int list_chunks = 8;
     double row_slack = 1.25;
-    DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, kin_part, export_tmp, snap, sogk;
+    DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, vir_part, kin_part, export_tmp, snap, sogk, neartab;
 
     // phase timing
     bool profiling = false;
@@ -304,6 +304,8 @@ Plan one(const rbsog_ctx* c, int r)
     P.n_chunks = c->plan.n_chunks;
     P.cap_core = c->plan.cap_core;
     P.cap_cand = c->plan.cap_cand;
+    P.near = c->plan.near;
+    P.langevin = c->plan.langevin;
     return P;
 }
 
@@ -367,7 +369,7 @@ void plan_lists(rbsog_ctx* c, int cap_core, int cap_cand)
     const bool stored = c->R > 0 && c->hs[0].shell_stored;
     // the memory form keeps candidate rows for one chunk of cells at a time
     // (the per-atom fallback kernel needs them all); otherwise one per atom
-    const int K = (stored && c->plan.list_mode != 2) ? std::max(1, std::min(c->list_chunks, kMaxListChunks)) : 1;
+    const int K = (stored && c->plan.list_mode != kListPerAtom) ? std::max(1, std::min(c->list_chunks, kMaxListChunks)) : 1;
     c->plan.stored = stored;
     c->plan.n_chunks = K;
     size_t bat_all = 0;
@@ -492,7 +494,7 @@ void grow_after_overflow(rbsog_ctx* c, int o)
         cap_cand = std::max(cap_cand, round_up(mk + mk / 4 + 8, 32));
         require(cap_cand <= 4096 && cap_core <= 4096, RBSOG_E_CAPACITY, "neighbour list capacity above 4096");
     }
-    if (o & 4) c->plan.list_mode = std::min(2, c->plan.list_mode + 1);
+    if (o & 4) c->plan.list_mode = std::min(kListPerAtom, c->plan.list_mode + 1);
     if (o & 8) c->row_slack *= 2.0;
     plan_lists(c, cap_core, cap_cand);
     plan_launches(c);
@@ -824,6 +826,17 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     if (!sog_kernel_coef(c->sog, c->chain, p0.r_shell, c->mixed, &c->coef, &err)) throw Error(RBSOG_E_ARG, err);
     double wsum = 0.0;
     for (double w : c->sog.w) wsum += w;
+    // FP32 near-field table of the mixed form (shared)
+    NearTable nt;
+    if (c->mixed) build_near_table(c->sog, p0.r_shell, &nt);
+    c->plan.near = NearTab{};
+    if (nt.nbin > 0) {
+        c->neartab.alloc(sizeof(float) * nt.coef.size());
+        HIP_OK(hipMemcpy(c->neartab.p, nt.coef.data(), sizeof(float) * nt.coef.size(), hipMemcpyHostToDevice));
+        c->plan.near.coef = c->neartab.as<float4>();
+        c->plan.near.lo = (127 + nt.e0) << 6;
+        c->plan.near.n = nt.nbin * kNearSub;
+    }
 
     c->drop_graphs();
     if (!c->aux) HIP_OK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
@@ -834,6 +847,9 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->sel = 0;
     c->row_slack = 1.25;
     c->plan.tune = Tuning{};
+    c->plan.langevin = false;
+    for (const auto& p : prm)
+        if (p.t_target > 0.0 && p.tau_t > 0.0 && p.thermostat == RBSOG_THERMO_LANGEVIN) c->plan.langevin = true;
     c->slot_off.assign(slot_off.begin(), slot_off.end() - 1);
     c->n_slots = slot_off[R];
     c->n_user = n_user;
@@ -863,7 +879,8 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     size_t n_waves = 0;
     for (const auto& s : c->hs) n_waves += blocks_for(s.n, 64);
     c->pair_part.alloc(sizeof(double) * kPairPart * std::max<size_t>(1, n_waves));
-    HIP_OK(hipMemsetAsync(c->pair_part.p, 0, c->pair_part.bytes, c->stream));
+    c->vir_part.alloc(sizeof(double) * kVirPart * std::max<size_t>(1, n_waves));
+    HIP_OK(hipMemsetAsync(c->vir_part.p, 0, c->vir_part.bytes, c->stream));
     c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
     c->scalars.alloc(sizeof(DeviceScalars) * R);
     HIP_OK(hipMemsetAsync(c->scalars.p, 0, sizeof(DeviceScalars) * R, c->stream));
@@ -905,6 +922,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             s.cell_start = cells + s.ncell;
             cells += 2 * (size_t)s.ncell + 1;
             s.pair_part = c->pair_part.as<double>() + wav * kPairPart;
+            s.vir_part = c->vir_part.as<double>() + wav * kVirPart;
             s.kin_part = c->kin_part.as<double>() + wav;
             wav += blocks_for(s.n, 64);
             s.sc = c->scalars.as<DeviceScalars>() + r;
@@ -962,7 +980,14 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
         for (int a = 0; a < 3; ++a) cell_vol *= p.box[a] / s.nc[a];
         const int ncell_st = (s.nc[0] >= 3 ? 3 : 1) * (s.nc[1] >= 3 ? 3 : 1) * (s.nc[2] >= 3 ? 3 : 1);
         const double stencil = std::min<double>(n, ncell_st * cell_vol * rho_n);
-        list_mode = std::max(list_mode, stencil * 1.3 + 64 <= 2048 ? 0 : (stencil * 1.3 + 64 <= 4096 ? 1 : 2));
+        // the smallest staging capacity that holds the stencil with room for
+        // density fluctuations (a cell that still overflows moves the build
+        // to the next one)
+        const double need = stencil + 5.0 * std::sqrt(stencil) + 32.0;
+        int mode = kListPerAtom;
+        for (int q = kListPerAtom - 1; q >= 0; --q)
+            if (need <= kListCaps[q]) mode = q;
+        list_mode = std::max(list_mode, mode);
     }
     cap_core = std::min(cap_core, std::max(32, round_up(n_max, 32)));
     cap_cand = std::min(cap_cand, std::max(32, round_up(n_max, 32)));
@@ -1131,6 +1156,29 @@ rbsog_status rbsog_sog_params(double eps, double r_shell, double* b, double* s, 
         if (w) {
             if (w_cap < sp.M + 1) return RBSOG_E_ARG;
             for (int m = 0; m <= sp.M; ++m) w[m] = sp.w[m];
+        }
+        return RBSOG_OK;
+    } catch (...) {
+        return RBSOG_E_ARG;
+    }
+}
+
+rbsog_status rbsog_near_table(double eps, double r_shell, float* coef, int32_t cap, int32_t* e0,
+                              int32_t* n_intervals)
+{
+    try {
+        if (!(r_shell > 0.0)) return RBSOG_E_ARG;
+        SogSplit sp;
+        std::string err;
+        if (!sog_split(eps > 0.0 ? eps : 1e-5, r_shell, &sp, &err)) return RBSOG_E_ARG;
+        NearTable nt;
+        build_near_table(sp, r_shell, &nt);
+        const int n = nt.nbin * kNearSub;
+        if (e0) *e0 = nt.e0;
+        if (n_intervals) *n_intervals = n;
+        if (coef) {
+            if (cap < 8 * n) return RBSOG_E_ARG;
+            std::memcpy(coef, nt.coef.data(), sizeof(float) * nt.coef.size());
         }
         return RBSOG_OK;
     } catch (...) {

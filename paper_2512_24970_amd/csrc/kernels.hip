@@ -52,7 +52,7 @@ __device__ inline DevSys global_view(DevSys s)
     s.core_cnt = glob(s.core_cnt), s.core_idx = glob(s.core_idx);
     s.cand_cnt = glob(s.cand_cnt), s.cand_idx = glob(s.cand_idx), s.bat_idx = glob(s.bat_idx);
     s.pair = glob(s.pair), s.sc = glob(s.sc), s.spc = glob(s.spc);
-    s.pair_part = glob(s.pair_part), s.kin_part = glob(s.kin_part);
+    s.pair_part = glob(s.pair_part), s.kin_part = glob(s.kin_part), s.vir_part = glob(s.vir_part);
     return s;
 }
 
@@ -930,34 +930,55 @@ __device__ inline double pair_scalar_f64(const PairCoef& c, const SogCoef& g, do
     return f;
 }
 
-// FP32 form: every narrow Gaussian by its own exponential.
+// FP32 form.  The SOG Coulomb kernels CF = -N'(r)/r and CU = N(r) come from
+// the near-field table: the exponent and six leading mantissa bits of r^2
+// pick the interval, whose cubic in t = r^2 - (its start) is evaluated by
+// Horner (no transcendental).  Below the table (r^2 < 2^e0, never reached by
+// a melt) every narrow Gaussian is evaluated by its own exponential.  The
+// BMH terms are evaluated directly.
 template <bool ENERGY>
-__device__ inline float pair_scalar_f32(const PairCoefF& c, const SogCoefF& g, float r2, float& u)
+__device__ inline float pair_scalar_f32(const PairCoefF& c, const SogCoefF& g, const float4* tab, int tab_lo,
+                                        int tab_n, float r2, float& u)
 {
     const float ir = __frsqrt_rn(r2);
     const float r = r2 * ir;
     const float ir2 = ir * ir;
-    float fsum = 0.f, esum = 0.f;
-    for (int m = 0; m < g.n_exp; ++m) {
-        const float gm = __expf(-r2 * g.a[m]);
-        fsum = fmaf(g.fw[m], gm, fsum);
-        if (ENERGY) esum = fmaf(g.ew[m], gm, esum);
-    }
-    if (g.n_poly > 0) {
-        float pf = g.pc[g.n_poly - 1];
-        float pe = g.pd[g.n_poly - 1];
-        for (int k = g.n_poly - 2; k >= 0; --k) {
-            pf = fmaf(pf, r2, g.pc[k]);
-            if (ENERGY) pe = fmaf(pe, r2, g.pd[k]);
+    float cf, cu = 0.f;
+    const uint32_t bits = __float_as_uint(r2);
+    const int idx = (int)(bits >> 17) - tab_lo;
+    if ((unsigned)idx < (unsigned)tab_n) {
+        const float t = r2 - __uint_as_float(bits & 0xFFFE0000u);
+        const float4 a = tab[ENERGY ? 2 * idx : idx];
+        cf = fmaf(fmaf(fmaf(a.w, t, a.z), t, a.y), t, a.x);
+        if (ENERGY) {
+            const float4 b = tab[2 * idx + 1];
+            cu = fmaf(fmaf(fmaf(b.w, t, b.z), t, b.y), t, b.x);
         }
-        fsum += pf;
-        if (ENERGY) esum += pe;
+    } else {
+        float fsum = 0.f, esum = 0.f;
+        for (int m = 0; m < g.n_exp; ++m) {
+            const float gm = __expf(-r2 * g.a[m]);
+            fsum = fmaf(g.fw[m], gm, fsum);
+            if (ENERGY) esum = fmaf(g.ew[m], gm, esum);
+        }
+        if (g.n_poly > 0) {
+            float pf = g.pc[g.n_poly - 1];
+            float pe = g.pd[g.n_poly - 1];
+            for (int k = g.n_poly - 2; k >= 0; --k) {
+                pf = fmaf(pf, r2, g.pc[k]);
+                if (ENERGY) pe = fmaf(pe, r2, g.pd[k]);
+            }
+            fsum += pf;
+            if (ENERGY) esum += pe;
+        }
+        cf = ir2 * ir - fsum;
+        if (ENERGY) cu = ir - esum;
     }
     const float rep = c.A * __expf((c.sig - r) * c.irho);
     const float ir6 = ir2 * ir2 * ir2;
     const float ir8 = ir6 * ir2;
-    const float f = c.qq * (ir2 * ir - fsum) + rep * c.irho * ir - 6.f * c.C * ir8 - 8.f * c.D * ir8 * ir2;
-    if (ENERGY) u = c.qq * (ir - esum) + rep - c.C * ir6 - c.D * ir8;
+    const float f = c.qq * cf + rep * c.irho * ir - 6.f * c.C * ir8 - 8.f * c.D * ir8 * ir2;
+    if (ENERGY) u = c.qq * cu + rep - c.C * ir6 - c.D * ir8;
     return f;
 }
 
@@ -1011,10 +1032,19 @@ __device__ inline void add_pair(double f, double uu, double dx, double dy, doubl
 // thread adds its reweighted sum to the core sum passed through LDS, in the
 // same order as one thread doing both.
 template <bool MIXED, bool ENERGY, int J, int KU>
-__global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf)
+__global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf, NearTab nt)
 {
     RB_SYS(xcd_block(blockIdx.x, gridDim.x))
-    extern __shared__ uint32_t mask_sm[];
+    // dynamic LDS: the near-field table (mixed form; F coefficients, with
+    // energies also U), then the Floyd masks of the per-evaluation draw
+    extern __shared__ float4 dyn_sm[];
+    const int tab_vecs = MIXED ? nt.n * (ENERGY ? 2 : 1) : 0;
+    float4* tab = dyn_sm;
+    uint32_t* mask_sm = reinterpret_cast<uint32_t*>(dyn_sm + tab_vecs);
+    if (MIXED) {
+        const float4* src = glob(nt.coef);
+        for (int t = threadIdx.x; t < tab_vecs; t += blockDim.x) tab[t] = ENERGY ? src[t] : src[2 * t];
+    }
     __shared__ PairCoef pc[kMaxSpecies * kMaxSpecies];
     __shared__ PairCoefF pcf[kMaxSpecies * kMaxSpecies];
     __shared__ double xch[ENERGY ? 10 : 4][kBlock];  // core F (3), energy and virial (6), per atom
@@ -1042,7 +1072,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
             const int t = ti * S + tj;
             if (MIXED) {
                 float uf = 0.f;
-                const double f = (double)pair_scalar_f32<ENERGY>(pcf[t], gf, (float)r2, uf);
+                const double f = (double)pair_scalar_f32<ENERGY>(pcf[t], gf, tab, nt.lo, nt.n, (float)r2, uf);
                 u = uf;
                 return f;
             }
@@ -1212,7 +1242,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
         wave_partial(Uc, i, s.n, s.pair_part, kPairPart, 3);
         wave_partial(Us, i, s.n, s.pair_part, kPairPart, 4);
         if (ENERGY)
-            for (int c = 0; c < 6; ++c) wave_partial(Wv[c], i, s.n, s.pair_part, kPairPart, 5 + c);
+            for (int c = 0; c < 6; ++c) wave_partial(Wv[c], i, s.n, s.vir_part, kVirPart, c);
     }
 }
 
@@ -1543,12 +1573,15 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
     const KDev k = global_view(kd[blockIdx.x]);
     const double* part = s.pair_part;
     const int nb = (s.n + 63) / 64;  // wavefront partials
-    const int nc = energy ? kPairPart : 5;
     __shared__ double red[16];
-    double v[kPairPart];
-    for (int c = 0; c < kPairPart; ++c) v[c] = 0.0;
+    double v[kPairPart + kVirPart];
+    for (int c = 0; c < kPairPart + kVirPart; ++c) v[c] = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x)
-        for (int c = 0; c < nc; ++c) v[c] += part[(size_t)b * kPairPart + c];
+        for (int c = 0; c < kPairPart; ++c) v[c] += part[(size_t)b * kPairPart + c];
+    if (energy)
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            for (int c = 0; c < kVirPart; ++c) v[kPairPart + c] += s.vir_part[(size_t)b * kVirPart + c];
+    const int nc = energy ? kPairPart + kVirPart : kPairPart;
     double ue = 0.0;
     double wk[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int nm = s.n > 0 ? k.n_modes : 0;  // an empty system sums no modes
@@ -1567,7 +1600,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
             wk[5] -= eg * ky * kz;
         }
     }
-    double tot[kPairPart];
+    double tot[kPairPart + kVirPart];
     for (int c = 0; c < nc; ++c) tot[c] = block_sum(v[c], red);
     const double ut = block_sum(ue, red);
     double wt[6];
@@ -1583,7 +1616,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
         sc->u_shell = tot[4];
         sc->u_kspace = 0.5 * s.coulomb_k * ut;
         if (energy)
-            for (int c = 0; c < 6; ++c) sc->virial[c] = tot[5 + c] + 0.5 * s.coulomb_k * wt[c];
+            for (int c = 0; c < 6; ++c) sc->virial[c] = tot[kPairPart + c] + 0.5 * s.coulomb_k * wt[c];
     }
 }
 
@@ -1711,13 +1744,16 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(RB_ARGS)
 // v += dt/2 F/m; r += dt v (wrapped); the displacement since the build is
 // checked against skin/2, which raises the rebuild flag, as does a build
 // scheduled for this step.
+// LANGEVIN: the variant launched when some system of the batch runs the
+// Langevin thermostat (its noise path needs many more registers).
+template <bool LANGEVIN>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
 {
     RB_SYS(blockIdx.x)
     __shared__ double red[4];
     const int i = lb * blockDim.x + threadIdx.x;
     double d2 = 0.0;
-    const bool langevin = s.thermo_c > 0.0 && s.thermostat == kThermoLangevin;
+    const bool langevin = LANGEVIN && s.thermo_c > 0.0 && s.thermostat == kThermoLangevin;
     const double lam = (s.thermo_c > 0.0 && !langevin) ? s.sc->vscale : 1.0;
     if (i < s.n) {
         const int ti = s.type[i];
@@ -1732,9 +1768,14 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
             // Box-Muller normals of the stream (id, step, kTagLangevin), half drift
             PhiloxStream st(s.seed, (uint32_t)s.id[i], (uint32_t)s.sc->eval, kTagLangevin, s.replica);
             const double u1 = st.uniform(), u2 = st.uniform(), u3 = st.uniform(), u4 = st.uniform();
+            // cos(2 pi u) and sin(2 pi u) as sincospi(2u): no large-argument reduction
+            double sn2, cs2, sn4, cs4;
+            sincospi(2.0 * u2, &sn2, &cs2);
+            sincospi(2.0 * u4, &sn4, &cs4);
+            (void)sn4;
             const double r = sqrt(-2.0 * log(1.0 - u1));
-            const double z0 = r * cos(2.0 * kPi * u2), z1 = r * sin(2.0 * kPi * u2);
-            const double z2 = sqrt(-2.0 * log(1.0 - u3)) * cos(2.0 * kPi * u4);
+            const double z0 = r * cs2, z1 = r * sn2;
+            const double z2 = sqrt(-2.0 * log(1.0 - u3)) * cs4;
             const double h = 0.5 * s.dt, c1 = s.lv_c1, c2 = s.lv_c2[ti];
             px = P.x + h * vx;
             py = P.y + h * vy;
@@ -1883,9 +1924,11 @@ void launch_build(const Plan& P, bool gate, hipStream_t st)
     for (int k = 0; k < K; ++k) {
         const Shape& cs = P.stored ? P.cell_chunk[k] : P.cells;
         if (P.list_mode == 0) {
-            if (cs.blocks > 0) k_lists_cell<2048><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
+            if (cs.blocks > 0) k_lists_cell<kListCaps[0]><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
         } else if (P.list_mode == 1) {
-            if (cs.blocks > 0) k_lists_cell<4096><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
+            if (cs.blocks > 0) k_lists_cell<kListCaps[1]><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
+        } else if (P.list_mode == 2) {
+            if (cs.blocks > 0) k_lists_cell<kListCaps[2]><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
         } else {
             int capP2 = 1;
             while (capP2 < P.cap_cand) capP2 <<= 1;
@@ -1906,10 +1949,12 @@ template <int KU>
 void launch_pair_ku(const Plan& P, const SogCoef& g, const SogCoefF& gf, bool mixed, bool energy, hipStream_t st)
 {
     const int bs = P.tune.pair_block;  // atoms per workgroup; twice as many threads
-    // Floyd masks of the per-evaluation batch draw (none for a stored batch)
-    const size_t sm = P.stored ? 0 : sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * bs;
+    // near-field table (mixed), then the Floyd masks of the per-evaluation
+    // batch draw (none for a stored batch)
+    const size_t tab = mixed ? sizeof(float4) * (size_t)P.near.n * (energy ? 2 : 1) : 0;
+    const size_t sm = tab + (P.stored ? 0 : sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * bs);
     const int nb = P.pair_atoms.blocks;
-#define RB_PAIR(M, E, J) k_pair<M, E, J, KU><<<nb, 2 * bs, sm, st>>>(RB_MAP(pair_atoms), g, gf)
+#define RB_PAIR(M, E, J) k_pair<M, E, J, KU><<<nb, 2 * bs, sm, st>>>(RB_MAP(pair_atoms), g, gf, P.near)
     if (mixed) {
         if (energy)
             RB_PAIR(true, true, 1);
@@ -2000,7 +2045,11 @@ void launch_kinetic(const Plan& P, hipStream_t st)
 
 void launch_kick_drift(const Plan& P, bool scheduled, hipStream_t st)
 {
-    if (P.atoms.blocks > 0) k_kick_drift<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), scheduled ? 1 : 0);
+    if (P.atoms.blocks <= 0) return;
+    if (P.langevin)
+        k_kick_drift<true><<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), scheduled ? 1 : 0);
+    else
+        k_kick_drift<false><<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), scheduled ? 1 : 0);
 }
 
 void launch_to_user3(const Plan& P, Field f, double* out, hipStream_t st)

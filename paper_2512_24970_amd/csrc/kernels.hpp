@@ -80,6 +80,7 @@ struct DevSys {
     const PairCoef* pair;
     DeviceScalars* sc;
     double* pair_part;     // [ceil(n/64)][kPairPart] wavefront partials of the pair kernel
+    double* vir_part;      // [ceil(n/64)][kVirPart] wavefront virial partials (evaluations with energies)
     double* kin_part;      // [ceil(n/64)] kinetic-energy wavefront partials
 };
 
@@ -108,8 +109,9 @@ struct KDev {
 };
 
 // Per-wavefront partial sums written by the pair kernel: F (3), u_core,
-// u_shell, and (evaluations with energies) the virial W (6).
-constexpr int kPairPart = 11;
+// u_shell; and, in evaluations with energies, the virial W (6) in vir_part.
+constexpr int kPairPart = 5;
+constexpr int kVirPart = 6;
 
 // The grid of one launch over a batch: block b works on local block map[b].y
 // of system map[b].x.  A null map means one system (system 0, local block b).
@@ -127,6 +129,22 @@ struct Tuning {
     int kf_block = 256;    // atoms per k-space force workgroup (64, 128, 256)
 };
 
+// FP32 near-field table of the mixed pair kernel (built on the host, shared
+// by a batch): interval idx = (bits(r^2) >> 17) - lo, valid below n; per
+// interval two float4: CF and CU cubic coefficients in t = r^2 - start.
+struct NearTab {
+    const float4* coef = nullptr;
+    int lo = 0;
+    int n = 0;  // 0: no table, the kernel evaluates the near field directly
+};
+
+// Staging capacities of the per-cell list kernel (atoms of a 27-cell stencil
+// held in LDS): the smallest fits three workgroups in a CU's LDS; a build
+// whose stencil overflows moves to the next; past the last, the per-atom
+// kernel.
+constexpr int kListCaps[3] = {1600, 2048, 4096};
+constexpr int kListPerAtom = 3;
+
 // Launch plan of a batch (or of one system of it, see api.cpp).
 struct Plan {
     const DevSys* sys = nullptr;  // device array [R]
@@ -143,10 +161,12 @@ struct Plan {
     Shape modes64;  // 64-mode blocks of the systems that draw modes
     Shape rho;      // rho blocks: local block = mode tile * n_chunks + chunk (tiles of 64 rho_mpl modes)
     Shape modes1;   // one block per mode
-    int list_mode = 0;  // 0/1: per-cell list kernel with a 2048/4096-atom stencil, 2: per-atom kernel
+    int list_mode = 0;  // < kListPerAtom: per-cell list kernel staging kListCaps[mode] atoms; else per-atom kernel
     bool stored = false;  // memory form: batch drawn at the build
+    bool langevin = false;  // some system runs the Langevin thermostat
     int n_chunks = 1;     // build chunks (1 unless stored)
     int cap_core = 0, cap_cand = 0;
+    NearTab near;
     Tuning tune;
 };
 

@@ -237,6 +237,60 @@ double far_hat(const SogSplit& sp, double k)
     return acc;
 }
 
+void build_near_table(const SogSplit& sp, double r_shell, NearTable* t)
+{
+    t->e0 = 0;
+    t->nbin = 0;
+    t->coef.clear();
+    const double rs2 = r_shell * r_shell;
+    int nb = 1;
+    while (std::ldexp(1.0, t->e0 + nb) <= rs2) ++nb;
+    if (nb > kMaxNearBins) return;
+    t->nbin = nb;
+    std::vector<double> a(sp.M + 1), fw(sp.M + 1);
+    for (int m = 0; m <= sp.M; ++m) {
+        const double sg = sp.s * std::pow(sp.b, (double)m);
+        a[m] = 1.0 / (2.0 * sg * sg);
+        fw[m] = sp.w[m] / (sg * sg);
+    }
+    // value and s-derivative of CF and CU
+    auto eval = [&](double s, double* cf, double* dcf, double* cu, double* dcu) {
+        double gf = 0.0, dgf = 0.0, gu = 0.0, dgu = 0.0;
+        for (int m = 0; m <= sp.M; ++m) {
+            const double e = std::exp(-a[m] * s);
+            gf += fw[m] * e;
+            dgf -= fw[m] * a[m] * e;
+            gu += sp.w[m] * e;
+            dgu -= sp.w[m] * a[m] * e;
+        }
+        const double is = 1.0 / s, rs = std::sqrt(is);
+        *cf = is * rs - gf;
+        *dcf = -1.5 * is * is * rs - dgf;
+        *cu = rs - gu;
+        *dcu = -0.5 * is * rs - dgu;
+    };
+    t->coef.assign((size_t)nb * kNearSub * 8, 0.0f);
+    for (int b = 0; b < nb; ++b)
+        for (int j = 0; j < kNearSub; ++j) {
+            const double s0 = std::ldexp(1.0 + (double)j / kNearSub, t->e0 + b);
+            const double s1 = std::ldexp(1.0 + (double)(j + 1) / kNearSub, t->e0 + b);
+            const double h = s1 - s0;
+            double f0[2], d0[2], f1[2], d1[2];
+            eval(s0, &f0[0], &d0[0], &f0[1], &d0[1]);
+            eval(s1, &f1[0], &d1[0], &f1[1], &d1[1]);
+            float* o = t->coef.data() + ((size_t)b * kNearSub + j) * 8;
+            for (int q = 0; q < 2; ++q) {
+                // cubic Hermite: value and slope at both ends
+                const double c2 = (3.0 * (f1[q] - f0[q]) / h - 2.0 * d0[q] - d1[q]) / h;
+                const double c3 = (2.0 * (f0[q] - f1[q]) / h + d0[q] + d1[q]) / (h * h);
+                o[4 * q + 0] = (float)f0[q];
+                o[4 * q + 1] = (float)d0[q];
+                o[4 * q + 2] = (float)c2;
+                o[4 * q + 3] = (float)c3;
+            }
+        }
+}
+
 void sog_kspace_terms(const SogSplit& sp, std::vector<double>* c, std::vector<double>* s2)
 {
     c->assign(sp.M + 1, 0.0);

@@ -42,6 +42,25 @@ void enumerate_modes(const SogSplit& sp, const double box[3], std::vector<int32_
 
 // F^(k) of eq. (21).
 double far_hat(const SogSplit& sp, double k);
+// FP32 table of the SOG near-field kernels for the mixed form, in s = r^2
+// (Section 2.4 evaluates the near field by table lookup with the table
+// indexed by bits of r^2): each binade [2^(e0+b), 2^(e0+b+1)), b < nbin, is
+// cut into 64 intervals, so the interval of s is given by its exponent and
+// its six leading mantissa bits.  Per interval, cubic Hermite polynomials in
+// t = s - s_j (ascending powers) of
+//   CF(s) = s^(-3/2) - sum_m (w_m / sigma_m^2) exp(-s / (2 sigma_m^2))
+//   CU(s) = s^(-1/2) - sum_m w_m exp(-s / (2 sigma_m^2))
+// (pair force k_e q_i q_j CF(r^2) r_ij and energy k_e q_i q_j CU(r^2); eqs.
+// 8, 14-15), coef[interval][8] = CF c0..c3, CU c0..c3.  nbin covers r_shell^2;
+// no table (nbin = 0) above kMaxNearBins binades.
+constexpr int kNearSub = 64;
+constexpr int kMaxNearBins = 12;
+struct NearTable {
+    int e0 = 0, nbin = 0;
+    std::vector<float> coef;
+};
+void build_near_table(const SogSplit& sp, double r_shell, NearTable* t);
+
 // Terms of F^ for the device: F^(k) = sum_m c[m] exp(-s2[m] k^2 / 2) with
 // c_m = (2 pi)^{3/2} w_m sigma_m^3 and s2_m = sigma_m^2, m = 0..M.
 void sog_kspace_terms(const SogSplit& sp, std::vector<double>* c, std::vector<double>* s2);

@@ -77,6 +77,8 @@ ABI = {
     "rbsog_sog_params": (C.c_int, [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32]),
     "rbsog_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "rbsog_near_table": (C.c_int, [C.c_double, C.c_double, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32)]),
     "rbsog_destroy": (C.c_int, [C.c_void_p]),
     "rbsog_last_error": (C.c_char_p, [C.c_void_p]),
     "rbsog_set_system": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
@@ -164,6 +166,19 @@ def make_params(sysp: dict, precision: int = FP64, n_atoms: int | None = None) -
     p.tau_t = float(sysp.get("tau_t", 0.0))
     p.thermostat = THERMOSTATS[sysp.get("thermostat", "berendsen")]
     return p
+
+
+def rbsog_near_table(eps: float, r_shell: float) -> dict:
+    """The mixed form's FP32 near-field table: e0, coef[n_intervals][8]."""
+    e0, n = C.c_int32(), C.c_int32()
+    rc = lib().rbsog_near_table(eps, r_shell, None, 0, C.byref(e0), C.byref(n))
+    if rc != 0:
+        raise RbsogError(rc, "rbsog_near_table failed")
+    coef = np.zeros((max(n.value, 1), 8), np.float32)
+    rc = lib().rbsog_near_table(eps, r_shell, _np_ptr(coef), coef.size, C.byref(e0), C.byref(n))
+    if rc != 0:
+        raise RbsogError(rc, "rbsog_near_table failed")
+    return {"e0": e0.value, "coef": coef[: n.value]}
 
 
 def rbsog_sog_params(eps: float, r_shell: float) -> dict:
