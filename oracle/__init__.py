@@ -50,6 +50,7 @@ class Params(C.Structure):
         ("D", C.c_double * (MAXS * MAXS)),
         ("t_target", C.c_double), ("tau_t", C.c_double),
         ("shell_stored", C.c_int32), ("thermostat", C.c_int32),
+        ("r_core_pair", C.c_double * (MAXS * MAXS)),
     ]
 
 
@@ -172,6 +173,11 @@ def make_params(sysp: dict) -> Params:
     p.tau_t = float(sysp.get("tau_t", 0.0))
     p.shell_stored = 1 if sysp.get("shell_stored", False) else 0
     p.thermostat = THERMOSTATS[sysp.get("thermostat", "berendsen")]
+    rcp = sysp.get("r_core_pair")
+    if rcp is not None:
+        for i in range(S):
+            for j in range(S):
+                p.r_core_pair[i * MAXS + j] = float(rcp[i][j])
     for i in range(S):
         p.q[i] = float(sp["q"][i])
         p.mass[i] = float(sp["mass"][i])

@@ -587,21 +587,29 @@ void orc_destroy(orc_ctx* c)
     free(c);
 }
 
+/* Core radius of the species pair (a, b): its own if set, else r_core. */
+static double core_radius(const orc_params* p, int a, int b)
+{
+    double r = p->r_core_pair[a * ORC_MAXS + b];
+    return r > 0.0 ? r : p->r_core;
+}
+
 /* Core and candidate lists of atom i by a scan over every other atom.
  * Candidates are ordered by (cell of the candidate, atom index), the order
  * that shell ranks refer to. */
 static void scan_atom(const orc_ctx* c, int i, int32_t* core, int* nc, int32_t* cand, int* nk, int count_only)
 {
     const orc_params* p = &c->p;
-    double rc = p->r_core + p->skin;
-    double rc2 = rc * rc;
-    double lo = p->r_core - p->skin;
-    double lo2 = lo > 0.0 ? lo * lo : 0.0;
     double hi = p->r_shell + p->skin;
     double hi2 = hi * hi;
     int a = 0, k = 0;
     for (int j = 0; j < c->n; ++j) {
         if (j == i) continue;
+        double rcp = core_radius(p, c->type[i], c->type[j]);
+        double rc = rcp + p->skin;
+        double rc2 = rc * rc;
+        double lo = rcp - p->skin;
+        double lo2 = lo > 0.0 ? lo * lo : 0.0;
         double d[3];
         min_image(p, c->pos + 3 * i, c->pos + 3 * j, d);
         double r2 = norm2(d);
@@ -790,7 +798,6 @@ static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32
                        double w_out[6])
 {
     double Wc[6] = {0, 0, 0, 0, 0, 0}, Ws[6] = {0, 0, 0, 0, 0, 0};
-    double rc2 = p->r_core * p->r_core;
     double rs2 = p->r_shell * p->r_shell;
     double F[3] = {0.0, 0.0, 0.0};
     double Uc = 0.0, Us = 0.0;
@@ -800,7 +807,8 @@ static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32
         double d[3];
         min_image(p, c->pos + 3 * i, c->pos + 3 * j, d);
         double r2 = norm2(d);
-        if (!(r2 < rc2)) continue;
+        double rcp = core_radius(p, ti, c->type[j]);
+        if (!(r2 < rcp * rcp)) continue;
         double u;
         double f = pair_scalar(p, ti, c->type[j], r2, &u);
         for (int x = 0; x < 3; ++x) F[x] += f * d[x];
@@ -818,7 +826,8 @@ static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32
         double d[3];
         min_image(p, c->pos + 3 * i, c->pos + 3 * j, d);
         double r2 = norm2(d);
-        if (!(r2 >= rc2 && r2 < rs2)) continue;
+        double rcp = core_radius(p, ti, c->type[j]);
+        if (!(r2 >= rcp * rcp && r2 < rs2)) continue;
         double u;
         double f = pair_scalar(p, ti, c->type[j], r2, &u);
         for (int x = 0; x < 3; ++x) Fs[x] += f * d[x];

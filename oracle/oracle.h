@@ -71,6 +71,10 @@ typedef struct {
                                counted from 0 (Section 2.4: O(core + P_R) list
                                entries per atom).  Needs p_r > 0. */
     int32_t thermostat;     /* ORC_THERMO_* */
+    double r_core_pair[ORC_MAXS * ORC_MAXS]; /* core radius per species pair (symmetric);
+                                                0 means r_core.  Pairs inside it are summed
+                                                in full (eq. 24), the rest of the shell is
+                                                sampled (eq. 25). */
 } orc_params;
 
 typedef struct {
@@ -122,8 +126,9 @@ typedef struct orc_ctx orc_ctx;
 orc_ctx* orc_create(const orc_params* p, int32_t n, const int32_t* type,
                     const double* pos, const double* vel);
 void orc_destroy(orc_ctx* c);
-/* Brute-force core list (r < r_core + skin) and shell candidates
- * (r_core - skin <= r < r_shell + skin).  Candidates are ordered by (cell,
+/* Brute-force core list (r < r_core(ti,tj) + skin) and shell candidates
+ * (r_core(ti,tj) - skin <= r < r_shell + skin), r_core(ti,tj) the pair's
+ * core radius.  Candidates are ordered by (cell,
  * atom index) on a grid of n_c = 2 floor(L / (r_shell + skin)) cells per
  * axis (one cell where floor(L / (r_shell + skin)) is below 3), cell =
  * floor(x n_c / L) with x fastest. */

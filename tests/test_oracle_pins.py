@@ -827,3 +827,57 @@ def test_virial_off_diagonal_from_a_rotated_supercell(plane):
     assert w_aa2 / 2 == pytest.approx((vir[f"{a}{a}"] + vir[f"{b}{b}"]) / 2 - w_ab,
                                       rel=1e-8, abs=1e-8 * abs(vir["00"]))
     assert abs(w_ab) > 1e-4 * abs(vir["00"])
+
+
+# --------------------------------------------------------------------------- species-dependent core radii
+_RCP = [[4.2, 5.6], [5.6, 6.4]]  # Na-Na, Na-Cl, Cl-Cl core radii (A), r_core 5 otherwise
+
+
+def test_species_core_radii_do_not_change_the_deterministic_force():
+    """With every shell candidate taken (P_R off) the short-range force is the
+    full sum to r_shell whatever the core/shell split: per-pair core radii
+    move pairs between eq. (24) and eq. (25) but change no force (to
+    rounding), and no energy."""
+    cfg = W.config("nacl_small")
+    base = dict(cfg["sys"], p_r=0)
+    f0, uc0, us0 = O.System(base, cfg["types"], cfg["pos"]).forces_short(0)
+    f1, uc1, us1 = O.System(dict(base, r_core_pair=_RCP), cfg["types"], cfg["pos"]).forces_short(0)
+    assert np.allclose(f1, f0, rtol=0, atol=1e-12 * np.abs(f0).max())
+    assert uc1 != uc0
+    assert uc1 + us1 == pytest.approx(uc0 + us0, rel=1e-13)
+
+
+def test_species_core_radii_shape_the_lists():
+    """Core lists hold exactly the pairs inside their own core radius + skin
+    (counted by brute force here), and an atom's candidates follow."""
+    cfg = W.config("nacl_small")
+    sysp = dict(cfg["sys"], r_core_pair=_RCP)
+    s = O.System(sysp, cfg["types"], cfg["pos"])
+    pos = np.array(cfg["pos"])
+    L = np.array(sysp["box"])
+    t = cfg["types"]
+    sk = sysp["skin"]
+    for i in (0, 17, 101):
+        d = pos[i] - pos
+        d -= L * np.rint(d / L)
+        r = np.sqrt((d ** 2).sum(1))
+        rc = np.array([_RCP[t[i]][t[j]] for j in range(len(t))])
+        core, cand = s.lists_of(i)
+        want_core = {j for j in range(len(t)) if j != i and r[j] < rc[j] + sk}
+        want_cand = {j for j in range(len(t)) if j != i and max(rc[j] - sk, 0) <= r[j] < sysp["r_shell"] + sk}
+        assert set(core.tolist()) == want_core
+        assert set(cand.tolist()) == want_cand
+
+
+def test_species_core_radii_estimator_unbiased():
+    """Eq. (25) with per-pair radii: over batches, the short-range force on an
+    atom averages to the deterministic one."""
+    cfg = W.config("nacl_small")
+    base = dict(cfg["sys"], r_core_pair=_RCP)
+    i = 7
+    f_det, _, _ = O.System(dict(base, p_r=0), cfg["types"], cfg["pos"]).forces_short(0)
+    s = O.System(base, cfg["types"], cfg["pos"])
+    K = 1500
+    est = np.array([s.forces_short(ev)[0][i] for ev in range(K)])
+    se = est.std(0) / math.sqrt(K)
+    assert np.all(np.abs(est.mean(0) - f_det[i]) < 5 * se)
