@@ -245,7 +245,7 @@ def roofline(precision: str, res: dict, n: int, sysp: dict, workload: str) -> di
                      for k in lines if k != top}
     # the k-space chain runs on a second stream beside the pair kernel, so
     # their launch durations overlap and each includes the other's share
-    out["concurrent"] = "k_pair runs beside k_ksample + k_rho (second stream); durations overlap"
+    out["concurrent"] = "k_pair runs beside k_ksample + k_rho + k_kforce (second stream); durations overlap"
     return out
 
 

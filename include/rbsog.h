@@ -104,6 +104,12 @@ typedef struct {
     double tau_t;          /* ps; coupling time of the thermostat (see `thermostat`) */
     int32_t thermostat;    /* RBSOG_THERMO_*; systems of a batch may differ */
     int32_t reserved;      /* 0 */
+    double r_core_pair[RBSOG_MAX_SPECIES * RBSOG_MAX_SPECIES];
+                           /* species-dependent core radii (Section 1 names the strategy, no rule):
+                              [i*MAX + j] symmetric, 0 < r < r_shell, or 0 = r_core.  A pair inside
+                              its own core radius is summed in full (eq. 24), outside it up to
+                              r_shell it is a shell candidate (eq. 25); lists use the pair's
+                              radius with the skin.  Equal across a batch. */
 } rbsog_params;
 
 /* Thermostats (rbsog_params.thermostat), with T from the kinetic energy and
@@ -273,17 +279,17 @@ rbsog_status rbsog_use_graphs(rbsog_ctx* ctx, int enable);
 /* ---- kernel timing ------------------------------------------------------ */
 
 /* Kernel phases timed with HIP events on the stream their kernels run on:
- * the context's stream, or for KSAMPLE and RHO a second stream of the
- * context on which the k-space chain runs beside the pair kernel (so phase
- * times can add up to more than the step). */
+ * the context's stream, or for KSAMPLE, RHO and KFORCE a second stream of
+ * the context on which the k-space chain runs beside the pair kernel (so
+ * phase times can add up to more than the step). */
 typedef enum {
     RBSOG_PHASE_BUILD = 0,     /* cell sort + list build */
     RBSOG_PHASE_KSAMPLE = 1,   /* mode draws of eq. (28) */
     RBSOG_PHASE_PAIR = 2,      /* shell batch + pair forces, eqs. (15), (24)-(25) */
     RBSOG_PHASE_RHO = 3,       /* structure factors, eq. (22), and their fixed-order reduction */
     RBSOG_PHASE_REDUCE = 4,    /* fixed-order reductions: momentum correction, energies */
-    RBSOG_PHASE_KFORCE = 5,    /* k-space force, eq. (29), + closing half kick */
-    RBSOG_PHASE_INTEGRATE = 6, /* opening half kick + drift */
+    RBSOG_PHASE_KFORCE = 5,    /* k-space force, eq. (29) */
+    RBSOG_PHASE_INTEGRATE = 6, /* opening half kick + drift; total force (eqs. 26-29) + closing half kick */
     RBSOG_N_PHASES = 7
 } rbsog_phase;
 

@@ -241,6 +241,11 @@ void validate(const rbsog_params* p)
     for (int i = 0; i < S; ++i) {
         require(p->species[i].mass > 0.0, RBSOG_E_ARG, "species mass must be positive");
         for (int j = 0; j < S; ++j) {
+            const double r = p->r_core_pair[i * RBSOG_MAX_SPECIES + j];
+            require(r == p->r_core_pair[j * RBSOG_MAX_SPECIES + i], RBSOG_E_ARG, "r_core_pair must be symmetric");
+            require(r == 0.0 || (r > 0.0 && r < p->r_shell), RBSOG_E_ARG, "need 0 < r_core_pair < r_shell");
+        }
+        for (int j = 0; j < S; ++j) {
             const rbsog_pair& a = p->pair[i * RBSOG_MAX_SPECIES + j];
             const rbsog_pair& b = p->pair[j * RBSOG_MAX_SPECIES + i];
             require(a.A == b.A && a.sigma == b.sigma && a.rho == b.rho && a.C == b.C && a.D == b.D, RBSOG_E_ARG,
@@ -256,7 +261,8 @@ void require_shared(const rbsog_params& a, const rbsog_params& b)
 {
     bool same = a.n_species == b.n_species && a.r_core == b.r_core && a.r_shell == b.r_shell &&
                 a.skin == b.skin && a.sog_eps == b.sog_eps && a.dt == b.dt && a.rebuild_every == b.rebuild_every &&
-                a.precision == b.precision && a.coulomb_k == b.coulomb_k && a.flags == b.flags;
+                a.precision == b.precision && a.coulomb_k == b.coulomb_k && a.flags == b.flags &&
+                std::memcmp(a.r_core_pair, b.r_core_pair, sizeof(a.r_core_pair)) == 0;
     for (int i = 0; same && i < a.n_species; ++i) {
         same = a.species[i].q == b.species[i].q && a.species[i].mass == b.species[i].mass;
         for (int j = 0; same && j < a.n_species; ++j) {
@@ -267,7 +273,7 @@ void require_shared(const rbsog_params& a, const rbsog_params& b)
     }
     require(same, RBSOG_E_ARG,
             "systems of a batch must share species, pair table, radii, skin, sog_eps, dt, rebuild_every, "
-            "precision, coulomb_k and flags");
+            "precision, coulomb_k, flags and r_core_pair");
 }
 
 // Device copies of the system records, after a host-side change.
@@ -306,6 +312,7 @@ Plan one(const rbsog_ctx* c, int r)
     P.cap_cand = c->plan.cap_cand;
     P.near = c->plan.near;
     P.langevin = c->plan.langevin;
+    P.species_cut = c->plan.species_cut;
     return P;
 }
 
@@ -522,9 +529,10 @@ bool any_thermostat(const rbsog_ctx* c)
     return false;
 }
 
-// The k-space chain (mode draws, structure factors and their reduction)
-// reads positions and writes only mode data, the pair kernel reads positions
-// and writes only short-range forces and its partials: the chain runs on the
+// The k-space chain (mode draws, structure factors, their reduction and the
+// k-space force) reads positions and writes only mode data and the k-space
+// force (into the total-force arrays), the pair kernel reads positions and
+// writes only short-range forces and its partials: the chain runs on the
 // second stream beside the pair kernel, and the first stream waits for it
 // before the sums that need both.
 void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
@@ -545,6 +553,9 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     launch_rho(P, c->mixed, ax);
     launch_rho_finalize(P, ax);
     c->end();
+    c->begin(RBSOG_PHASE_KFORCE, true);
+    launch_kforce(P, c->mixed, ax);
+    c->end();
     HIP_OK(hipEventRecord(c->ev_join, ax));
     c->begin(RBSOG_PHASE_PAIR);
     launch_pair(P, c->coef, c->mixed, energy, st);
@@ -554,8 +565,8 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     c->begin(RBSOG_PHASE_REDUCE);
     launch_finalize(P, energy, st);
     c->end();
-    c->begin(RBSOG_PHASE_KFORCE);
-    launch_kforce(P, c->mixed, kick, ke, st);
+    c->begin(RBSOG_PHASE_INTEGRATE);
+    launch_combine(P, kick, ke, st);
     c->end();
     if (ke) launch_kinetic_finalize(P, kick, st);
 }
@@ -690,7 +701,7 @@ void autotune(rbsog_ctx* c, int reps)
         Tuning t = best;
         t.kf_block = bs;
         try_shape(t);
-        const double ms = time_ms(c, reps, [&] { launch_kforce(c->plan, c->mixed, false, false, st); });
+        const double ms = time_ms(c, reps, [&] { launch_kforce(c->plan, c->mixed, st); });
         if (ms < tb) {
             tb = ms;
             best.kf_block = bs;
@@ -726,6 +737,12 @@ void init_devsys(const rbsog_params& p, int n, DevSys& s)
     }
     const double rcl = p.r_core + p.skin;
     s.rc2_list = rcl * rcl;
+    s.species_cut = 0;
+    for (int i = 0; i < p.n_species; ++i)
+        for (int j = 0; j < p.n_species; ++j) {
+            const double r = p.r_core_pair[i * RBSOG_MAX_SPECIES + j];
+            if (r > 0.0 && r != p.r_core) s.species_cut = 1;
+        }
     const double lo = p.r_core - p.skin;
     s.lo2_list = lo > 0.0 ? lo * lo : 0.0;
     const double hi = p.r_shell + p.skin;
@@ -848,6 +865,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->row_slack = 1.25;
     c->plan.tune = Tuning{};
     c->plan.langevin = false;
+    c->plan.species_cut = false;
     for (const auto& p : prm)
         if (p.t_target > 0.0 && p.tau_t > 0.0 && p.thermostat == RBSOG_THERMO_LANGEVIN) c->plan.langevin = true;
     c->slot_off.assign(slot_off.begin(), slot_off.end() - 1);
@@ -860,6 +878,10 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     for (int r = 0; r < R; ++r) {
         init_devsys(prm[r], prm[r].n_atoms, c->hs[r]);
         c->hs[r].user_off = user_off[r];
+        // the list kernel packs the species above a 28-bit atom index
+        require(!c->hs[r].species_cut || prm[r].n_atoms < (1 << 28), RBSOG_E_ARG,
+                "species-dependent core radii need fewer than 2^28 atoms per system");
+        if (c->hs[r].species_cut) c->plan.species_cut = true;
         c->u_self[r] = 0.5 * p0.coulomb_k * q2[r] * wsum;
     }
     c->d_sys.alloc(sizeof(DevSys) * R);
@@ -936,6 +958,13 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             const rbsog_pair& a = p0.pair[i * RBSOG_MAX_SPECIES + j];
             PairCoef& pc = pcs[i * p0.n_species + j];
             pc.qq = p0.coulomb_k * p0.species[i].q * p0.species[j].q;
+            const double rp = p0.r_core_pair[i * RBSOG_MAX_SPECIES + j];
+            const double rc = rp > 0.0 ? rp : p0.r_core;
+            pc.rc2 = rc * rc;
+            pc.rc2_list = (rc + p0.skin) * (rc + p0.skin);
+            const double lo = rc - p0.skin;
+            pc.lo2_list = lo > 0.0 ? lo * lo : 0.0;
+            pc.pad = 0.0;
             pc.A = a.A;
             pc.sig = a.sigma;
             pc.irho = a.rho > 0.0 ? 1.0 / a.rho : 0.0;
@@ -968,7 +997,15 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
         n_max = std::max(n_max, n);
         const double V = p.box[0] * p.box[1] * p.box[2];
         const double rho_n = n / V;
-        const double rcl = p.r_core + p.skin, lo = p.r_core - p.skin, hi = p.r_shell + p.skin;
+        double rc_max = p.r_core, rc_min = p.r_core;
+        for (int a = 0; a < p.n_species * p.n_species; ++a) {
+            const double r = p.r_core_pair[(a / p.n_species) * RBSOG_MAX_SPECIES + a % p.n_species];
+            if (r > 0.0) {
+                rc_max = std::max(rc_max, r);
+                rc_min = std::min(rc_min, r);
+            }
+        }
+        const double rcl = rc_max + p.skin, lo = rc_min - p.skin, hi = p.r_shell + p.skin;
         const double vc = 4.0 / 3.0 * kPi * rcl * rcl * rcl;
         const double lo3 = lo > 0.0 ? lo * lo * lo : 0.0;
         const double vk = 4.0 / 3.0 * kPi * (hi * hi * hi - lo3);

@@ -32,6 +32,11 @@ struct PairCoef {
     double irho;  // 1/rho
     double C;
     double D;
+    // core/shell split of the pair (species-dependent core radius r_c):
+    double rc2;       // r_c^2 (core sum inside, shell sample outside)
+    double rc2_list;  // (r_c + skin)^2, core-list bound
+    double lo2_list;  // (r_c - skin)^2 (0 if negative), candidate lower bound
+    double pad;
 };
 
 // Near-field SOG sum, split for the kernels.  With b^(2J) = 2 the Gaussian

@@ -435,8 +435,14 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
                         const double dy = min_image(yi - Pj.y, s.L[1], s.invL[1]);
                         const double dz = min_image(zi - Pj.z, s.L[2], s.invL[2]);
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        is_core = r2 < s.rc2_list;
-                        is_cand = r2 >= s.lo2_list && r2 < s.hi2_list;
+                        double rcl = s.rc2_list, lol = s.lo2_list;
+                        if (s.species_cut) {
+                            const PairCoef& pcj = s.pair[(int)Pi.w * s.n_species + (int)Pj.w];
+                            rcl = pcj.rc2_list;
+                            lol = pcj.lo2_list;
+                        }
+                        is_core = r2 < rcl;
+                        is_cand = r2 >= lol && r2 < s.hi2_list;
                     }
                     const uint64_t mc = __ballot(is_core);
                     const uint64_t mk = __ballot(is_cand);
@@ -529,11 +535,20 @@ __device__ inline int chunk_first_atom(const DevSys& s, int chunk)
     return s.cell_start[(int)(((long long)chunk * s.ncell) / s.n_chunks)];
 }
 
-template <int CAP>
+// PC: species-dependent core radii; staged indices then carry the species in
+// their top bits and the core/candidate bounds come per pair from LDS.
+constexpr int kIdxBits = 28;
+constexpr int kIdxMask = (1 << kIdxBits) - 1;
+
+template <int CAP, bool PC>
 __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, int chunk)
 {
     RB_SYS(xcd_block(blockIdx.x, gridDim.x))
     RB_GATE
+    __shared__ double2 thr[PC ? kMaxSpecies * kMaxSpecies : 1];  // (rc2_list, lo2_list) per pair
+    if (PC)
+        for (int t = threadIdx.x; t < s.n_species * s.n_species; t += blockDim.x)
+            thr[t] = make_double2(s.pair[t].rc2_list, s.pair[t].lo2_list);
     if (chunk >= s.n_chunks) return;
     // candidate rows of this chunk's atoms start at its first atom
     const int row0 = chunk_first_atom(s, chunk);
@@ -640,7 +655,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
                             px[d] = P.x;
                             py[d] = P.y;
                             pz[d] = P.z;
-                            val[d] = j;
+                            val[d] = PC ? (j | ((int)P.w << kIdxBits)) : j;
                         }
                         if (lane == leader) lcur[ql] = first + __popcll(m);
                     } else if (lane == leader) {
@@ -785,7 +800,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         // atoms of the unit (indices and list rows in scalar registers); a
         // missing one (index -1) takes part in the sweep but never matches
         double xu[kListA], yu[kListA], zu[kListA];
-        int iu[kListA], ncore[kListA], ncand[kListA];
+        int iu[kListA], tu[kListA], ncore[kListA], ncand[kListA];
         int32_t* crow[kListA];
         int32_t* ccol[kListA];
 #pragma unroll
@@ -795,10 +810,13 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             xu[u] = px[a];
             yu[u] = py[a];
             zu[u] = pz[a];
-            iu[u] = here ? __builtin_amdgcn_readfirstlane(val[a]) : -1;
+            const int va = __builtin_amdgcn_readfirstlane(val[a]);
+            iu[u] = here ? (PC ? va & kIdxMask : va) : -1;
+            tu[u] = (PC && here) ? va >> kIdxBits : 0;
             // a missing atom sweeps into the rows of the unit's first atom,
             // where its misses land on the unused last entry
-            const int ii = here ? iu[u] : __builtin_amdgcn_readfirstlane(val[a0]);
+            const int v0 = __builtin_amdgcn_readfirstlane(val[a0]);
+            const int ii = here ? iu[u] : (PC ? v0 & kIdxMask : v0);
             crow[u] = s.cand_idx + (size_t)(ii - row0) * s.cap_cand;
             ccol[u] = s.core_idx + (size_t)(ii >> 6) * s.cap_core * 64 + (ii & 63);
             ncore[u] = 0;
@@ -817,7 +835,9 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
                 while (rp[k + 1] <= t) ++k;
                 idx = rb[k] + (t - rp[k]);
             }
-            const int j = in ? val[idx] : -1;
+            const int vj = val[idx];
+            const int j = in ? (PC ? vj & kIdxMask : vj) : -1;
+            const int tj = (PC && in) ? vj >> kIdxBits : 0;
             const double pxj = px[idx], pyj = py[idx], pzj = pz[idx];
 #pragma unroll
             for (int u = 0; u < kListA; ++u) {
@@ -831,8 +851,14 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
                 // j = -1 marks an empty lane; iu = -1 an empty atom (bitwise
                 // operators: no short-circuit branches)
                 const bool ok = (j >= 0) & (iu[u] >= 0) & (j != iu[u]);
-                const bool is_core = ok & (r2 < s.rc2_list);
-                const bool is_cand = ok & (r2 >= s.lo2_list) & (r2 < s.hi2_list);
+                double rcl = s.rc2_list, lol = s.lo2_list;
+                if (PC) {
+                    const double2 th = thr[tu[u] * s.n_species + tj];
+                    rcl = th.x;
+                    lol = th.y;
+                }
+                const bool is_core = ok & (r2 < rcl);
+                const bool is_cand = ok & (r2 >= lol) & (r2 < s.hi2_list);
                 const uint64_t mc = __ballot(is_core);
                 const uint64_t mk = __ballot(is_cand);
                 // Every lane stores (no exec-mask branches): a miss goes to the
@@ -1110,7 +1136,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
                     const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < s.rc2) {
+                    if (r2 < (s.species_cut ? pc[ti * S + T[u]].rc2 : s.rc2)) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
                         add_pair<ENERGY>(f, uu, dx, dy, dz, Fx, Fy, Fz, Uc, Wv);
@@ -1147,7 +1173,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
                     const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 >= s.rc2 && r2 < s.rs2) {
+                    if (r2 >= (s.species_cut ? pc[ti * S + T[u]].rc2 : s.rc2) && r2 < s.rs2) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
                         add_pair<ENERGY>(f, uu, dx, dy, dz, Sx, Sy, Sz, Su, Wv);
@@ -1204,7 +1230,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
                     const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 >= s.rc2 && r2 < s.rs2) {
+                    if (r2 >= (s.species_cut ? pc[ti * S + T[u]].rc2 : s.rc2) && r2 < s.rs2) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
                         add_pair<ENERGY>(f, uu, dx, dy, dz, Sx, Sy, Sz, Su, Wv);
@@ -1624,7 +1650,12 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
 // modes two at a time; adds the short-range force minus the momentum
 // correction, optionally the closing half kick of velocity Verlet.  The mixed
 // form takes Im(e^{-i theta} rho) coef in FP32 and accumulates in FP64.
-template <bool MIXED, bool KICK, bool ENERGY>
+// k-space force of eq. (29) (eq. (23) for the full sum) of each atom,
+// -k_e q_i sum_p (2 pi m_p / L) coef_p Im(e^{-i theta} rho_p), written into
+// the total-force arrays, which hold it until k_combine adds the short-range
+// part.  Needs only the positions and rho: it runs on the second stream
+// beside the pair kernel.
+template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restrict__ kd)
 {
     RB_SYS(blockIdx.x)
@@ -1636,7 +1667,6 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
         __syncthreads();
     }
     const int i = lb * blockDim.x + threadIdx.x;
-    double ke = 0.0;
     if (i < s.n) {
         const double4 Pi = s.p[i];
         const double sc = MIXED ? 1.0 : (double)kTableSize;
@@ -1669,12 +1699,27 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
             one(m1);
         }
         if (p < k.n_modes) one(k.modes[p]);
+        const double qk = -s.coulomb_k * s.spc->q[s.type[i]];
+        s.fx[i] = qk * s.two_pi_L[0] * Gx;
+        s.fy[i] = qk * s.two_pi_L[1] * Gy;
+        s.fz[i] = qk * s.two_pi_L[2] * Gz;
+    }
+}
+
+// Total force F = (F_short - F_corr) + F_k (eqs. 26-29; F_k from k_kforce),
+// the closing half kick, and kinetic-energy partials.
+template <bool KICK, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_combine(RB_ARGS)
+{
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
+    double ke = 0.0;
+    if (i < s.n) {
         const int ti = s.type[i];
-        const double qk = -s.coulomb_k * s.spc->q[ti];
         const DeviceScalars* scal = s.sc;
-        const double fx = s.fsx[i] - scal->p_corr[0] + qk * s.two_pi_L[0] * Gx;
-        const double fy = s.fsy[i] - scal->p_corr[1] + qk * s.two_pi_L[1] * Gy;
-        const double fz = s.fsz[i] - scal->p_corr[2] + qk * s.two_pi_L[2] * Gz;
+        const double fx = s.fsx[i] - scal->p_corr[0] + s.fx[i];
+        const double fy = s.fsy[i] - scal->p_corr[1] + s.fy[i];
+        const double fz = s.fsz[i] - scal->p_corr[2] + s.fz[i];
         s.fx[i] = fx;
         s.fy[i] = fy;
         s.fz[i] = fz;
@@ -1923,12 +1968,22 @@ void launch_build(const Plan& P, bool gate, hipStream_t st)
     const size_t sm_sel = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * 64;
     for (int k = 0; k < K; ++k) {
         const Shape& cs = P.stored ? P.cell_chunk[k] : P.cells;
-        if (P.list_mode == 0) {
-            if (cs.blocks > 0) k_lists_cell<kListCaps[0]><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
-        } else if (P.list_mode == 1) {
-            if (cs.blocks > 0) k_lists_cell<kListCaps[1]><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
-        } else if (P.list_mode == 2) {
-            if (cs.blocks > 0) k_lists_cell<kListCaps[2]><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);
+#define RB_LISTS(C)                                                                                    \
+    do {                                                                                               \
+        if (P.species_cut)                                                                             \
+            k_lists_cell<kListCaps[C], true><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k);  \
+        else                                                                                           \
+            k_lists_cell<kListCaps[C], false><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k); \
+    } while (0)
+        if (P.list_mode < kListPerAtom) {
+            if (cs.blocks > 0) {
+                if (P.list_mode == 0)
+                    RB_LISTS(0);
+                else if (P.list_mode == 1)
+                    RB_LISTS(1);
+                else
+                    RB_LISTS(2);
+            }
         } else {
             int capP2 = 1;
             while (capP2 < P.cap_cand) capP2 <<= 1;
@@ -1937,6 +1992,7 @@ void launch_build(const Plan& P, bool gate, hipStream_t st)
         }
         if (P.stored && P.rows64.blocks > 0) k_select<<<P.rows64.blocks, 64, sm_sel, st>>>(RB_MAP(rows64), g, k);
     }
+#undef RB_LISTS
     k_build_done<<<1, 64, 0, st>>>(P.sys, P.R, g);
 }
 
@@ -2011,26 +2067,32 @@ void launch_finalize(const Plan& P, bool energy, hipStream_t st)
     if (P.R > 0) k_finalize<<<P.R, 1024, 0, st>>>(P.sys, P.kd, energy ? 1 : 0);
 }
 
-void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st)
+void launch_kforce(const Plan& P, bool mixed, hipStream_t st)
 {
     const int nb = P.kf_atoms.blocks;
     const int bs = P.tune.kf_block;
     if (nb <= 0) return;
-#define RB_KF(M, K, E) k_kforce<M, K, E><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd)
-    if (mixed) {
-        if (kick) {
-            if (energy) RB_KF(true, true, true); else RB_KF(true, true, false);
-        } else {
-            if (energy) RB_KF(true, false, true); else RB_KF(true, false, false);
-        }
+    if (mixed)
+        k_kforce<true><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+    else
+        k_kforce<false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+}
+
+void launch_combine(const Plan& P, bool kick, bool energy, hipStream_t st)
+{
+    const int nb = P.atoms.blocks;
+    if (nb <= 0) return;
+    if (kick) {
+        if (energy)
+            k_combine<true, true><<<nb, kBlock, 0, st>>>(RB_MAP(atoms));
+        else
+            k_combine<true, false><<<nb, kBlock, 0, st>>>(RB_MAP(atoms));
     } else {
-        if (kick) {
-            if (energy) RB_KF(false, true, true); else RB_KF(false, true, false);
-        } else {
-            if (energy) RB_KF(false, false, true); else RB_KF(false, false, false);
-        }
+        if (energy)
+            k_combine<false, true><<<nb, kBlock, 0, st>>>(RB_MAP(atoms));
+        else
+            k_combine<false, false><<<nb, kBlock, 0, st>>>(RB_MAP(atoms));
     }
-#undef RB_KF
 }
 
 void launch_kinetic_finalize(const Plan& P, bool step_end, hipStream_t st)

@@ -38,6 +38,7 @@ struct DevSys {
     double two_pi_L[3];
     double rc2_list, lo2_list, hi2_list;  // (r_core+skin)^2, (r_core-skin)^2, (r_shell+skin)^2
     double rc2, rs2;                      // r_core^2, r_shell^2
+    int species_cut;       // core radii differ between species pairs (PairCoef rc2, rc2_list, lo2_list)
     double half_skin2;
     double dt, coulomb_k;
     double thermo_c;       // dt / tau_t (0: no thermostat)
@@ -164,6 +165,7 @@ struct Plan {
     int list_mode = 0;  // < kListPerAtom: per-cell list kernel staging kListCaps[mode] atoms; else per-atom kernel
     bool stored = false;  // memory form: batch drawn at the build
     bool langevin = false;  // some system runs the Langevin thermostat
+    bool species_cut = false;  // species-dependent core radii
     int n_chunks = 1;     // build chunks (1 unless stored)
     int cap_core = 0, cap_cand = 0;
     NearTab near;
@@ -188,7 +190,11 @@ void launch_rho(const Plan& P, bool mixed, hipStream_t st);
 void launch_rho_finalize(const Plan& P, hipStream_t st);
 // momentum correction and energies; with `energy` also the virial
 void launch_finalize(const Plan& P, bool energy, hipStream_t st);
-void launch_kforce(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st);
+// k-space force (eq. 29) into the total-force arrays
+void launch_kforce(const Plan& P, bool mixed, hipStream_t st);
+// total force = short range - momentum correction + k-space; with kick the
+// closing half kick; with energy the kinetic-energy partials
+void launch_combine(const Plan& P, bool kick, bool energy, hipStream_t st);
 // kinetic energy from the partials; with a thermostat also the velocity
 // factor of the next step.  step_end: the partials are those of a step's
 // closing kick (the Nose-Hoover closing half step is taken), else a

@@ -50,6 +50,7 @@ class Params(C.Structure):
         ("rebuild_every", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
         ("replica", C.c_uint32), ("flags", C.c_uint32), ("coulomb_k", C.c_double),
         ("t_target", C.c_double), ("tau_t", C.c_double), ("thermostat", C.c_int32), ("reserved", C.c_int32),
+        ("r_core_pair", C.c_double * (MAX_SPECIES * MAX_SPECIES)),
     ]
 
 
@@ -165,6 +166,11 @@ def make_params(sysp: dict, precision: int = FP64, n_atoms: int | None = None) -
     p.t_target = float(sysp.get("t_target", 0.0))
     p.tau_t = float(sysp.get("tau_t", 0.0))
     p.thermostat = THERMOSTATS[sysp.get("thermostat", "berendsen")]
+    rcp = sysp.get("r_core_pair")
+    if rcp is not None:
+        for i in range(S):
+            for j in range(S):
+                p.r_core_pair[i * MAX_SPECIES + j] = float(rcp[i][j])
     return p
 
 
