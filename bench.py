@@ -55,7 +55,7 @@ def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-TUNING_KEYS = ("pair_block", "pair_ku", "rho_mpl", "kf_block")
+TUNING_KEYS = ("pair_block", "pair_ku", "rho_mpl", "kf_block", "kf_aux")
 
 
 def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto", thermostat: str = "berendsen",
@@ -312,7 +312,7 @@ def main() -> int:
                     help="timed steps of the Nose-Hoover and Langevin legs on the main workload (0: skip)")
     ap.add_argument("--tuning", default="auto",
                     help="launch shapes of the single-system runs: auto (autotuned) or "
-                         "pair_block,pair_ku,rho_mpl,kf_block")
+                         "pair_block,pair_ku,rho_mpl,kf_block,kf_aux")
     args = ap.parse_args()
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)

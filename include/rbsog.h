@@ -251,14 +251,17 @@ rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* f
  * calls.  Needs no GPU work. */
 rbsog_status rbsog_set_list_chunks(rbsog_ctx* ctx, int32_t chunks);
 
-/* Launch shapes of the hot kernels.  No choice changes a result bit: partial
- * sums are taken per 64-atom wavefront and every structure factor is summed
- * over the atoms in the same order whatever the shape. */
+/* Launch shapes of the hot kernels and the stream of the k-space force.  No
+ * choice changes a result bit: partial sums are taken per 64-atom wavefront
+ * and every structure factor is summed over the atoms in the same order
+ * whatever the shape. */
 typedef struct {
     int32_t pair_block; /* atoms per workgroup of the pair kernel: 64, 128, 256 (default 256) */
     int32_t pair_ku;    /* neighbour positions fetched ahead per lane (shell-batch tile): 4, 8 (4) */
     int32_t rho_mpl;    /* k-modes per lane of the rho kernel (64 rho_mpl per workgroup): 1, 2 (1) */
     int32_t kf_block;   /* atoms per workgroup of the k-space force kernel: 64, 128, 256 (256) */
+    int32_t kf_aux;     /* 1: the k-space force follows rho on the second stream, beside the pair
+                           kernel; 0: it runs after the pair kernel on the context's stream (1) */
 } rbsog_tuning;
 
 /* Time every candidate shape of each hot kernel with `reps` launches at the
@@ -288,8 +291,10 @@ typedef enum {
     RBSOG_PHASE_PAIR = 2,      /* shell batch + pair forces, eqs. (15), (24)-(25) */
     RBSOG_PHASE_RHO = 3,       /* structure factors, eq. (22), and their fixed-order reduction */
     RBSOG_PHASE_REDUCE = 4,    /* fixed-order reductions: momentum correction, energies */
-    RBSOG_PHASE_KFORCE = 5,    /* k-space force, eq. (29) */
-    RBSOG_PHASE_INTEGRATE = 6, /* opening half kick + drift; total force (eqs. 26-29) + closing half kick */
+    RBSOG_PHASE_KFORCE = 5,    /* k-space force, eq. (29); with kf_aux = 0 fused with the total
+                                  force (eqs. 26-29) and the closing half kick */
+    RBSOG_PHASE_INTEGRATE = 6, /* opening half kick + drift; with kf_aux = 1 also the total force
+                                  (eqs. 26-29) and the closing half kick */
     RBSOG_N_PHASES = 7
 } rbsog_phase;
 

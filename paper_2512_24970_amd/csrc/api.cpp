@@ -553,9 +553,11 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     launch_rho(P, c->mixed, ax);
     launch_rho_finalize(P, ax);
     c->end();
-    c->begin(RBSOG_PHASE_KFORCE, true);
-    launch_kforce(P, c->mixed, ax);
-    c->end();
+    if (P.tune.kf_aux) {
+        c->begin(RBSOG_PHASE_KFORCE, true);
+        launch_kforce(P, c->mixed, ax);
+        c->end();
+    }
     HIP_OK(hipEventRecord(c->ev_join, ax));
     c->begin(RBSOG_PHASE_PAIR);
     launch_pair(P, c->coef, c->mixed, energy, st);
@@ -565,9 +567,15 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     c->begin(RBSOG_PHASE_REDUCE);
     launch_finalize(P, energy, st);
     c->end();
-    c->begin(RBSOG_PHASE_INTEGRATE);
-    launch_combine(P, kick, ke, st);
-    c->end();
+    if (P.tune.kf_aux) {
+        c->begin(RBSOG_PHASE_INTEGRATE);
+        launch_combine(P, kick, ke, st);
+        c->end();
+    } else {
+        c->begin(RBSOG_PHASE_KFORCE);
+        launch_kforce_fused(P, c->mixed, kick, ke, st);
+        c->end();
+    }
     if (ke) launch_kinetic_finalize(P, kick, st);
 }
 
@@ -707,6 +715,18 @@ void autotune(rbsog_ctx* c, int reps)
             best.kf_block = bs;
         }
     }
+    // the k-space force beside the pair kernel pays off while the chain on the
+    // second stream stays the shorter one: time whole evaluations both ways
+    // (alternating, best of several rounds: the two are often close)
+    double tk[2] = {1e300, 1e300};
+    for (int round = 0; round < 4; ++round)
+        for (int aux : {1, 0}) {
+            Tuning t = best;
+            t.kf_aux = aux;
+            c->plan.tune = t;  // same launch shapes: no new block maps
+            tk[aux] = std::min(tk[aux], time_ms(c, std::max(reps, 5), [&] { enqueue_forces(c, false, false); }));
+        }
+    best.kf_aux = tk[1] <= tk[0] ? 1 : 0;
     try_shape(best);
     enqueue_forces(c, false, false);
     HIP_OK(hipStreamSynchronize(st));
@@ -1298,7 +1318,7 @@ rbsog_status rbsog_autotune(rbsog_ctx* ctx, int32_t reps, rbsog_tuning* chosen)
         autotune(ctx, reps);
         if (chosen) {
             const Tuning& t = ctx->plan.tune;
-            *chosen = rbsog_tuning{t.pair_block, t.pair_ku, t.rho_mpl, t.kf_block};
+            *chosen = rbsog_tuning{t.pair_block, t.pair_ku, t.rho_mpl, t.kf_block, t.kf_aux};
         }
     });
 }
@@ -1314,9 +1334,9 @@ rbsog_status rbsog_set_tuning(rbsog_ctx* ctx, const rbsog_tuning* t)
             return false;
         };
         require(one_of(t->pair_block, {64, 128, 256}) && one_of(t->pair_ku, {4, 8}) && one_of(t->rho_mpl, {1, 2}) &&
-                    one_of(t->kf_block, {64, 128, 256}),
+                    one_of(t->kf_block, {64, 128, 256}) && one_of(t->kf_aux, {0, 1}),
                 RBSOG_E_ARG, "tuning value out of range");
-        ctx->plan.tune = Tuning{t->pair_block, t->pair_ku, t->rho_mpl, t->kf_block};
+        ctx->plan.tune = Tuning{t->pair_block, t->pair_ku, t->rho_mpl, t->kf_block, t->kf_aux};
         plan_launches(ctx);
     });
 }
@@ -1327,7 +1347,7 @@ rbsog_status rbsog_get_tuning(rbsog_ctx* ctx, rbsog_tuning* t)
         need_system(ctx);
         require(t != nullptr, RBSOG_E_ARG, "tuning is NULL");
         const Tuning& u = ctx->plan.tune;
-        *t = rbsog_tuning{u.pair_block, u.pair_ku, u.rho_mpl, u.kf_block};
+        *t = rbsog_tuning{u.pair_block, u.pair_ku, u.rho_mpl, u.kf_block, u.kf_aux};
     });
 }
 

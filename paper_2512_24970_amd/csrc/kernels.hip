@@ -1651,11 +1651,13 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
 // correction, optionally the closing half kick of velocity Verlet.  The mixed
 // form takes Im(e^{-i theta} rho) coef in FP32 and accumulates in FP64.
 // k-space force of eq. (29) (eq. (23) for the full sum) of each atom,
-// -k_e q_i sum_p (2 pi m_p / L) coef_p Im(e^{-i theta} rho_p), written into
-// the total-force arrays, which hold it until k_combine adds the short-range
-// part.  Needs only the positions and rho: it runs on the second stream
-// beside the pair kernel.
-template <bool MIXED>
+// F_k = -k_e q_i sum_p (2 pi m_p / L) coef_p Im(e^{-i theta} rho_p).
+// FUSED = false: written into the total-force arrays, which hold it until
+// k_combine adds the short-range part (it needs only the positions and rho,
+// so it can run on the second stream beside the pair kernel).  FUSED: the
+// total force (F_short - F_corr) + F_k, closing kick and kinetic-energy
+// partials in the same pass, as k_combine computes them.
+template <bool MIXED, bool FUSED, bool KICK, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restrict__ kd)
 {
     RB_SYS(blockIdx.x)
@@ -1667,6 +1669,7 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
         __syncthreads();
     }
     const int i = lb * blockDim.x + threadIdx.x;
+    double ke = 0.0;
     if (i < s.n) {
         const double4 Pi = s.p[i];
         const double sc = MIXED ? 1.0 : (double)kTableSize;
@@ -1699,11 +1702,34 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
             one(m1);
         }
         if (p < k.n_modes) one(k.modes[p]);
-        const double qk = -s.coulomb_k * s.spc->q[s.type[i]];
-        s.fx[i] = qk * s.two_pi_L[0] * Gx;
-        s.fy[i] = qk * s.two_pi_L[1] * Gy;
-        s.fz[i] = qk * s.two_pi_L[2] * Gz;
+        const int ti = s.type[i];
+        const double qk = -s.coulomb_k * s.spc->q[ti];
+        if (!FUSED) {
+            s.fx[i] = qk * s.two_pi_L[0] * Gx;
+            s.fy[i] = qk * s.two_pi_L[1] * Gy;
+            s.fz[i] = qk * s.two_pi_L[2] * Gz;
+        } else {
+            const DeviceScalars* scal = s.sc;
+            const double fx = s.fsx[i] - scal->p_corr[0] + qk * s.two_pi_L[0] * Gx;
+            const double fy = s.fsy[i] - scal->p_corr[1] + qk * s.two_pi_L[1] * Gy;
+            const double fz = s.fsz[i] - scal->p_corr[2] + qk * s.two_pi_L[2] * Gz;
+            s.fx[i] = fx;
+            s.fy[i] = fy;
+            s.fz[i] = fz;
+            if (KICK) {
+                const double a = 0.5 * s.dt * s.spc->inv_mass_acc[ti];
+                const double vx = s.vx[i] + a * fx, vy = s.vy[i] + a * fy, vz = s.vz[i] + a * fz;
+                s.vx[i] = vx;
+                s.vy[i] = vy;
+                s.vz[i] = vz;
+                if (ENERGY) ke = 0.5 * s.spc->mass[ti] * (vx * vx + vy * vy + vz * vz);
+            } else if (ENERGY) {
+                const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+                ke = 0.5 * s.spc->mass[ti] * (vx * vx + vy * vy + vz * vz);
+            }
+        }
     }
+    if (FUSED && ENERGY) wave_partial(ke, i, s.n, s.kin_part, 1, 0);
 }
 
 // Total force F = (F_short - F_corr) + F_k (eqs. 26-29; F_k from k_kforce),
@@ -2073,9 +2099,31 @@ void launch_kforce(const Plan& P, bool mixed, hipStream_t st)
     const int bs = P.tune.kf_block;
     if (nb <= 0) return;
     if (mixed)
-        k_kforce<true><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+        k_kforce<true, false, false, false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
     else
-        k_kforce<false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+        k_kforce<false, false, false, false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+}
+
+void launch_kforce_fused(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st)
+{
+    const int nb = P.kf_atoms.blocks;
+    const int bs = P.tune.kf_block;
+    if (nb <= 0) return;
+#define RB_KF(M, K, E) k_kforce<M, true, K, E><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd)
+    if (mixed) {
+        if (kick) {
+            if (energy) RB_KF(true, true, true); else RB_KF(true, true, false);
+        } else {
+            if (energy) RB_KF(true, false, true); else RB_KF(true, false, false);
+        }
+    } else {
+        if (kick) {
+            if (energy) RB_KF(false, true, true); else RB_KF(false, true, false);
+        } else {
+            if (energy) RB_KF(false, false, true); else RB_KF(false, false, false);
+        }
+    }
+#undef RB_KF
 }
 
 void launch_combine(const Plan& P, bool kick, bool energy, hipStream_t st)

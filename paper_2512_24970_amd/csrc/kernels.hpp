@@ -128,6 +128,7 @@ struct Tuning {
     int pair_ku = 4;       // neighbours fetched ahead in the pair kernel (4, 8)
     int rho_mpl = 1;       // modes per lane in the rho kernel (1, 2)
     int kf_block = 256;    // atoms per k-space force workgroup (64, 128, 256)
+    int kf_aux = 1;        // k-space force on the second stream (1) or after the pair kernel (0)
 };
 
 // FP32 near-field table of the mixed pair kernel (built on the host, shared
@@ -195,6 +196,8 @@ void launch_kforce(const Plan& P, bool mixed, hipStream_t st);
 // total force = short range - momentum correction + k-space; with kick the
 // closing half kick; with energy the kinetic-energy partials
 void launch_combine(const Plan& P, bool kick, bool energy, hipStream_t st);
+// the k-space force and the combine in one pass (no second stream)
+void launch_kforce_fused(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st);
 // kinetic energy from the partials; with a thermostat also the velocity
 // factor of the next step.  step_end: the partials are those of a step's
 // closing kick (the Nose-Hoover closing half step is taken), else a

@@ -55,7 +55,8 @@ class Params(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("pair_block", C.c_int32), ("pair_ku", C.c_int32), ("rho_mpl", C.c_int32), ("kf_block", C.c_int32)]
+    _fields_ = [("pair_block", C.c_int32), ("pair_ku", C.c_int32), ("rho_mpl", C.c_int32), ("kf_block", C.c_int32),
+                ("kf_aux", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -207,15 +207,15 @@ def _same(a, b):
 
 @pytest.mark.parametrize("precision", [R.FP64, R.MIXED])
 def test_tuning_changes_no_bit(precision):
-    """Every launch shape the tuner can pick gives bitwise the same forces and
-    12-step trajectory (with rebuilds) as the default shapes; so does the
-    autotuned one."""
+    """Every launch shape the tuner can pick (and either stream for the
+    k-space force) gives bitwise the same forces and 12-step trajectory (with
+    rebuilds) as the default shapes; so does the autotuned one."""
     _say(f"case: tuning shapes, batch of 5, precision {precision}")
     cfgs = _small_batch(skin=0.3, rebuild_every=5)
     ctx, _ = _gpu_batch(cfgs, precision)
     ref = _trajectory(ctx)
-    shapes = [dict(pair_block=64, pair_ku=8, rho_mpl=2, kf_block=64),
-              dict(pair_block=128, pair_ku=4, rho_mpl=2, kf_block=128)]
+    shapes = [dict(pair_block=64, pair_ku=8, rho_mpl=2, kf_block=64, kf_aux=0),
+              dict(pair_block=128, pair_ku=4, rho_mpl=2, kf_block=128, kf_aux=1)]
     for sh in shapes:
         ctx, _ = _gpu_batch(cfgs, precision)
         ctx.rbsog_set_tuning(**sh)
