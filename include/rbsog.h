@@ -243,6 +243,15 @@ rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* f
 
 /* ---- launch shapes and step graphs -------------------------------------- */
 
+/* Per-atom list capacities (entries; one is kept as a write sink, so a list
+ * holds at most cap - 1): replan the lists with these capacities and build
+ * them at the current positions (a new list build).  A build that later
+ * overflows them grows them again (rbsog_step restarts its call from the
+ * state at its start).  got_core / got_cand (may be NULL) receive the
+ * capacities in force after the build.  8..4096.  Synchronises. */
+rbsog_status rbsog_set_list_capacity(rbsog_ctx* ctx, int32_t cap_core, int32_t cap_cand, int32_t* got_core,
+                                     int32_t* got_cand);
+
 /* Memory form (RBSOG_FLAG_SHELL_STORED): build the lists in `chunks`
  * launches over consecutive ranges of cells (1..64, default 8; a system
  * with fewer cells uses one chunk per cell), so the candidate rows exist for

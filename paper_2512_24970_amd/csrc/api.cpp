@@ -1604,6 +1604,22 @@ rbsog_status rbsog_get_shell_batch(rbsog_ctx* ctx, int32_t* n_cand, int32_t* ids
     });
 }
 
+rbsog_status rbsog_set_list_capacity(rbsog_ctx* ctx, int32_t cap_core, int32_t cap_cand, int32_t* got_core,
+                                     int32_t* got_cand)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        require(cap_core >= 8 && cap_core <= 4096 && cap_cand >= 8 && cap_cand <= 4096, RBSOG_E_ARG,
+                "capacities out of range (8..4096)");
+        plan_lists(ctx, cap_core, cap_cand);
+        plan_launches(ctx);
+        build_checked(ctx);
+        ctx->forces_valid = false;
+        if (got_core) *got_core = ctx->plan.cap_core;
+        if (got_cand) *got_cand = ctx->plan.cap_cand;
+    });
+}
+
 rbsog_status rbsog_set_list_chunks(rbsog_ctx* ctx, int32_t chunks)
 {
     return guarded(ctx, [&] {

@@ -104,6 +104,8 @@ ABI = {
     "rbsog_get_shell_ranks": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "rbsog_get_shell_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbsog_set_list_chunks": (C.c_int, [C.c_void_p, C.c_int32]),
+    "rbsog_set_list_capacity": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32)]),
     "rbsog_get_kmodes": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_double)]),
     "rbsog_get_rho": (C.c_int, [C.c_void_p, C.c_void_p]),
     "rbsog_get_sog": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -307,6 +309,12 @@ class Context:
 
     def rbsog_use_graphs(self, on: bool = True):
         self._check(lib().rbsog_use_graphs(self._h, 1 if on else 0), "rbsog_use_graphs")
+
+    def rbsog_set_list_capacity(self, cap_core: int, cap_cand: int):
+        gc, gk = C.c_int32(), C.c_int32()
+        self._check(lib().rbsog_set_list_capacity(self._h, cap_core, cap_cand, C.byref(gc), C.byref(gk)),
+                    "rbsog_set_list_capacity")
+        return gc.value, gk.value
 
     def rbsog_set_list_chunks(self, chunks: int):
         self._check(lib().rbsog_set_list_chunks(self._h, chunks), "rbsog_set_list_chunks")
