@@ -57,12 +57,14 @@ class Params(C.Structure):
 class Energy(C.Structure):
     _fields_ = [("u_core", C.c_double), ("u_shell", C.c_double), ("u_kspace", C.c_double),
                 ("u_self", C.c_double), ("u_total", C.c_double), ("kinetic", C.c_double),
-                ("p_corr", C.c_double * 3), ("e_thermostat", C.c_double), ("virial", C.c_double * 6)]
+                ("p_corr", C.c_double * 3), ("e_thermostat", C.c_double), ("virial", C.c_double * 6),
+                ("stress", C.c_double * 6), ("heat_flux", C.c_double * 3)]
 
     def as_dict(self) -> dict:
         return {"u_core": self.u_core, "u_shell": self.u_shell, "u_kspace": self.u_kspace,
                 "u_self": self.u_self, "u_total": self.u_total, "kinetic": self.kinetic,
-                "p_corr": list(self.p_corr), "e_thermostat": self.e_thermostat, "virial": list(self.virial)}
+                "p_corr": list(self.p_corr), "e_thermostat": self.e_thermostat, "virial": list(self.virial),
+                "stress": list(self.stress), "heat_flux": list(self.heat_flux)}
 
 
 _lib = None

@@ -474,6 +474,8 @@ struct orc_ctx {
     uint64_t eval;
     uint64_t n_builds; /* list builds so far */
     double nh_x, nh_v; /* Nose-Hoover variable xi and its velocity */
+    double* epot;      /* [n] per-atom potential energy of the last evaluation */
+    double* wat;       /* [n][6] per-atom virial of the last evaluation */
     /* lists */
     int32_t* core_off;
     int32_t* core;
@@ -583,6 +585,8 @@ void orc_destroy(orc_ctx* c)
     free(c->cand_off);
     free(c->cand);
     free(c->ref);
+    free(c->epot);
+    free(c->wat);
     if (c->have_kt) ktab_free(&c->kt);
     free(c);
 }
@@ -842,21 +846,28 @@ static void short_atom(const orc_params* p, const orc_ctx* c, int i, const int32
         for (int a = 0; a < 6; ++a) w_out[a] = Wc[a] + wgt * Ws[a];
 }
 
-int orc_forces_short(orc_ctx* c, uint64_t eval, double* force, double* u_core, double* u_shell,
-                     double* virial)
+/* Short-range force, and per atom its core energy, shell energy and virial. */
+static void short_parts(orc_ctx* c, uint64_t eval, double* force, double* uc, double* us, double* wv)
 {
     if (!c->core_off) orc_build_lists(c);
     const orc_params* p = &c->p;
     int n = c->n;
-    double* uc = (double*)calloc(n > 0 ? n : 1, sizeof(double));
-    double* us = (double*)calloc(n > 0 ? n : 1, sizeof(double));
-    double* wv = (double*)calloc(6 * (n > 0 ? n : 1), sizeof(double));
 #pragma omp parallel for schedule(dynamic, 16) num_threads(ORC_NT)
     for (int i = 0; i < n; ++i) {
         short_atom(p, c, i, c->core + c->core_off[i], c->core_off[i + 1] - c->core_off[i],
                    c->cand + c->cand_off[i], c->cand_off[i + 1] - c->cand_off[i], eval, force + 3 * i, uc + i,
                    us + i, wv + 6 * i);
     }
+}
+
+int orc_forces_short(orc_ctx* c, uint64_t eval, double* force, double* u_core, double* u_shell,
+                     double* virial)
+{
+    int n = c->n;
+    double* uc = (double*)calloc(n > 0 ? n : 1, sizeof(double));
+    double* us = (double*)calloc(n > 0 ? n : 1, sizeof(double));
+    double* wv = (double*)calloc(6 * (n > 0 ? n : 1), sizeof(double));
+    short_parts(c, eval, force, uc, us, wv);
     double Uc = 0.0, Us = 0.0;
     for (int i = 0; i < n; ++i) {
         Uc += uc[i];
@@ -949,9 +960,37 @@ void orc_kforce_atoms(const orc_ctx* c, int32_t n_modes, const int32_t* m, const
 
 static double box_volume(const orc_params* p) { return p->box[0] * p->box[1] * p->box[2]; }
 
+/* Per-atom split of the k-space energy and virial: mode p's energy
+ * (k_e/2) coef_p |rho_p|^2 is shared among atoms as (k_e/2) coef_p q_i
+ * Re(e^{-ik.r_i} rho_p) (these sum to it), its virial alike with the
+ * factor (delta_ab - g_p k_a k_b).  Adds into epot[n] and wat[n][6]. */
+static void kspace_atom_parts(const orc_ctx* c, long cnt, const int32_t* m, const double* rho, const double* coef,
+                              const double* g, double* epot, double* wat)
+{
+    const orc_params* p = &c->p;
+#pragma omp parallel for schedule(static) num_threads(ORC_NT)
+    for (int i = 0; i < c->n; ++i) {
+        const double* r = c->pos + 3 * i;
+        double qh = 0.5 * p->coulomb_k * p->q[c->type[i]];
+        double e = 0.0, w[6] = {0, 0, 0, 0, 0, 0};
+        for (long t = 0; t < cnt; ++t) {
+            double k[3];
+            for (int a = 0; a < 3; ++a) k[a] = 2.0 * ORC_PI * (double)m[3 * t + a] / p->box[a];
+            double th = k[0] * r[0] + k[1] * r[1] + k[2] * r[2];
+            /* Re(e^{-i th} rho) = cos(th) Re rho + sin(th) Im rho */
+            double re = cos(th) * rho[2 * t] + sin(th) * rho[2 * t + 1];
+            double x = qh * coef[t] * re;
+            e += x;
+            mode_virial(x, g[t], k, w);
+        }
+        epot[i] += e;
+        for (int a = 0; a < 6; ++a) wat[6 * i + a] += w[a];
+    }
+}
+
 /* Full k-sum of eq. (23) over every k != 0 whose narrowest-Gaussian factor
  * exp(-s^2 k^2 / 2) is at least e^-45. */
-static int kspace_full(orc_ctx* c, double* force, double* u_k, double* virial)
+static int kspace_full(orc_ctx* c, double* force, double* u_k, double* virial, double* epot, double* wat)
 {
     const orc_params* p = &c->p;
     int nmax[3];
@@ -1001,6 +1040,22 @@ static int kspace_full(orc_ctx* c, double* force, double* u_k, double* virial)
             mode_virial(0.5 * p->coulomb_k * e, orc_far_hat_g(p, kk) / fh[t], k, virial);
         }
     }
+    if (epot) {
+        double* coef = (double*)malloc(sizeof(double) * (cnt + 1));
+        double* g = (double*)malloc(sizeof(double) * (cnt + 1));
+        for (long t = 0; t < cnt; ++t) {
+            double k2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double k = 2.0 * ORC_PI * (double)m[3 * t + a] / p->box[a];
+                k2 += k * k;
+            }
+            coef[t] = fh[t] / V;
+            g[t] = orc_far_hat_g(p, sqrt(k2)) / fh[t];
+        }
+        kspace_atom_parts(c, cnt, m, rho, coef, g, epot, wat);
+        free(coef);
+        free(g);
+    }
     /* eq. (23): F_i = -sum_k (q_i k / V) F^(k) Im(e^{-ik.r_i} rho(k)) */
 #pragma omp parallel for schedule(static) num_threads(ORC_NT)
     for (int i = 0; i < c->n; ++i) {
@@ -1022,10 +1077,19 @@ static int kspace_full(orc_ctx* c, double* force, double* u_k, double* virial)
     return 0;
 }
 
+static int kspace_parts(orc_ctx* c, uint64_t eval, double* force, double* u_k, double* virial, double* epot,
+                        double* wat);
+
 int orc_forces_kspace(orc_ctx* c, uint64_t eval, double* force, double* u_k, double* virial)
 {
+    return kspace_parts(c, eval, force, u_k, virial, NULL, NULL);
+}
+
+static int kspace_parts(orc_ctx* c, uint64_t eval, double* force, double* u_k, double* virial, double* epot,
+                        double* wat)
+{
     const orc_params* p = &c->p;
-    if (p->p_f <= 0) return kspace_full(c, force, u_k, virial);
+    if (p->p_f <= 0) return kspace_full(c, force, u_k, virial, epot, wat);
     if (!c->have_kt) {
         ktab_build(p, &c->kt);
         c->have_kt = 1;
@@ -1062,6 +1126,22 @@ int orc_forces_kspace(orc_ctx* c, uint64_t eval, double* force, double* u_k, dou
             mode_virial(0.5 * p->coulomb_k * e, orc_far_hat_g(p, kk) / orc_far_hat(p, kk), k, virial);
         }
     }
+    if (epot) {
+        double* coef = (double*)malloc(sizeof(double) * P);
+        double* g = (double*)malloc(sizeof(double) * P);
+        for (int q = 0; q < P; ++q) {
+            double k2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double k = 2.0 * ORC_PI * (double)m[3 * q + a] / p->box[a];
+                k2 += k * k;
+            }
+            coef[q] = S / ((double)P * V * k2);
+            g[q] = orc_far_hat_g(p, sqrt(k2)) / orc_far_hat(p, sqrt(k2));
+        }
+        kspace_atom_parts(c, P, m, rho, coef, g, epot, wat);
+        free(coef);
+        free(g);
+    }
     free(m);
     free(rho);
     return 0;
@@ -1088,12 +1168,43 @@ static double kinetic(const orc_ctx* c)
     return K / ORC_ACC;
 }
 
-int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
+/* Per-atom energy and virial shares of the last evaluation (kept when the
+ * evaluation is asked for them): the core and shell half-pair sums of the
+ * atom's own lists (the shell part with its batch weight), the atom's share
+ * of each k-space mode, minus its self term k_e q_i^2 sum_m w_m / 2. */
+static void forces_eval(orc_ctx* c, uint64_t eval, double* force, orc_energy* e, int parts)
 {
     int n = c->n;
-    double* fk = (double*)calloc(3 * (n > 0 ? n : 1), sizeof(double));
-    double uc = 0.0, us = 0.0, uk = 0.0, ws[6], wk[6] = {0, 0, 0, 0, 0, 0};
-    orc_forces_short(c, eval, force, &uc, &us, ws);
+    int n1 = n > 0 ? n : 1;
+    double* fk = (double*)calloc(3 * n1, sizeof(double));
+    double* ucs = (double*)calloc(n1, sizeof(double));
+    double* uss = (double*)calloc(n1, sizeof(double));
+    double* wv = (double*)calloc(6 * n1, sizeof(double));
+    double uc = 0.0, us = 0.0, uk = 0.0, ws[6] = {0, 0, 0, 0, 0, 0}, wk[6] = {0, 0, 0, 0, 0, 0};
+    short_parts(c, eval, force, ucs, uss, wv);
+    for (int i = 0; i < n; ++i) {
+        uc += ucs[i];
+        us += uss[i];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 6; ++a) ws[a] += wv[6 * i + a];
+    if (parts) {
+        if (!c->epot) {
+            c->epot = (double*)malloc(sizeof(double) * n1);
+            c->wat = (double*)malloc(sizeof(double) * 6 * n1);
+        }
+        const orc_params* p = &c->p;
+        double wsum = 0.0;
+        for (int m = 0; m <= p->M; ++m) wsum += p->w[m];
+        for (int i = 0; i < n; ++i) {
+            double qi = p->q[c->type[i]];
+            c->epot[i] = ucs[i] + uss[i] - 0.5 * p->coulomb_k * qi * qi * wsum;
+        }
+        memcpy(c->wat, wv, sizeof(double) * 6 * n);
+    }
+    free(ucs);
+    free(uss);
+    free(wv);
     /* eq. (26)-(27): subtract the mean short-range force */
     double corr[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < n; ++i)
@@ -1101,7 +1212,7 @@ int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
     for (int a = 0; a < 3; ++a) corr[a] = n > 0 ? corr[a] / n : 0.0;
     for (int i = 0; i < n; ++i)
         for (int a = 0; a < 3; ++a) force[3 * i + a] -= corr[a];
-    if (n > 0) orc_forces_kspace(c, eval, fk, &uk, wk);
+    if (n > 0) kspace_parts(c, eval, fk, &uk, wk, parts ? c->epot : NULL, parts ? c->wat : NULL);
     for (int i = 0; i < 3 * n; ++i) force[i] += fk[i];
     free(fk);
     memcpy(c->frc, force, sizeof(double) * 3 * n);
@@ -1116,6 +1227,41 @@ int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
         for (int a = 0; a < 3; ++a) e->p_corr[a] = corr[a];
         for (int a = 0; a < 6; ++a) e->virial[a] = ws[a] + wk[a];
     }
+}
+
+/* Eq. (50) and eq. (51) at the current velocities, from the per-atom shares
+ * of the last evaluation.  The pair term of eq. (51), half the sum over pairs
+ * of (F_ij . (v_i + v_j)) r_ij, equals sum_i W_i v_i with W_i half the sum of
+ * r_ij (x) F_ij over the atom's partners; the k-space modes enter through
+ * their per-atom virial shares the same way. */
+static void transport_terms(const orc_ctx* c, orc_energy* e)
+{
+    const orc_params* p = &c->p;
+    double S[6] = {0, 0, 0, 0, 0, 0}, J[3] = {0, 0, 0};
+    for (int i = 0; i < c->n; ++i) {
+        double m = p->mass[c->type[i]] / ORC_ACC;
+        const double* v = c->vel + 3 * i;
+        const double* w = c->wat + 6 * i;
+        S[0] += m * v[0] * v[0];
+        S[1] += m * v[1] * v[1];
+        S[2] += m * v[2] * v[2];
+        S[3] += m * v[0] * v[1];
+        S[4] += m * v[0] * v[2];
+        S[5] += m * v[1] * v[2];
+        double ei = 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + c->epot[i];
+        J[0] += ei * v[0] + w[0] * v[0] + w[3] * v[1] + w[4] * v[2];
+        J[1] += ei * v[1] + w[3] * v[0] + w[1] * v[1] + w[5] * v[2];
+        J[2] += ei * v[2] + w[4] * v[0] + w[5] * v[1] + w[2] * v[2];
+    }
+    double V = box_volume(p);
+    for (int a = 0; a < 6; ++a) e->stress[a] = S[a] + e->virial[a];
+    for (int a = 0; a < 3; ++a) e->heat_flux[a] = J[a] / V;
+}
+
+int orc_forces(orc_ctx* c, uint64_t eval, double* force, orc_energy* e)
+{
+    forces_eval(c, eval, force, e, e != NULL);
+    if (e) transport_terms(c, e);
     return 0;
 }
 
@@ -1221,7 +1367,7 @@ int orc_vv_steps(orc_ctx* c, int32_t n_steps, orc_energy* e_last)
             if (norm2(d) > half2) moved = 1;
         }
         if (step % (uint64_t)every == 0 || moved) orc_build_lists(c);
-        orc_forces(c, step, f, &e);
+        forces_eval(c, step, f, &e, k == n_steps - 1);
         for (int i = 0; i < n; ++i) {
             double a = 0.5 * p->dt * ORC_ACC / p->mass[c->type[i]];
             for (int x = 0; x < 3; ++x) c->vel[3 * i + x] += a * f[3 * i + x];
@@ -1231,6 +1377,7 @@ int orc_vv_steps(orc_ctx* c, int32_t n_steps, orc_energy* e_last)
     e.kinetic = kinetic(c);
     e.u_total = e.u_core + e.u_shell + e.u_kspace - e.u_self;
     e.e_thermostat = kind == ORC_THERMO_NOSE_HOOVER ? 0.5 * Q * c->nh_v * c->nh_v + gkt * c->nh_x : 0.0;
+    if (n_steps > 0) transport_terms(c, &e);
     if (e_last) *e_last = e;
     free(f);
     return (int)c->eval;

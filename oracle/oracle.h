@@ -84,6 +84,10 @@ typedef struct {
     double virial[6];       /* W_ab = -dU/de_ab (xx, yy, zz, xy, xz, yz), eV; pressure
                                tensor V P_ab = sum m v_a v_b + W_ab.  Excludes the
                                momentum correction (a uniform force of zero mean). */
+    double stress[6];       /* S_ab of eq. (50): sum m v_a v_b + W_ab, eV (same order) */
+    double heat_flux[3];    /* J of eq. (51), eV / (A^2 ps): (1/V) [sum e_i v_i + sum W_i v_i]
+                               with e_i = m v_i^2 / 2 + the atom's share of the potential
+                               energy and W_i its share of the virial */
 } orc_energy;
 
 /* ---- Philox4x32-10 (Salmon et al., SC'11).  Pinned: published test vectors. */

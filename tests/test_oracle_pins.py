@@ -881,3 +881,154 @@ def test_species_core_radii_estimator_unbiased():
     est = np.array([s.forces_short(ev)[0][i] for ev in range(K)])
     se = est.std(0) / math.sqrt(K)
     assert np.all(np.abs(est.mean(0) - f_det[i]) < 5 * se)
+
+
+# --------------------------------------------------------------------------- stress and heat flux
+# 1 amu A^2 / ps^2 in eV with 1 amu = (1 g/mol) / N_A: 1e-3 kg/mol * 1e4 m^2/s^2
+# over the Faraday constant e N_A = 96485.33212331 C/mol (CODATA 2018)
+_MV2_EV = 1e-3 * 1e4 / 96485.33212331
+
+
+def _flux_vec(e, V):
+    return V * np.array(e["heat_flux"])
+
+
+def _sym(w):
+    return np.array([[w[0], w[3], w[4]], [w[3], w[1], w[5]], [w[4], w[5], w[2]]])
+
+
+def test_heat_flux_with_uniform_velocity_is_energy_plus_virial_drift():
+    """Every ion moving with one velocity v0: eq. (51) collapses to
+    V J = (U + K) v0 + W v0 and eq. (50) to S = M v0 v0^T + W, with U, K and
+    W the totals (U and W pinned above by energy and strain derivatives) —
+    the per-atom energy and virial shares, the shell batch weight and the
+    sampled k-space modes all have to add up.  Random-batch form."""
+    cfg = W.config("nacl_small")
+    n = len(cfg["types"])
+    v0 = np.array([1.3, -0.7, 2.1])
+    vel = np.tile(v0, (n, 1))
+    s = O.System(cfg["sys"], cfg["types"], cfg["pos"], vel)
+    V = float(np.prod(cfg["sys"]["box"]))
+    M = float(np.array(cfg["sys"]["species"]["mass"])[cfg["types"]].sum())
+    for ev in (0, 5):
+        _, e = s.forces(ev)
+        K = 0.5 * M * (v0 @ v0) * _MV2_EV
+        assert e["kinetic"] == pytest.approx(K, rel=1e-12)
+        Wm = _sym(e["virial"])
+        want = (e["u_total"] + K) * v0 + Wm @ v0
+        assert np.allclose(_flux_vec(e, V), want, rtol=1e-11, atol=1e-9 * np.abs(want).max())
+        S = _sym(e["stress"])
+        assert np.allclose(S, M * _MV2_EV * np.outer(v0, v0) + Wm, rtol=1e-12, atol=1e-9)
+    s.close()
+
+
+def test_heat_flux_and_stress_vanish_at_rest():
+    cfg = W.config("nacl_small")
+    s = O.System(cfg["sys"], cfg["types"], cfg["pos"], np.zeros_like(cfg["vel"]))
+    _, e = s.forces(2)
+    assert e["heat_flux"] == [0.0, 0.0, 0.0]
+    assert e["stress"] == e["virial"]
+    s.close()
+
+
+def test_heat_flux_pair_form_of_eq51_by_brute_force():
+    """Short-range BMH only (charges zero), deterministic lists, 48 ions of
+    the melt: eq. (51) written as in the paper — per-atom energy e_i = m v_i^2/2
+    plus half of each pair energy, and half the sum over pairs of
+    (F_ij . (v_i + v_j)) r_ij — with u_ij and F_ij from two-ion systems of
+    the same box, each pair on its own."""
+    cfg = W.config("nacl_small")
+    m = 48
+    types = cfg["types"][:m]
+    pos = np.array(cfg["pos"][:m])
+    vel = np.array(cfg["vel"][:m])
+    sysp = _deterministic(cfg)
+    sp = dict(sysp["species"])
+    sp["q"] = [0.0, 0.0]
+    sysp["species"] = sp
+    L = np.array(sysp["box"])
+    mass = np.array(sp["mass"])[types]
+    e_i = 0.5 * mass * (vel ** 2).sum(1) * _MV2_EV
+    pair = np.zeros(3)
+    npairs = 0
+    for i in range(m):
+        for j in range(i + 1, m):
+            d = pos[i] - pos[j]
+            d -= L * np.rint(d / L)
+            if np.sqrt(d @ d) >= sysp["r_shell"]:
+                continue
+            two = O.System(sysp, types[[i, j]], pos[[i, j]], np.zeros((2, 3)))
+            f2, e2 = two.forces(0)
+            two.close()
+            u = e2["u_total"]
+            e_i[i] += 0.5 * u
+            e_i[j] += 0.5 * u
+            F = f2[0]
+            pair += 0.5 * (F @ (vel[i] + vel[j])) * d
+            npairs += 1
+    assert npairs > 100
+    want = (e_i[:, None] * vel).sum(0) + pair
+    s = O.System(sysp, types, pos, vel)
+    _, e = s.forces(0)
+    got = _flux_vec(e, float(np.prod(L)))
+    assert np.allclose(got, want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+    s.close()
+
+
+def test_heat_flux_coulomb_shares_are_half_charge_derivatives():
+    """Coulomb only, deterministic (every shell pair, full k-sum), each
+    species moving with its own velocity: the energy and virial are
+    quadratic in the two charges, so a species' share of either is
+    q_t/2 times its charge derivative (exact central differences).  Then
+    V J = sum_t (K_t + E_t) v_t + W_t v_t — this pins how the near field, the
+    k-space modes and the self term split among the ions."""
+    cfg = W.config("nacl_small")
+    sysp = _deterministic(cfg, coulomb_only=True)
+    types = cfg["types"]
+    vt = np.array([[0.9, -1.7, 0.4], [-0.6, 0.3, 1.1]])
+    vel = vt[types]
+    q = list(sysp["species"]["q"])
+    h = 0.1
+
+    def run(qv):
+        sp = dict(sysp["species"], q=qv)
+        s = O.System(dict(sysp, species=sp), types, cfg["pos"], vel)
+        _, e = s.forces(0)
+        s.close()
+        return e
+
+    e0 = run(q)
+    mass = np.array(sysp["species"]["mass"])
+    want = np.zeros(3)
+    for t in range(2):
+        qp = list(q)
+        qm = list(q)
+        qp[t] += h
+        qm[t] -= h
+        ep, em = run(qp), run(qm)
+        E_t = 0.5 * q[t] * (ep["u_total"] - em["u_total"]) / (2 * h)
+        W_t = 0.5 * q[t] * (_sym(ep["virial"]) - _sym(em["virial"])) / (2 * h)
+        K_t = 0.5 * mass[t] * (vt[t] @ vt[t]) * _MV2_EV * (types == t).sum()
+        want += (K_t + E_t) * vt[t] + W_t @ vt[t]
+    got = _flux_vec(e0, float(np.prod(sysp["box"])))
+    assert np.allclose(got, want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
+
+
+def test_heat_flux_after_steps_uses_the_final_velocities():
+    """Deterministic force (the lists hold every pair within r_shell + skin,
+    so the force does not depend on when they were built): the flux and
+    stress a Nose-Hoover trajectory reports after its last step equal those of
+    a fresh system at the final positions and velocities (the closing
+    thermostat half step included)."""
+    cfg = W.config("nacl_small")
+    sysp = dict(_deterministic(cfg), thermostat="nose_hoover", t_target=900.0, tau_t=0.01)
+    s = O.System(sysp, cfg["types"], cfg["pos"], cfg["vel"])
+    s.forces(0)
+    e = s.vv_steps(4)
+    pos, vel, _, _ = s.state()
+    s.close()
+    f = O.System(dict(sysp, thermostat="berendsen", t_target=0.0), cfg["types"], pos, vel)
+    _, e2 = f.forces(4)
+    f.close()
+    assert np.allclose(e["heat_flux"], e2["heat_flux"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(e["stress"], e2["stress"], rtol=1e-10, atol=1e-9)
