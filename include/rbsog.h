@@ -150,6 +150,17 @@ typedef struct {
                             sampled form is unbiased for the full sum.  The momentum correction
                             (eq. 26) is not included.  Pressure tensor: P_ab V = sum_i m v_a v_b
                             + W_ab. */
+    double stress[6];    /* S_ab of eq. (50), eV: sum_i m v_a v_b + W_ab, same order as virial,
+                            with the velocities at the end of the call (after a step's closing
+                            thermostat half step) */
+    double heat_flux[3]; /* J of eq. (51), eV / (A^2 ps), at the same velocities:
+                            (1/V) sum_i (e_i v_i + W_i v_i).  e_i = m v_i^2 / 2 plus the ion's
+                            share of the potential energy: half of each core pair energy, the
+                            shell batch's half pair energies times N_shell/P_R, the share
+                            (k_e/2) q_i coef Re(e^{-ik.r_i} rho) of each k-space mode, less
+                            k_e q_i^2 sum_m w_m / 2; W_i the ion's share of the virial, alike
+                            (per mode times delta_ab - g k_a k_b).  For pairs, sum_i W_i v_i is
+                            the pair term of eq. (51). */
 } rbsog_energy;
 
 /* Library version string. */

@@ -99,6 +99,7 @@ struct rbsog_ctx {
     int list_chunks = 8;
     double row_slack = 1.25;
     DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, vir_part, kin_part, export_tmp, snap, sogk, neartab;
+    DBuf flux_part, at_ew;
 
     // phase timing
     bool profiling = false;
@@ -539,6 +540,9 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
 {
     const bool ke = energy || (kick && any_thermostat(c));
     const Plan& P = c->plan;
+    // an evaluation with energies takes the fused k-space pass, which forms
+    // the per-atom k-space shares of the stress and heat flux
+    const bool aux_kf = P.tune.kf_aux && !energy;
     hipStream_t st = c->stream;
     hipStream_t ax = c->aux;
     if (P.atoms.blocks <= 0) return;
@@ -553,7 +557,7 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     launch_rho(P, c->mixed, ax);
     launch_rho_finalize(P, ax);
     c->end();
-    if (P.tune.kf_aux) {
+    if (aux_kf) {
         c->begin(RBSOG_PHASE_KFORCE, true);
         launch_kforce(P, c->mixed, ax);
         c->end();
@@ -567,16 +571,16 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     c->begin(RBSOG_PHASE_REDUCE);
     launch_finalize(P, energy, st);
     c->end();
-    if (P.tune.kf_aux) {
+    if (aux_kf) {
         c->begin(RBSOG_PHASE_INTEGRATE);
         launch_combine(P, kick, ke, st);
         c->end();
     } else {
         c->begin(RBSOG_PHASE_KFORCE);
-        launch_kforce_fused(P, c->mixed, kick, ke, st);
+        launch_kforce_fused(P, c->mixed, kick, energy ? 2 : (ke ? 1 : 0), st);
         c->end();
     }
-    if (ke) launch_kinetic_finalize(P, kick, st);
+    if (ke) launch_kinetic_finalize(P, kick, energy, st);
 }
 
 void fill_energy(rbsog_ctx* c, const std::vector<DeviceScalars>& hv, rbsog_energy* e)
@@ -593,6 +597,8 @@ void fill_energy(rbsog_ctx* c, const std::vector<DeviceScalars>& hv, rbsog_energ
         e[r].max_disp = std::sqrt(h.max_disp2);
         e[r].n_builds = h.n_builds;
         for (int a = 0; a < 6; ++a) e[r].virial[a] = h.virial[a];
+        for (int a = 0; a < 6; ++a) e[r].stress[a] = h.stress[a];
+        for (int a = 0; a < 3; ++a) e[r].heat_flux[a] = h.heat_flux[a];
         const DevSys& s = c->hs[r];
         e[r].e_thermostat = (s.thermo_c > 0.0 && s.thermostat == RBSOG_THERMO_NOSE_HOOVER)
                                 ? 0.5 * s.nh_q * h.nh_v * h.nh_v + s.dof_kb * s.t_target * h.nh_x
@@ -924,6 +930,8 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->vir_part.alloc(sizeof(double) * kVirPart * std::max<size_t>(1, n_waves));
     HIP_OK(hipMemsetAsync(c->vir_part.p, 0, c->vir_part.bytes, c->stream));
     c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
+    c->flux_part.alloc(sizeof(double) * kFluxPart * std::max<size_t>(1, n_waves));
+    c->at_ew.alloc(sizeof(double4) * 2 * N);
     c->scalars.alloc(sizeof(DeviceScalars) * R);
     HIP_OK(hipMemsetAsync(c->scalars.p, 0, sizeof(DeviceScalars) * R, c->stream));
     {
@@ -966,6 +974,8 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             s.pair_part = c->pair_part.as<double>() + wav * kPairPart;
             s.vir_part = c->vir_part.as<double>() + wav * kVirPart;
             s.kin_part = c->kin_part.as<double>() + wav;
+            s.flux_part = c->flux_part.as<double>() + wav * kFluxPart;
+            s.at_ew = c->at_ew.as<double4>() + 2 * o;
             wav += blocks_for(s.n, 64);
             s.sc = c->scalars.as<DeviceScalars>() + r;
         }
@@ -996,6 +1006,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
         spc.q[t] = t < p0.n_species ? p0.species[t].q : 0.0;
         spc.mass[t] = t < p0.n_species ? p0.species[t].mass : 1.0;
         spc.inv_mass_acc[t] = kAccUnit / spc.mass[t];
+        spc.self_e[t] = 0.5 * p0.coulomb_k * spc.q[t] * spc.q[t] * wsum;
     }
     const size_t pair_bytes = round_up((int)(sizeof(PairCoef) * pcs.size()), 256);
     c->pair_tab.alloc(pair_bytes + sizeof(SpeciesDev));
@@ -1109,7 +1120,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->kcdf.alloc(sizeof(double) * std::max<size_t>(1, cdf_doubles) + sizeof(int32_t) * cdf_ints);
     c->kmodes.alloc(std::max<size_t>(1, n_modes_all) * (sizeof(ModeRec) + 3 * sizeof(int32_t)));
     c->krho_part.alloc(sizeof(double) * std::max<size_t>(1, rho_part_all));
-    c->krho.alloc(sizeof(double) * 2 * std::max<size_t>(1, n_modes_all));
+    c->krho.alloc(sizeof(double) * 3 * std::max<size_t>(1, n_modes_all));  // rho (2), g (1)
     {
         double* dd = c->kcdf.as<double>();
         int32_t* di = reinterpret_cast<int32_t*>(dd + cdf_doubles);
@@ -1117,6 +1128,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
         int32_t* mm = reinterpret_cast<int32_t*>(mr + std::max<size_t>(1, n_modes_all));
         double* rp = c->krho_part.as<double>();
         double* rh = c->krho.as<double>();
+        double* gh = rh + 2 * std::max<size_t>(1, n_modes_all);
         auto put = [](void* dst, const void* src, size_t b) {
             if (b) HIP_OK(hipMemcpy(dst, src, b, hipMemcpyHostToDevice));
         };
@@ -1154,6 +1166,8 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             rp += 2 * (size_t)k.n_chunks * k.n_modes_pad;
             k.rho = rh;
             rh += 2 * (size_t)k.n_modes;
+            k.mode_g = gh;
+            gh += (size_t)k.n_modes;
         }
     }
 
@@ -1410,7 +1424,7 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
         if (any_thermostat(ctx)) {
             // velocity factor of the first step from the current velocities
             launch_kinetic(ctx->plan, ctx->stream);
-            launch_kinetic_finalize(ctx->plan, false, ctx->stream);
+            launch_kinetic_finalize(ctx->plan, false, false, ctx->stream);
         }
         const int every = ctx->prm[0].rebuild_every;
         // a list overflow inside the loop restarts the call from a snapshot
@@ -1437,7 +1451,7 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
             launch_set_eval(ctx->plan, ctx->eval, ctx->stream);
             if (any_thermostat(ctx)) {
                 launch_kinetic(ctx->plan, ctx->stream);
-                launch_kinetic_finalize(ctx->plan, false, ctx->stream);
+                launch_kinetic_finalize(ctx->plan, false, false, ctx->stream);
             }
         }
     });

@@ -146,6 +146,8 @@ struct DeviceScalars {
     double nh_x, nh_v;    // Nose-Hoover variable and its velocity
     double vpend;         // factor the stored velocities still owe (Nose-Hoover half step at a step's end)
     double virial[6];     // W_ab of the last evaluation with energies (xx, yy, zz, xy, xz, yz)
+    double stress[6];     // S_ab of eq. (50) at the end of that evaluation (same order), eV
+    double heat_flux[3];  // J of eq. (51), eV / (A^2 ps)
 };
 
 }  // namespace rbsog

@@ -1261,6 +1261,11 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
             __builtin_nontemporal_store(Fx, s.fsx + i);
             __builtin_nontemporal_store(Fy, s.fsy + i);
             __builtin_nontemporal_store(Fz, s.fsz + i);
+            if (ENERGY) {
+                // the atom's shares of the short-range energy and virial
+                s.at_ew[2 * (size_t)i] = make_double4(Uc + Us, Wv[0], Wv[1], Wv[2]);
+                s.at_ew[2 * (size_t)i + 1] = make_double4(Wv[3], Wv[4], Wv[5], 0.0);
+            }
         }
         wave_partial(Fx, i, s.n, s.pair_part, kPairPart, 0);
         wave_partial(Fy, i, s.n, s.pair_part, kPairPart, 1);
@@ -1549,11 +1554,25 @@ __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict_
     }
 }
 
+// Sum of F^(k) terms at k^2 (value and -F^'(k)/k) for the mode virial.
+// Lanes of one wavefront share the Gaussians.
+__device__ inline double mode_g(const KDev& k, double k2)
+{
+    double F = 0.0, G = 0.0;
+    for (int m = threadIdx.x & 63; m < k.n_sog; m += 64) {
+        const double e = k.sog_c[m] * exp(-0.5 * k.sog_s2[m] * k2);
+        F += e;
+        G = fma(e, k.sog_s2[m], G);
+    }
+    F = wave_sum(F);
+    G = wave_sum(G);
+    return F > 0.0 ? G / F : 0.0;
+}
+
 // rho_p = sum over chunks (fixed tree), then the per-mode force coefficients.
 __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __restrict__ kd)
 {
     RB_SYS(blockIdx.x)
-    (void)s;
     const KDev k = global_view(kd[rb_m.x]);
     const int p = lb;
     const int lane = threadIdx.x;
@@ -1565,7 +1584,11 @@ __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __rest
     }
     re = wave_sum(re);
     im = wave_sum(im);
+    const ModeRec mq = k.modes[p];
+    const double kx = s.two_pi_L[0] * mq.mx, ky = s.two_pi_L[1] * mq.my, kz = s.two_pi_L[2] * mq.mz;
+    const double g = mode_g(k, (kx * kx + ky * ky) + kz * kz);
     if (lane == 0) {
+        k.mode_g[p] = g;
         k.rho[2 * p] = re;
         k.rho[2 * p + 1] = im;
         ModeRec& r = k.modes[p];
@@ -1580,18 +1603,6 @@ __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __rest
 
 // Momentum correction (eq. 26) and energy sums; one 1024-thread block per
 // system.
-// Sum of F^(k) terms at k^2 (value and -F^'(k)/k) for the mode virial.
-__device__ inline double mode_g(const KDev& k, double k2)
-{
-    double F = 0.0, G = 0.0;
-    for (int m = 0; m < k.n_sog; ++m) {
-        const double e = k.sog_c[m] * exp(-0.5 * k.sog_s2[m] * k2);
-        F += e;
-        G = fma(e, k.sog_s2[m], G);
-    }
-    return F > 0.0 ? G / F : 0.0;
-}
-
 __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sys, const KDev* __restrict__ kd,
                                                    int energy)
 {
@@ -1617,7 +1628,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
         if (energy) {
             // strain derivative of the mode's energy: e (delta_ab - g k_a k_b)
             const double kx = s.two_pi_L[0] * r.mx, ky = s.two_pi_L[1] * r.my, kz = s.two_pi_L[2] * r.mz;
-            const double eg = r.e * mode_g(k, (kx * kx + ky * ky) + kz * kz);
+            const double eg = r.e * k.mode_g[p];
             wk[0] += r.e - eg * kx * kx;
             wk[1] += r.e - eg * ky * ky;
             wk[2] += r.e - eg * kz * kz;
@@ -1656,10 +1667,16 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
 // k_combine adds the short-range part (it needs only the positions and rho,
 // so it can run on the second stream beside the pair kernel).  FUSED: the
 // total force (F_short - F_corr) + F_k, closing kick and kinetic-energy
-// partials in the same pass, as k_combine computes them.
-template <bool MIXED, bool FUSED, bool KICK, bool ENERGY>
+// partials (KE > 0) in the same pass, as k_combine computes them.  KE = 2
+// (evaluations with energies): also the atom's share of each mode's energy,
+// (k_e/2) q_i Re(e^{-i theta} rho_p) coef_p, and of its virial, that times
+// (delta_ab - g_p k_a k_b); with the pair kernel's shares and the final
+// velocity they give the stress and heat-flux partials of eqs. (50)-(51).
+template <bool MIXED, bool FUSED, bool KICK, int KE>
 __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restrict__ kd)
 {
+    constexpr bool ENERGY = KE > 0;
+    constexpr bool FLUX = FUSED && KE == 2;
     RB_SYS(blockIdx.x)
     const KDev k = global_view(kd[rb_m.x]);
     __shared__ double2 tab[MIXED ? 1 : kTableSize];
@@ -1670,6 +1687,9 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
     }
     const int i = lb * blockDim.x + threadIdx.x;
     double ke = 0.0;
+    double fl[kFluxPart];
+    if (FLUX)
+        for (int c = 0; c < kFluxPart; ++c) fl[c] = 0.0;
     if (i < s.n) {
         const double4 Pi = s.p[i];
         const double sc = MIXED ? 1.0 : (double)kTableSize;
@@ -1677,31 +1697,47 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
         const double4 U = make_double4(Pi.x * (sc * s.invL[0]), Pi.y * (sc * s.invL[1]),
                                        Pi.z * (sc * s.invL[2]), 0.0);
         double Gx = 0.0, Gy = 0.0, Gz = 0.0;
-        auto one = [&](const ModeRec& mr) {
+        // FLUX: sum_p Re(e^{-i theta} rho_p) coef_p, and that times g_p m_a m_b
+        double Ek = 0.0, Txx = 0.0, Tyy = 0.0, Tzz = 0.0, Txy = 0.0, Txz = 0.0, Tyz = 0.0;
+        auto one = [&](const ModeRec& mr, double gm) {
             const double t = mode_phase(mr.mx, mr.my, mr.mz, U);
-            double w;
+            double w, re = 0.0;
             if (MIXED) {
                 float c, sn;
                 sincos_turns_f32(t, c, sn);
                 // Im(e^{-i theta} rho) * coef = c * A - s * B
                 w = (double)fmaf(c, mr.Af, -(sn * mr.Bf));
+                // Re(e^{-i theta} rho) * coef = c * B + s * A
+                if (FLUX) re = (double)fmaf(c, mr.Bf, sn * mr.Af);
             } else {
                 double c, sn;
                 sincos1024(t, tab, c, sn);
                 w = fma(c, mr.A, -(sn * mr.B));
+                if (FLUX) re = fma(c, mr.B, sn * mr.A);
             }
             Gx = fma(w, mr.mx, Gx);
             Gy = fma(w, mr.my, Gy);
             Gz = fma(w, mr.mz, Gz);
+            if (FLUX) {
+                Ek += re;
+                const double rg = re * gm;
+                const double ax = rg * mr.mx, ay = rg * mr.my;
+                Txx = fma(ax, mr.mx, Txx);
+                Tyy = fma(ay, mr.my, Tyy);
+                Tzz = fma(rg * mr.mz, mr.mz, Tzz);
+                Txy = fma(ax, mr.my, Txy);
+                Txz = fma(ax, mr.mz, Txz);
+                Tyz = fma(ay, mr.mz, Tyz);
+            }
         };
         int p = 0;
         for (; p + 2 <= k.n_modes; p += 2) {
             const ModeRec m0 = k.modes[p];
             const ModeRec m1 = k.modes[p + 1];
-            one(m0);
-            one(m1);
+            one(m0, FLUX ? k.mode_g[p] : 0.0);
+            one(m1, FLUX ? k.mode_g[p + 1] : 0.0);
         }
-        if (p < k.n_modes) one(k.modes[p]);
+        if (p < k.n_modes) one(k.modes[p], FLUX ? k.mode_g[p] : 0.0);
         const int ti = s.type[i];
         const double qk = -s.coulomb_k * s.spc->q[ti];
         if (!FUSED) {
@@ -1716,20 +1752,48 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
             s.fx[i] = fx;
             s.fy[i] = fy;
             s.fz[i] = fz;
+            double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
             if (KICK) {
                 const double a = 0.5 * s.dt * s.spc->inv_mass_acc[ti];
-                const double vx = s.vx[i] + a * fx, vy = s.vy[i] + a * fy, vz = s.vz[i] + a * fz;
+                vx += a * fx;
+                vy += a * fy;
+                vz += a * fz;
                 s.vx[i] = vx;
                 s.vy[i] = vy;
                 s.vz[i] = vz;
-                if (ENERGY) ke = 0.5 * s.spc->mass[ti] * (vx * vx + vy * vy + vz * vz);
-            } else if (ENERGY) {
-                const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
-                ke = 0.5 * s.spc->mass[ti] * (vx * vx + vy * vy + vz * vz);
+            }
+            const double m = s.spc->mass[ti];
+            if (ENERGY) ke = 0.5 * m * (vx * vx + vy * vy + vz * vz);
+            if (FLUX) {
+                const double hq = 0.5 * s.coulomb_k * s.spc->q[ti];
+                const double tx = s.two_pi_L[0], ty = s.two_pi_L[1], tz = s.two_pi_L[2];
+                const double4 a0 = s.at_ew[2 * (size_t)i];
+                const double4 a1 = s.at_ew[2 * (size_t)i + 1];
+                const double ep = a0.x + hq * Ek - s.spc->self_e[ti];
+                const double wxx = a0.y + hq * (Ek - tx * tx * Txx);
+                const double wyy = a0.z + hq * (Ek - ty * ty * Tyy);
+                const double wzz = a0.w + hq * (Ek - tz * tz * Tzz);
+                const double wxy = a1.x - hq * (tx * ty) * Txy;
+                const double wxz = a1.y - hq * (tx * tz) * Txz;
+                const double wyz = a1.z - hq * (ty * tz) * Tyz;
+                fl[0] = m * vx * vx;
+                fl[1] = m * vy * vy;
+                fl[2] = m * vz * vz;
+                fl[3] = m * vx * vy;
+                fl[4] = m * vx * vz;
+                fl[5] = m * vy * vz;
+                fl[6] = ke * vx;
+                fl[7] = ke * vy;
+                fl[8] = ke * vz;
+                fl[9] = ep * vx + (wxx * vx + wxy * vy + wxz * vz);
+                fl[10] = ep * vy + (wxy * vx + wyy * vy + wyz * vz);
+                fl[11] = ep * vz + (wxz * vx + wyz * vy + wzz * vz);
             }
         }
     }
     if (FUSED && ENERGY) wave_partial(ke, i, s.n, s.kin_part, 1, 0);
+    if (FLUX)
+        for (int c = 0; c < kFluxPart; ++c) wave_partial(fl[c], i, s.n, s.flux_part, kFluxPart, c);
 }
 
 // Total force F = (F_short - F_corr) + F_k (eqs. 26-29; F_k from k_kforce),
@@ -1764,7 +1828,12 @@ __global__ __launch_bounds__(kBlock) void k_combine(RB_ARGS)
     if (ENERGY) wave_partial(ke, i, s.n, s.kin_part, 1, 0);
 }
 
-__global__ __launch_bounds__(1024) void k_kinetic_finalize(const DevSys* __restrict__ sys, int step_end)
+// flux: the stress tensor (eq. 50) and heat flux (eq. 51) from the partials
+// of the fused k-space pass.  The partials are of the stored velocities; the
+// true ones are f times them, f the Nose-Hoover factor they owe (1 without
+// it), so the kinetic tensor scales by f^2, the kinetic part of the flux by
+// f^3 and the potential part by f.
+__global__ __launch_bounds__(1024) void k_kinetic_finalize(const DevSys* __restrict__ sys, int step_end, int flux)
 {
     const DevSys s = global_view(sys[blockIdx.x]);
     const double* part = s.kin_part;
@@ -1773,28 +1842,45 @@ __global__ __launch_bounds__(1024) void k_kinetic_finalize(const DevSys* __restr
     double v = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[b];
     const double t = block_sum(v, red);
+    double ft[kFluxPart];
+    if (flux) {
+        for (int c = 0; c < kFluxPart; ++c) {
+            double x = 0.0;
+            for (int b = threadIdx.x; b < nb; b += blockDim.x) x += s.flux_part[(size_t)b * kFluxPart + c];
+            ft[c] = block_sum(x, red);
+        }
+    }
     if (threadIdx.x == 0) {
         const double ke = t / kAccUnit;
+        double f = 1.0;
         if (is_nh(s)) {
             if (step_end) {
                 // closing half step; the velocities owe its factor until the
                 // next opening kick (exports apply it)
                 double K = ke;
-                s.sc->vpend = nh_half(s, s.sc, K);
+                f = nh_half(s, s.sc, K);
+                s.sc->vpend = f;
                 s.sc->kinetic = K;
             } else {
-                s.sc->kinetic = ke * (s.sc->vpend * s.sc->vpend);
+                f = s.sc->vpend;
+                s.sc->kinetic = ke * (f * f);
             }
         } else {
             s.sc->kinetic = ke;
-            double f = 1.0;
+            double lam = 1.0;
             if (s.thermo_c > 0.0 && s.thermostat == kThermoBerendsen && ke > 0.0) {
                 // Berendsen: lambda^2 = 1 + (dt/tau)(T0/T - 1)
                 const double T = 2.0 * ke / s.dof_kb;
                 const double l2 = 1.0 + s.thermo_c * (s.t_target / T - 1.0);
-                f = l2 > 0.0 ? sqrt(l2) : 0.0;
+                lam = l2 > 0.0 ? sqrt(l2) : 0.0;
             }
-            s.sc->vscale = f;
+            s.sc->vscale = lam;
+        }
+        if (flux) {
+            const double f2 = (f * f) / kAccUnit, f3 = f * f * f / kAccUnit;
+            for (int c = 0; c < 6; ++c) s.sc->stress[c] = f2 * ft[c] + s.sc->virial[c];
+            const double iV = 1.0 / ((s.L[0] * s.L[1]) * s.L[2]);
+            for (int c = 0; c < 3; ++c) s.sc->heat_flux[c] = (f3 * ft[6 + c] + f * ft[9 + c]) * iV;
         }
     }
 }
@@ -2099,30 +2185,32 @@ void launch_kforce(const Plan& P, bool mixed, hipStream_t st)
     const int bs = P.tune.kf_block;
     if (nb <= 0) return;
     if (mixed)
-        k_kforce<true, false, false, false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+        k_kforce<true, false, false, 0><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
     else
-        k_kforce<false, false, false, false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+        k_kforce<false, false, false, 0><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
 }
 
-void launch_kforce_fused(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st)
+void launch_kforce_fused(const Plan& P, bool mixed, bool kick, int ke, hipStream_t st)
 {
     const int nb = P.kf_atoms.blocks;
     const int bs = P.tune.kf_block;
     if (nb <= 0) return;
 #define RB_KF(M, K, E) k_kforce<M, true, K, E><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd)
+#define RB_KF_KE(M, K)        \
+    do {                      \
+        if (ke == 2)          \
+            RB_KF(M, K, 2);   \
+        else if (ke == 1)     \
+            RB_KF(M, K, 1);   \
+        else                  \
+            RB_KF(M, K, 0);   \
+    } while (0)
     if (mixed) {
-        if (kick) {
-            if (energy) RB_KF(true, true, true); else RB_KF(true, true, false);
-        } else {
-            if (energy) RB_KF(true, false, true); else RB_KF(true, false, false);
-        }
+        if (kick) RB_KF_KE(true, true); else RB_KF_KE(true, false);
     } else {
-        if (kick) {
-            if (energy) RB_KF(false, true, true); else RB_KF(false, true, false);
-        } else {
-            if (energy) RB_KF(false, false, true); else RB_KF(false, false, false);
-        }
+        if (kick) RB_KF_KE(false, true); else RB_KF_KE(false, false);
     }
+#undef RB_KF_KE
 #undef RB_KF
 }
 
@@ -2143,9 +2231,9 @@ void launch_combine(const Plan& P, bool kick, bool energy, hipStream_t st)
     }
 }
 
-void launch_kinetic_finalize(const Plan& P, bool step_end, hipStream_t st)
+void launch_kinetic_finalize(const Plan& P, bool step_end, bool flux, hipStream_t st)
 {
-    if (P.R > 0) k_kinetic_finalize<<<P.R, 1024, 0, st>>>(P.sys, step_end ? 1 : 0);
+    if (P.R > 0) k_kinetic_finalize<<<P.R, 1024, 0, st>>>(P.sys, step_end ? 1 : 0, flux ? 1 : 0);
 }
 
 void launch_kinetic(const Plan& P, hipStream_t st)

@@ -20,6 +20,7 @@ struct SpeciesDev {
     double q[kMaxSpecies];
     double inv_mass_acc[kMaxSpecies];  // kAccUnit / m
     double mass[kMaxSpecies];
+    double self_e[kMaxSpecies];  // k_e q^2 sum_m w_m / 2, the self term of one ion
 };
 
 // Everything the kernels read or write about one system of a batch.  Per-atom
@@ -83,6 +84,9 @@ struct DevSys {
     double* pair_part;     // [ceil(n/64)][kPairPart] wavefront partials of the pair kernel
     double* vir_part;      // [ceil(n/64)][kVirPart] wavefront virial partials (evaluations with energies)
     double* kin_part;      // [ceil(n/64)] kinetic-energy wavefront partials
+    double* flux_part;     // [ceil(n/64)][kFluxPart] kinetic tensor and heat-flux partials
+    double4* at_ew;        // [n][2] per-atom short-range energy and virial shares of the
+                           // last evaluation with energies: {e, W_xx, W_yy, W_zz}, {W_xy, W_xz, W_yz, 0}
 };
 
 struct KDev {
@@ -107,12 +111,16 @@ struct KDev {
     int n_sog;            // terms of F^(k): c[m] exp(-s2[m] k^2 / 2), m < n_sog
     const double* sog_c;
     const double* sog_s2;
+    double* mode_g;       // [n_modes] g = G/F^ of each mode (strain derivative), set with rho
 };
 
 // Per-wavefront partial sums written by the pair kernel: F (3), u_core,
 // u_shell; and, in evaluations with energies, the virial W (6) in vir_part.
 constexpr int kPairPart = 5;
 constexpr int kVirPart = 6;
+// Per-wavefront partials of the closing pass of an evaluation with energies:
+// sum m v_a v_b (6), sum (m v^2 / 2) v (3), sum (e_i v + W_i v) (3).
+constexpr int kFluxPart = 12;
 
 // The grid of one launch over a batch: block b works on local block map[b].y
 // of system map[b].x.  A null map means one system (system 0, local block b).
@@ -196,13 +204,16 @@ void launch_kforce(const Plan& P, bool mixed, hipStream_t st);
 // total force = short range - momentum correction + k-space; with kick the
 // closing half kick; with energy the kinetic-energy partials
 void launch_combine(const Plan& P, bool kick, bool energy, hipStream_t st);
-// the k-space force and the combine in one pass (no second stream)
-void launch_kforce_fused(const Plan& P, bool mixed, bool kick, bool energy, hipStream_t st);
+// the k-space force and the combine in one pass (no second stream).  ke: 0
+// no partials, 1 kinetic-energy partials, 2 those and the per-atom k-space
+// shares combined with the pair kernel's into stress and heat-flux partials
+// (evaluations with energies)
+void launch_kforce_fused(const Plan& P, bool mixed, bool kick, int ke, hipStream_t st);
 // kinetic energy from the partials; with a thermostat also the velocity
 // factor of the next step.  step_end: the partials are those of a step's
 // closing kick (the Nose-Hoover closing half step is taken), else a
-// measurement of the current velocities
-void launch_kinetic_finalize(const Plan& P, bool step_end, hipStream_t st);
+// measurement of the current velocities.  flux: also the stress and heat flux
+void launch_kinetic_finalize(const Plan& P, bool step_end, bool flux, hipStream_t st);
 // kinetic-energy partials of the current velocities
 void launch_kinetic(const Plan& P, hipStream_t st);
 

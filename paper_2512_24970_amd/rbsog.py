@@ -66,11 +66,12 @@ class Energy(C.Structure):
     _fields_ = [("u_core", C.c_double), ("u_shell", C.c_double), ("u_kspace", C.c_double),
                 ("u_self", C.c_double), ("u_total", C.c_double), ("kinetic", C.c_double),
                 ("p_corr", C.c_double * 3), ("max_disp", C.c_double), ("n_builds", C.c_int64),
-                ("e_thermostat", C.c_double), ("virial", C.c_double * 6)]
+                ("e_thermostat", C.c_double), ("virial", C.c_double * 6), ("stress", C.c_double * 6),
+                ("heat_flux", C.c_double * 3)]
 
     def as_dict(self) -> dict:
-        return {k: (list(getattr(self, k)) if k in ("p_corr", "virial") else getattr(self, k))
-                for k, _ in self._fields_}
+        arrays = ("p_corr", "virial", "stress", "heat_flux")
+        return {k: (list(getattr(self, k)) if k in arrays else getattr(self, k)) for k, _ in self._fields_}
 
 
 ABI = {
