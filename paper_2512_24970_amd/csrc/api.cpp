@@ -536,7 +536,10 @@ bool any_thermostat(const rbsog_ctx* c)
 // writes only short-range forces and its partials: the chain runs on the
 // second stream beside the pair kernel, and the first stream waits for it
 // before the sums that need both.
-void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
+// build: a step's gated list build goes in first.  Only its cell sort
+// (which reorders the atoms) precedes the fork: the k-space chain needs the
+// sorted positions but not the lists, so it runs beside the list kernels.
+void enqueue_forces(rbsog_ctx* c, bool energy, bool kick, bool build = false)
 {
     const bool ke = energy || (kick && any_thermostat(c));
     const Plan& P = c->plan;
@@ -546,6 +549,11 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
     hipStream_t st = c->stream;
     hipStream_t ax = c->aux;
     if (P.atoms.blocks <= 0) return;
+    if (build) {
+        c->begin(RBSOG_PHASE_BUILD);
+        launch_sort(P, true, st);
+        c->end();
+    }
     HIP_OK(hipEventRecord(c->ev_fork, st));
     HIP_OK(hipStreamWaitEvent(ax, c->ev_fork, 0));
     if (P.modes64.blocks > 0) {
@@ -563,6 +571,11 @@ void enqueue_forces(rbsog_ctx* c, bool energy, bool kick)
         c->end();
     }
     HIP_OK(hipEventRecord(c->ev_join, ax));
+    if (build) {
+        c->begin(RBSOG_PHASE_BUILD);
+        launch_lists(P, true, st);
+        c->end();
+    }
     c->begin(RBSOG_PHASE_PAIR);
     launch_pair(P, c->coef, c->mixed, energy, st);
     HIP_OK(hipGetLastError());  // a launch the device refuses (e.g. LDS size) must not pass silently
@@ -620,8 +633,7 @@ void enqueue_step(rbsog_ctx* c, bool scheduled, bool energy)
     launch_step_begin(c->plan, c->stream);
     launch_kick_drift(c->plan, scheduled, c->stream);
     c->end();
-    enqueue_build(c, true);
-    enqueue_forces(c, energy, true);
+    enqueue_forces(c, energy, true, true);
 }
 
 // The same step as one HIP graph launch: the kernel sequence of each variant
@@ -905,8 +917,9 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
         init_devsys(prm[r], prm[r].n_atoms, c->hs[r]);
         c->hs[r].user_off = user_off[r];
         // the list kernel packs the species above a 28-bit atom index
-        require(!c->hs[r].species_cut || prm[r].n_atoms < (1 << 28), RBSOG_E_ARG,
-                "species-dependent core radii need fewer than 2^28 atoms per system");
+        // the cell sort keys (sub-cell, atom index) and the list kernel packs
+        // the species above the index: 28 bits of index
+        require(prm[r].n_atoms < (1 << 28), RBSOG_E_ARG, "a system holds fewer than 2^28 atoms");
         if (c->hs[r].species_cut) c->plan.species_cut = true;
         c->u_self[r] = 0.5 * p0.coulomb_k * q2[r] * wsum;
     }
@@ -921,7 +934,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->counts.alloc(2 * sizeof(int32_t) * N);
     HIP_OK(hipMemsetAsync(c->counts.p, 0, 2 * sizeof(int32_t) * N, c->stream));
     size_t n_cells = 0;
-    for (const auto& s : c->hs) n_cells += 2 * (size_t)s.ncell + 1;
+    for (const auto& s : c->hs) n_cells += 10 * (size_t)s.ncell + 1;
     c->cells.alloc(sizeof(int32_t) * n_cells);
     HIP_OK(hipMemsetAsync(c->cells.p, 0, sizeof(int32_t) * n_cells, c->stream));
     size_t n_waves = 0;
@@ -970,7 +983,8 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             s.cand_cnt = c->counts.as<int32_t>() + N + o;
             s.cell_count = cells;
             s.cell_start = cells + s.ncell;
-            cells += 2 * (size_t)s.ncell + 1;
+            s.sub_beg = cells + 2 * (size_t)s.ncell + 1;
+            cells += 10 * (size_t)s.ncell + 1;
             s.pair_part = c->pair_part.as<double>() + wav * kPairPart;
             s.vir_part = c->vir_part.as<double>() + wav * kVirPart;
             s.kin_part = c->kin_part.as<double>() + wav;

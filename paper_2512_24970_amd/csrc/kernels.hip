@@ -234,9 +234,11 @@ __global__ void k_bin(RB_ARGS, int gate)
     const double x = wrap_coord(P.x, s.L[0], s.invL[0]);
     const double y = wrap_coord(P.y, s.L[1], s.invL[1]);
     const double z = wrap_coord(P.z, s.L[2], s.invL[2]);
-    const int cx = cell_coord(x, s.cell_scale[0], s.nc[0]);
-    const int cy = cell_coord(y, s.cell_scale[1], s.nc[1]);
-    const int cz = cell_coord(z, s.cell_scale[2], s.nc[2]);
+    // list cell = ordering-grid cell >> 1 per axis (n_f = 2 n_c, or 1 with
+    // n_c = 1), so every ordering cell lies in exactly one list cell
+    const int cx = cell_coord(x, s.fine_scale[0], s.nf[0]) >> 1;
+    const int cy = cell_coord(y, s.fine_scale[1], s.nf[1]) >> 1;
+    const int cz = cell_coord(z, s.fine_scale[2], s.nf[2]) >> 1;
     const int c = (cz * s.nc[1] + cy) * s.nc[0] + cx;
     if (live) {
         s.p[i] = make_double4(x, y, z, P.w);
@@ -312,7 +314,9 @@ __global__ void k_scatter(RB_ARGS, int gate)
     s.tid[d] = s.id[i];
 }
 
-// Within each cell, order atoms by id so the cell order is deterministic.
+// Within each list cell, order atoms by (ordering sub-cell, id): the order is
+// deterministic and each of the eight sub-cells is a contiguous range, whose
+// first positions go to sub_beg.  Keys: sub-cell << 28 | id (ids < 2^28).
 __global__ __launch_bounds__(kBlock) void k_cell_sort(RB_ARGS, int gate)
 {
     RB_SYS(blockIdx.x)
@@ -322,16 +326,28 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(RB_ARGS, int gate)
     const int c = lb;
     const int beg = s.cell_start[c];
     const int cnt = s.cell_start[c + 1] - beg;
+    int32_t* sb = s.sub_beg + (size_t)c * 8;
     if (cnt > kCellCap) {
-        // keep a valid (unsorted) permutation; the host reports the overflow
+        // keep a valid (unsorted) permutation and in-range sub-cell bounds;
+        // the host reports the overflow
         for (int t = threadIdx.x; t < cnt; t += blockDim.x) s.order[beg + t] = beg + t;
+        if (threadIdx.x < 8) sb[threadIdx.x] = threadIdx.x == 0 ? 0 : cnt;
         if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 2);
         return;
     }
     int P = 1;
     while (P < cnt) P <<= 1;
     for (int t = threadIdx.x; t < P; t += blockDim.x) {
-        key[t] = t < cnt ? s.tid[beg + t] : INT_MAX;
+        int k = INT_MAX;
+        if (t < cnt) {
+            const double4 Q = s.tp[beg + t];
+            const int fx = cell_coord(Q.x, s.fine_scale[0], s.nf[0]);
+            const int fy = cell_coord(Q.y, s.fine_scale[1], s.nf[1]);
+            const int fz = cell_coord(Q.z, s.fine_scale[2], s.nf[2]);
+            const int sub = ((fz & 1) * 2 + (fy & 1)) * 2 + (fx & 1);
+            k = (sub << 28) | s.tid[beg + t];
+        }
+        key[t] = k;
         val[t] = t < cnt ? beg + t : -1;
     }
     __syncthreads();
@@ -355,6 +371,19 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(RB_ARGS, int gate)
         }
     }
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) s.order[beg + t] = val[t];
+    if (threadIdx.x < 8) {
+        // first sorted position whose sub-cell is >= this one
+        const int32_t want = (int32_t)threadIdx.x << 28;
+        int lo = 0, hi = cnt;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (key[mid] < want)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        sb[threadIdx.x] = lo;
+    }
 }
 
 __global__ void k_gather(RB_ARGS, int gate)
@@ -523,10 +552,10 @@ constexpr int kListA = 4;     // atoms per sweep
 
 __device__ inline int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Rank of this lane among the set lanes of m below it.
-__device__ inline int mbcnt64(uint64_t m)
+// Rank of this lane among the set lanes of m below it (plus base).
+__device__ inline int mbcnt64(uint64_t m, int base = 0)
 {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)base));
 }
 
 // First atom of build chunk `chunk` (cells [chunk ncell / K, (chunk+1) ncell / K)).
@@ -561,15 +590,14 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     __shared__ double py[CAP];
     __shared__ double pz[CAP];
     __shared__ int lcnt[kRegion];       // atoms per region cell
-    __shared__ int lcur[kRegion];       // next free sorted position of each region cell
-    __shared__ int cstart[kRegion];     // first sorted position of each region cell
+    __shared__ int gbeg[kRegion];       // first (sorted) atom of each region cell
+    __shared__ int cstart[kRegion];     // first staged position of each region cell
     __shared__ int rcell[kRegion];      // region cell of each rank (ascending global index)
+    __shared__ int rstart[kRegion];     // first staged position of each rank
     __shared__ int run_beg[8][kMaxRuns];
     __shared__ int run_pre[8][kMaxRuns + 1];
     __shared__ int n_runs[8];
-    __shared__ int cq[27];
-    __shared__ int cb[27];
-    __shared__ int coff[28];
+    __shared__ int total_sm;
     __shared__ int bad;
     const int c = lb;
     const int lane = threadIdx.x & 63;
@@ -578,97 +606,30 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     const int cx0 = c % s.nc[0];
     const int cy0 = (c / s.nc[0]) % s.nc[1];
     const int cz0 = c / (s.nc[0] * s.nc[1]);
-    // stencil: offsets -1..1 along axes with at least 3 list cells, else 0
+    // region of ordering cells: the 3 x 3 x 3 list cells around this one,
+    // 6 ordering cells per split axis starting 2 below the block's first
+    // (axes with fewer than 3 list cells are not split: 1 cell)
     const bool sx = s.nc[0] >= 3, sy = s.nc[1] >= 3, sz = s.nc[2] >= 3;
-    const int n0 = sx ? 3 : 1, n1 = sy ? 3 : 1, n2 = sz ? 3 : 1;
-    const int nst = n0 * n1 * n2;
-    if (threadIdx.x < nst) {
-        const int k = threadIdx.x;
-        const int ox = sx ? k % 3 - 1 : 0;
-        const int oy = sy ? (k / n0) % 3 - 1 : 0;
-        const int oz = sz ? k / (n0 * n1) - 1 : 0;
-        const int cx = (cx0 + ox + s.nc[0]) % s.nc[0];
-        const int cy = (cy0 + oy + s.nc[1]) % s.nc[1];
-        const int cz = (cz0 + oz + s.nc[2]) % s.nc[2];
-        cq[k] = (cz * s.nc[1] + cy) * s.nc[0] + cx;
-    }
-    // region of ordering cells: 6 per split axis starting 2 below the block's
-    // first one, 1 otherwise
     const int R0 = sx ? 6 : 1, R1 = sy ? 6 : 1, R2 = sz ? 6 : 1;
     const int R = R0 * R1 * R2;
     const int gx0 = sx ? 2 * cx0 - 2 : 0, gy0 = sy ? 2 * cy0 - 2 : 0, gz0 = sz ? 2 * cz0 - 2 : 0;
-    for (int q = threadIdx.x; q < R; q += blockDim.x) lcnt[q] = 0;
     if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    if (threadIdx.x < nst) {
-        const int q = cq[threadIdx.x];
-        const int b = s.cell_start[q];
-        cb[threadIdx.x] = b;
-        coff[threadIdx.x + 1] = s.cell_start[q + 1] - b;
+    // each region cell is a contiguous range of the sorted atoms: its list
+    // cell's range, cut at the sub-cell bounds the cell sort recorded
+    for (int q = threadIdx.x; q < R; q += blockDim.x) {
+        const int lx = q % R0, ly = (q / R0) % R1, lz = q / (R0 * R1);
+        const int gx = sx ? wrap_index(gx0 + lx, s.nf[0]) : 0;
+        const int gy = sy ? wrap_index(gy0 + ly, s.nf[1]) : 0;
+        const int gz = sz ? wrap_index(gz0 + lz, s.nf[2]) : 0;
+        const int lc = ((gz >> 1) * s.nc[1] + (gy >> 1)) * s.nc[0] + (gx >> 1);
+        const int sub = ((gz & 1) * 2 + (gy & 1)) * 2 + (gx & 1);
+        const int32_t* sbc = s.sub_beg + (size_t)lc * 8;
+        const int cb0 = s.cell_start[lc];
+        const int b0 = cb0 + sbc[sub];
+        const int e0 = sub < 7 ? cb0 + sbc[sub + 1] : s.cell_start[lc + 1];
+        gbeg[q] = b0;
+        lcnt[q] = max(e0 - b0, 0);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        coff[0] = 0;
-        for (int k = 0; k < nst; ++k) coff[k + 1] += coff[k];
-    }
-    __syncthreads();
-    const int total = coff[nst];
-    if (total > CAP) {
-        // the stencil does not fit: the host moves to a larger stencil or the per-atom kernel
-        if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 4);
-        return;
-    }
-    // stage, sorted by region cell and stably (index order) within one:
-    // every region cell lies in one stencil cell, so each wavefront takes
-    // whole stencil cells and ranks their atoms with ballots, first to count
-    // (pass 0), then, once the cells' first positions are known, to place
-    // (pass 1; the positions are read again)
-    auto region_cell = [&](const double4& P) {
-        const int lx = sx ? wrap_index(cell_coord(P.x, s.fine_scale[0], s.nf[0]) - gx0, s.nf[0]) : 0;
-        const int ly = sy ? wrap_index(cell_coord(P.y, s.fine_scale[1], s.nf[1]) - gy0, s.nf[1]) : 0;
-        const int lz = sz ? wrap_index(cell_coord(P.z, s.fine_scale[2], s.nf[2]) - gz0, s.nf[2]) : 0;
-        return (lz * R1 + ly) * R0 + lx;
-    };
-    auto stage_pass = [&](bool place) {
-        for (int k = wave; k < nst; k += kListBlock / 64) {
-            const int b = cb[k], n = coff[k + 1] - coff[k];
-            for (int base = 0; base < n; base += 64) {
-                const bool live = base + lane < n;
-                const int j = b + base + lane;
-                double4 P = make_double4(0.0, 0.0, 0.0, 0.0);
-                int q = -1;
-                if (live) {
-                    P = s.p[j];
-                    q = region_cell(P);
-                }
-                bool pending = live;
-                uint64_t pm = __ballot(pending);
-                while (pm) {
-                    const int leader = __builtin_ctzll(pm);
-                    const int ql = __shfl(q, leader, 64);
-                    const bool mine = pending && q == ql;
-                    const uint64_t m = __ballot(mine);
-                    if (place) {
-                        const int first = lcur[ql];
-                        if (mine) {
-                            const int d = first + mbcnt64(m);
-                            px[d] = P.x;
-                            py[d] = P.y;
-                            pz[d] = P.z;
-                            val[d] = PC ? (j | ((int)P.w << kIdxBits)) : j;
-                        }
-                        if (lane == leader) lcur[ql] = first + __popcll(m);
-                    } else if (lane == leader) {
-                        lcnt[ql] += __popcll(m);
-                    }
-                    if (mine) pending = false;
-                    pm = __ballot(pending);
-                }
-            }
-        }
-    };
-    stage_pass(false);
-    __syncthreads();
     // rank of each region cell in ascending global index: lexicographic in
     // (z, y, x) of the wrapped global coordinates, so per-axis ranks combine
     for (int q = threadIdx.x; q < R; q += blockDim.x) {
@@ -684,7 +645,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         rcell[rank] = q;
     }
     __syncthreads();
-    // first sorted position of each region cell: exclusive scan over ranks
+    // first staged position of each region cell: exclusive scan over ranks
     if (wave == 0) {
         int carry = 0;
         for (int r0c = 0; r0c < R; r0c += 64) {
@@ -699,13 +660,39 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             }
             if (r < R) {
                 cstart[q] = carry + x - v;
-                lcur[q] = carry + x - v;
+                rstart[r] = carry + x - v;
             }
             carry += __shfl(x, 63, 64);
         }
+        if (lane == 0) total_sm = carry;
     }
     __syncthreads();
-    stage_pass(true);
+    const int total = total_sm;
+    if (total > CAP) {
+        // the region does not fit: the host moves to a larger staging
+        // capacity or the per-atom kernel
+        if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 4);
+        return;
+    }
+    // stage, in rank order: staged position d belongs to the last rank whose
+    // first position is <= d (that rank holds atoms)
+    for (int d = threadIdx.x; d < total; d += blockDim.x) {
+        int lo = 0, hi = R - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rstart[mid] <= d)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int j = gbeg[rcell[lo]] + (d - rstart[lo]);
+        const double4 P = s.p[j];
+        px[d] = P.x;
+        py[d] = P.y;
+        pz[d] = P.z;
+        val[d] = PC ? (j | ((int)P.w << kIdxBits)) : j;
+    }
+    __syncthreads();
     // ordering cells of the block: 2 per split axis
     const int F0 = sx ? 2 : 1, F1 = sy ? 2 : 1, F2 = sz ? 2 : 1;
     const int F = F0 * F1 * F2;
@@ -787,36 +774,33 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     // the wavefronts in turn
     int n_units = 0;
     for (int f = 0; f < F; ++f) n_units += (lcnt[own_cell(f)] + kListA - 1) / kListA;
-    for (int unit = wave; unit < n_units; unit += kListBlock / 64) {
-        int f = 0, g = unit;
-        for (;; ++f) {
-            const int nu = (lcnt[own_cell(f)] + kListA - 1) / kListA;
-            if (g < nu) break;
-            g -= nu;
-        }
-        const int q0 = own_cell(f);
-        const int a0 = cstart[q0] + g * kListA;
-        const int na = min(kListA, cstart[q0] + lcnt[q0] - a0);
-        // atoms of the unit (indices and list rows in scalar registers); a
-        // missing one (index -1) takes part in the sweep but never matches
+    const int cmax = s.cap_core - 1, kmax = s.cap_cand - 1;
+    // One unit: its atoms against the ordering cell's window, 64 window
+    // entries at a time.  An empty lane (past the window) and a missing atom
+    // of the unit sit at infinity, so every distance test fails for them
+    // (inf or NaN compare false); the atom itself is excluded by its staged
+    // index.  Hit masks come straight from the compares; a lane's slot is
+    // the row count plus its rank among the hits below it.
+    auto sweep = [&](auto interior_tag, int f, int a0, int na) {
+        constexpr bool INTERIOR = decltype(interior_tag)::value;
         double xu[kListA], yu[kListA], zu[kListA];
-        int iu[kListA], tu[kListA], ncore[kListA], ncand[kListA];
+        int tu[kListA], ncore[kListA], ncand[kListA];
         int32_t* crow[kListA];
         int32_t* ccol[kListA];
+        const int v0 = __builtin_amdgcn_readfirstlane(val[a0]);
+        const int i0 = PC ? v0 & kIdxMask : v0;
 #pragma unroll
         for (int u = 0; u < kListA; ++u) {
             const bool here = u < na;
             const int a = here ? a0 + u : a0;
-            xu[u] = px[a];
+            xu[u] = here ? px[a] : __builtin_inf();
             yu[u] = py[a];
             zu[u] = pz[a];
             const int va = __builtin_amdgcn_readfirstlane(val[a]);
-            iu[u] = here ? (PC ? va & kIdxMask : va) : -1;
             tu[u] = (PC && here) ? va >> kIdxBits : 0;
             // a missing atom sweeps into the rows of the unit's first atom,
-            // where its misses land on the unused last entry
-            const int v0 = __builtin_amdgcn_readfirstlane(val[a0]);
-            const int ii = here ? iu[u] : (PC ? v0 & kIdxMask : v0);
+            // where its (no-hit) stores land on the unused last entry
+            const int ii = here ? (PC ? va & kIdxMask : va) : i0;
             crow[u] = s.cand_idx + (size_t)(ii - row0) * s.cap_cand;
             ccol[u] = s.core_idx + (size_t)(ii >> 6) * s.cap_core * 64 + (ii & 63);
             ncore[u] = 0;
@@ -825,7 +809,6 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         const int* rb = run_beg[f];
         const int* rp = run_pre[f];
         const int W = rp[n_runs[f]];  // window size
-        const int cmax = s.cap_core - 1, kmax = s.cap_cand - 1;
         int k = 0;                    // run cursor of this lane
         for (int t0 = 0; t0 < W; t0 += 64) {
             const int t = t0 + lane;
@@ -836,48 +819,51 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
                 idx = rb[k] + (t - rp[k]);
             }
             const int vj = val[idx];
-            const int j = in ? (PC ? vj & kIdxMask : vj) : -1;
-            const int tj = (PC && in) ? vj >> kIdxBits : 0;
-            const double pxj = px[idx], pyj = py[idx], pzj = pz[idx];
+            const int j = PC ? vj & kIdxMask : vj;
+            const int tj = PC ? vj >> kIdxBits : 0;
+            const double pxj = in ? px[idx] : __builtin_inf();
+            const double pyj = py[idx], pzj = pz[idx];
 #pragma unroll
             for (int u = 0; u < kListA; ++u) {
                 double dx = xu[u] - pxj, dy = yu[u] - pyj, dz = zu[u] - pzj;
-                if (!interior) {
+                if (!INTERIOR) {
                     dx = min_image(dx, s.L[0], s.invL[0]);
                     dy = min_image(dy, s.L[1], s.invL[1]);
                     dz = min_image(dz, s.L[2], s.invL[2]);
                 }
                 const double r2 = (dx * dx + dy * dy) + dz * dz;
-                // j = -1 marks an empty lane; iu = -1 an empty atom (bitwise
-                // operators: no short-circuit branches)
-                const bool ok = (j >= 0) & (iu[u] >= 0) & (j != iu[u]);
                 double rcl = s.rc2_list, lol = s.lo2_list;
                 if (PC) {
                     const double2 th = thr[tu[u] * s.n_species + tj];
                     rcl = th.x;
                     lol = th.y;
                 }
-                const bool is_core = ok & (r2 < rcl);
-                const bool is_cand = ok & (r2 >= lol) & (r2 < s.hi2_list);
-                const uint64_t mc = __ballot(is_core);
-                const uint64_t mk = __ballot(is_cand);
-                // Every lane stores (no exec-mask branches): a miss goes to the
-                // last entry of the atom's row, which is never read (a count
-                // that reaches it is an overflow), and so do hits past the
-                // capacity; the counts report the overflow and the host
-                // builds again with longer rows.
-                const uint32_t sc_ = (uint32_t)(is_core ? min(ncore[u] + mbcnt64(mc), cmax - 1) : cmax);
-                const uint32_t sk_ = (uint32_t)(is_cand ? min(ncand[u] + mbcnt64(mk), kmax - 1) : kmax);
-                *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ccol[u]) + sc_ * 256u) = j;
-                *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(crow[u]) + sk_ * 4u) = j;
+                // masks of single compares (each is the compare's own lane
+                // mask), combined on the scalar unit
+                const bool other = idx != a0 + u;
+                const bool in_core = r2 < rcl, above = r2 >= lol, below = r2 < s.hi2_list;
+                const uint64_t m_other = __builtin_amdgcn_ballot_w64(other);
+                const uint64_t mc = __builtin_amdgcn_ballot_w64(in_core) & m_other;
+                const uint64_t mk = __builtin_amdgcn_ballot_w64(above) & __builtin_amdgcn_ballot_w64(below) & m_other;
+                const bool is_core = in_core & other;
+                const bool is_cand = above & below & other;
+                // Only hit lanes store (a step without hits issues no store);
+                // hits past the capacity all land on the row's last usable
+                // entry: the counts report the overflow and the host builds
+                // again with longer rows.
+                const int rc_ = min(mbcnt64(mc, ncore[u]), cmax - 1);
+                const int rk_ = min(mbcnt64(mk, ncand[u]), kmax - 1);
+                if (is_core) *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ccol[u]) + ((uint32_t)rc_ << 8)) = j;
+                if (is_cand) *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(crow[u]) + ((uint32_t)rk_ << 2)) = j;
                 ncore[u] += __popcll(mc);
                 ncand[u] += __popcll(mk);
             }
         }
 #pragma unroll
         for (int u = 0; u < kListA; ++u) {
-            const int i = iu[u];
             if (lane == 0 && u < na) {
+                const int va = val[a0 + u];
+                const int i = PC ? va & kIdxMask : va;
                 s.core_cnt[i] = ncore[u];
                 s.cand_cnt[i] = ncand[u];
                 // same-address atomics serialise: only overflowing atoms
@@ -889,6 +875,21 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
                 }
             }
         }
+    };
+    for (int unit = wave; unit < n_units; unit += kListBlock / 64) {
+        int f = 0, g = unit;
+        for (;; ++f) {
+            const int nu = (lcnt[own_cell(f)] + kListA - 1) / kListA;
+            if (g < nu) break;
+            g -= nu;
+        }
+        const int q0 = own_cell(f);
+        const int a0 = cstart[q0] + g * kListA;
+        const int na = min(kListA, cstart[q0] + lcnt[q0] - a0);
+        if (interior)
+            sweep(std::true_type{}, f, a0, na);
+        else
+            sweep(std::false_type{}, f, a0, na);
     }
 }
 
@@ -2065,7 +2066,7 @@ void launch_clear_flags(const Plan& P, hipStream_t st) { k_clear_flags<<<1, 64, 
 
 #define RB_MAP(shape) P.sys, P.shape.map
 
-void launch_build(const Plan& P, bool gate, hipStream_t st)
+void launch_sort(const Plan& P, bool gate, hipStream_t st)
 {
     if (P.atoms.blocks <= 0) return;
     const int g = gate ? 1 : 0;
@@ -2074,6 +2075,12 @@ void launch_build(const Plan& P, bool gate, hipStream_t st)
     k_scatter<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), g);
     k_cell_sort<<<P.cells.blocks, kBlock, 0, st>>>(RB_MAP(cells), g);
     k_gather<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), g);
+}
+
+void launch_lists(const Plan& P, bool gate, hipStream_t st)
+{
+    if (P.atoms.blocks <= 0) return;
+    const int g = gate ? 1 : 0;
     // the memory form builds chunk by chunk: candidate rows of one chunk of
     // cells, then the batch draw from them, in the same scratch rows
     const int K = P.stored ? P.n_chunks : 1;
@@ -2106,6 +2113,12 @@ void launch_build(const Plan& P, bool gate, hipStream_t st)
     }
 #undef RB_LISTS
     k_build_done<<<1, 64, 0, st>>>(P.sys, P.R, g);
+}
+
+void launch_build(const Plan& P, bool gate, hipStream_t st)
+{
+    launch_sort(P, gate, st);
+    launch_lists(P, gate, st);
 }
 
 void launch_ksample(const Plan& P, hipStream_t st)

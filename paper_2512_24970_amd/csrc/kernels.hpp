@@ -75,6 +75,10 @@ struct DevSys {
     double *tvx, *tvy, *tvz, *tfx, *tfy, *tfz;
     int32_t *ttype, *tid, *cell_of, *slot_of, *order;
     int32_t *cell_count, *cell_start;
+    // [ncell][8]: first position, within its list cell, of each of the
+    // cell's eight ordering-grid sub-cells (x fastest); the cell sort keeps
+    // each sub-cell's atoms contiguous, in index order
+    int32_t* sub_beg;
     // lists
     int32_t *core_cnt, *core_idx, *cand_cnt, *cand_idx;
     int32_t* bat_idx;      // [ceil(n/64)][p_r][64] stored shell batch (sorted atom indices)
@@ -191,6 +195,10 @@ void launch_clear_flags(const Plan& P, hipStream_t st);
 // cell sort + lists; with gate the kernels of a system run only when its
 // device-side rebuild flag is up (and lower it at the end)
 void launch_build(const Plan& P, bool gate, hipStream_t st);
+// the two halves of launch_build: the cell sort (atoms reordered), then the
+// lists (which read the sorted positions and write only list data)
+void launch_sort(const Plan& P, bool gate, hipStream_t st);
+void launch_lists(const Plan& P, bool gate, hipStream_t st);
 
 // forces
 void launch_ksample(const Plan& P, hipStream_t st);
