@@ -194,7 +194,9 @@ rbsog_status rbsog_create(rbsog_ctx** out, int hip_device, void* hip_stream);
 rbsog_status rbsog_destroy(rbsog_ctx* ctx);
 const char* rbsog_last_error(const rbsog_ctx* ctx);
 
-/* Validate parameters (neutrality, box >= 2(r_shell+skin), species count),
+/* Validate parameters (neutrality, box >= 2(r_shell+skin), species count,
+ * fewer than 2^28 atoms per system: the cell sort keys and the staged list
+ * entries keep the atom index in 28 bits),
  * set up the SOG split and the k-space sampling tables (eq. 28) and copy
  * type[N], pos[N][3] and vel[N][3] (vel may be NULL = zero) into device
  * memory.  Pointers are device pointers if ptrs_on_device != 0, else host.

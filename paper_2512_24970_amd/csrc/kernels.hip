@@ -1556,17 +1556,14 @@ __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict_
 }
 
 // Sum of F^(k) terms at k^2 (value and -F^'(k)/k) for the mode virial.
-// Lanes of one wavefront share the Gaussians.
 __device__ inline double mode_g(const KDev& k, double k2)
 {
     double F = 0.0, G = 0.0;
-    for (int m = threadIdx.x & 63; m < k.n_sog; m += 64) {
+    for (int m = 0; m < k.n_sog; ++m) {
         const double e = k.sog_c[m] * exp(-0.5 * k.sog_s2[m] * k2);
         F += e;
         G = fma(e, k.sog_s2[m], G);
     }
-    F = wave_sum(F);
-    G = wave_sum(G);
     return F > 0.0 ? G / F : 0.0;
 }
 
@@ -1574,6 +1571,7 @@ __device__ inline double mode_g(const KDev& k, double k2)
 __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __restrict__ kd)
 {
     RB_SYS(blockIdx.x)
+    (void)s;
     const KDev k = global_view(kd[rb_m.x]);
     const int p = lb;
     const int lane = threadIdx.x;
@@ -1585,11 +1583,7 @@ __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __rest
     }
     re = wave_sum(re);
     im = wave_sum(im);
-    const ModeRec mq = k.modes[p];
-    const double kx = s.two_pi_L[0] * mq.mx, ky = s.two_pi_L[1] * mq.my, kz = s.two_pi_L[2] * mq.mz;
-    const double g = mode_g(k, (kx * kx + ky * ky) + kz * kz);
     if (lane == 0) {
-        k.mode_g[p] = g;
         k.rho[2 * p] = re;
         k.rho[2 * p + 1] = im;
         ModeRec& r = k.modes[p];
@@ -1628,8 +1622,11 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
         ue += r.e;
         if (energy) {
             // strain derivative of the mode's energy: e (delta_ab - g k_a k_b)
+            // g of the mode, kept for the per-atom shares of the fused pass
             const double kx = s.two_pi_L[0] * r.mx, ky = s.two_pi_L[1] * r.my, kz = s.two_pi_L[2] * r.mz;
-            const double eg = r.e * k.mode_g[p];
+            const double g = mode_g(k, (kx * kx + ky * ky) + kz * kz);
+            k.mode_g[p] = g;
+            const double eg = r.e * g;
             wk[0] += r.e - eg * kx * kx;
             wk[1] += r.e - eg * ky * ky;
             wk[2] += r.e - eg * kz * kz;

@@ -115,7 +115,8 @@ struct KDev {
     int n_sog;            // terms of F^(k): c[m] exp(-s2[m] k^2 / 2), m < n_sog
     const double* sog_c;
     const double* sog_s2;
-    double* mode_g;       // [n_modes] g = G/F^ of each mode (strain derivative), set with rho
+    double* mode_g;       // [n_modes] g = G/F^ of each mode (strain derivative), set by the
+                          // finalize of evaluations with energies
 };
 
 // Per-wavefront partial sums written by the pair kernel: F (3), u_core,
