@@ -265,7 +265,9 @@ __global__ void k_bin(RB_ARGS, int gate)
 }
 
 // Exclusive scan of count[0..n) into start[0..n], one block of 1024 threads
-// per system.
+// per system, over tiles of kScanTile counts staged in LDS (coalesced loads
+// and stores); counts are zeroed for the next build.
+constexpr int kScanTile = 8192;
 __global__ __launch_bounds__(1024) void k_scan(const DevSys* __restrict__ sys, int gate)
 {
     const DevSys s = global_view(sys[blockIdx.x]);
@@ -273,27 +275,53 @@ __global__ __launch_bounds__(1024) void k_scan(const DevSys* __restrict__ sys, i
     int32_t* count = s.cell_count;
     int32_t* start = s.cell_start;
     const int n = s.ncell;
+    __shared__ int32_t tile[kScanTile];
     __shared__ int32_t part[1024];
     const int t = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int b = t * per, e = min(n, b + per);
-    int32_t sum = 0;
-    for (int i = b; i < e; ++i) sum += count[i];
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int32_t v = t >= o ? part[t - o] : 0;
+    constexpr int per = kScanTile / 1024;
+    int32_t carry = 0;
+    for (int base = 0; base < n; base += kScanTile) {
+        const int m = min(kScanTile, n - base);
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            const int i = t + 1024 * k;
+            if (i < m) tile[i] = count[base + i];
+        }
         __syncthreads();
-        part[t] += v;
+        const int b = t * per;
+        int32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < per; ++k)
+            if (b + k < m) sum += tile[b + k];
+        part[t] = sum;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int32_t v = t >= o ? part[t - o] : 0;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        int32_t run = carry + part[t] - sum;
+#pragma unroll
+        for (int k = 0; k < per; ++k)
+            if (b + k < m) {
+                const int32_t v = tile[b + k];
+                tile[b + k] = run;
+                run += v;
+            }
+        carry += part[1023];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            const int i = t + 1024 * k;
+            if (i < m) {
+                start[base + i] = tile[i];
+                count[base + i] = 0;  // ready for the next build
+            }
+        }
         __syncthreads();
     }
-    int32_t run = part[t] - sum;
-    for (int i = b; i < e; ++i) {
-        start[i] = run;
-        run += count[i];
-        count[i] = 0;  // ready for the next build
-    }
-    if (t == 1023) start[n] = part[1023];
+    if (t == 0) start[n] = carry;
 }
 
 __global__ void k_scatter(RB_ARGS, int gate)
@@ -1969,7 +1997,11 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
     __syncthreads();
     if (threadIdx.x == 0) {
         const double b = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        atomicMax((unsigned long long*)&s.sc->max_disp2, (unsigned long long)__double_as_longlong(b));
+        // same-address atomics serialise: only a block above the value
+        // already there (which only grows until the next build) updates it
+        unsigned long long* slot = (unsigned long long*)&s.sc->max_disp2;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(b);
+        if (bits > __atomic_load_n(slot, __ATOMIC_RELAXED)) atomicMax(slot, bits);
     }
 }
 
