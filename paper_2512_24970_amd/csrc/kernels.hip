@@ -1396,29 +1396,62 @@ __device__ inline int first_above(const double* cdf, int len, double u)
     return lo < len ? lo : len - 1;
 }
 
+// The same index by one wavefront: each round the lanes probe the ends of 64
+// equal slices of [lo, hi) and keep the first slice that reaches above u,
+// so a table of L entries takes about log64(L) dependent loads instead of
+// log2(L).  Every lane returns the index.
+__device__ inline int first_above_wave(const double* cdf, int len, double u)
+{
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = len;  // the first index above u (len: none) lies in [lo, hi]
+    while (hi - lo > 64) {
+        const int step = (hi - lo + 63) >> 6;
+        const int probe = lo + (lane + 1) * step - 1;
+        const bool above = probe >= hi || u < cdf[probe];
+        const uint64_t m = __builtin_amdgcn_ballot_w64(above);
+        if (m == 0) {
+            lo = hi;
+            break;
+        }
+        const int f = __builtin_ctzll(m);
+        const int nlo = f == 0 ? lo : lo + f * step;
+        hi = min(lo + (f + 1) * step - 1, hi);
+        lo = nlo;
+    }
+    if (hi - lo > 0) {
+        const int idx = lo + lane;
+        const bool above = idx >= hi || u < cdf[idx];
+        const uint64_t m = __builtin_amdgcn_ballot_w64(above);
+        lo = m == 0 ? hi : lo + __builtin_ctzll(m);
+    }
+    return lo < len ? lo : len - 1;
+}
+
 // Draw the P_F modes of eq. (28): component (m, d) by its mass, then the
-// three axis indices from their 1D lattice distributions, then signs.
-__global__ void k_ksample(RB_ARGS, const KDev* __restrict__ kd)
+// three axis indices from their 1D lattice distributions, then signs.  One
+// wavefront per mode (the searches are wave-cooperative).
+__global__ __launch_bounds__(64) void k_ksample(RB_ARGS, const KDev* __restrict__ kd)
 {
     RB_SYS(blockIdx.x)
     const KDev k = global_view(kd[rb_m.x]);
-    const int p = lb * blockDim.x + threadIdx.x;
-    if (p >= k.n_modes) return;
+    const int p = lb;
+    if (!k.sampled || p >= k.n_modes) return;
     PhiloxStream st(s.seed, (uint32_t)p, (uint32_t)s.sc->eval, kTagKmode, s.replica);
     const double uc = st.uniform();
     double ua[3];
     for (int a = 0; a < 3; ++a) ua[a] = st.uniform();
     const uint32_t signs = st.next();
-    const int c = first_above(k.comp_cdf, k.nm * 3, uc);
+    const int c = first_above_wave(k.comp_cdf, k.nm * 3, uc);
     const int m = c / 3, d = c % 3;
     int mi[3];
     for (int a = 0; a < 3; ++a) {
         const int o = k.off[m * 3 + a], L = k.len[m * 3 + a];
         const double* cdf = (a == d) ? k.g2cdf + o : k.g0cdf + o;
-        int nn = first_above(cdf, L, ua[a]);
+        int nn = first_above_wave(cdf, L, ua[a]);
         if (nn > 0 && ((signs >> a) & 1u)) nn = -nn;
         mi[a] = nn;
     }
+    if (threadIdx.x != 0) return;
     k.m[3 * p] = mi[0];
     k.m[3 * p + 1] = mi[1];
     k.m[3 * p + 2] = mi[2];
@@ -1604,6 +1637,8 @@ __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __rest
     const int p = lb;
     const int lane = threadIdx.x;
     double re = 0.0, im = 0.0;
+    // unrolled so the loads are in flight together; the sum order is unchanged
+#pragma unroll 8
     for (int c = lane; c < k.n_chunks; c += 64) {
         const double* o = k.rho_part + ((size_t)c * k.n_modes_pad + p) * 2;
         re += o[0];
@@ -2152,7 +2187,8 @@ void launch_build(const Plan& P, bool gate, hipStream_t st)
 
 void launch_ksample(const Plan& P, hipStream_t st)
 {
-    if (P.modes64.blocks > 0) k_ksample<<<P.modes64.blocks, 64, 0, st>>>(RB_MAP(modes64), P.kd);
+    // one wavefront per mode of every system (non-sampled systems return)
+    if (P.modes64.blocks > 0) k_ksample<<<P.modes1.blocks, 64, 0, st>>>(RB_MAP(modes1), P.kd);
 }
 
 template <int KU>
