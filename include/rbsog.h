@@ -286,10 +286,15 @@ typedef struct {
                            kernel; 0: it runs after the pair kernel on the context's stream (1) */
 } rbsog_tuning;
 
-/* Time every candidate shape of each hot kernel with `reps` launches at the
- * current positions (HIP events on the context's stream) and keep the
- * fastest; the chosen shapes are returned in `chosen` (may be NULL).  Leaves
- * positions, velocities and forces as they were.  Synchronises. */
+/* Choose the launch shapes by timing from the current state (HIP events on
+ * the context's stream): the k-space force workgroup alone, then every
+ * combination of pair_block, pair_ku, rho_mpl and kf_aux on whole steps
+ * (both streams, graphs if enabled), max(reps, 3) steps per candidate from
+ * one saved device state, best of three alternating rounds; the chosen
+ * shapes are returned in `chosen` (may be NULL).  Restores the saved state
+ * (positions, velocities, forces, lists, counters), so the trajectory that
+ * follows is bit for bit the one without tuning; holds a second copy of the
+ * atom and list arrays while it runs.  Synchronises. */
 rbsog_status rbsog_autotune(rbsog_ctx* ctx, int32_t reps, rbsog_tuning* chosen);
 /* Set or read the shapes directly (values outside the lists: RBSOG_E_ARG). */
 rbsog_status rbsog_set_tuning(rbsog_ctx* ctx, const rbsog_tuning* t);

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <exception>
 #include <functional>
+#include <memory>
 #include <initializer_list>
 #include <new>
 #include <stdexcept>
@@ -694,35 +695,13 @@ void autotune(rbsog_ctx* c, int reps)
         c->plan.tune = t;
         plan_launches(c);
     };
-    double tb = 1e300;
-    for (int bs : {64, 128, 256})
-        for (int ku : {4, 8}) {
-            Tuning t = best;
-            t.pair_block = bs;
-            t.pair_ku = ku;
-            try_shape(t);
-            const double ms = time_ms(c, reps, [&] { launch_pair(c->plan, c->coef, c->mixed, false, st); });
-            if (ms < tb) {
-                tb = ms;
-                best.pair_block = bs;
-                best.pair_ku = ku;
-            }
-        }
-    tb = 1e300;
-    for (int mpl : {1, 2}) {
-        Tuning t = best;
-        t.rho_mpl = mpl;
-        try_shape(t);
-        const double ms = time_ms(c, reps, [&] { launch_rho(c->plan, c->mixed, st); });
-        if (ms < tb) {
-            tb = ms;
-            best.rho_mpl = mpl;
-        }
-    }
     try_shape(best);
+    launch_rho(c->plan, c->mixed, st);
     launch_rho_finalize(c->plan, st);
+    launch_pair(c->plan, c->coef, c->mixed, false, st);
     launch_finalize(c->plan, false, st);
-    tb = 1e300;
+    // the k-space force kernel alone: its workgroup size
+    double tb = 1e300;
     for (int bs : {64, 128, 256}) {
         Tuning t = best;
         t.kf_block = bs;
@@ -733,20 +712,63 @@ void autotune(rbsog_ctx* c, int reps)
             best.kf_block = bs;
         }
     }
-    // the k-space force beside the pair kernel pays off while the chain on the
-    // second stream stays the shorter one: time whole evaluations both ways
-    // (alternating, best of several rounds: the two are often close)
-    double tk[2] = {1e300, 1e300};
-    for (int round = 0; round < 4; ++round)
-        for (int aux : {1, 0}) {
-            Tuning t = best;
-            t.kf_aux = aux;
-            c->plan.tune = t;  // same launch shapes: no new block maps
-            tk[aux] = std::min(tk[aux], time_ms(c, std::max(reps, 5), [&] { enqueue_forces(c, false, false); }));
+    // The pair kernel shares the device with the k-space chain on the second
+    // stream, and the passes around it in a step (drift, gated build) change
+    // what the caches hold when it starts: its shape, the rho modes per lane
+    // and where the k-space force runs are chosen together on whole steps
+    // (timed on back-to-back force evaluations, larger pair workgroups look
+    // faster and still lengthen the step).  Every candidate runs the same
+    // steps from one saved device state (atoms, list counts, lists and
+    // scalars), which is put back afterwards: tuning leaves the trajectory
+    // bit for bit as it was.  Alternating rounds, best of three.
+    DBuf* state[] = {&c->atoms, &c->counts, &c->lists_core, &c->lists_cand, &c->lists_bat, &c->scalars};
+    constexpr int kState = sizeof(state) / sizeof(state[0]);
+    std::unique_ptr<DBuf[]> saved(new DBuf[kState]);
+    auto copy_state = [&](bool save) {
+        for (int q = 0; q < kState; ++q) {
+            DBuf& live = *state[q];
+            if (!live.p) continue;
+            if (save) saved[q].alloc(live.bytes);
+            HIP_OK(hipMemcpyAsync(save ? saved[q].p : live.p, save ? live.p : saved[q].p, live.bytes,
+                                  hipMemcpyDeviceToDevice, st));
         }
-    best.kf_aux = tk[1] <= tk[0] ? 1 : 0;
+    };
+    copy_state(true);
+    const int n_steps = std::max(reps, 3);
+    struct Cand {
+        Tuning t;
+        double ms;
+    };
+    std::vector<Cand> cands;
+    for (int bs : {64, 128, 256})
+        for (int ku : {4, 8})
+            for (int mpl : {1, 2})
+                for (int aux : {1, 0}) {
+                    Tuning t = best;
+                    t.pair_block = bs;
+                    t.pair_ku = ku;
+                    t.rho_mpl = mpl;
+                    t.kf_aux = aux;
+                    cands.push_back(Cand{t, 1e300});
+                }
+    for (int round = 0; round < 3; ++round)
+        for (Cand& cd : cands) {
+            try_shape(cd.t);
+            copy_state(false);
+            // time_ms runs the steps once untimed first (which also captures
+            // the step graph when graphs are on), then once timed
+            cd.ms = std::min(cd.ms, time_ms(c, 1, [&] {
+                for (int k = 0; k < n_steps; ++k) launch_step(c, false, false);
+            }));
+        }
+    double t_best = 1e300;
+    for (const Cand& cd : cands)
+        if (cd.ms < t_best) {
+            t_best = cd.ms;
+            best = cd.t;
+        }
     try_shape(best);
-    enqueue_forces(c, false, false);
+    copy_state(false);
     HIP_OK(hipStreamSynchronize(st));
     c->forces_valid = true;
     c->profiling = was_profiling;

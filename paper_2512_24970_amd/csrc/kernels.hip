@@ -1090,28 +1090,38 @@ template <bool MIXED, bool ENERGY, int J, int KU>
 __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoefF gf, NearTab nt)
 {
     RB_SYS(xcd_block(blockIdx.x, gridDim.x))
-    // dynamic LDS: the near-field table (mixed form; F coefficients, with
-    // energies also U), then the Floyd masks of the per-evaluation draw
+    // dynamic LDS, sized by the launch: the near-field table (mixed form; F
+    // coefficients, with energies also U), the core lanes' sums handed to the
+    // shell lanes (F, and with energies u and the virial: 4 or 10 per atom),
+    // then the Floyd masks of the per-evaluation draw.  Kept small: the
+    // kernel waits on neighbour gathers, so resident waves are what counts.
     extern __shared__ float4 dyn_sm[];
     const int tab_vecs = MIXED ? nt.n * (ENERGY ? 2 : 1) : 0;
+    const int A = blockDim.x >> 1;
+    constexpr int kXch = ENERGY ? 10 : 4;
     float4* tab = dyn_sm;
-    uint32_t* mask_sm = reinterpret_cast<uint32_t*>(dyn_sm + tab_vecs);
+    double* xch = reinterpret_cast<double*>(dyn_sm + tab_vecs);  // [kXch][A]
+    uint32_t* mask_sm = reinterpret_cast<uint32_t*>(xch + kXch * A);
     if (MIXED) {
         const float4* src = glob(nt.coef);
         for (int t = threadIdx.x; t < tab_vecs; t += blockDim.x) tab[t] = ENERGY ? src[t] : src[2 * t];
     }
-    __shared__ PairCoef pc[kMaxSpecies * kMaxSpecies];
-    __shared__ PairCoefF pcf[kMaxSpecies * kMaxSpecies];
-    __shared__ double xch[ENERGY ? 10 : 4][kBlock];  // core F (3), energy and virial (6), per atom
+    // pair coefficients: FP64 for the FP64 form; the mixed form keeps FP32
+    // copies and only the FP64 core radii (the core/shell test stays FP64)
+    __shared__ PairCoef pc[MIXED ? 1 : kMaxSpecies * kMaxSpecies];
+    __shared__ PairCoefF pcf[MIXED ? kMaxSpecies * kMaxSpecies : 1];
+    __shared__ double rc2s[kMaxSpecies * kMaxSpecies];
     const int S = s.n_species;
     for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
         const PairCoef c = s.pair[t];
-        pc[t] = c;
-        pcf[t] = PairCoefF{(float)c.qq, (float)c.A, (float)c.sig, (float)c.irho, (float)c.C, (float)c.D};
+        if (MIXED)
+            pcf[t] = PairCoefF{(float)c.qq, (float)c.A, (float)c.sig, (float)c.irho, (float)c.C, (float)c.D};
+        else
+            pc[t] = c;
+        rc2s[t] = c.rc2;
     }
     __syncthreads();
 
-    const int A = blockDim.x >> 1;
     const bool shell = threadIdx.x >= A;  // uniform per wavefront (A is a multiple of 64)
     const int ta = shell ? threadIdx.x - A : threadIdx.x;
     const int i = lb * A + ta;
@@ -1165,7 +1175,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
                     const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < (s.species_cut ? pc[ti * S + T[u]].rc2 : s.rc2)) {
+                    if (r2 < (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2)) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
                         add_pair<ENERGY>(f, uu, dx, dy, dz, Fx, Fy, Fz, Uc, Wv);
@@ -1202,7 +1212,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
                     const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 >= (s.species_cut ? pc[ti * S + T[u]].rc2 : s.rc2) && r2 < s.rs2) {
+                    if (r2 >= (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2) && r2 < s.rs2) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
                         add_pair<ENERGY>(f, uu, dx, dy, dz, Sx, Sy, Sz, Su, Wv);
@@ -1259,7 +1269,7 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
                     const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 >= (s.species_cut ? pc[ti * S + T[u]].rc2 : s.rc2) && r2 < s.rs2) {
+                    if (r2 >= (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2) && r2 < s.rs2) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
                         add_pair<ENERGY>(f, uu, dx, dy, dz, Sx, Sy, Sz, Su, Wv);
@@ -1269,23 +1279,23 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
         }
     }
     if (!shell) {
-        xch[0][ta] = Fx;
-        xch[1][ta] = Fy;
-        xch[2][ta] = Fz;
-        xch[3][ta] = Uc;
+        xch[0 * A + ta] = Fx;
+        xch[1 * A + ta] = Fy;
+        xch[2 * A + ta] = Fz;
+        xch[3 * A + ta] = Uc;
         if (ENERGY)
-            for (int c = 0; c < 6; ++c) xch[4 + c][ta] = Wv[c];
+            for (int c = 0; c < 6; ++c) xch[(4 + c) * A + ta] = Wv[c];
     }
     __syncthreads();
     if (shell) {
         if (i < s.n) {
-            Fx = fma(wgt, Sx, xch[0][ta]);
-            Fy = fma(wgt, Sy, xch[1][ta]);
-            Fz = fma(wgt, Sz, xch[2][ta]);
-            Uc = xch[3][ta];
+            Fx = fma(wgt, Sx, xch[0 * A + ta]);
+            Fy = fma(wgt, Sy, xch[1 * A + ta]);
+            Fz = fma(wgt, Sz, xch[2 * A + ta]);
+            Uc = xch[3 * A + ta];
             if (ENERGY) {
                 Us = wgt * Su;
-                for (int c = 0; c < 6; ++c) Wv[c] = fma(wgt, Wv[c], xch[4 + c][ta]);
+                for (int c = 0; c < 6; ++c) Wv[c] = fma(wgt, Wv[c], xch[(4 + c) * A + ta]);
             }
             __builtin_nontemporal_store(Fx, s.fsx + i);
             __builtin_nontemporal_store(Fy, s.fsy + i);
@@ -2198,7 +2208,8 @@ void launch_pair_ku(const Plan& P, const SogCoef& g, const SogCoefF& gf, bool mi
     // near-field table (mixed), then the Floyd masks of the per-evaluation
     // batch draw (none for a stored batch)
     const size_t tab = mixed ? sizeof(float4) * (size_t)P.near.n * (energy ? 2 : 1) : 0;
-    const size_t sm = tab + (P.stored ? 0 : sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * bs);
+    const size_t xch = sizeof(double) * (energy ? 10 : 4) * (size_t)bs;
+    const size_t sm = tab + xch + (P.stored ? 0 : sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * bs);
     const int nb = P.pair_atoms.blocks;
 #define RB_PAIR(M, E, J) k_pair<M, E, J, KU><<<nb, 2 * bs, sm, st>>>(RB_MAP(pair_atoms), g, gf, P.near)
     if (mixed) {
