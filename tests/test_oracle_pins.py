@@ -1032,3 +1032,61 @@ def test_heat_flux_after_steps_uses_the_final_velocities():
     f.close()
     assert np.allclose(e["heat_flux"], e2["heat_flux"], rtol=1e-10, atol=1e-12)
     assert np.allclose(e["stress"], e2["stress"], rtol=1e-10, atol=1e-9)
+
+
+# --------------------------------------------------------------------------- finite-time error theorem
+def _langevin_end(cfg, sysp, dt, seed, p_r, p_f):
+    n = int(round(0.02 / dt))
+    s = O.System(dict(sysp, dt=dt, seed=seed, p_r=p_r, p_f=p_f), cfg["types"], cfg["pos"], cfg["vel"])
+    s.forces(0)
+    s.vv_steps(n)
+    p, v, _, _ = s.state()
+    s.close()
+    return p, v
+
+
+def _force_variance(cfg, sysp, p_r, p_f, draws=12):
+    ex = O.System(dict(sysp, p_r=0, p_f=0), cfg["types"], cfg["pos"], cfg["vel"])
+    f0, _ = ex.forces(0)
+    ex.close()
+    s = O.System(dict(sysp, p_r=p_r, p_f=p_f), cfg["types"], cfg["pos"], cfg["vel"])
+    acc = 0.0
+    for ev in range(draws):
+        f, _ = s.forces(ev)
+        acc += ((f - f0) ** 2).sum(1).mean()
+    s.close()
+    return acc / draws
+
+
+def test_finite_time_error_scales_as_sqrt_lambda_dt():
+    """The finite-time error theorem of Section 2.3 (eq. (47)): with the same
+    initial data and the same Wiener increments (the Langevin noise is keyed
+    by seed, atom and step only, so a random-batch run and an exact-force run
+    with P_R = P_F = 0 share it), the RMS over ions of |r - r*|^2 + |v - v*|^2
+    at T = 20 fs scales as sqrt(Lambda dt).  A 4x smaller step halves it; a
+    larger batch shrinks it by the square root of the ratio of the estimators'
+    force variances, measured at the initial positions (with ~134 candidates
+    per ion the finite-population correction makes that ratio more than the
+    batch-size ratio).  Four seeds; 216 ions of the melt, BAOAB at 1200 K."""
+    cfg = W.config("nacl_small")
+    sysp = dict(cfg["sys"], thermostat="langevin", t_target=1200.0, tau_t=0.1, skin=1.0, rebuild_every=5)
+    L = np.array(sysp["box"])
+
+    def rms(dt, p_r, p_f):
+        e2 = []
+        for seed in range(101, 105):
+            pa, va = _langevin_end(cfg, sysp, dt, seed, p_r, p_f)
+            pb, vb = _langevin_end(cfg, sysp, dt, seed, 0, 0)
+            d = pa - pb
+            d -= L * np.rint(d / L)
+            e2.append(((d ** 2).sum(1) + ((va - vb) ** 2).sum(1)).mean())
+        return math.sqrt(np.mean(e2))
+
+    e_1 = rms(0.001, 20, 100)
+    e_q = rms(0.00025, 20, 100)
+    assert e_1 > 0.0 and e_q > 0.0
+    assert 1.6 < e_1 / e_q < 2.5, (e_1, e_q)
+    e_big = rms(0.001, 80, 400)
+    lam_ratio = _force_variance(cfg, sysp, 20, 100) / _force_variance(cfg, sysp, 80, 400)
+    assert lam_ratio > 4.0
+    assert e_1 / e_big == pytest.approx(math.sqrt(lam_ratio), rel=0.3), (e_1, e_big, lam_ratio)
