@@ -105,6 +105,7 @@ def lib():
             "orc_vv_steps": (C.c_int, [C.c_void_p, C.c_int32, P(Energy)]),
             "orc_get_state": (None, [C.c_void_p, dp, dp, dp, P(C.c_uint64)]),
             "orc_forces_short_atoms": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, i32p, dp]),
+            "orc_rdf_counts": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.POINTER(C.c_uint64)]),
             "orc_kforce_atoms": (None, [C.c_void_p, C.c_int32, i32p, dp, C.c_double, C.c_int32, i32p, dp]),
             "orc_set_threads": (None, [C.c_int]),
             "orc_get_threads": (C.c_int, []),
@@ -329,6 +330,15 @@ class System:
         m = np.ascontiguousarray(m, dtype=np.int32).reshape(-1, 3)
         out = np.zeros((len(m), 2))
         lib().orc_rho(self._h, len(m), _ptr(m, C.c_int32), _ptr(out, C.c_double))
+        return out
+
+    def rdf_counts(self, r_max: float, n_bins: int) -> np.ndarray:
+        """Pair-distance histogram [S, S, n_bins] (ordered pairs, all by brute force)."""
+        S = self.params.n_species
+        out = np.zeros((S, S, n_bins), dtype=np.uint64)
+        rc = lib().orc_rdf_counts(self._h, float(r_max), int(n_bins), _ptr(out, C.c_uint64))
+        if rc != 0:
+            raise ValueError("orc_rdf_counts: bad arguments")
         return out
 
     def forces_short_atoms(self, ev: int, sel) -> np.ndarray:

@@ -886,6 +886,28 @@ int orc_forces_short(orc_ctx* c, uint64_t eval, double* force, double* u_core, d
     return 0;
 }
 
+int orc_rdf_counts(const orc_ctx* c, double r_max, int32_t n_bins, uint64_t* counts)
+{
+    if (n_bins < 1 || !(r_max > 0.0)) return -1;
+    const orc_params* p = &c->p;
+    const int S = p->n_species;
+    const double D = r_max / (double)n_bins;
+    const double top = ((double)n_bins * D) * ((double)n_bins * D);
+    memset(counts, 0, sizeof(uint64_t) * (size_t)S * S * n_bins);
+    for (int i = 0; i < c->n; ++i)
+        for (int j = 0; j < c->n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            min_image(p, c->pos + 3 * i, c->pos + 3 * j, d);
+            double r2 = norm2(d);
+            if (!(r2 < top)) continue;
+            int k = n_bins - 1;  /* the last bin whose lower edge is at or below r^2 */
+            while (((double)k * D) * ((double)k * D) > r2) --k;
+            counts[((size_t)c->type[i] * S + c->type[j]) * n_bins + k] += 1;
+        }
+    return 0;
+}
+
 int orc_forces_short_atoms(const orc_ctx* c, uint64_t eval, int32_t n_sel, const int32_t* sel, double* force)
 {
     const orc_params* p = &c->p;

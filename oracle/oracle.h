@@ -180,6 +180,14 @@ void orc_kforce_atoms(const orc_ctx* c, int32_t n_modes, const int32_t* m,
                       const double* rho, double coef_scale, int32_t n_sel,
                       const int32_t* sel, double* force);
 
+/* Radial distribution counts at the current positions (the pair histogram
+ * behind the RDF of Section 3.1): counts[(a S + b) n_bins + k] (S species)
+ * = ordered pairs i != j of types (a, b) whose minimum-image r^2 satisfies
+ * e_k <= r^2 < e_{k+1}, e_k = (k D)(k D) in FP64, D = r_max / n_bins.  All
+ * pairs by brute force (O(N^2)).  Returns 0, or -1 for n_bins < 1 or
+ * r_max <= 0. */
+int orc_rdf_counts(const orc_ctx* c, double r_max, int32_t n_bins, uint64_t* counts);
+
 /* Threads the oracle's parallel loops use (OpenMP), 0 = library default. */
 void orc_set_threads(int n);
 int orc_get_threads(void);

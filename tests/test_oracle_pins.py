@@ -1090,3 +1090,55 @@ def test_finite_time_error_scales_as_sqrt_lambda_dt():
     lam_ratio = _force_variance(cfg, sysp, 20, 100) / _force_variance(cfg, sysp, 80, 400)
     assert lam_ratio > 4.0
     assert e_1 / e_big == pytest.approx(math.sqrt(lam_ratio), rel=0.3), (e_1, e_big, lam_ratio)
+
+
+# --------------------------------------------------------------------------- radial distribution counts
+def test_rdf_counts_of_the_perfect_rock_salt_lattice():
+    """512 ions on the perfect rock-salt lattice (a = 3.15 A): every ion sees
+    6 unlike ions at a, 12 like at a sqrt2, 8 unlike at a sqrt3, 6 like at
+    2a, 24 unlike at a sqrt5, 24 like at a sqrt6, 12 like at 2a sqrt2 and 30
+    unlike at 3a; no other distance below 9.9 A.  Bins of 0.11 A keep every
+    shell away from a bin edge."""
+    cfg = W.config("nacl_512", jitter=0.0)
+    s = O.System(cfg["sys"], cfg["types"], cfg["pos"], cfg["vel"])
+    cnt = s.rdf_counts(9.9, 90)
+    s.close()
+    a = 25.2 / 8
+    shells = [(1, 6, True), (2, 12, False), (3, 8, True), (4, 6, False), (5, 24, True), (6, 24, False),
+              (8, 12, False), (9, 30, True)]
+    want = np.zeros_like(cnt)
+    na = int((cfg["types"] == 0).sum())
+    for m2, k, unlike in shells:
+        b = int(math.floor(a * math.sqrt(m2) / 0.11))
+        for t in (0, 1):
+            u = 1 - t if unlike else t
+            want[t, u, b] += k * na
+    assert np.array_equal(cnt, want)
+
+
+def test_rdf_counts_of_an_ideal_gas():
+    """Uniform random positions (two species, 400 + 400 ions in a 30 A box):
+    the expected count of ordered pairs in bin k is N_a (N_b - delta_ab) / V
+    times the shell volume 4 pi (r_{k+1}^3 - r_k^3) / 3; chi-squared over the
+    bins on unordered pairs (like pairs are counted in both directions)."""
+    from scipy import stats
+    rng = np.random.default_rng(23)
+    n, L = 800, 30.0
+    base = W.config("nacl_512")
+    sysp = dict(base["sys"], box=[L, L, L])
+    types = np.repeat(np.array([0, 1], np.int32), n // 2)
+    pos = rng.uniform(0.0, L, size=(n, 3))
+    s = O.System(sysp, types, pos)
+    r_max, nb = 10.0, 40
+    cnt = s.rdf_counts(r_max, nb).astype(float)
+    s.close()
+    edges = np.arange(nb + 1) * (r_max / nb)
+    vol = 4.0 * math.pi / 3.0 * (edges[1:] ** 3 - edges[:-1] ** 3)
+    for a in (0, 1):
+        for b in (0, 1):
+            # like pairs appear twice (i -> j and j -> i): compare unordered pairs
+            half = 2.0 if a == b else 1.0
+            exp = (n // 2) * (n // 2 - (a == b)) / L ** 3 * vol / half
+            chi2 = (((cnt[a, b] / half - exp) ** 2) / exp)[1:].sum()
+            assert stats.chi2.sf(chi2, nb - 2) > 1e-4, (a, b, chi2)
+    assert np.array_equal(cnt[0, 1], cnt[1, 0])
