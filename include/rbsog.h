@@ -355,6 +355,17 @@ rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ran
  * min(P_R, n_cand)), and the candidate count N_shell of each atom at that
  * build, n_cand[N].  Either may be NULL. */
 rbsog_status rbsog_get_shell_batch(rbsog_ctx* ctx, int32_t* n_cand, int32_t* ids);
+/* Radial distribution counts of the selected system at its current positions
+ * (the pair histogram behind the RDF g_ab(r) of Section 3.1):
+ * counts[(a S + b) n_bins + k] (host, S = n_species, S*S*n_bins entries,
+ * overwritten) = ordered pairs i != j of species (a, b) whose minimum-image
+ * r^2 satisfies e_k <= r^2 < e_{k+1}, e_k = (k D)(k D) in FP64 with
+ * D = r_max / n_bins.  Taken from the lists (every pair within r_shell
+ * appears in them), so r_max <= r_shell, and S*S*n_bins <= 16384; else
+ * RBSOG_E_ARG.  The memory form keeps no candidate rows: RBSOG_E_STATE.
+ * g_ab(r) = counts / (N_a (N_b - delta_ab) / V * shell volume).
+ * Synchronises. */
+rbsog_status rbsog_rdf_counts(rbsog_ctx* ctx, double r_max, int32_t n_bins, uint64_t* counts);
 /* The P_F modes m[P_F][3] drawn for evaluation `eval` and S of eq. (28). */
 rbsog_status rbsog_get_kmodes(rbsog_ctx* ctx, uint64_t eval, int32_t* m, double* S);
 /* Structure factors rho[P_F][2] (eq. 22) of the last force evaluation. */

@@ -1601,6 +1601,30 @@ rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_
     });
 }
 
+rbsog_status rbsog_rdf_counts(rbsog_ctx* ctx, double r_max, int32_t n_bins, uint64_t* counts)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        const DevSys& s = ctx->hs[ctx->sel];
+        const rbsog_params& p = ctx->prm[ctx->sel];
+        require(n_bins >= 1 && r_max > 0.0 && r_max <= p.r_shell, RBSOG_E_ARG,
+                "rdf: need n_bins >= 1 and 0 < r_max <= r_shell");
+        const int S = s.n_species;
+        require((long long)S * S * n_bins <= 16384, RBSOG_E_ARG, "rdf: n_species^2 * n_bins > 16384");
+        require(!s.shell_stored, RBSOG_E_STATE, "rdf: the memory form keeps no candidate rows");
+        require(counts != nullptr, RBSOG_E_ARG, "rdf: counts is NULL");
+        const size_t nh = (size_t)S * S * n_bins;
+        DBuf out;
+        out.alloc(sizeof(unsigned long long) * nh);
+        HIP_OK(hipMemsetAsync(out.p, 0, out.bytes, ctx->stream));
+        const Plan P1 = one(ctx, ctx->sel);
+        launch_rdf(P1, S, r_max / (double)n_bins, n_bins, out.as<unsigned long long>(), ctx->stream);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(counts, out.p, out.bytes, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
 rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ranks, int32_t* ranks)
 {
     return guarded(ctx, [&] {

@@ -2051,6 +2051,55 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
 }
 
 // ---------------------------------------------------------------- exports
+// Pair-distance histogram at the current positions, taken from the lists
+// with the split the force uses (core entries inside the pair's core radius,
+// candidates from there to r_shell), so every pair within r_shell appears
+// once per direction while the lists are valid.  Bin k holds
+// e_k <= r^2 < e_{k+1}, e_k = (k D)^2 in FP64: an estimate from sqrt is
+// corrected against the exact edges.  Per-workgroup LDS counters, one
+// global atomic per nonzero bin (integer sums: the counts do not depend on
+// the order).
+__global__ __launch_bounds__(kBlock) void k_rdf(RB_ARGS, double D, int n_bins, unsigned long long* counts)
+{
+    RB_SYS(blockIdx.x)
+    extern __shared__ uint32_t hist[];  // [S][S][n_bins]
+    const int S = s.n_species;
+    const int nh = S * S * n_bins;
+    for (int t = threadIdx.x; t < nh; t += blockDim.x) hist[t] = 0u;
+    __syncthreads();
+    const int i = lb * blockDim.x + threadIdx.x;
+    if (i < s.n) {
+        const double4 Pi = s.p[i];
+        const int ti = s.type[i];
+        const double top = ((double)n_bins * D) * ((double)n_bins * D);
+        auto edge = [&](int k) { return ((double)k * D) * ((double)k * D); };
+        auto visit = [&](int j, bool core) {
+            const double4 Q = s.p[j];
+            const double dx = min_image(Pi.x - Q.x, s.L[0], s.invL[0]);
+            const double dy = min_image(Pi.y - Q.y, s.L[1], s.invL[1]);
+            const double dz = min_image(Pi.z - Q.z, s.L[2], s.invL[2]);
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            const int tj = (int)Q.w;
+            const double rc2 = s.species_cut ? s.pair[ti * S + tj].rc2 : s.rc2;
+            const bool in = core ? r2 < rc2 : (r2 >= rc2 && r2 < s.rs2);
+            if (!in || !(r2 < top)) return;
+            int k = min((int)(sqrt(r2) / D), n_bins - 1);
+            while (k + 1 < n_bins && edge(k + 1) <= r2) ++k;
+            while (k > 0 && edge(k) > r2) --k;
+            atomicAdd(&hist[(ti * S + tj) * n_bins + k], 1u);
+        };
+        const int nc = min(s.core_cnt[i], s.cap_core - 1);
+        const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
+        for (int k = 0; k < nc; ++k) visit(ctile[(size_t)k * 64], true);
+        const int nk = min(s.cand_cnt[i], s.cap_cand - 1);
+        const int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
+        for (int k = 0; k < nk; ++k) visit(crow[k], false);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nh; t += blockDim.x)
+        if (hist[t]) atomicAdd(&counts[t], (unsigned long long)hist[t]);
+}
+
 __global__ void k_to_user3(RB_ARGS, int field, double* out)
 {
     RB_SYS(blockIdx.x)
@@ -2337,6 +2386,12 @@ void launch_kick_drift(const Plan& P, bool scheduled, hipStream_t st)
         k_kick_drift<true><<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), scheduled ? 1 : 0);
     else
         k_kick_drift<false><<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), scheduled ? 1 : 0);
+}
+
+void launch_rdf(const Plan& P, int n_species, double D, int n_bins, unsigned long long* counts, hipStream_t st)
+{
+    const size_t sm = sizeof(uint32_t) * (size_t)n_species * n_species * n_bins;
+    if (P.atoms.blocks > 0) k_rdf<<<P.atoms.blocks, kBlock, sm, st>>>(RB_MAP(atoms), D, n_bins, counts);
 }
 
 void launch_to_user3(const Plan& P, Field f, double* out, hipStream_t st)

@@ -233,6 +233,8 @@ void launch_kick_drift(const Plan& P, bool scheduled, hipStream_t st);
 
 // exports into the caller's [N][3] arrays (row user_off + id)
 enum class Field { force = 0, short_force = 1, velocity = 2 };
+// pair-distance histogram [S][S][n_bins] (uint64, accumulated) from the lists
+void launch_rdf(const Plan& P, int n_species, double D, int n_bins, unsigned long long* counts, hipStream_t st);
 void launch_to_user3(const Plan& P, Field f, double* out, hipStream_t st);
 void launch_pos_to_user(const Plan& P, double* out, hipStream_t st);
 void launch_kspace_part(const Plan& P, double* out, hipStream_t st);

@@ -104,6 +104,7 @@ ABI = {
     "rbsog_get_lists_of": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "rbsog_get_shell_ranks": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "rbsog_get_shell_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rbsog_rdf_counts": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
     "rbsog_set_list_chunks": (C.c_int, [C.c_void_p, C.c_int32]),
     "rbsog_set_list_capacity": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32)]),
@@ -411,6 +412,13 @@ class Context:
         ids = np.zeros((self._sel_n, P), np.int32)
         self._check(lib().rbsog_get_shell_batch(self._h, _np_ptr(nk), _np_ptr(ids)), "rbsog_get_shell_batch")
         return nk, ids
+
+    def rbsog_rdf_counts(self, r_max: float, n_bins: int) -> np.ndarray:
+        """Pair-distance histogram [S, S, n_bins] (uint64) of the selected system."""
+        S = self.params_list[self.sel].n_species
+        out = np.zeros((S, S, int(n_bins)), np.uint64)
+        self._check(lib().rbsog_rdf_counts(self._h, float(r_max), int(n_bins), _np_ptr(out)), "rbsog_rdf_counts")
+        return out
 
     def rbsog_get_kmodes(self, ev: int):
         p_f = self.params_list[self.sel].p_f
