@@ -366,6 +366,17 @@ rbsog_status rbsog_get_shell_batch(rbsog_ctx* ctx, int32_t* n_cand, int32_t* ids
  * g_ab(r) = counts / (N_a (N_b - delta_ab) / V * shell volume).
  * Synchronises. */
 rbsog_status rbsog_rdf_counts(rbsog_ctx* ctx, double r_max, int32_t n_bins, uint64_t* counts);
+/* Mean-square displacement of the selected system (the MSD of Section 3.1),
+ * per species, from an origin the caller marks.  mark != 0: the origin is the
+ * current positions (each ion's unwrapped displacement D_i restarts at 0).
+ * mark == 0: D_i gains the minimum-image displacement since the previous call
+ * and msd[a] (host, n_species entries, may be NULL) = mean of |D_i|^2 over
+ * the ions of species a (0 for a species with none), A^2.  Unwrapping is
+ * exact while no ion moves half a box length between two calls (call every
+ * few hundred steps at most in a melt).  RBSOG_E_STATE without a marked
+ * origin; a new rbsog_set_system/batch forgets it.  Device memory: six
+ * doubles per ion, kept.  Synchronises. */
+rbsog_status rbsog_msd(rbsog_ctx* ctx, int32_t mark, double* msd);
 /* The P_F modes m[P_F][3] drawn for evaluation `eval` and S of eq. (28). */
 rbsog_status rbsog_get_kmodes(rbsog_ctx* ctx, uint64_t eval, int32_t* m, double* S);
 /* Structure factors rho[P_F][2] (eq. 22) of the last force evaluation. */

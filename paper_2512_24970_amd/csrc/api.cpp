@@ -101,6 +101,10 @@ struct rbsog_ctx {
     double row_slack = 1.25;
     DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, vir_part, kin_part, export_tmp, snap, sogk, neartab;
     DBuf flux_part, at_ew;
+    // mean-square displacement: [n_user][3] last positions, then [n_user][3]
+    // unwrapped displacements; which systems have a marked origin
+    DBuf msd_buf;
+    std::vector<char> msd_marked;
 
     // phase timing
     bool profiling = false;
@@ -921,6 +925,8 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     if (!c->ev_join) HIP_OK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     c->R = R;
     c->prm = prm;
+    c->msd_buf.release();
+    c->msd_marked.assign(R, 0);
     c->sel = 0;
     c->row_slack = 1.25;
     c->plan.tune = Tuning{};
@@ -1598,6 +1604,39 @@ rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_
                                  hipMemcpyDeviceToHost));
             for (int q = 0; q < nk; ++q) cand[q] = id[row[q]];
         }
+    });
+}
+
+rbsog_status rbsog_msd(rbsog_ctx* ctx, int32_t mark, double* msd)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        const int r = ctx->sel;
+        const DevSys& s = ctx->hs[r];
+        require(mark != 0 || ctx->msd_marked[r], RBSOG_E_STATE, "msd: no origin marked for this system");
+        const size_t nu = (size_t)std::max(ctx->n_user, 1);
+        if (!ctx->msd_buf.p) ctx->msd_buf.alloc(sizeof(double) * 6 * nu);
+        const size_t waves = (size_t)std::max(1, (s.n + 63) / 64);
+        DBuf part;
+        part.alloc(sizeof(double) * 2 * kMaxSpecies * waves);
+        HIP_OK(hipMemsetAsync(part.p, 0, part.bytes, ctx->stream));
+        double* last = ctx->msd_buf.as<double>();
+        const Plan P1 = one(ctx, r);
+        launch_msd(P1, last, last + 3 * nu, part.as<double>(), mark != 0, ctx->stream);
+        HIP_OK(hipGetLastError());
+        std::vector<double> h(2 * kMaxSpecies * waves);
+        HIP_OK(hipMemcpyAsync(h.data(), part.p, part.bytes, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        if (mark) ctx->msd_marked[r] = 1;
+        if (msd)
+            for (int a = 0; a < s.n_species; ++a) {
+                double q = 0.0, n = 0.0;
+                for (size_t w = 0; w < waves; ++w) {
+                    q += h[w * 2 * kMaxSpecies + a];
+                    n += h[w * 2 * kMaxSpecies + kMaxSpecies + a];
+                }
+                msd[a] = n > 0.0 ? q / n : 0.0;
+            }
     });
 }
 

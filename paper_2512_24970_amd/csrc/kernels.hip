@@ -2100,6 +2100,47 @@ __global__ __launch_bounds__(kBlock) void k_rdf(RB_ARGS, double D, int n_bins, u
         if (hist[t]) atomicAdd(&counts[t], (unsigned long long)hist[t]);
 }
 
+// Mean-square displacement bookkeeping, per atom by user index: the
+// minimum-image increment since the last call is added to the unwrapped
+// displacement D and the position kept (mark: D restarts at zero from the
+// current positions).  Wavefront partials of |D|^2 and of the atom count per
+// species, [waves][2 kMaxSpecies].
+__global__ __launch_bounds__(kBlock) void k_msd(RB_ARGS, double* last, double* disp, double* part, int mark)
+{
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
+    int ti = -1;
+    double q = 0.0;
+    if (i < s.n) {
+        const size_t u = 3 * (size_t)(s.user_off + s.id[i]);
+        const double4 P = s.p[i];
+        double* Lp = last + u;
+        double* Dp = disp + u;
+        if (mark) {
+            Lp[0] = P.x;
+            Lp[1] = P.y;
+            Lp[2] = P.z;
+            Dp[0] = Dp[1] = Dp[2] = 0.0;
+        } else {
+            const double dx = Dp[0] + min_image(P.x - Lp[0], s.L[0], s.invL[0]);
+            const double dy = Dp[1] + min_image(P.y - Lp[1], s.L[1], s.invL[1]);
+            const double dz = Dp[2] + min_image(P.z - Lp[2], s.L[2], s.invL[2]);
+            Dp[0] = dx;
+            Dp[1] = dy;
+            Dp[2] = dz;
+            Lp[0] = P.x;
+            Lp[1] = P.y;
+            Lp[2] = P.z;
+            q = (dx * dx + dy * dy) + dz * dz;
+        }
+        ti = s.type[i];
+    }
+    for (int a = 0; a < s.n_species; ++a) {
+        wave_partial(ti == a ? q : 0.0, i, s.n, part, 2 * kMaxSpecies, a);
+        wave_partial(ti == a ? 1.0 : 0.0, i, s.n, part, 2 * kMaxSpecies, kMaxSpecies + a);
+    }
+}
+
 __global__ void k_to_user3(RB_ARGS, int field, double* out)
 {
     RB_SYS(blockIdx.x)
@@ -2392,6 +2433,11 @@ void launch_rdf(const Plan& P, int n_species, double D, int n_bins, unsigned lon
 {
     const size_t sm = sizeof(uint32_t) * (size_t)n_species * n_species * n_bins;
     if (P.atoms.blocks > 0) k_rdf<<<P.atoms.blocks, kBlock, sm, st>>>(RB_MAP(atoms), D, n_bins, counts);
+}
+
+void launch_msd(const Plan& P, double* last, double* disp, double* part, bool mark, hipStream_t st)
+{
+    if (P.atoms.blocks > 0) k_msd<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), last, disp, part, mark ? 1 : 0);
 }
 
 void launch_to_user3(const Plan& P, Field f, double* out, hipStream_t st)

@@ -235,6 +235,9 @@ void launch_kick_drift(const Plan& P, bool scheduled, hipStream_t st);
 enum class Field { force = 0, short_force = 1, velocity = 2 };
 // pair-distance histogram [S][S][n_bins] (uint64, accumulated) from the lists
 void launch_rdf(const Plan& P, int n_species, double D, int n_bins, unsigned long long* counts, hipStream_t st);
+// mean-square displacement bookkeeping of one system (Plan of that system);
+// part: [ceil(n/64)][2 kMaxSpecies] wavefront partials
+void launch_msd(const Plan& P, double* last, double* disp, double* part, bool mark, hipStream_t st);
 void launch_to_user3(const Plan& P, Field f, double* out, hipStream_t st);
 void launch_pos_to_user(const Plan& P, double* out, hipStream_t st);
 void launch_kspace_part(const Plan& P, double* out, hipStream_t st);
