@@ -1681,11 +1681,14 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
     __shared__ double red[16];
     double v[kPairPart + kVirPart];
     for (int c = 0; c < kPairPart + kVirPart; ++c) v[c] = 0.0;
+#pragma unroll 4
     for (int b = threadIdx.x; b < nb; b += blockDim.x)
         for (int c = 0; c < kPairPart; ++c) v[c] += part[(size_t)b * kPairPart + c];
-    if (energy)
+    if (energy) {
+#pragma unroll 4
         for (int b = threadIdx.x; b < nb; b += blockDim.x)
             for (int c = 0; c < kVirPart; ++c) v[kPairPart + c] += s.vir_part[(size_t)b * kVirPart + c];
+    }
     const int nc = energy ? kPairPart + kVirPart : kPairPart;
     double ue = 0.0;
     double wk[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1911,12 +1914,14 @@ __global__ __launch_bounds__(1024) void k_kinetic_finalize(const DevSys* __restr
     const int nb = (s.n + 63) / 64;  // wavefront partials
     __shared__ double red[16];
     double v = 0.0;
+#pragma unroll 4
     for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[b];
     const double t = block_sum(v, red);
     double ft[kFluxPart];
     if (flux) {
         for (int c = 0; c < kFluxPart; ++c) {
             double x = 0.0;
+#pragma unroll 4
             for (int b = threadIdx.x; b < nb; b += blockDim.x) x += s.flux_part[(size_t)b * kFluxPart + c];
             ft[c] = block_sum(x, red);
         }
