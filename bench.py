@@ -84,14 +84,21 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto", 
     f0, _ = ctx.rbsog_compute_forces(0, want_energy=False)
     f0 = f0.cpu().numpy()
     e0 = ctx.rbsog_step(warmup) if warmup > 0 else None
+    # the timed steps bracket only the hot kernels with events (their live
+    # durations give the roofline); every phase is timed on a short extra
+    # run, since events around each phase cost a few per cent of a step
     ctx.rbsog_profile_read()
-    ctx.rbsog_profile_enable(True)
+    ctx.rbsog_profile_enable(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e1 = ctx.rbsog_step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.rbsog_profile_read()
+    phase_steps = min(steps, 30)
+    ctx.rbsog_profile_enable(1)
+    ctx.rbsog_step(phase_steps)
+    prof_all = ctx.rbsog_profile_read()
     ctx.rbsog_profile_enable(False)
     # device memory held for the system: everything the library allocated
     # (torch's own cache emptied first)
@@ -104,6 +111,7 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto", 
     ctx.close()
     T = 2 * e1["kinetic"] / ((3 * n - 3) * 8.617333262e-5)
     return {"seconds": dt, "value": n * steps / dt, "ms_per_step": 1e3 * dt / steps, "phases": prof,
+            "phases_all": prof_all, "phase_steps": phase_steps,
             "energy": e1, "energy_warm": e0, "T_end": T, "force0": f0, "tuning": tuning,
             "device_mem_GB": round(mem_gb, 3)}
 
@@ -183,6 +191,11 @@ def run_batch(n_rep: int, steps: int, warmup: int):
 FLOPS_TEST, FLOPS_PAIR = 17, 123
 
 KERNEL_OF_PHASE = {"pair": "k_pair", "rho": "k_rho", "kforce": "k_kforce"}
+
+
+def phase_ms(res) -> dict:
+    """Milliseconds per step of every phase, from the short all-phase run."""
+    return {k: round(v[0] / res["phase_steps"], 4) for k, v in res["phases_all"].items()}
 
 
 def pair_flops_per_atom(sysp: dict, n: int) -> float:
@@ -360,7 +373,7 @@ def main() -> int:
             "shell_batch": "stored at the list build" if args.shell_stored else "drawn every evaluation",
         },
         "roofline": roofline(head, r, n, cfg["sys"], wl_key),
-        "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
+        "phases_ms_per_step": phase_ms(r),
         "tuning": r["tuning"],
         "device_mem_GB": r["device_mem_GB"],
     }
@@ -373,7 +386,7 @@ def main() -> int:
         line[f] = {"value": rf["value"], "ms_per_step": rf["ms_per_step"], "T_end_K": round(rf["T_end"], 1),
                    "tuning": rf["tuning"],
                    "roofline": roofline(f, rf, n, cfg["sys"], wl_key),
-                   "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in rf["phases"].items()}}
+                   "phases_ms_per_step": phase_ms(rf)}
     if args.batch > 0:
         line["batch"] = run_batch(args.batch, args.steps, args.warmup)
     if args.large_steps > 0:
@@ -389,8 +402,7 @@ def main() -> int:
                          "T_end_K": round(rl["T_end"], 1), "tuning": rl["tuning"],
                          "device_mem_GB": rl["device_mem_GB"],
                          "roofline": roofline("mixed", rl, nb, big["sys"], "nacl_5m"),
-                         "phases_ms_per_step": {k: round(v[0] / args.large_steps, 4)
-                                                for k, v in rl["phases"].items()}}
+                         "phases_ms_per_step": phase_ms(rl)}
     if args.stored:
         # memory form of the random batch list: the shell batch is drawn at the
         # list build and kept until the next one (P_R entries per atom)
@@ -402,7 +414,7 @@ def main() -> int:
                     "steps": steps, "ms_per_step": rs["ms_per_step"], "T_end_K": round(rs["T_end"], 1),
                     "tuning": rs["tuning"], "device_mem_GB": rs["device_mem_GB"],
                     "roofline": roofline("mixed", rs, nn, c["sys"], wl + "_stored"),
-                    "phases_ms_per_step": {k: round(v[0] / steps, 4) for k, v in rs["phases"].items()}}
+                    "phases_ms_per_step": phase_ms(rs)}
         line["stored"] = stored_leg(cfg, args.steps, args.workload)
         if args.large_steps > 0:
             line["stored"]["large"] = stored_leg(big, args.large_steps, "nacl_5m")
@@ -413,8 +425,7 @@ def main() -> int:
             rt = run_gpu(cfg, "mixed", args.thermo_steps, args.warmup, "auto", kind, 0.01)
             line["thermostats"][kind] = {"tau_ps": 0.01, "value": rt["value"], "ms_per_step": rt["ms_per_step"],
                                          "steps": args.thermo_steps, "T_end_K": round(rt["T_end"], 1),
-                                         "phases_ms_per_step": {k: round(v[0] / args.thermo_steps, 4)
-                                                                for k, v in rt["phases"].items()}}
+                                         "phases_ms_per_step": phase_ms(rt)}
     if args.cpu_sample > 0:
         _log(f"[bench] cpu baseline: oracle on {args.cpu_sample} atoms")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)

@@ -325,8 +325,10 @@ typedef enum {
     RBSOG_N_PHASES = 7
 } rbsog_phase;
 
-/* Turn per-phase event timing on or off (off by default).  While on, every
- * phase launched on the stream is bracketed by two HIP events. */
+/* Per-phase event timing (off by default).  enable = 1: every phase launched
+ * is bracketed by two HIP events; 2: only the pair, rho and k-space force
+ * phases (the hot kernels; fewer events disturb the timing less); 0: off.
+ * While on, steps run kernel by kernel (no graphs). */
 rbsog_status rbsog_profile_enable(rbsog_ctx* ctx, int enable);
 /* Synchronise, add up the timed phases since the last read and reset:
  * ms[RBSOG_N_PHASES] total milliseconds, launches[RBSOG_N_PHASES] counts. */

@@ -106,8 +106,9 @@ struct rbsog_ctx {
     DBuf msd_buf;
     std::vector<char> msd_marked;
 
-    // phase timing
+    // phase timing (hot_only: the pair, rho and k-space force phases)
     bool profiling = false;
+    bool hot_only = false;
     struct Rec {
         int phase;
         hipEvent_t a, b;
@@ -133,6 +134,7 @@ struct rbsog_ctx {
     void begin(int phase, bool on_aux = false)
     {
         if (!profiling) return;
+        if (hot_only && phase != RBSOG_PHASE_PAIR && phase != RBSOG_PHASE_RHO && phase != RBSOG_PHASE_KFORCE) return;
         open_phase = phase;
         open_aux = on_aux;
         open_a = take_event();
@@ -1526,7 +1528,11 @@ rbsog_status rbsog_get_state(rbsog_ctx* ctx, double* pos, double* vel, double* f
 
 rbsog_status rbsog_profile_enable(rbsog_ctx* ctx, int enable)
 {
-    return guarded(ctx, [&] { ctx->profiling = enable != 0; });
+    return guarded(ctx, [&] {
+        require(enable >= 0 && enable <= 2, RBSOG_E_ARG, "profile mode is 0, 1 or 2");
+        ctx->profiling = enable != 0;
+        ctx->hot_only = enable == 2;
+    });
 }
 
 rbsog_status rbsog_profile_read(rbsog_ctx* ctx, double* ms, int64_t* launches)

@@ -372,8 +372,10 @@ class Context:
     # -- kernel timing -----------------------------------------------------------
     PHASES = ["build", "ksample", "pair", "rho", "reduce", "kforce", "integrate"]
 
-    def rbsog_profile_enable(self, on: bool = True):
-        self._check(lib().rbsog_profile_enable(self._h, 1 if on else 0), "rbsog_profile_enable")
+    def rbsog_profile_enable(self, on=True):
+        """on: True/1 every phase, 2 only the hot kernels' phases, False/0 off."""
+        mode = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        self._check(lib().rbsog_profile_enable(self._h, mode), "rbsog_profile_enable")
 
     def rbsog_profile_read(self) -> dict:
         ms = np.zeros(len(self.PHASES))
