@@ -323,6 +323,8 @@ def main() -> int:
                          "on the 1e6-ion workload and, with --large-steps, on the 5e6-ion melt")
     ap.add_argument("--thermo-steps", type=int, default=30,
                     help="timed steps of the Nose-Hoover and Langevin legs on the main workload (0: skip)")
+    ap.add_argument("--paper-steps", type=int, default=100,
+                    help="timed steps of the leg at the size and batch sizes of the paper's timing table (0: skip)")
     ap.add_argument("--tuning", default="auto",
                     help="launch shapes of the single-system runs: auto (autotuned) or "
                          "pair_block,pair_ku,rho_mpl,kf_block,kf_aux")
@@ -418,6 +420,24 @@ def main() -> int:
         line["stored"] = stored_leg(cfg, args.steps, args.workload)
         if args.large_steps > 0:
             line["stored"]["large"] = stored_leg(big, args.large_steps, "nacl_5m")
+    if args.paper_steps > 0:
+        # Context, not the metric: molten NaCl at the size and batch sizes of
+        # the paper's timing table (Section 3.2, Table 2: 1.024e6 ions,
+        # P_R = 30, P_F = 100, r_core 5 A, r_shell 10 A), both forms, beside
+        # that table's IRBSOG total of 9.04 ms per step on 1000 CPU cores
+        # (LAMMPS, double precision, 2x Xeon Platinum 8358 per node).
+        pc = W.config("nacl_1024k")
+        npc = len(pc["types"])
+        leg = {"workload": "nacl_1024k", "n_atoms": npc, "p_r": 30, "p_f": 100, "r_core_A": 5.0,
+               "r_shell_A": 10.0, "unit": "atom-steps/s", "steps": args.paper_steps}
+        for form in ("mixed", "fp64"):
+            rp = run_gpu(pc, form, args.paper_steps, args.warmup, "auto")
+            leg[form] = {"value": rp["value"], "ms_per_step": rp["ms_per_step"], "tuning": rp["tuning"],
+                         "phases_ms_per_step": phase_ms(rp)}
+        leg["paper_cpu_context"] = {"ms_per_step": 9.04, "atom_steps_per_s": round(npc / 9.04e-3, 1),
+                                    "cores": 1000, "precision": "fp64",
+                                    "hardware": "2x Intel Xeon Platinum 8358 per node", "source": "Table 2"}
+        line["paper_workload"] = leg
     if args.thermo_steps > 0:
         # the other thermostats on the main workload (mixed form), tau = 10 fs
         line["thermostats"] = {}

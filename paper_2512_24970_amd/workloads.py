@@ -152,6 +152,9 @@ def config(name: str, **over) -> dict:
                  (Li, Na, Cl, Na2) with Na2 a second sodium slot of identical
                  parameters, holding half of the sodium ions
     nacl_5m      molten NaCl 2.5M+2.5M, L = 539 A, 1200 K, P_R 20, P_F 1000
+    nacl_1024k   molten NaCl 512000+512000 at the 512-ion melt's density
+                 (L = 317.5 A), 1200 K, Table 1, r_core 5, r_shell 10, P_R 30,
+                 P_F 100: the size and batch sizes of the paper's timing table
     """
     table1 = species_block(["Na", "Cl"], TABLE1)
     if name == "nacl_512":
@@ -168,6 +171,9 @@ def config(name: str, **over) -> dict:
     elif name == "nacl_5m":
         d = dict(n=5_000_000, box=539.0, T=1200.0, species=table1, cat=[0], frac=[1.0],
                  r_core=5.0, r_shell=10.0, skin=1.0, p_r=20, p_f=1000, seed=BASE_SEED + 5)
+    elif name == "nacl_1024k":
+        d = dict(n=1_024_000, box=25.2 * 2000.0 ** (1 / 3), T=1200.0, species=table1, cat=[0], frac=[1.0],
+                 r_core=5.0, r_shell=10.0, skin=1.0, p_r=30, p_f=100, seed=BASE_SEED + 6)
     elif name == "nacl_small":
         # a few hundred ions in a box that still holds the 11 A list radius
         d = dict(n=216, box=22.5, T=1200.0, species=table1, cat=[0], frac=[1.0],
