@@ -170,6 +170,28 @@ def test_forces_fp64_nacl32768():
     _force_parity(cfg, R.FP64, TOL64, evs=(0,))
 
 
+def test_nacl32768_fp64_thousand_steps():
+    """The 32768-ion FP64 run: forces against the oracle at the first step
+    (above), then 1000 velocity-Verlet steps of 1 fs with a scheduled
+    rebuild every 10 steps (Berendsen at 1200 K with tau = 10 fs against the
+    estimator's heating, which at this size outruns tau = 0.1 ps: T climbs
+    past 1500 K within 200 steps): at least the 100 scheduled builds happen, the
+    forces stay finite and the temperature stays within 15 % of the target
+    (a list overflow would restart the call with longer lists or raise)."""
+    _say("case: nacl_32768 fp64 1000 steps")
+    cfg = W.config("nacl_32768")
+    ctx, _ = gpu_system(cfg, R.FP64, t_target=1200.0, tau_t=0.01)
+    n = len(cfg["types"])
+    for block in range(10):
+        e = ctx.rbsog_step(100)
+        T = 2 * e["kinetic"] / ((3 * n - 3) * W.KB)
+        _say(f"  after {100 * (block + 1)} steps: T {T:.1f} K, builds {e['n_builds']}")
+        assert abs(T - 1200.0) < 180.0
+    assert e["n_builds"] >= 100
+    _, _, f, _ = ctx.rbsog_get_state()
+    assert np.isfinite(f.cpu().numpy()).all()
+
+
 def test_forces_mixed_nacl32768():
     _say("case: forces mixed nacl_32768")
     cfg = W.config("nacl_32768")
