@@ -757,16 +757,28 @@ void autotune(rbsog_ctx* c, int reps)
                     t.kf_aux = aux;
                     cands.push_back(Cand{t, 1e300});
                 }
-    for (int round = 0; round < 3; ++round)
-        for (Cand& cd : cands) {
-            try_shape(cd.t);
+    try {
+        for (int round = 0; round < 3; ++round)
+            for (Cand& cd : cands) {
+                try_shape(cd.t);
+                copy_state(false);
+                // time_ms runs the steps once untimed first (which also
+                // captures the step graph when graphs are on), then once timed
+                cd.ms = std::min(cd.ms, time_ms(c, 1, [&] {
+                    for (int k = 0; k < n_steps; ++k) launch_step(c, false, false);
+                }));
+            }
+    } catch (...) {
+        // put the saved state back before reporting the failure
+        try {
+            try_shape(best);
             copy_state(false);
-            // time_ms runs the steps once untimed first (which also captures
-            // the step graph when graphs are on), then once timed
-            cd.ms = std::min(cd.ms, time_ms(c, 1, [&] {
-                for (int k = 0; k < n_steps; ++k) launch_step(c, false, false);
-            }));
+            (void)hipStreamSynchronize(st);
+        } catch (...) {
         }
+        c->profiling = was_profiling;
+        throw;
+    }
     double t_best = 1e300;
     for (const Cand& cd : cands)
         if (cd.ms < t_best) {
