@@ -314,7 +314,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=20000, help="atoms in the CPU-baseline sample (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--batch", type=int, default=64, help="replicas in the batched-form leg (0: skip)")
-    ap.add_argument("--large-steps", type=int, default=50,
+    ap.add_argument("--large-steps", type=int, default=500,
                     help="timed steps of the 5e6-ion leg (0: skip)")
     ap.add_argument("--shell-stored", type=int, default=0,
                     help="1: the main legs use the memory form of the list (shell batch drawn at the build)")
