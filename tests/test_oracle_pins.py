@@ -501,6 +501,69 @@ def test_energy_estimator_unbiased():
     assert abs(us.mean() - u_exact) < 5 * us.std() / math.sqrt(len(us))
 
 
+def _kspace_moments(cfg, P):
+    """Per-atom mean and single-batch variance of the eq. (29) force
+    estimator, enumerated over every lattice mode that carries probability:
+    a batch of P iid draws from P(k) = k^2 F^(k)/S (eq. 28) averages
+    Y(k) = -(S q_i / V) k Im(e^{-ik.r_i} rho(k)) / |k|^2, so its variance is
+    (sum_k P(k) Y^2 - (sum_k P(k) Y)^2) / P.  rho(k) of eq. (22) is summed
+    here from the positions; the Coulomb constant is left out."""
+    p = O.make_params(cfg["sys"])
+    L = np.array(cfg["sys"]["box"], float)
+    q = np.array(cfg["sys"]["species"]["q"], float)[cfg["types"]]
+    r = np.asarray(cfg["pos"], float)
+    S = O.kspace_S(p)
+    V = L.prod()
+    # the widest Gaussian in k has width 1/s: exp(-s^2 k^2 / 2) < 1e-13 beyond 8/s
+    n = [int(math.ceil(8.0 / p.s * L[a] / (2 * math.pi))) for a in range(3)]
+    m = np.stack(np.meshgrid(*[np.arange(-x, x + 1) for x in n], indexing="ij"), -1).reshape(-1, 3)
+    m = m[np.any(m != 0, 1)]
+    k = 2 * math.pi * m / L
+    k2 = (k * k).sum(1)
+    pk = k2 * np.array([O.far_hat(p, math.sqrt(x)) for x in k2]) / S
+    assert pk.sum() == pytest.approx(1.0, abs=1e-12)
+    mean = np.zeros((len(r), 3))
+    sec = np.zeros((len(r), 3))
+    for c0 in range(0, len(m), 2000):
+        kk, kq, pq = k[c0:c0 + 2000], k2[c0:c0 + 2000], pk[c0:c0 + 2000]
+        ph = r @ kk.T
+        cs, sn = np.cos(ph), np.sin(ph)
+        rc, rs = q @ cs, q @ sn
+        w = (S / V) * q[:, None] * (cs * rs[None] - sn * rc[None]) / kq[None]
+        for a in range(3):
+            Y = -w * kk[:, a][None]
+            mean[:, a] += Y @ pq
+            sec[:, a] += (Y * Y) @ pq
+    return mean, (sec - mean ** 2) / P
+
+
+def test_rbsog_estimator_variance_closed_form_and_growth_with_n():
+    """The second moment of eq. (29): enumerated over all modes, the mean is
+    the exact k-sum of eq. (23) (times the Coulomb constant) and the variance
+    of the oracle's force over 4000 independent batches matches the closed
+    form.  At fixed density and P_F the closed form grows in proportion to N
+    (216 -> 1000 ions: x4.6): |rho(k)|^2 is extensive, so Lemma 2.1's
+    N-independent bound does not hold for the estimator as defined."""
+    cfg = W.config("nacl_small")
+    P = 50
+    mean, var = _kspace_moments(cfg, P)
+    s = O.System(dict(cfg["sys"], p_f=P), cfg["types"], cfg["pos"])
+    sd = O.System(dict(cfg["sys"], p_f=0), cfg["types"], cfg["pos"])
+    exact, _ = sd.forces_kspace(0)
+    kc = O.make_params(cfg["sys"]).coulomb_k
+    assert np.abs(exact - kc * mean).max() < 1e-12 * np.abs(exact).max()
+    tot = 0.0
+    K = 4000
+    for ev in range(1000, 1000 + K):
+        f, _ = s.forces_kspace(ev)
+        tot += ((f - exact) ** 2).sum()
+    assert tot / K == pytest.approx(kc * kc * var.sum(), rel=0.05)
+    big = W.config("nacl_small", n=1000, box=37.5)
+    _, var_big = _kspace_moments(big, P)
+    growth = var_big.sum(1).mean() / var.sum(1).mean()
+    assert 0.75 * 1000 / 216 < growth < 1.25 * 1000 / 216
+
+
 def test_nve_energy_conserved_without_randomness():
     """Velocity Verlet with the deterministic force (P_R, P_F off): the total
     energy stays flat over 100 steps at dt = 1 fs (drift bounded by the
