@@ -828,6 +828,16 @@ void init_devsys(const rbsog_params& p, int n, DevSys& s)
     s.rc2 = p.r_core * p.r_core;
     s.rs2 = p.r_shell * p.r_shell;
     s.half_skin2 = 0.25 * p.skin * p.skin;
+    // A list entry was within r_shell + skin at the build and both atoms
+    // have moved at most skin/2 since, so it is now within M = r_shell +
+    // 2 skin; an atom at least M inside every face sees all its entries
+    // without wrap, and with M < 0.4 L their differences need no minimum image.
+    const double margin = (p.r_shell + 2.0 * p.skin) * (1.0 + 1e-9);
+    for (int a = 0; a < 3; ++a) {
+        const bool room = p.box[a] > 2.5 * margin;
+        s.inner_lo[a] = room ? margin : 1.0e300;
+        s.inner_hi[a] = room ? p.box[a] - margin : -1.0e300;
+    }
     s.dt = p.dt;
     s.coulomb_k = p.coulomb_k;
     const bool thermo = p.t_target > 0.0 && p.tau_t > 0.0;

@@ -1128,6 +1128,21 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, Uc = 0.0, Us = 0.0;
     double Sx = 0.0, Sy = 0.0, Sz = 0.0, Su = 0.0, wgt = 1.0;
     double Wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // this lane's virial (core or shell sum)
+    // A wavefront whose atoms all lie at least the list radius plus a skin
+    // inside every face (inner_lo <= x <= inner_hi) has no list neighbour
+    // across the box edge: each stored difference already is the minimum
+    // image (|d| < 0.4 L, so rint(d / L) = 0) and the wrap is skipped, with
+    // the same bits.
+    bool inner = true;
+    if (i < s.n) {
+        const double4 Pi = s.p[i];
+        inner = Pi.x >= s.inner_lo[0] && Pi.x <= s.inner_hi[0] && Pi.y >= s.inner_lo[1] && Pi.y <= s.inner_hi[1] &&
+                Pi.z >= s.inner_lo[2] && Pi.z <= s.inner_hi[2];
+    }
+    const bool wave_inner = __builtin_amdgcn_ballot_w64(!inner) == 0ull;
+    auto body = [&](auto inner_tag) {
+    constexpr bool INNER = decltype(inner_tag)::value;
+    auto mi = [&](double d, int a) { return INNER ? d : min_image(d, s.L[a], s.invL[a]); };
     if (i < s.n) {
         const double4 Pi = s.p[i];
         const double xi = Pi.x, yi = Pi.y, zi = Pi.z;
@@ -1171,9 +1186,9 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     if (k0 + u >= nc) break;
-                    const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
-                    const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
-                    const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
+                    const double dx = mi(xi - X[u], 0);
+                    const double dy = mi(yi - Y[u], 1);
+                    const double dz = mi(zi - Z[u], 2);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                     if (r2 < (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2)) {
                         double uu = 0.0;
@@ -1208,9 +1223,9 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     if (k0 + u >= cnt) break;
-                    const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
-                    const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
-                    const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
+                    const double dx = mi(xi - X[u], 0);
+                    const double dy = mi(yi - Y[u], 1);
+                    const double dz = mi(zi - Z[u], 2);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                     if (r2 >= (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2) && r2 < s.rs2) {
                         double uu = 0.0;
@@ -1265,9 +1280,9 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     if (k0 + u >= cnt) break;
-                    const double dx = min_image(xi - X[u], s.L[0], s.invL[0]);
-                    const double dy = min_image(yi - Y[u], s.L[1], s.invL[1]);
-                    const double dz = min_image(zi - Z[u], s.L[2], s.invL[2]);
+                    const double dx = mi(xi - X[u], 0);
+                    const double dy = mi(yi - Y[u], 1);
+                    const double dz = mi(zi - Z[u], 2);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                     if (r2 >= (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2) && r2 < s.rs2) {
                         double uu = 0.0;
@@ -1278,6 +1293,11 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
             }
         }
     }
+    };
+    if (wave_inner)
+        body(std::true_type{});
+    else
+        body(std::false_type{});
     if (!shell) {
         xch[0 * A + ta] = Fx;
         xch[1 * A + ta] = Fy;

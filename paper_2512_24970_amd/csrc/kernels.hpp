@@ -41,6 +41,9 @@ struct DevSys {
     double rc2, rs2;                      // r_core^2, r_shell^2
     int species_cut;       // core radii differ between species pairs (PairCoef rc2, rc2_list, lo2_list)
     double half_skin2;
+    // atoms with inner_lo <= x <= inner_hi on every axis have no list
+    // neighbour across the box edge (empty range where the box is short)
+    double inner_lo[3], inner_hi[3];
     double dt, coulomb_k;
     double thermo_c;       // dt / tau_t (0: no thermostat)
     double t_target;
