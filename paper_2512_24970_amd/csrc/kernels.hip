@@ -1731,8 +1731,10 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
             wk[5] -= eg * ky * kz;
         }
     }
+    // fixed trip count (nc is uniform): constant indices keep tot in registers
     double tot[kPairPart + kVirPart];
-    for (int c = 0; c < nc; ++c) tot[c] = block_sum(v[c], red);
+#pragma unroll
+    for (int c = 0; c < kPairPart + kVirPart; ++c) tot[c] = c < nc ? block_sum(v[c], red) : 0.0;
     const double ut = block_sum(ue, red);
     double wt[6];
     if (energy)
@@ -2029,7 +2031,10 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
             const double r = sqrt(-2.0 * log(1.0 - u1));
             const double z0 = r * cs2, z1 = r * sn2;
             const double z2 = sqrt(-2.0 * log(1.0 - u3)) * cs4;
-            const double h = 0.5 * s.dt, c1 = s.lv_c1, c2 = s.lv_c2[ti];
+            // the species constant read through the pointer: a per-lane index
+            // into the local copy of the system record would move that copy
+            // to scratch memory
+            const double h = 0.5 * s.dt, c1 = s.lv_c1, c2 = sys[rb_m.x].lv_c2[ti];
             px = P.x + h * vx;
             py = P.y + h * vy;
             pz = P.z + h * vz;
