@@ -307,8 +307,8 @@ def cpu_baseline(cfg, n_sample: int, ev: int = 1):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="licl_nacl_1m")
     ap.add_argument("--forms", default="mixed,fp64", help="comma list of mixed,fp64; the first is reported")
     ap.add_argument("--cpu-sample", type=int, default=20000, help="atoms in the CPU-baseline sample (0: skip)")
