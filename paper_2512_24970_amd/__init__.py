@@ -6,4 +6,4 @@ in ``include/rbsog.h``; :mod:`paper_2512_24970_amd.rbsog` is its ctypes
 binding.  Importing this package loads nothing; the binding loads the library
 on first use and raises if it is missing.
 """
-__all__ = ["rbsog", "workloads"]
+__all__ = ["rbsog", "workloads", "green_kubo"]
