@@ -45,10 +45,13 @@ typedef enum {
     RBSOG_E_STATE = -2,      /* call out of order (e.g. no system set) */
     RBSOG_E_HIP = -3,        /* a HIP runtime call failed */
     RBSOG_E_OOM = -4,        /* device allocation failed */
-    RBSOG_E_LIST_STALE = -5, /* reserved: lists are rebuilt before they go stale */
+    RBSOG_E_LIST_STALE = -5, /* rbsog_compute_forces after rbsog_set_positions moved an atom more
+                                than skin/2 from its position at the last list build */
     RBSOG_E_NONNEUTRAL = -6, /* total charge is not zero */
     RBSOG_E_BOX = -7,        /* box shorter than 2 (r_shell + skin) along some axis */
-    RBSOG_E_NONFINITE = -8,  /* a non-finite force or position was produced */
+    RBSOG_E_NONFINITE = -8,  /* a non-finite input, or a non-finite force or position produced by a
+                                step or an evaluation that synchronises; the context then refuses
+                                every call that would use its state until a system is set again */
     RBSOG_E_CAPACITY = -9    /* a per-cell or per-atom capacity was exceeded */
 } rbsog_status;
 
@@ -226,12 +229,25 @@ rbsog_status rbsog_select_system(rbsog_ctx* ctx, int32_t r);
  * positions (Section 2.2 core-shell lists). */
 rbsog_status rbsog_build_lists(rbsog_ctx* ctx);
 
+/* Replace the positions of every atom (pos[N][3], user order; device pointer
+ * if ptrs_on_device != 0, else host), for a caller that moves the atoms with
+ * its own integrator and asks for forces (Section 2.2 evaluates the force at
+ * given positions).  Positions are wrapped into the box; velocities and lists
+ * are kept.  If an atom is now more than skin/2 from its position at the last
+ * list build, the lists no longer hold every pair within r_shell (eqs.
+ * 24-25): rbsog_compute_forces then returns RBSOG_E_LIST_STALE until
+ * rbsog_build_lists, and rbsog_step builds first (counted in n_builds).
+ * Non-finite input: RBSOG_E_NONFINITE, nothing changed.  Synchronises. */
+rbsog_status rbsog_set_positions(rbsog_ctx* ctx, const double* pos, int ptrs_on_device);
+
 /* One IRBSOG force evaluation at the current positions with Philox counter
  * `eval` (shell batches of eq. 25, modes of eq. 28): F = F_core + F*_shell -
  * F_corr + F*_F (eqs. 24-27, 29), for every system held.  Writes the force
  * in user order to the device array force_out[N][3] if non-NULL.  Energies
  * are returned in e_out[n_sys] (one record per system) if non-NULL (the call
- * then synchronises).  Does not move atoms. */
+ * then synchronises and returns RBSOG_E_NONFINITE if a force is not
+ * finite).  Does not move atoms.  RBSOG_E_LIST_STALE after
+ * rbsog_set_positions moved an atom more than skin/2 since the last build. */
 rbsog_status rbsog_compute_forces(rbsog_ctx* ctx, uint64_t eval, double* force_out, rbsog_energy* e_out);
 
 /* Force parts of the last evaluation in user order into device arrays
@@ -244,8 +260,17 @@ rbsog_status rbsog_get_force_parts(rbsog_ctx* ctx, double* f_short, double* f_ks
  * skin/2 since the last build (decided on the device), force with eval =
  * step number, kick.  Each system of a batch decides its own rebuilds.
  * e_last[n_sys] (may be NULL) receives the energies of the last step; the
- * call synchronises at the end. */
+ * call synchronises at the end and returns RBSOG_E_NONFINITE if a position
+ * or force of any step was not finite (such a system is not rebuilt in the
+ * meantime). */
 rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last);
+
+/* The batched form's step call (Section 2.2 applied to every system held):
+ * rbsog_step without energies, each step replayed from a captured HIP graph
+ * (captured on first use per variant, as with rbsog_use_graphs) whatever the
+ * rbsog_use_graphs setting; the same bits as rbsog_step.  Needs a context
+ * created on a non-default stream (else RBSOG_E_STATE).  Synchronises. */
+rbsog_status rbsog_step_batch(rbsog_ctx* ctx, int32_t n_steps);
 
 /* Current positions, velocities, forces (user order, [N][3]) and the eval
  * index of the last force evaluation.  Pointers are device pointers if
@@ -352,6 +377,15 @@ rbsog_status rbsog_get_lists_of(rbsog_ctx* ctx, int32_t i, int32_t* core, int32_
  * n_ranks[N] gets min(P_R, n_cand).  Not available with
  * RBSOG_FLAG_SHELL_STORED (RBSOG_E_STATE). */
 rbsog_status rbsog_get_shell_ranks(rbsog_ctx* ctx, uint64_t eval, int32_t* n_ranks, int32_t* ranks);
+/* Shell samples of eq. (25) in use for the selected system: with a batch
+ * drawn every evaluation, the batch of the last force evaluation (its eval
+ * index); with RBSOG_FLAG_SHELL_STORED, the batch drawn at the last list
+ * build.  idx[N][P_R] (host, may be NULL) receives per atom the neighbour ids
+ * of the batch sorted ascending, -1 past min(P_R, n_cand); n_cand[N] (host,
+ * may be NULL) the candidate count N_shell that weights it (N_shell/P_R when
+ * N_shell > P_R).  Needs P_R >= 1 and, without a stored batch, a force
+ * evaluation since the system was set (else RBSOG_E_STATE). */
+rbsog_status rbsog_get_shell_samples(rbsog_ctx* ctx, int32_t* n_cand, int32_t* idx);
 /* With RBSOG_FLAG_SHELL_STORED (else RBSOG_E_STATE): the batch drawn at the
  * last list build as atom ids in ascending rank order, ids[N][P_R] (-1 past
  * min(P_R, n_cand)), and the candidate count N_shell of each atom at that

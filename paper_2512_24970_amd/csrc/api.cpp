@@ -87,6 +87,12 @@ struct rbsog_ctx {
     int sel = 0;                     // system the parity exports refer to
     uint64_t eval = 0;               // eval index of the last force evaluation
     bool forces_valid = false;
+    // positions set by the caller moved an atom more than skin/2 from its
+    // position at the last build (compute_forces refuses, step rebuilds)
+    bool stale = false;
+    // a step or evaluation produced a non-finite position or force: every
+    // call that would use the state refuses until a system is set again
+    bool nonfinite = false;
 
     std::vector<DevSys> hs;          // host images of the device system records
     std::vector<KDev> hk;
@@ -626,8 +632,27 @@ void fill_energy(rbsog_ctx* c, const std::vector<DeviceScalars>& hv, rbsog_energ
     }
 }
 
-void check_flags(const std::vector<DeviceScalars>& h)
+// A non-finite position or force seen by the kernels (checked before any
+// capacity overflow, which NaN positions can cause).
+void check_finite(rbsog_ctx* c, const std::vector<DeviceScalars>& h)
 {
+    for (size_t r = 0; r < h.size(); ++r)
+        if (h[r].nonfinite) {
+            c->nonfinite = true;
+            throw Error(RBSOG_E_NONFINITE, "system " + std::to_string(r) +
+                                               " produced a non-finite position or force; set the system again");
+        }
+}
+
+void need_finite(const rbsog_ctx* c)
+{
+    require(!c->nonfinite, RBSOG_E_NONFINITE,
+            "the state holds non-finite positions or forces from an earlier call; set the system again");
+}
+
+void check_flags(rbsog_ctx* c, const std::vector<DeviceScalars>& h)
+{
+    check_finite(c, h);
     if (any_overflow(h)) throw Error(RBSOG_E_CAPACITY, "list capacity exceeded during the step loop");
 }
 
@@ -1266,6 +1291,8 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->have_system = true;
     c->eval = 0;
     c->forces_valid = false;
+    c->stale = false;
+    c->nonfinite = false;
     build_checked(c);
     HIP_OK(hipStreamSynchronize(c->stream));
 }
@@ -1395,6 +1422,8 @@ rbsog_status rbsog_autotune(rbsog_ctx* ctx, int32_t reps, rbsog_tuning* chosen)
     return guarded(ctx, [&] {
         need_system(ctx);
         require(reps >= 1, RBSOG_E_ARG, "reps < 1");
+        need_finite(ctx);
+        require(!ctx->stale, RBSOG_E_LIST_STALE, "lists are stale; call rbsog_build_lists before tuning");
         autotune(ctx, reps);
         if (chosen) {
             const Tuning& t = ctx->plan.tune;
@@ -1443,7 +1472,35 @@ rbsog_status rbsog_build_lists(rbsog_ctx* ctx)
 {
     return guarded(ctx, [&] {
         need_system(ctx);
+        need_finite(ctx);
         build_checked(ctx);
+        ctx->stale = false;
+    });
+}
+
+rbsog_status rbsog_set_positions(rbsog_ctx* ctx, const double* pos, int ptrs_on_device)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        need_finite(ctx);
+        require(pos != nullptr || ctx->n_user == 0, RBSOG_E_ARG, "pos is NULL");
+        const int n = ctx->n_user;
+        if (n == 0) return;
+        std::vector<double> hp(3 * (size_t)n);
+        if (ptrs_on_device)
+            HIP_OK(hipMemcpy(hp.data(), pos, sizeof(double) * hp.size(), hipMemcpyDeviceToHost));
+        else
+            std::memcpy(hp.data(), pos, sizeof(double) * hp.size());
+        for (double v : hp) require(std::isfinite(v), RBSOG_E_NONFINITE, "non-finite position");
+        ctx->export_tmp.alloc(sizeof(double) * hp.size());
+        HIP_OK(hipMemcpyAsync(ctx->export_tmp.p, hp.data(), sizeof(double) * hp.size(), hipMemcpyHostToDevice,
+                              ctx->stream));
+        launch_set_positions(ctx->plan, ctx->export_tmp.as<double>(), ctx->stream);
+        HIP_OK(hipGetLastError());
+        bool stale = false;
+        for (const auto& h : read_scalars(ctx)) stale = stale || h.stale != 0;
+        ctx->stale = stale;
+        ctx->forces_valid = false;
     });
 }
 
@@ -1451,6 +1508,9 @@ rbsog_status rbsog_compute_forces(rbsog_ctx* ctx, uint64_t eval, double* force_o
 {
     return guarded(ctx, [&] {
         need_system(ctx);
+        need_finite(ctx);
+        require(!ctx->stale, RBSOG_E_LIST_STALE,
+                "an atom moved more than skin/2 since the last list build; call rbsog_build_lists");
         launch_set_eval(ctx->plan, eval, ctx->stream);
         enqueue_forces(ctx, e_out != nullptr, false);
         ctx->eval = eval;
@@ -1458,8 +1518,8 @@ rbsog_status rbsog_compute_forces(rbsog_ctx* ctx, uint64_t eval, double* force_o
         if (force_out) launch_to_user3(ctx->plan, Field::force, force_out, ctx->stream);
         if (e_out) {
             const auto h = read_scalars(ctx);
+            check_flags(ctx, h);
             fill_energy(ctx, h, e_out);
-            check_flags(h);
         }
     });
 }
@@ -1474,12 +1534,23 @@ rbsog_status rbsog_get_force_parts(rbsog_ctx* ctx, double* f_short, double* f_ks
     });
 }
 
-rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
+}  // extern "C"
+
+namespace {
+
+void step_impl(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
 {
-    return guarded(ctx, [&] {
+    {
         need_system(ctx);
+        need_finite(ctx);
         require(n_steps >= 0, RBSOG_E_ARG, "n_steps < 0");
         if (n_steps == 0) return;
+        if (ctx->stale) {
+            // positions set by the caller outran the lists: an extra build
+            build_checked(ctx);
+            ctx->stale = false;
+            ctx->forces_valid = false;
+        }
         if (!ctx->forces_valid) {
             // forces at the current positions start the integrator
             launch_set_eval(ctx->plan, ctx->eval, ctx->stream);
@@ -1504,6 +1575,7 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
                 launch_step(ctx, scheduled, energy);
             }
             const auto h = read_scalars(ctx);
+            check_finite(ctx, h);
             const int o = any_overflow(h);
             if (o == 0) {
                 ctx->eval += (uint64_t)n_steps;
@@ -1520,6 +1592,31 @@ rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
                 launch_kinetic_finalize(ctx->plan, false, false, ctx->stream);
             }
         }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+rbsog_status rbsog_step(rbsog_ctx* ctx, int32_t n_steps, rbsog_energy* e_last)
+{
+    return guarded(ctx, [&] { step_impl(ctx, n_steps, e_last); });
+}
+
+rbsog_status rbsog_step_batch(rbsog_ctx* ctx, int32_t n_steps)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        require(ctx->stream != nullptr, RBSOG_E_STATE,
+                "rbsog_step_batch replays captured step graphs: create the context on a non-default stream");
+        struct Restore {
+            rbsog_ctx* c;
+            bool was;
+            ~Restore() { c->use_graph = was; }
+        } restore{ctx, ctx->use_graph};
+        ctx->use_graph = true;
+        step_impl(ctx, n_steps, nullptr);
     });
 }
 
@@ -1745,6 +1842,42 @@ rbsog_status rbsog_get_shell_batch(rbsog_ctx* ctx, int32_t* n_cand, int32_t* ids
     });
 }
 
+rbsog_status rbsog_get_shell_samples(rbsog_ctx* ctx, int32_t* n_cand, int32_t* idx)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        const DevSys& s = ctx->hs[ctx->sel];
+        require(s.p_r >= 1, RBSOG_E_STATE, "p_r <= 0: every candidate is taken, there is no sample to export");
+        require(s.shell_stored || ctx->forces_valid, RBSOG_E_STATE, "no force evaluation yet");
+        const Plan P1 = one(ctx, ctx->sel);
+        const int P = s.p_r;
+        DBuf out;
+        out.alloc(sizeof(int32_t) * ((size_t)s.n * P + s.n + 1));
+        int32_t* d = out.as<int32_t>();
+        int32_t* cnt = d + (size_t)s.n * P;
+        if (s.shell_stored)
+            launch_batch_ids(P1, d, cnt, ctx->stream);
+        else
+            launch_shell_samples(P1, d, cnt, ctx->stream);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        std::vector<int32_t> h((size_t)s.n * P), hc(s.n);
+        if (s.n > 0) {
+            HIP_OK(hipMemcpy(h.data(), d, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(hc.data(), cnt, sizeof(int32_t) * hc.size(), hipMemcpyDeviceToHost));
+        }
+        for (int u = 0; u < s.n; ++u) {
+            if (n_cand) n_cand[u] = hc[u];
+            if (idx) {
+                int32_t* row = h.data() + (size_t)u * P;
+                const int k = std::min(hc[u], P);
+                std::sort(row, row + k);
+                std::copy(row, row + P, idx + (size_t)u * P);
+            }
+        }
+    });
+}
+
 rbsog_status rbsog_set_list_capacity(rbsog_ctx* ctx, int32_t cap_core, int32_t cap_cand, int32_t* got_core,
                                      int32_t* got_cand)
 {
@@ -1752,9 +1885,11 @@ rbsog_status rbsog_set_list_capacity(rbsog_ctx* ctx, int32_t cap_core, int32_t c
         need_system(ctx);
         require(cap_core >= 8 && cap_core <= 4096 && cap_cand >= 8 && cap_cand <= 4096, RBSOG_E_ARG,
                 "capacities out of range (8..4096)");
+        need_finite(ctx);
         plan_lists(ctx, cap_core, cap_cand);
         plan_launches(ctx);
         build_checked(ctx);
+        ctx->stale = false;
         ctx->forces_valid = false;
         if (got_core) *got_core = ctx->plan.cap_core;
         if (got_cand) *got_cand = ctx->plan.cap_cand;

@@ -137,8 +137,8 @@ struct DeviceScalars {
     double max_disp2;     // largest squared displacement since the build
     int32_t overflow;     // list or cell capacity exceeded
     int32_t rebuild;      // the lists are rebuilt in this step
-    int32_t nonfinite;
-    int32_t pad;
+    int32_t nonfinite;    // a non-finite position or force was produced
+    int32_t stale;        // positions set by the caller moved an atom more than skin/2 from its build position
     int64_t n_builds;     // list builds since the system was set
     int32_t max_core;     // largest core / candidate list seen (true sizes)
     int32_t max_cand;

@@ -22,9 +22,11 @@ constexpr int kBlock = 256;
 constexpr int kCellCap = 2048;  // atoms per cell the in-cell sort can hold
 
 // Build kernels take `gate`: when set they run only if the rebuild flag is up
-// (set by the drift kernel), so a step can enqueue them unconditionally.
+// (set by the drift kernel), so a step can enqueue them unconditionally.  A
+// system that produced a non-finite value is not rebuilt (its positions may
+// be NaN; the host reports the error at the end of the call).
 #define RB_GATE                                        \
-    if (gate && s.sc->rebuild == 0) return;
+    if (gate && (s.sc->rebuild == 0 || s.sc->nonfinite)) return;
 
 // Pointers read from device memory are generic (flat) to the compiler; every
 // buffer here is global memory, and saying so (through an integer, which the
@@ -142,6 +144,15 @@ __device__ inline int fine_cell(const DevSys& s, const double4& P)
     return (fz * s.nf[1] + fy) * s.nf[0] + fx;
 }
 
+// One flag write per wavefront holding a non-finite value (every lane of the
+// wavefront calls it).
+__device__ inline void flag_nonfinite(bool bad, DeviceScalars* sc)
+{
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&sc->nonfinite, 1);
+}
+
+__device__ inline bool finite3(double x, double y, double z) { return isfinite(x) && isfinite(y) && isfinite(z); }
+
 // Workgroups are dealt to the 8 XCDs in turn (block b on XCD b mod 8), each
 // XCD with its own L2.  Renumbering so that XCD x gets a contiguous range of
 // logical blocks keeps spatially neighbouring atoms (cell order) on one L2.
@@ -205,7 +216,7 @@ __global__ void k_build_done(const DevSys* __restrict__ sys, int R, int gate)
 {
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
         DeviceScalars* sc = glob(sys[r].sc);
-        if (gate && sc->rebuild == 0) continue;
+        if (gate && (sc->rebuild == 0 || sc->nonfinite)) continue;
         sc->rebuild = 0;
         sc->max_disp2 = 0.0;
         if (sc->overflow == 0) sc->n_builds += 1;
@@ -1359,6 +1370,39 @@ __global__ __launch_bounds__(kBlock) void k_shell_ranks(RB_ARGS, int32_t* out, i
     n_out[uid] = P;
 }
 
+// Export of the shell batch of the current evaluation as atom ids, in
+// ascending rank order: the pair kernel's selection mapped through the
+// candidate row (P_R >= 1).
+__global__ __launch_bounds__(kBlock) void k_shell_samples(RB_ARGS, int32_t* out, int32_t* n_out)
+{
+    RB_SYS(blockIdx.x)
+    extern __shared__ uint32_t mask_sm[];
+    const int i = lb * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const int n = min(s.cand_cnt[i], s.cap_cand - 1);
+    const int P = s.p_r;
+    const int uid = s.id[i];
+    const int32_t* crow = s.cand_idx + (size_t)i * s.cap_cand;
+    int32_t* o = out + (size_t)uid * P;
+    n_out[uid] = n;
+    if (n <= P) {
+        for (int k = 0; k < P; ++k) o[k] = k < n ? s.id[crow[k]] : -1;
+        return;
+    }
+    FloydMask fm{mask_sm + threadIdx.x, (int)blockDim.x};
+    PhiloxStream st(s.seed, (uint32_t)uid, (uint32_t)s.sc->eval, kTagShell, s.replica);
+    fm.clear(n);
+    for (int k = 0; k < P; ++k) fm.step(st, n - P + k);
+    int w = 0;
+    uint32_t m = fm.m[0];
+    for (int k = 0; k < P; ++k) {
+        while (m == 0u) m = fm.m[(++w) * fm.stride];
+        const int e = w * 32 + __builtin_ctz(m);
+        m &= m - 1u;
+        o[k] = s.id[crow[e]];
+    }
+}
+
 // Memory form of the list: the shell batch of each atom of build chunk
 // `chunk`, drawn once at the build (Floyd's selection as in the pair kernel,
 // on the stream (id, build number, kTagShellBuild)) from its candidate row,
@@ -1783,6 +1827,7 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
     }
     const int i = lb * blockDim.x + threadIdx.x;
     double ke = 0.0;
+    bool bad = false;
     double fl[kFluxPart];
     if (FLUX)
         for (int c = 0; c < kFluxPart; ++c) fl[c] = 0.0;
@@ -1848,6 +1893,7 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
             s.fx[i] = fx;
             s.fy[i] = fy;
             s.fz[i] = fz;
+            bad = !finite3(fx, fy, fz);
             double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
             if (KICK) {
                 const double a = 0.5 * s.dt * s.spc->inv_mass_acc[ti];
@@ -1887,6 +1933,7 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
             }
         }
     }
+    if (FUSED) flag_nonfinite(bad, s.sc);
     if (FUSED && ENERGY) wave_partial(ke, i, s.n, s.kin_part, 1, 0);
     if (FLUX)
         for (int c = 0; c < kFluxPart; ++c) wave_partial(fl[c], i, s.n, s.flux_part, kFluxPart, c);
@@ -1900,6 +1947,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(RB_ARGS)
     RB_SYS(blockIdx.x)
     const int i = lb * blockDim.x + threadIdx.x;
     double ke = 0.0;
+    bool bad = false;
     if (i < s.n) {
         const int ti = s.type[i];
         const DeviceScalars* scal = s.sc;
@@ -1909,6 +1957,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(RB_ARGS)
         s.fx[i] = fx;
         s.fy[i] = fy;
         s.fz[i] = fz;
+        bad = !finite3(fx, fy, fz);
         if (KICK) {
             const double a = 0.5 * s.dt * s.spc->inv_mass_acc[ti];
             const double vx = s.vx[i] + a * fx, vy = s.vy[i] + a * fy, vz = s.vz[i] + a * fz;
@@ -1921,6 +1970,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(RB_ARGS)
             ke = 0.5 * s.spc->mass[ti] * (vx * vx + vy * vy + vz * vz);
         }
     }
+    flag_nonfinite(bad, s.sc);
     if (ENERGY) wave_partial(ke, i, s.n, s.kin_part, 1, 0);
 }
 
@@ -2008,6 +2058,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
     __shared__ double red[4];
     const int i = lb * blockDim.x + threadIdx.x;
     double d2 = 0.0;
+    bool bad = false;
     const bool langevin = LANGEVIN && s.thermo_c > 0.0 && s.thermostat == kThermoLangevin;
     const double lam = (s.thermo_c > 0.0 && !langevin) ? s.sc->vscale : 1.0;
     if (i < s.n) {
@@ -2056,6 +2107,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
         const double y = wrap_coord(py, s.L[1], s.invL[1]);
         const double z = wrap_coord(pz, s.L[2], s.invL[2]);
         s.p[i] = make_double4(x, y, z, P.w);
+        bad = !finite3(x, y, z);
         const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
         const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
         const double dz = min_image(z - s.zr[i], s.L[2], s.invL[2]);
@@ -2065,6 +2117,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
     const uint64_t moved = __ballot(!(d2 <= s.half_skin2));
     if (moved && (threadIdx.x & 63) == 0) atomicOr(&s.sc->rebuild, 1);
     if (scheduled && lb == 0 && threadIdx.x == 0) atomicOr(&s.sc->rebuild, 1);
+    flag_nonfinite(bad, s.sc);
     // block maximum, then a device-wide max on the bit pattern (d2 >= 0)
     double m = d2;
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
@@ -2228,6 +2281,40 @@ __global__ void k_from_user(RB_ARGS, const int32_t* type, const double* pos, con
     s.type[i] = type[u];
     s.id[i] = i;
     s.inv[i] = i;
+}
+
+// New positions from the caller (user order), wrapped into the box; the
+// lists stay.  Raises the system's stale flag when an atom now sits more
+// than skin/2 from where it was at the last build, and keeps the largest
+// displacement.
+__global__ void k_set_pos(RB_ARGS, const double* pos)
+{
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
+    double d2 = 0.0;
+    if (i < s.n) {
+        const size_t u = (size_t)s.user_off + s.id[i];
+        const double x = wrap_coord(pos[3 * u], s.L[0], s.invL[0]);
+        const double y = wrap_coord(pos[3 * u + 1], s.L[1], s.invL[1]);
+        const double z = wrap_coord(pos[3 * u + 2], s.L[2], s.invL[2]);
+        s.p[i] = make_double4(x, y, z, s.p[i].w);
+        const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
+        const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
+        const double dz = min_image(z - s.zr[i], s.L[2], s.invL[2]);
+        d2 = (dx * dx + dy * dy) + dz * dz;
+    }
+    if (__ballot(d2 > s.half_skin2) && (threadIdx.x & 63) == 0) atomicOr(&s.sc->stale, 1);
+    double m = d2;
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&s.sc->max_disp2, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void k_clear_stale(DeviceScalars* sc, int R)
+{
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        sc[r].stale = 0;
+        sc[r].max_disp2 = 0.0;
+    }
 }
 
 inline int blocks_for(int n, int b) { return (n + b - 1) / b; }
@@ -2489,6 +2576,18 @@ void launch_shell_ranks(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t
 {
     const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * kBlock;
     if (P.atoms.blocks > 0) k_shell_ranks<<<P.atoms.blocks, kBlock, sm, st>>>(RB_MAP(atoms), out, n_out);
+}
+
+void launch_shell_samples(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st)
+{
+    const size_t sm = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * kBlock;
+    if (P.atoms.blocks > 0) k_shell_samples<<<P.atoms.blocks, kBlock, sm, st>>>(RB_MAP(atoms), out, n_out);
+}
+
+void launch_set_positions(const Plan& P, const double* pos, hipStream_t st)
+{
+    k_clear_stale<<<1, 64, 0, st>>>(P.sc, P.R);
+    if (P.atoms.blocks > 0) k_set_pos<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), pos);
 }
 
 void launch_batch_ids(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st)

@@ -249,6 +249,14 @@ void launch_shell_ranks(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t
 // stored shell batch of one system (P.R == 1) as atom ids into out[n][P_R]
 // (-1 past the batch) and candidate counts into n_out[n], by atom id
 void launch_batch_ids(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st);
+// shell batch of the current evaluation of one system (P.R == 1, P_R >= 1)
+// as atom ids in ascending rank order into out[n][P_R], candidate counts into
+// n_out[n], by atom id
+void launch_shell_samples(const Plan& P, int32_t* out, int32_t* n_out, hipStream_t st);
+// positions from the caller's [N][3] array (user order, device); raises the
+// stale flag of a system with an atom more than skin/2 from its build
+// position and records the largest displacement
+void launch_set_positions(const Plan& P, const double* pos, hipStream_t st);
 void launch_from_user(const Plan& P, const int32_t* type, const double* pos, const double* vel, hipStream_t st);
 
 }  // namespace rbsog

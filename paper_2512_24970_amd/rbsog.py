@@ -94,6 +94,9 @@ ABI = {
     "rbsog_get_tuning": (C.c_int, [C.c_void_p, C.c_void_p]),
     "rbsog_use_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "rbsog_build_lists": (C.c_int, [C.c_void_p]),
+    "rbsog_set_positions": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "rbsog_step_batch": (C.c_int, [C.c_void_p, C.c_int32]),
+    "rbsog_get_shell_samples": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbsog_compute_forces": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(Energy)]),
     "rbsog_get_force_parts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbsog_step": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Energy)]),
@@ -336,6 +339,12 @@ class Context:
     def rbsog_build_lists(self):
         self._check(lib().rbsog_build_lists(self._h), "rbsog_build_lists")
 
+    def rbsog_set_positions(self, pos):
+        """pos: [N, 3] float64 torch tensor on this device (user order)."""
+        t = self._torch
+        pos = t.as_tensor(pos, dtype=t.float64, device=self.torch_device).contiguous()
+        self._check(lib().rbsog_set_positions(self._h, C.c_void_p(pos.data_ptr()), 1), "rbsog_set_positions")
+
     # -- evaluation ------------------------------------------------------------
     def rbsog_compute_forces(self, ev: int, want_energy: bool = True):
         t = self._torch
@@ -359,6 +368,9 @@ class Context:
         e = (Energy * max(self.R, 1))()
         self._check(lib().rbsog_step(self._h, n_steps, e if want_energy else None), "rbsog_step")
         return self._energies(e) if want_energy else None
+
+    def rbsog_step_batch(self, n_steps: int):
+        self._check(lib().rbsog_step_batch(self._h, n_steps), "rbsog_step_batch")
 
     def rbsog_get_state(self):
         t = self._torch
@@ -414,6 +426,14 @@ class Context:
         nk = np.zeros(self._sel_n, np.int32)
         ids = np.zeros((self._sel_n, P), np.int32)
         self._check(lib().rbsog_get_shell_batch(self._h, _np_ptr(nk), _np_ptr(ids)), "rbsog_get_shell_batch")
+        return nk, ids
+
+    def rbsog_get_shell_samples(self):
+        """(n_cand[N], ids[N, P_R]): the shell batch in use, neighbour ids sorted, -1 padded."""
+        P = max(self.params_list[self.sel].p_r, 1)
+        nk = np.zeros(self._sel_n, np.int32)
+        ids = np.zeros((self._sel_n, P), np.int32)
+        self._check(lib().rbsog_get_shell_samples(self._h, _np_ptr(nk), _np_ptr(ids)), "rbsog_get_shell_samples")
         return nk, ids
 
     def rbsog_rdf_counts(self, r_max: float, n_bins: int) -> np.ndarray:

@@ -159,8 +159,51 @@ def test_sog_c1_continuity_at_cutoff():
     slope = ((1 / (rc + h) - O.far(p, rc + h)) - (1 / (rc - h) - O.far(p, rc - h))) / (2 * h)
     assert abs(val) < 1e-14
     assert abs(slope) < 1e-9
-    # and the smallest root: the residual has no sign change below x_c
-    assert p.x_c == pytest.approx(3.8316608908694345, rel=1e-9)
+
+
+def _slope_residual(b, M, x):
+    """C1 slope residual F'(x) + 1/x^2 of the truncated series (eqs. 8-10) in
+    units s = 1, written independently of the oracle: sigma_m = b^m, the BSA
+    weights of eq. (7) for m >= 1, w_0 chosen at each x so that the value
+    condition x F(x) = 1 holds, then F' summed term by term over m = 0..M
+    (w_0 is not eliminated algebraically)."""
+    x = np.asarray(x, dtype=np.float64)[:, None]
+    m = np.arange(1, M + 1, dtype=np.float64)[None, :]
+    sig2 = b ** (2.0 * m)
+    wm = math.sqrt(2.0) * math.log(b) / (math.sqrt(math.pi) * b ** m)
+    gm = np.exp(-x * x / (2.0 * sig2))
+    w0 = (1.0 / x[:, 0] - (wm * gm).sum(1)) * np.exp(x[:, 0] ** 2 / 2.0)
+    dF = -x[:, 0] * w0 * np.exp(-x[:, 0] ** 2 / 2.0) - (wm * x / sig2 * gm).sum(1)
+    return dF + 1.0 / x[:, 0] ** 2
+
+
+@pytest.mark.parametrize("eps,r_shell", [(1e-5, 10.0), (1e-5, 11.0), (1e-7, 10.0)])
+def test_sog_cutoff_is_the_smallest_root(eps, r_shell):
+    """Section 2.1 takes r_c at the smallest root of the C1 conditions.  The
+    residual, computed here without the oracle's formula, keeps one sign on
+    a 1e-4 grid from x = 0.05 up to x_c, changes sign across x_c, has its
+    root (found by Brent's method) at the oracle's x_c, and any next root
+    lies well above it.  A solver that skipped the first root, or scanned
+    from too large an x, fails here."""
+    from scipy.optimize import brentq
+    p, _ = _p(sog_eps=eps, r_shell=r_shell, r_core=r_shell / 2)
+    b, M, xc = p.b, p.M, p.x_c
+    assert p.s == pytest.approx(r_shell / xc, rel=1e-15)
+    grid = np.arange(0.05, xc - 1e-6, 1e-4)
+    g = _slope_residual(b, M, grid)
+    assert np.all(g > 0.0), grid[np.argmax(g <= 0.0)]
+    d = 1e-6 * xc
+    lo, hi = _slope_residual(b, M, [xc - d, xc + d])
+    assert lo > 0.0 > hi
+    # the residual is flat at the root (its slope is of the order of the
+    # eq. (5) bound), so two roundings of it place the root a few 1e-8 apart
+    root = brentq(lambda t: _slope_residual(b, M, [t])[0], xc - 1e-3, xc + 1e-3, xtol=1e-15, rtol=1e-15)
+    assert root == pytest.approx(xc, rel=1e-6)
+    # any further root is well separated from the first
+    after = np.arange(xc + 1e-3, xc + 4.0, 1e-4)
+    ga = _slope_residual(b, M, after)
+    flips = np.nonzero(np.sign(ga[1:]) != np.sign(ga[:-1]))[0]
+    assert len(flips) == 0 or after[flips[0]] > xc + 0.1
 
 
 def test_far_field_accuracy_beyond_cutoff():
