@@ -14,10 +14,17 @@ replayed from a captured HIP graph; its aggregate atom-steps/s is reported
 against the same replicas stepped one after another, each in its own context
 with plain launches.
 
-Prints one JSON line.  The roofline object describes the dominant kernel of
-the reported form, timed with HIP events on the library's stream during the
-timed steps; its algorithmic flop count per (atom, mode) pair is fixed below.
-The CPU baseline is the FP64 oracle on a bounded sample of the same workload.
+Prints one JSON line.  Each leg's rate is the median of `--repeats` timed
+runs of `--steps` steps, and each leg states its FP32-mixed force error
+against the FP64 path at its starting positions.  The roofline object
+describes the dominant kernel of the reported form, timed with HIP events on
+the library's stream during the timed steps, against per-form work models
+(FP64 and FP32 flops separately, FP32 transcendentals, algorithmic HBM
+bytes) stated below; where the committed counter summaries in profiles/ were
+taken on the current kernel source, the measured VALU instruction mix and
+HBM bytes stand beside the models.  The CPU baseline is the FP64 oracle on
+a bounded sample of the same workload, plus direct timings of the 512- and
+32768-ion melts at one thread and at all host threads.
 """
 from __future__ import annotations
 
@@ -37,17 +44,37 @@ sys.path.insert(0, HERE)
 # rate holds for FP64 and for non-packed FP32 (packed FP32 is not used).
 PEAK_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# VALU issue: one wave64 instruction per SIMD every 4 cycles, i.e. 256 x 4 x
+# 16 lane-instructions per cycle at 2.4 GHz; an FP32 transcendental
+# (v_exp, v_rsq, v_sin, v_cos) takes four of those slots.
+PEAK_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
+TRANS_SLOTS = 4
 
-# Algorithmic flops per (atom, mode) pair, FMA = 2, as the kernels compute
-# them (see the kernel comments):
-#   FP64 k-space force: phase 5, table sincos 18, Im(e^{-i theta} rho) 3,
-#                       accumulation 6                                  = 32
-#   FP64 rho:           phase 5, sincos 18, accumulation 4              = 27
-#   mixed k-space force: phase 5, turn reduction 2, sin + cos 2, 3, 6   = 18
-#   mixed rho:           phase 5, reduction 2, sin + cos 2, accumulation 4 = 13
-FLOPS_PER_PAIR = {
-    ("fp64", "kforce"): 32, ("fp64", "rho"): 27,
-    ("mixed", "kforce"): 18, ("mixed", "rho"): 13,
+# Work models, FMA = 2 flops, a transcendental = 1 flop (and 4 issue slots).
+# k-space kernels, per (atom, mode):
+#   FP64 rho:     phase 5 (mul + 2 FMA), table sincos 18, accumulation 4       FP64 27
+#   FP64 force:   phase 5, sincos 18, Im(e^{-i theta} rho) coef 3, sum 6       FP64 32
+#   mixed rho:    phase 5, accumulation of four atoms' FP32 sums 0.5           FP64 5.5
+#                 q cos, q sin (2 FMA), hardware sin + cos (2 transcendentals)  FP32 6
+#   mixed force:  phase 5, sum of w m_a (3 FMA)                                FP64 11
+#                 c A - s B (FMA + mul), sin + cos                             FP32 5
+# pair kernel, per distance test (every core-list entry and every batch
+# entry): three differences and r^2 (8), the minimum image (9) in the
+# wavefronts that touch the box edge (a quarter at the 10^6-ion size), so
+# 10.25 FP64; per evaluated pair: FP64 form 181 for the pair function (two
+# software exponentials, the squaring chain of the narrow Gaussians, the
+# 13-term polynomial of the wide ones, BMH terms) plus 6 to accumulate F;
+# mixed form 40 FP32 for the table-driven pair function as compiled (rsqrt
+# and two exponentials among them: 3 transcendentals) plus 6 FP64 to
+# accumulate.  These per-pair constants were checked against the counted
+# SQ_INSTS_VALU_FLOPS_FP64/FP32 of the kernels (within 15 %).
+KSPACE_MODEL = {
+    ("fp64", "rho"): (27.0, 0.0, 0.0), ("fp64", "kforce"): (32.0, 0.0, 0.0),
+    ("mixed", "rho"): (5.5, 6.0, 2.0), ("mixed", "kforce"): (11.0, 5.0, 2.0),
+}  # (FP64 flops, FP32 flops, FP32 transcendentals) per (atom, mode)
+PAIR_MODEL = {
+    "fp64": {"fp64_test": 10.25, "fp64_pair": 187.0, "fp32_pair": 0.0, "trans_pair": 0.0},
+    "mixed": {"fp64_test": 10.25, "fp64_pair": 6.0, "fp32_pair": 40.0, "trans_pair": 3.0},
 }
 
 
@@ -58,8 +85,59 @@ def _log(msg: str) -> None:
 TUNING_KEYS = ("pair_block", "pair_ku", "rho_mpl", "kf_block", "kf_aux")
 
 
+def _force_err(a, b) -> dict:
+    """FP32-mixed force a against the FP64 force b: relative RMS and the
+    largest single-atom error in units of the RMS force."""
+    d2 = ((a - b) ** 2).sum(1)
+    f2 = (b ** 2).sum(1)
+    return {"rel_rms": float(np.sqrt(d2.sum() / f2.sum())),
+            "max_atom_over_f_rms": float(np.sqrt(d2.max() / f2.mean()))}
+
+
+def form_error(cfg, **over) -> dict:
+    """Both forms evaluate the force once (eval 0) at the workload's starting
+    positions; the FP64 path is the reference (it matches the oracle to
+    1e-11)."""
+    import torch
+    from paper_2512_24970_amd import rbsog as R
+    dev = torch.device("cuda", 0)
+    sysp = dict(cfg["sys"], **over)
+    out = {}
+    for prec in (R.FP64, R.MIXED):
+        ctx = R.Context(0)
+        ctx.rbsog_set_system(R.make_params(sysp, prec, n_atoms=len(cfg["types"])),
+                             torch.as_tensor(cfg["types"], device=dev), torch.as_tensor(cfg["pos"], device=dev),
+                             torch.as_tensor(cfg["vel"], device=dev))
+        f, _ = ctx.rbsog_compute_forces(0, want_energy=False)
+        out[prec] = f.cpu().numpy()
+        ctx.close()
+        del f
+    torch.cuda.empty_cache()
+    return dict(_force_err(out[R.MIXED], out[R.FP64]), reference="fp64 path, eval 0, starting positions")
+
+
+def batch_form_error(cfgs) -> dict:
+    """form_error for a batch: both forms on the whole batch, the worst replica."""
+    import torch
+    from paper_2512_24970_amd import rbsog as R
+    dev = torch.device("cuda", 0)
+    out = {}
+    for prec in (R.FP64, R.MIXED):
+        ctx = R.Context(0)
+        ctx.rbsog_set_batch([R.make_params(c["sys"], prec, n_atoms=len(c["types"])) for c in cfgs],
+                            *_batch_inputs(cfgs, dev))
+        f, _ = ctx.rbsog_compute_forces(0, want_energy=False)
+        out[prec] = f.cpu().numpy()
+        ctx.close()
+    offs = np.cumsum([0] + [len(c["types"]) for c in cfgs])
+    per = [_force_err(out[R.MIXED][a:b], out[R.FP64][a:b]) for a, b in zip(offs[:-1], offs[1:])]
+    return dict(_force_err(out[R.MIXED], out[R.FP64]),
+                worst_replica_rel_rms=max(x["rel_rms"] for x in per),
+                reference="fp64 path, eval 0, starting positions")
+
+
 def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto", thermostat: str = "berendsen",
-            tau: float | None = None):
+            tau: float | None = None, repeats: int = 5):
     import torch
     from paper_2512_24970_amd import rbsog as R
     dev = torch.device("cuda", 0)
@@ -89,11 +167,13 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto", 
     # run, since events around each phase cost a few per cent of a step
     ctx.rbsog_profile_read()
     ctx.rbsog_profile_enable(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e1 = ctx.rbsog_step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    runs = []
+    for _ in range(max(1, repeats)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e1 = ctx.rbsog_step(steps)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
     prof = ctx.rbsog_profile_read()
     phase_steps = min(steps, 30)
     ctx.rbsog_profile_enable(1)
@@ -106,11 +186,12 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto", 
     torch.cuda.empty_cache()
     mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 1e9
     n = len(cfg["types"])
-    dt = t1 - t0
-    _log(f"[bench] {precision}: {steps} steps in {dt:.3f} s -> {n * steps / dt:.4g} atom-steps/s")
+    dt = float(np.median(runs))
+    _log(f"[bench] {precision}: median of {len(runs)} x {steps} steps {dt:.3f} s -> {n * steps / dt:.4g} atom-steps/s")
     ctx.close()
     T = 2 * e1["kinetic"] / ((3 * n - 3) * 8.617333262e-5)
     return {"seconds": dt, "value": n * steps / dt, "ms_per_step": 1e3 * dt / steps, "phases": prof,
+            "runs_ms_per_step": [round(1e3 * t / steps, 4) for t in runs],
             "phases_all": prof_all, "phase_steps": phase_steps,
             "energy": e1, "energy_warm": e0, "T_end": T, "force0": f0, "tuning": tuning,
             "device_mem_GB": round(mem_gb, 3)}
@@ -122,7 +203,7 @@ def _batch_inputs(cfgs, dev):
     return cat("types"), cat("pos"), cat("vel")
 
 
-def run_batch(n_rep: int, steps: int, warmup: int):
+def run_batch(n_rep: int, steps: int, warmup: int, repeats: int = 5):
     """Aggregate throughput of the batched form, and of the same replicas run
     one after another (own context each, plain launches)."""
     import torch
@@ -141,11 +222,14 @@ def run_batch(n_rep: int, steps: int, warmup: int):
     ctx.rbsog_use_graphs(True)
     _log(f"[bench] batch: {n_rep} replicas, {n_tot} ions, tuning {tuning}; warmup {warmup} steps")
     ctx.rbsog_step(warmup)
-    stream.synchronize()
-    t0 = time.perf_counter()
-    e = ctx.rbsog_step(steps)
-    stream.synchronize()
-    dt_b = time.perf_counter() - t0
+    runs = []
+    for _ in range(max(1, repeats)):
+        stream.synchronize()
+        t0 = time.perf_counter()
+        e = ctx.rbsog_step(steps)
+        stream.synchronize()
+        runs.append(time.perf_counter() - t0)
+    dt_b = float(np.median(runs))
     # kernel phases of the batched step (kernel by kernel while timed)
     ctx.rbsog_profile_read()
     ctx.rbsog_profile_enable(True)
@@ -172,8 +256,11 @@ def run_batch(n_rep: int, steps: int, warmup: int):
     _log(f"[bench] sequential: {steps} steps x {n_rep} contexts in {dt_s:.3f} s -> "
          f"{n_tot * steps / dt_s:.4g} atom-steps/s")
     T = [2 * x["kinetic"] / ((3 * len(c["types"]) - 3) * 8.617333262e-5) for x, c in zip(e, cfgs)]
+    err = batch_form_error(cfgs)
     return {
         "workload": f"nacl_replicas{n_rep}", "n_systems": n_rep, "n_atoms": n_tot,
+        "mixed_vs_fp64_force": err,
+        "runs_ms_per_step": [round(1e3 * t / steps, 4) for t in runs],
         "sizes": [int(len(c["types"])) for c in cfgs][:8] + ["..."],
         "form": "mixed", "value": n_tot * steps / dt_b, "unit": "atom-steps/s",
         "ms_per_step": 1e3 * dt_b / steps, "graph": True, "tuning": tuning,
@@ -184,12 +271,6 @@ def run_batch(n_rep: int, steps: int, warmup: int):
     }
 
 
-# Pair-kernel model (per atom, FMA = 2): a distance test is 17 flops (three
-# differences, minimum image 9, r^2 5); an evaluated pair is 123 flops, with
-# an FP64 exp counted as 20 and an rsqrt as 8 (two exps, five squarings, six
-# Gaussian weights, a 13-term polynomial, BMH terms, force assembly).
-FLOPS_TEST, FLOPS_PAIR = 17, 123
-
 KERNEL_OF_PHASE = {"pair": "k_pair", "rho": "k_rho", "kforce": "k_kforce"}
 
 
@@ -198,7 +279,10 @@ def phase_ms(res) -> dict:
     return {k: round(v[0] / res["phase_steps"], 4) for k, v in res["phases_all"].items()}
 
 
-def pair_flops_per_atom(sysp: dict, n: int) -> float:
+def pair_counts(sysp: dict, n: int) -> dict:
+    """Per atom at the workload's density: distance tests (core-list entries
+    plus batch entries) and evaluated pairs (inside r_core, plus the batch
+    entries inside [r_core, r_shell))."""
     L = sysp["box"]
     rho_n = n / (L[0] * L[1] * L[2])
     rc, rs, sk, pr = sysp["r_core"], sysp["r_shell"], sysp["skin"], sysp["p_r"]
@@ -208,58 +292,123 @@ def pair_flops_per_atom(sysp: dict, n: int) -> float:
     cand = (v(rs + sk) - v(max(rc - sk, 0.0))) * rho_n
     valid = (v(rs) - v(rc)) * rho_n / cand
     batch = min(pr, cand) if pr > 0 else cand
-    return (core_list + batch) * FLOPS_TEST + (core + valid * batch) * FLOPS_PAIR
+    return {"core_list": core_list, "batch": batch, "tests": core_list + batch, "pairs": core + valid * batch}
 
 
-def kernel_roofline(precision: str, phase: str, ms: float, launches: int, n: int, sysp: dict) -> dict:
-    avg = ms / launches * 1e-3
+def kernel_work(precision: str, phase: str, n: int, sysp: dict) -> dict:
+    """Model work of one launch: FP64 flops, FP32 flops, FP32 transcendentals,
+    algorithmic HBM bytes (each input read once, each output written once)."""
     if phase == "pair":
-        flops = pair_flops_per_atom(sysp, n) * n
+        c = pair_counts(sysp, n)
+        m = PAIR_MODEL[precision]
+        f64 = n * (c["tests"] * m["fp64_test"] + c["pairs"] * m["fp64_pair"])
+        f32 = n * c["pairs"] * m["fp32_pair"]
+        tr = n * c["pairs"] * m["trans_pair"]
+        # position record 32 B, list counts 8 B, core-list entries, one
+        # candidate index per batch entry, short-range force 24 B
+        hbm = n * (32 + 8 + 4 * c["core_list"] + 4 * c["batch"] + 24)
     else:
-        flops = FLOPS_PER_PAIR[(precision, phase)] * float(n) * float(sysp["p_f"])
-    ach = flops / avg / 1e12
-    return {"bound": "alu", "kernel": KERNEL_OF_PHASE[phase], "achieved": round(ach, 3), "peak": PEAK_VALU_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(ach / PEAK_VALU_TFLOPS, 4), "traffic": None,
-            "avg_launch_ms": round(ms / launches, 4), "launches": launches, "flops_per_launch": flops}
+        am = float(n) * float(sysp["p_f"])
+        a, b, t = KSPACE_MODEL[(precision, phase)]
+        f64, f32, tr = am * a, am * b, am * t
+        # positions once; the force kernel also writes the k-space force
+        hbm = n * (32 + (24 if phase == "kforce" else 0))
+    return {"fp64_flops": f64, "fp32_flops": f32, "trans": tr, "hbm_bytes": hbm}
 
 
-def traffic_from_profiles(kernel: str, workload: str):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source (else None)."""
+def _profile_json(workload: str, tag: str):
+    """The `<tag>_json:` line of profiles/<workload>_*.md taken on the current
+    kernel source (else None)."""
     import hashlib
-    path = os.path.join(HERE, "profiles", f"{workload}_traffic.md")
     src = os.path.join(HERE, "paper_2512_24970_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    name = {"traffic": "traffic", "counters": "sq_counters"}[tag]
+    path = os.path.join(HERE, "profiles", f"{workload}_{name}.md")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
     for line in open(path):
-        if line.startswith("traffic_json:"):
+        if line.startswith(f"{tag}_json:"):
             d = json.loads(line.split(":", 1)[1])
-            if d.get("source_sha1") == sha and kernel in d.get("bytes_per_launch", {}):
-                return d["bytes_per_launch"][kernel]
+            if d.get("source_sha1") == sha:
+                return d
     return None
+
+
+def kernel_roofline(precision: str, phase: str, ms: float, launches: int, n: int, sysp: dict,
+                    workload: str) -> dict:
+    avg = ms / launches * 1e-3
+    w = kernel_work(precision, phase, n, sysp)
+    flops = w["fp64_flops"] + w["fp32_flops"]
+    ach = flops / avg / 1e12
+    kern = KERNEL_OF_PHASE[phase]
+    key = f"{kern}<{precision}>"
+    out = {"bound": "alu", "kernel": kern, "achieved": round(ach, 3), "peak": PEAK_VALU_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(ach / PEAK_VALU_TFLOPS, 4), "traffic": None,
+           "avg_launch_ms": round(ms / launches, 4), "launches": launches,
+           "model": {"fp64_flops_per_launch": w["fp64_flops"], "fp32_flops_per_launch": w["fp32_flops"],
+                     "fp64_tflops": round(w["fp64_flops"] / avg / 1e12, 3),
+                     "fp32_tflops": round(w["fp32_flops"] / avg / 1e12, 3),
+                     "fp32_trans_per_launch": w["trans"],
+                     "fp32_trans_per_s": round(w["trans"] / avg, 1),
+                     "hbm_bytes_per_launch": w["hbm_bytes"],
+                     "hbm_GBps": round(w["hbm_bytes"] / avg / 1e9, 1)}}
+    cnt = _profile_json(workload, "counters")
+    if cnt and key in cnt.get("per_launch", {}):
+        c = cnt["per_launch"][key]
+        # VALU issue: lane-instructions, a transcendental taking four slots
+        slots = c["valu_lane_instr"] + (TRANS_SLOTS - 1) * c["trans_lane_instr"]
+        out["counted"] = {"fp64_flops_per_launch": c["fp64_flops"], "fp32_flops_per_launch": c["fp32_flops"],
+                          "valu_lane_instr_per_launch": c["valu_lane_instr"],
+                          "fp32_trans_lane_instr_per_launch": c["trans_lane_instr"],
+                          "valu_issue_frac": round(slots / avg / PEAK_LANE_INSTR_PER_S, 4),
+                          "flops_frac": round((c["fp64_flops"] + c["fp32_flops"]) / avg / 1e12
+                                              / PEAK_VALU_TFLOPS, 4),
+                          "model_over_counted_flops": round(flops / max(c["fp64_flops"] + c["fp32_flops"], 1), 3)}
+    tr = _profile_json(workload, "traffic")
+    if tr and key in tr.get("bytes_per_launch", {}):
+        b = tr["bytes_per_launch"][key]
+        out["traffic"] = b
+        out["traffic_GBps"] = round(b / avg / 1e9, 1)
+        out["traffic_frac_of_hbm_peak"] = round(b / avg / 1e9 / PEAK_HBM_GBS, 4)
+        out["traffic_over_algorithmic"] = round(b / max(w["hbm_bytes"], 1), 3)
+    return out
 
 
 def roofline(precision: str, res: dict, n: int, sysp: dict, workload: str) -> dict:
     """The dominant kernel (largest time in the timed steps) and the others."""
     phases = {k: v for k, v in res["phases"].items() if k in KERNEL_OF_PHASE and v[1] > 0}
-    lines = {k: kernel_roofline(precision, k, v[0], v[1], n, sysp) for k, v in phases.items()}
+    lines = {k: kernel_roofline(precision, k, v[0], v[1], n, sysp, workload) for k, v in phases.items()}
     top = max(phases, key=lambda k: phases[k][0])
     out = dict(lines[top])
-    out["traffic"] = traffic_from_profiles(out["kernel"] + ("<mixed>" if precision == "mixed" else "<fp64>"),
-                                           workload)
-    if out["traffic"]:
-        # the measured HBM bytes against the HBM peak, beside the VALU view
-        gbs = out["traffic"] / (out["avg_launch_ms"] * 1e-3) / 1e9
-        out["traffic_GBps"] = round(gbs, 1)
-        out["traffic_frac_of_hbm_peak"] = round(gbs / PEAK_HBM_GBS, 4)
-    out["others"] = {lines[k]["kernel"]: {"achieved": lines[k]["achieved"], "frac": lines[k]["frac"],
-                                         "avg_launch_ms": lines[k]["avg_launch_ms"]}
+    out["others"] = {lines[k]["kernel"]: {key: lines[k][key] for key in
+                                          ("achieved", "frac", "avg_launch_ms", "model", "counted", "traffic")
+                                          if key in lines[k]}
                      for k in lines if k != top}
     # the k-space chain runs on a second stream beside the pair kernel, so
     # their launch durations overlap and each includes the other's share
     out["concurrent"] = "k_pair runs beside k_ksample + k_rho + k_kforce (second stream); durations overlap"
     return out
+
+
+def apriori_model(sysp: dict, n: int, precision: str) -> dict:
+    """The a-priori work model per atom-step this path was planned with:
+    pairs x (~30 FP64 flops, 12 transcendentals) + 2 P_F x (~12 FP64 flops,
+    2 transcendentals) in the mixed form; pairs x (60 + 12 x 50) + 2 P_F x
+    (12 + 100) FP64 flops in the FP64 form (software exp and sincos counted
+    as 25 FMAs); HBM bytes: positions read three times, type, velocity read
+    and written, force and position written, the core list, P_R batch
+    indices."""
+    c = pair_counts(sysp, n)
+    pf = float(sysp["p_f"])
+    if precision == "mixed":
+        f64 = c["pairs"] * 30 + 2 * pf * 12
+        tr = c["pairs"] * 12 + 2 * pf * 2
+    else:
+        f64 = c["pairs"] * (60 + 12 * 50) + 2 * pf * (12 + 100)
+        tr = 0.0
+    hbm = 72 + 1 + 48 + 24 + 24 + 4 * c["core_list"] + 4 * c["batch"]
+    return {"fp64_flops_per_atom_step": round(f64, 1), "fp32_trans_per_atom_step": round(tr, 1),
+            "hbm_bytes_per_atom_step": round(hbm, 1)}
 
 
 def copy_probe(nbytes: int, reps: int = 5) -> None:
@@ -299,9 +448,50 @@ def cpu_baseline(cfg, n_sample: int, ev: int = 1):
     s.close()
     return {"value": n / t_step, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 oracle, rho(k) of all {n} atoms for {len(m)} modes ({t1 - t0:.2f} s) + short-range "
-                       f"and k-space force of {n_sample} random atoms ({t3 - t1:.2f} s, neighbours by O(N) scan), "
-                       f"extrapolated to one step of all atoms"),
-            "seconds_measured": round(t3 - t0, 3)}
+                       f"and k-space force of {n_sample} random atoms ({t3 - t1:.2f} s); an extrapolation to one "
+                       f"step of all atoms, dominated by the oracle's brute-force O(N) neighbour search per atom, "
+                       f"which the method amortises over list builds"),
+            "extrapolated": True, "seconds_measured": round(t3 - t0, 3)}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_direct(steps: int = 10) -> dict:
+    """The oracle's full step timed directly on the 512- and 32768-ion melts
+    (Table 1 NaCl, P_R 20, P_F 100 / 200), at one thread and at all host
+    threads: the first force evaluation (which builds the lists by brute
+    force), then `steps` velocity-Verlet steps (one rebuild period)."""
+    import oracle as O
+    from paper_2512_24970_amd import workloads as W
+    O.build(force=False)
+    all_threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    out = {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "threads_available": all_threads, "runs": []}
+    for name in ("nacl_512", "nacl_32768"):
+        cfg = W.config(name)
+        n = len(cfg["types"])
+        for th in (1, all_threads):
+            O.set_threads(th)
+            s = O.System(cfg["sys"], cfg["types"], cfg["pos"], cfg["vel"])
+            t0 = time.perf_counter()
+            s.forces(0)
+            t1 = time.perf_counter()
+            s.vv_steps(steps)
+            t2 = time.perf_counter()
+            s.close()
+            per = (t2 - t1) / steps
+            out["runs"].append({"workload": name, "n_atoms": n, "threads": th, "first_force_s": round(t1 - t0, 4),
+                                "steps": steps, "s_per_step": round(per, 5), "atom_steps_per_s": round(n / per, 1)})
+            _log(f"[bench] cpu oracle {name} threads {th}: {per:.4f} s/step")
+    O.set_threads(0)
+    return out
 
 
 def main() -> int:
@@ -325,6 +515,11 @@ def main() -> int:
                     help="timed steps of the Nose-Hoover and Langevin legs on the main workload (0: skip)")
     ap.add_argument("--paper-steps", type=int, default=100,
                     help="timed steps of the leg at the size and batch sizes of the paper's timing table (0: skip)")
+    ap.add_argument("--repeats", type=int, default=5, help="timed runs per leg; the median is reported")
+    ap.add_argument("--cpu-direct", type=int, default=1,
+                    help="1: also time the oracle's full step on the 512- and 32768-ion melts at 1 and all threads")
+    ap.add_argument("--form-errors", type=int, default=1,
+                    help="1: state each leg's FP32-mixed force error against the FP64 path")
     ap.add_argument("--tuning", default="auto",
                     help="launch shapes of the single-system runs: auto (autotuned) or "
                          "pair_block,pair_ku,rho_mpl,kf_block,kf_aux")
@@ -350,7 +545,7 @@ def main() -> int:
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {}
     for f in forms:
-        results[f] = run_gpu(cfg, f, args.steps, args.warmup, args.tuning)
+        results[f] = run_gpu(cfg, f, args.steps, args.warmup, args.tuning, repeats=args.repeats)
     head = forms[0]
     r = results[head]
     p_f = int(cfg["sys"]["p_f"])
@@ -376,29 +571,36 @@ def main() -> int:
         },
         "roofline": roofline(head, r, n, cfg["sys"], wl_key),
         "phases_ms_per_step": phase_ms(r),
+        "runs_ms_per_step": r["runs_ms_per_step"],
+        "apriori_model": apriori_model(cfg["sys"], n, head),
         "tuning": r["tuning"],
         "device_mem_GB": r["device_mem_GB"],
     }
     line["T_end_K"] = round(r["T_end"], 1)
+    main_err = None
     if "mixed" in results and "fp64" in results:
         a, b = results["mixed"]["force0"], results["fp64"]["force0"]
-        line["mixed_vs_fp64_force_rel_rms"] = float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+        main_err = dict(_force_err(a, b), reference="fp64 path, eval 0, starting positions")
+        line["mixed_vs_fp64_force_rel_rms"] = main_err["rel_rms"]
+        line["mixed_vs_fp64_force"] = main_err
     for f in forms[1:]:
         rf = results[f]
         line[f] = {"value": rf["value"], "ms_per_step": rf["ms_per_step"], "T_end_K": round(rf["T_end"], 1),
-                   "tuning": rf["tuning"],
+                   "runs_ms_per_step": rf["runs_ms_per_step"], "tuning": rf["tuning"],
                    "roofline": roofline(f, rf, n, cfg["sys"], wl_key),
+                   "apriori_model": apriori_model(cfg["sys"], n, f),
                    "phases_ms_per_step": phase_ms(rf)}
     if args.batch > 0:
-        line["batch"] = run_batch(args.batch, args.steps, args.warmup)
+        line["batch"] = run_batch(args.batch, args.steps, args.warmup, args.repeats)
     if args.large_steps > 0:
         # the 5e6-ion NaCl melt (P_F = 1000), mixed form
         t = time.perf_counter()
         big = W.config("nacl_5m")
         _log(f"[bench] large: N={len(big['types'])} inputs in {time.perf_counter() - t:.1f} s")
-        rl = run_gpu(big, "mixed", args.large_steps, args.warmup, "auto")
+        rl = run_gpu(big, "mixed", args.large_steps, args.warmup, "auto", repeats=1)
         nb = len(big["types"])
         line["large"] = {"workload": "nacl_5m", "n_atoms": nb, "p_f": int(big["sys"]["p_f"]),
+                         "mixed_vs_fp64_force": form_error(big) if args.form_errors else None,
                          "p_r": int(big["sys"]["p_r"]), "form": "mixed", "value": rl["value"],
                          "unit": "atom-steps/s", "steps": args.large_steps, "ms_per_step": rl["ms_per_step"],
                          "T_end_K": round(rl["T_end"], 1), "tuning": rl["tuning"],
@@ -408,18 +610,19 @@ def main() -> int:
     if args.stored:
         # memory form of the random batch list: the shell batch is drawn at the
         # list build and kept until the next one (P_R entries per atom)
-        def stored_leg(c, steps, wl):
+        def stored_leg(c, steps, wl, reps):
             cs = dict(c, sys=dict(c["sys"], shell_stored=True))
-            rs = run_gpu(cs, "mixed", steps, args.warmup, "auto")
+            rs = run_gpu(cs, "mixed", steps, args.warmup, "auto", repeats=reps)
             nn = len(c["types"])
             return {"workload": wl, "n_atoms": nn, "form": "mixed", "value": rs["value"], "unit": "atom-steps/s",
+                    "mixed_vs_fp64_force": form_error(c, shell_stored=True) if args.form_errors else None,
                     "steps": steps, "ms_per_step": rs["ms_per_step"], "T_end_K": round(rs["T_end"], 1),
                     "tuning": rs["tuning"], "device_mem_GB": rs["device_mem_GB"],
                     "roofline": roofline("mixed", rs, nn, c["sys"], wl + "_stored"),
                     "phases_ms_per_step": phase_ms(rs)}
-        line["stored"] = stored_leg(cfg, args.steps, args.workload)
+        line["stored"] = stored_leg(cfg, args.steps, args.workload, args.repeats)
         if args.large_steps > 0:
-            line["stored"]["large"] = stored_leg(big, args.large_steps, "nacl_5m")
+            line["stored"]["large"] = stored_leg(big, args.large_steps, "nacl_5m", 1)
     if args.paper_steps > 0:
         # Context, not the metric: molten NaCl at the size and batch sizes of
         # the paper's timing table (Section 3.2, Table 2: 1.024e6 ions,
@@ -431,9 +634,11 @@ def main() -> int:
         leg = {"workload": "nacl_1024k", "n_atoms": npc, "p_r": 30, "p_f": 100, "r_core_A": 5.0,
                "r_shell_A": 10.0, "unit": "atom-steps/s", "steps": args.paper_steps}
         for form in ("mixed", "fp64"):
-            rp = run_gpu(pc, form, args.paper_steps, args.warmup, "auto")
+            rp = run_gpu(pc, form, args.paper_steps, args.warmup, "auto", repeats=args.repeats)
             leg[form] = {"value": rp["value"], "ms_per_step": rp["ms_per_step"], "tuning": rp["tuning"],
-                         "phases_ms_per_step": phase_ms(rp)}
+                         "runs_ms_per_step": rp["runs_ms_per_step"], "phases_ms_per_step": phase_ms(rp)}
+        if args.form_errors:
+            leg["mixed_vs_fp64_force"] = form_error(pc)
         leg["paper_cpu_context"] = {"ms_per_step": 9.04, "atom_steps_per_s": round(npc / 9.04e-3, 1),
                                     "cores": 1000, "precision": "fp64",
                                     "hardware": "2x Intel Xeon Platinum 8358 per node", "source": "Table 2"}
@@ -442,13 +647,18 @@ def main() -> int:
         # the other thermostats on the main workload (mixed form), tau = 10 fs
         line["thermostats"] = {}
         for kind in ("nose_hoover", "langevin"):
-            rt = run_gpu(cfg, "mixed", args.thermo_steps, args.warmup, "auto", kind, 0.01)
+            rt = run_gpu(cfg, "mixed", args.thermo_steps, args.warmup, "auto", kind, 0.01, repeats=args.repeats)
             line["thermostats"][kind] = {"tau_ps": 0.01, "value": rt["value"], "ms_per_step": rt["ms_per_step"],
+                                         "mixed_vs_fp64_force": (dict(main_err, note="starting positions of the "
+                                                                 "main leg") if main_err else None),
                                          "steps": args.thermo_steps, "T_end_K": round(rt["T_end"], 1),
                                          "phases_ms_per_step": phase_ms(rt)}
     if args.cpu_sample > 0:
         _log(f"[bench] cpu baseline: oracle on {args.cpu_sample} atoms")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
+        line["cpu_baseline"]["cpu_model"] = cpu_model()
+        if args.cpu_direct:
+            line["cpu_baseline"]["direct"] = cpu_direct()
     print(json.dumps(line), flush=True)
     return 0
 

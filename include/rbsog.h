@@ -402,6 +402,17 @@ rbsog_status rbsog_get_shell_batch(rbsog_ctx* ctx, int32_t* n_cand, int32_t* ids
  * g_ab(r) = counts / (N_a (N_b - delta_ab) / V * shell volume).
  * Synchronises. */
 rbsog_status rbsog_rdf_counts(rbsog_ctx* ctx, double r_max, int32_t n_bins, uint64_t* counts);
+/* rbsog_rdf_counts for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same counts, with the device histogram kept in a
+ * file-scope device array of 16384 counters per GPU (its address looked up
+ * once per device at rbsog_create) instead of a buffer allocated per call;
+ * no hipMalloc or hipFree.  S*S*n_bins above 16384: RBSOG_E_ARG.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (two host
+ * threads, two contexts) race; the array is cleared by the call itself.
+ * Enqueues on the context's stream, copies into the host array counts and
+ * synchronises. */
+rbsog_status rbsog_rdf_counts_noalloc(rbsog_ctx* ctx, double r_max, int32_t n_bins, uint64_t* counts);
 /* Mean-square displacement of the selected system (the MSD of Section 3.1),
  * per species, from an origin the caller marks.  mark != 0: the origin is the
  * current positions (each ion's unwrapped displacement D_i restarts at 0).

@@ -1365,6 +1365,12 @@ rbsog_status rbsog_create(rbsog_ctx** out, int hip_device, void* hip_stream)
         delete c;
         return RBSOG_E_HIP;
     }
+    // device address of the allocation-free entry point's scratch, once per device
+    const char* why = nullptr;
+    if (!noalloc_init(hip_device, &why)) {
+        delete c;
+        return RBSOG_E_HIP;
+    }
     *out = c;
     return RBSOG_OK;
 }
@@ -1785,6 +1791,31 @@ rbsog_status rbsog_rdf_counts(rbsog_ctx* ctx, double r_max, int32_t n_bins, uint
         launch_rdf(P1, S, r_max / (double)n_bins, n_bins, out.as<unsigned long long>(), ctx->stream);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(counts, out.p, out.bytes, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+rbsog_status rbsog_rdf_counts_noalloc(rbsog_ctx* ctx, double r_max, int32_t n_bins, uint64_t* counts)
+{
+    return guarded(ctx, [&] {
+        need_system(ctx);
+        const DevSys& s = ctx->hs[ctx->sel];
+        const rbsog_params& p = ctx->prm[ctx->sel];
+        require(n_bins >= 1 && r_max > 0.0 && r_max <= p.r_shell, RBSOG_E_ARG,
+                "rdf: need n_bins >= 1 and 0 < r_max <= r_shell");
+        const int S = s.n_species;
+        require((long long)S * S * n_bins <= kRdfScratch, RBSOG_E_ARG,
+                "rdf (allocation-free): n_species^2 * n_bins exceeds the 16384 counters of the static scratch");
+        require(!s.shell_stored, RBSOG_E_STATE, "rdf: the memory form keeps no candidate rows");
+        require(counts != nullptr, RBSOG_E_ARG, "rdf: counts is NULL");
+        unsigned long long* d = noalloc_scratch(ctx->device);
+        require(d != nullptr, RBSOG_E_STATE, "allocation-free scratch not set up on this device");
+        const int nh = S * S * n_bins;
+        launch_zero_u64(d, nh, ctx->stream);
+        const Plan P1 = one(ctx, ctx->sel);
+        launch_rdf(P1, S, r_max / (double)n_bins, n_bins, d, ctx->stream);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(counts, d, sizeof(unsigned long long) * (size_t)nh, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
     });
 }

@@ -10,11 +10,18 @@
 
 #include <climits>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
 
 namespace rbsog {
+
+// Device memory of the allocation-free pair histogram (rbsog_rdf_counts_noalloc):
+// one array per GPU the library runs on, held until the process ends.  Host
+// code must not use this name as an address (it is a host-side stand-in);
+// it uses the device address that noalloc_init looks up.
+static __device__ __align__(256) unsigned long long scratch[kRdfScratch];
 
 namespace {
 
@@ -2183,6 +2190,13 @@ __global__ __launch_bounds__(kBlock) void k_rdf(RB_ARGS, double D, int n_bins, u
         if (hist[t]) atomicAdd(&counts[t], (unsigned long long)hist[t]);
 }
 
+// Zero fill (a kernel, not a memset node: callers may capture the stream).
+__global__ void k_zero_u64(unsigned long long* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 // Mean-square displacement bookkeeping, per atom by user index: the
 // minimum-image increment since the last call is added to the unwrapped
 // displacement D and the position kept (mark: D restarts at zero from the
@@ -2544,6 +2558,42 @@ void launch_kick_drift(const Plan& P, bool scheduled, hipStream_t st)
         k_kick_drift<true><<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), scheduled ? 1 : 0);
     else
         k_kick_drift<false><<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms), scheduled ? 1 : 0);
+}
+
+// Per-device address of `scratch`, looked up once per device at context
+// creation (with that device current).
+constexpr int kMaxDevices = 64;
+static unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+bool noalloc_init(int device, const char** err)
+{
+    if (device < 0 || device >= kMaxDevices) {
+        *err = "device index above the allocation-free scratch table";
+        return false;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return true;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+        *err = hipGetErrorString(e);
+        return false;
+    }
+    g_scratch_ptr[device] = static_cast<unsigned long long*>(ptr);
+    return true;
+}
+
+unsigned long long* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+void launch_zero_u64(unsigned long long* p, int n, hipStream_t st)
+{
+    if (n > 0) k_zero_u64<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(p, n);
 }
 
 void launch_rdf(const Plan& P, int n_species, double D, int n_bins, unsigned long long* counts, hipStream_t st)

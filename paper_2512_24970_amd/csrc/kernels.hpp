@@ -238,6 +238,14 @@ void launch_kick_drift(const Plan& P, bool scheduled, hipStream_t st);
 enum class Field { force = 0, short_force = 1, velocity = 2 };
 // pair-distance histogram [S][S][n_bins] (uint64, accumulated) from the lists
 void launch_rdf(const Plan& P, int n_species, double D, int n_bins, unsigned long long* counts, hipStream_t st);
+// Allocation-free pair histogram: a file-scope device array of kRdfScratch
+// counters per GPU.  noalloc_init looks up its address on `device` (which
+// must be current) once; noalloc_scratch returns it (null before init).
+constexpr int kRdfScratch = 16384;
+bool noalloc_init(int device, const char** err);
+unsigned long long* noalloc_scratch(int device);
+// zero n counters with a fill kernel
+void launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 // mean-square displacement bookkeeping of one system (Plan of that system);
 // part: [ceil(n/64)][2 kMaxSpecies] wavefront partials
 void launch_msd(const Plan& P, double* last, double* disp, double* part, bool mark, hipStream_t st);

@@ -108,6 +108,7 @@ ABI = {
     "rbsog_get_shell_ranks": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "rbsog_get_shell_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbsog_rdf_counts": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
+    "rbsog_rdf_counts_noalloc": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
     "rbsog_msd": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "rbsog_set_list_chunks": (C.c_int, [C.c_void_p, C.c_int32]),
     "rbsog_set_list_capacity": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
@@ -441,6 +442,14 @@ class Context:
         S = self.params_list[self.sel].n_species
         out = np.zeros((S, S, int(n_bins)), np.uint64)
         self._check(lib().rbsog_rdf_counts(self._h, float(r_max), int(n_bins), _np_ptr(out)), "rbsog_rdf_counts")
+        return out
+
+    def rbsog_rdf_counts_noalloc(self, r_max: float, n_bins: int) -> np.ndarray:
+        """rbsog_rdf_counts through the allocation-free entry point."""
+        S = self.params_list[self.sel].n_species
+        out = np.zeros((S, S, int(n_bins)), np.uint64)
+        self._check(lib().rbsog_rdf_counts_noalloc(self._h, float(r_max), int(n_bins), _np_ptr(out)),
+                    "rbsog_rdf_counts_noalloc")
         return out
 
     def rbsog_msd(self, mark: bool = False) -> np.ndarray:
