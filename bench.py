@@ -94,10 +94,10 @@ def _force_err(a, b) -> dict:
             "max_atom_over_f_rms": float(np.sqrt(d2.max() / f2.mean()))}
 
 
-def form_error(cfg, **over) -> dict:
+def form_error(cfg, mixed_only=None, **over) -> dict:
     """Both forms evaluate the force once (eval 0) at the workload's starting
     positions; the FP64 path is the reference (it matches the oracle to
-    1e-11)."""
+    1e-11).  mixed_only: parameters set for the mixed form alone."""
     import torch
     from paper_2512_24970_amd import rbsog as R
     dev = torch.device("cuda", 0)
@@ -105,7 +105,8 @@ def form_error(cfg, **over) -> dict:
     out = {}
     for prec in (R.FP64, R.MIXED):
         ctx = R.Context(0)
-        ctx.rbsog_set_system(R.make_params(sysp, prec, n_atoms=len(cfg["types"])),
+        sp = dict(sysp, **(mixed_only or {})) if prec == R.MIXED else sysp
+        ctx.rbsog_set_system(R.make_params(sp, prec, n_atoms=len(cfg["types"])),
                              torch.as_tensor(cfg["types"], device=dev), torch.as_tensor(cfg["pos"], device=dev),
                              torch.as_tensor(cfg["vel"], device=dev))
         f, _ = ctx.rbsog_compute_forces(0, want_energy=False)
@@ -511,6 +512,8 @@ def main() -> int:
     ap.add_argument("--stored", type=int, default=1,
                     help="1: also time the memory form of the list (shell batch drawn at the build) "
                          "on the 1e6-ion workload and, with --large-steps, on the 5e6-ion melt")
+    ap.add_argument("--int-phase", type=int, default=1,
+                    help="1: also time the mixed form with the k-space phase in 32-bit fixed point")
     ap.add_argument("--thermo-steps", type=int, default=30,
                     help="timed steps of the Nose-Hoover and Langevin legs on the main workload (0: skip)")
     ap.add_argument("--paper-steps", type=int, default=100,
@@ -623,6 +626,17 @@ def main() -> int:
         line["stored"] = stored_leg(cfg, args.steps, args.workload, args.repeats)
         if args.large_steps > 0:
             line["stored"]["large"] = stored_leg(big, args.large_steps, "nacl_5m", 1)
+    if args.int_phase:
+        # the mixed form with the k-space phase reduced in 32-bit fixed point
+        # instead of FP64 (same workload and protocol)
+        ci = dict(cfg, sys=dict(cfg["sys"], int_phase=True))
+        ri = run_gpu(ci, "mixed", args.steps, args.warmup, "auto", repeats=args.repeats)
+        hot = {k: round(v[0] / max(v[1], 1), 4) for k, v in ri["phases"].items() if v[1] > 0}
+        line["int_phase"] = {"workload": args.workload, "form": "mixed", "phase": "32-bit fixed point",
+                             "value": ri["value"], "ms_per_step": ri["ms_per_step"],
+                             "runs_ms_per_step": ri["runs_ms_per_step"], "tuning": ri["tuning"],
+                             "hot_kernel_avg_launch_ms": hot, "phases_ms_per_step": phase_ms(ri),
+                             "mixed_vs_fp64_force": form_error(cfg, mixed_only={"int_phase": True}) if args.form_errors else None}
     if args.paper_steps > 0:
         # Context, not the metric: molten NaCl at the size and batch sizes of
         # the paper's timing table (Section 3.2, Table 2: 1.024e6 ions,

@@ -71,6 +71,16 @@ typedef enum { RBSOG_FP64 = 0, RBSOG_MIXED = 1 } rbsog_precision;
  *   r_core <= r < r_shell at the current positions and weights it by
  *   N_shell/P_R (N_shell = candidate count at the build).  Needs p_r >= 1. */
 #define RBSOG_FLAG_SHELL_STORED 1u
+/* RBSOG_FLAG_INT_PHASE (FP32-mixed form only): the phase k.r of the
+ * structure factors and the k-space force (eqs. 22, 29) is reduced in 32-bit
+ * fixed point (Section 2.4 names fixed-point phases as an implementation
+ * choice): each position is held as the fraction u = floor(2^32 x / L) of the
+ * box, the phase m.u of an integer mode m wraps exactly modulo 2^32 (one
+ * turn), and its signed value times 2^-32 is the FP32 turn given to the
+ * hardware sine and cosine.  Without the flag the phase is formed in FP64
+ * and its fractional turn rounded to FP32.  Both are within the mixed form's
+ * error; the flag is equal across a batch. */
+#define RBSOG_FLAG_INT_PHASE 2u
 
 typedef struct {
     double q;    /* charge, e */

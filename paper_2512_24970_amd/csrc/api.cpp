@@ -106,7 +106,7 @@ struct rbsog_ctx {
     int list_chunks = 8;
     double row_slack = 1.25;
     DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, vir_part, kin_part, export_tmp, snap, sogk, neartab;
-    DBuf flux_part, at_ew;
+    DBuf flux_part, at_ew, ufix;
     // mean-square displacement: [n_user][3] last positions, then [n_user][3]
     // unwrapped displacements; which systems have a marked origin
     DBuf msd_buf;
@@ -241,7 +241,9 @@ void validate(const rbsog_params* p)
     require(p->precision == RBSOG_FP64 || p->precision == RBSOG_MIXED, RBSOG_E_ARG, "unknown precision");
     require(!(p->t_target > 0.0 && p->tau_t > 0.0) || p->tau_t >= p->dt, RBSOG_E_ARG, "tau_t < dt");
     require(!(p->t_target > 0.0 && p->tau_t > 0.0) || p->n_atoms >= 2, RBSOG_E_ARG, "thermostat needs 2+ atoms");
-    require((p->flags & ~(uint32_t)RBSOG_FLAG_SHELL_STORED) == 0, RBSOG_E_ARG, "unknown flag");
+    require((p->flags & ~(uint32_t)(RBSOG_FLAG_SHELL_STORED | RBSOG_FLAG_INT_PHASE)) == 0, RBSOG_E_ARG, "unknown flag");
+    require(!(p->flags & RBSOG_FLAG_INT_PHASE) || p->precision == RBSOG_MIXED, RBSOG_E_ARG,
+            "the fixed-point phase is an option of the FP32-mixed form");
     require(p->thermostat == RBSOG_THERMO_BERENDSEN || p->thermostat == RBSOG_THERMO_NOSE_HOOVER ||
                 p->thermostat == RBSOG_THERMO_LANGEVIN,
             RBSOG_E_ARG, "unknown thermostat");
@@ -313,6 +315,7 @@ Plan one(const rbsog_ctx* c, int r)
     P.pair_atoms.blocks = blocks_for(s.n, P.tune.pair_block);
     P.kf_atoms.blocks = blocks_for(s.n, P.tune.kf_block);
     P.cells.blocks = s.n > 0 ? s.ncell : 0;
+    P.list_cells.blocks = s.n > 0 ? s.ncell * s.list_parts : 0;
     P.atom1.blocks = s.n;
     // an empty system draws no modes and sums no structure factors
     P.modes64.blocks = (s.n > 0 && k.sampled) ? blocks_for(k.n_modes, 64) : 0;
@@ -326,6 +329,7 @@ Plan one(const rbsog_ctx* c, int r)
     P.cap_cand = c->plan.cap_cand;
     P.near = c->plan.near;
     P.langevin = c->plan.langevin;
+    P.iph = c->plan.iph;
     P.species_cut = c->plan.species_cut;
     return P;
 }
@@ -342,15 +346,15 @@ void plan_launches(rbsog_ctx* c)
     P.kd = c->d_kd.as<KDev>();
     P.sc = c->scalars.as<DeviceScalars>();
     P.R = c->R;
-    constexpr int kShapes = 9;
+    constexpr int kShapes = 10;
     Shape* dst[kShapes] = {&P.atoms, &P.pair_atoms, &P.kf_atoms, &P.cells, &P.atom1,
-                           &P.modes64, &P.rho, &P.modes1, &P.rows64};
+                           &P.modes64, &P.rho, &P.modes1, &P.rows64, &P.list_cells};
     std::vector<std::vector<int2>> m(kShapes + kMaxListChunks);
     const bool maps = c->R > 1;
     for (int r = 0; r < c->R; ++r) {
         const Plan o = one(c, r);
         const Shape* sh[kShapes] = {&o.atoms, &o.pair_atoms, &o.kf_atoms, &o.cells, &o.atom1,
-                                    &o.modes64, &o.rho, &o.modes1, &o.rows64};
+                                    &o.modes64, &o.rho, &o.modes1, &o.rows64, &o.list_cells};
         for (int q = 0; q < kShapes; ++q) {
             if (maps)
                 for (int b = 0; b < sh[q]->blocks; ++b) m[q].push_back(make_int2(r, b));
@@ -363,7 +367,8 @@ void plan_launches(rbsog_ctx* c)
             for (int k = 0; k < s.n_chunks; ++k) {
                 const int c0 = (int)(((long long)k * s.ncell) / s.n_chunks);
                 const int c1 = (int)(((long long)(k + 1) * s.ncell) / s.n_chunks);
-                for (int cc = c0; cc < c1; ++cc) m[kShapes + k].push_back(make_int2(r, cc));
+                for (int cc = c0; cc < c1; ++cc)
+                    for (int q = 0; q < s.list_parts; ++q) m[kShapes + k].push_back(make_int2(r, cc * s.list_parts + q));
             }
     }
     for (int k = 0; k < kMaxListChunks; ++k) P.cell_chunk[k] = Shape{};
@@ -877,6 +882,8 @@ void init_devsys(const rbsog_params& p, int n, DevSys& s)
             s.lv_c2[t] = std::sqrt((1.0 - s.lv_c1 * s.lv_c1) * kBoltzmann * p.t_target * kAccUnit / p.species[t].mass);
     }
     s.p_r = p.p_r;
+    // about 96 atoms (24 work units, three per wavefront) per list workgroup
+    s.list_parts = std::max(1, std::min(32, (int)std::ceil((double)n / s.ncell / 96.0)));
     s.shell_stored = (p.flags & RBSOG_FLAG_SHELL_STORED) ? 1 : 0;
     s.n_chunks = 1;
     s.replica = p.replica;
@@ -981,6 +988,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->plan.tune = Tuning{};
     c->plan.langevin = false;
     c->plan.species_cut = false;
+    c->plan.iph = (p0.flags & RBSOG_FLAG_INT_PHASE) != 0;
     for (const auto& p : prm)
         if (p.t_target > 0.0 && p.tau_t > 0.0 && p.thermostat == RBSOG_THERMO_LANGEVIN) c->plan.langevin = true;
     c->slot_off.assign(slot_off.begin(), slot_off.end() - 1);
@@ -1022,6 +1030,10 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
     c->flux_part.alloc(sizeof(double) * kFluxPart * std::max<size_t>(1, n_waves));
     c->at_ew.alloc(sizeof(double4) * 2 * N);
+    if (c->plan.iph)
+        c->ufix.alloc(sizeof(uint4) * N);
+    else
+        c->ufix.release();
     c->scalars.alloc(sizeof(DeviceScalars) * R);
     HIP_OK(hipMemsetAsync(c->scalars.p, 0, sizeof(DeviceScalars) * R, c->stream));
     {
@@ -1067,6 +1079,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             s.kin_part = c->kin_part.as<double>() + wav;
             s.flux_part = c->flux_part.as<double>() + wav * kFluxPart;
             s.at_ew = c->at_ew.as<double4>() + 2 * o;
+            s.ufix = c->plan.iph ? c->ufix.as<uint4>() + o : nullptr;
             wav += blocks_for(s.n, 64);
             s.sc = c->scalars.as<DeviceScalars>() + r;
         }

@@ -62,6 +62,7 @@ __device__ inline DevSys global_view(DevSys s)
     s.cand_cnt = glob(s.cand_cnt), s.cand_idx = glob(s.cand_idx), s.bat_idx = glob(s.bat_idx);
     s.pair = glob(s.pair), s.sc = glob(s.sc), s.spc = glob(s.spc);
     s.pair_part = glob(s.pair_part), s.kin_part = glob(s.kin_part), s.vir_part = glob(s.vir_part);
+    s.ufix = glob(s.ufix);
     return s;
 }
 
@@ -645,7 +646,10 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     __shared__ int n_runs[8];
     __shared__ int total_sm;
     __shared__ int bad;
-    const int c = lb;
+    // block lb is part `part` of list cell c: the parts share the staging and
+    // take every list_parts-th group of work units
+    const int c = lb / s.list_parts;
+    const int part = lb - c * s.list_parts;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -922,7 +926,8 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             }
         }
     };
-    for (int unit = wave; unit < n_units; unit += kListBlock / 64) {
+    constexpr int kWaves = kListBlock / 64;
+    for (int unit = part * kWaves + wave; unit < n_units; unit += s.list_parts * kWaves) {
         int f = 0, g = unit;
         for (;; ++f) {
             const int nu = (lcnt[own_cell(f)] + kListA - 1) / kListA;
@@ -1592,7 +1597,32 @@ __device__ inline void sincos_turns_f32(double t, float& c, float& s)
 // order; MPL changes neither the per-mode summation order nor the result.
 // The mixed form sums the four FP32 products q cos, q sin of an iteration in
 // FP32 and adds that to the FP64 accumulators.
-template <bool MIXED, int MPL>
+// Fixed-point phase (IPH, mixed form): positions as 32-bit fractions of the
+// box u (k_fixpos), the phase m . u wraps exactly modulo 2^32 (one turn), and
+// its signed value times 2^-32 is the FP32 turn fed to the hardware sin/cos.
+__device__ inline float turns_fix(int mx, int my, int mz, const uint4& U)
+{
+    const uint32_t ph = (uint32_t)mx * U.x + (uint32_t)my * U.y + (uint32_t)mz * U.z;
+    return (float)(int32_t)ph * 2.3283064365386963e-10f;
+}
+
+__device__ inline uint32_t frac32(double f)
+{
+    // f in [0, 1]: floor(f 2^32), with 2^32 wrapping to 0 (the same turn)
+    return (uint32_t)(uint64_t)(f * 4294967296.0);
+}
+
+__global__ void k_fixpos(RB_ARGS)
+{
+    RB_SYS(blockIdx.x)
+    const int i = lb * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const double4 P = s.p[i];
+    s.ufix[i] = make_uint4(frac32(P.x * s.invL[0]), frac32(P.y * s.invL[1]), frac32(P.z * s.invL[2]),
+                           (uint32_t)s.type[i]);
+}
+
+template <bool MIXED, int MPL, bool IPH>
 __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict__ kd)
 {
     RB_SYS(blockIdx.x)
@@ -1612,6 +1642,7 @@ __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict_
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double sc = MIXED ? 1.0 : (double)kTableSize;
     double kx[MPL], ky[MPL], kz[MPL], re[MPL], im[MPL];
+    int mi[MPL][3];
 #pragma unroll
     for (int j = 0; j < MPL; ++j) {
         const int p = tile * 64 * MPL + 64 * j + lane;
@@ -1619,6 +1650,7 @@ __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict_
         kx[j] = mr.mx * (sc * s.invL[0]);
         ky[j] = mr.my * (sc * s.invL[1]);
         kz[j] = mr.mz * (sc * s.invL[2]);
+        for (int a = 0; a < 3; ++a) mi[j][a] = (IPH && p < k.n_modes) ? k.m[3 * p + a] : 0;
         re[j] = 0.0;
         im[j] = 0.0;
     }
@@ -1628,7 +1660,38 @@ __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict_
     const int a0 = chunk * k.chunk + wave * qw;
     const int a1 = min(s.n, a0 + qw);
     int a = a0;
-    for (; a + 4 <= a1; a += 4) {
+    if (IPH) {
+        for (; a + 4 <= a1; a += 4) {
+            const uint4 U0 = s.ufix[a], U1 = s.ufix[a + 1], U2 = s.ufix[a + 2], U3 = s.ufix[a + 3];
+            const qreal q0 = qs[U0.w], q1 = qs[U1.w], q2 = qs[U2.w], q3 = qs[U3.w];
+#pragma unroll
+            for (int j = 0; j < MPL; ++j) {
+                const float t0 = turns_fix(mi[j][0], mi[j][1], mi[j][2], U0);
+                const float t1 = turns_fix(mi[j][0], mi[j][1], mi[j][2], U1);
+                const float t2 = turns_fix(mi[j][0], mi[j][1], mi[j][2], U2);
+                const float t3 = turns_fix(mi[j][0], mi[j][1], mi[j][2], U3);
+                const float c0 = __builtin_amdgcn_cosf(t0), s0 = __builtin_amdgcn_sinf(t0);
+                const float c1 = __builtin_amdgcn_cosf(t1), s1 = __builtin_amdgcn_sinf(t1);
+                const float c2 = __builtin_amdgcn_cosf(t2), s2 = __builtin_amdgcn_sinf(t2);
+                const float c3 = __builtin_amdgcn_cosf(t3), s3 = __builtin_amdgcn_sinf(t3);
+                const float rs = fmaf(q3, c3, fmaf(q2, c2, fmaf(q1, c1, q0 * c0)));
+                const float is = fmaf(q3, s3, fmaf(q2, s2, fmaf(q1, s1, q0 * s0)));
+                re[j] += (double)rs;
+                im[j] += (double)is;
+            }
+        }
+        for (; a < a1; ++a) {
+            const uint4 U = s.ufix[a];
+            const qreal q = qs[U.w];
+#pragma unroll
+            for (int j = 0; j < MPL; ++j) {
+                const float t = turns_fix(mi[j][0], mi[j][1], mi[j][2], U);
+                re[j] += (double)(q * __builtin_amdgcn_cosf(t));
+                im[j] += (double)(q * __builtin_amdgcn_sinf(t));
+            }
+        }
+    }
+    for (; !IPH && a + 4 <= a1; a += 4) {
         const double4 P0 = s.p[a], P1 = s.p[a + 1], P2 = s.p[a + 2], P3 = s.p[a + 3];
         const int4 T = *reinterpret_cast<const int4*>(s.type + a);
         const qreal q0 = qs[T.x], q1 = qs[T.y], q2 = qs[T.z], q3 = qs[T.w];
@@ -1657,7 +1720,7 @@ __global__ __launch_bounds__(kBlock) void k_rho(RB_ARGS, const KDev* __restrict_
             }
         }
     }
-    for (; a < a1; ++a) {
+    for (; !IPH && a < a1; ++a) {
         const double4 P = s.p[a];
         const qreal q = qs[s.type[a]];
 #pragma unroll
@@ -1819,7 +1882,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
 // (k_e/2) q_i Re(e^{-i theta} rho_p) coef_p, and of its virial, that times
 // (delta_ab - g_p k_a k_b); with the pair kernel's shares and the final
 // velocity they give the stress and heat-flux partials of eqs. (50)-(51).
-template <bool MIXED, bool FUSED, bool KICK, int KE>
+template <bool MIXED, bool FUSED, bool KICK, int KE, bool IPH>
 __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restrict__ kd)
 {
     constexpr bool ENERGY = KE > 0;
@@ -1847,19 +1910,25 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
         double Gx = 0.0, Gy = 0.0, Gz = 0.0;
         // FLUX: sum_p Re(e^{-i theta} rho_p) coef_p, and that times g_p m_a m_b
         double Ek = 0.0, Txx = 0.0, Tyy = 0.0, Tzz = 0.0, Txy = 0.0, Txz = 0.0, Tyz = 0.0;
-        auto one = [&](const ModeRec& mr, double gm) {
-            const double t = mode_phase(mr.mx, mr.my, mr.mz, U);
+        const uint4 Uf = IPH ? s.ufix[i] : make_uint4(0, 0, 0, 0);
+        auto one = [&](const ModeRec& mr, int p, double gm) {
             double w, re = 0.0;
             if (MIXED) {
                 float c, sn;
-                sincos_turns_f32(t, c, sn);
+                if (IPH) {
+                    const float tf = turns_fix(k.m[3 * p], k.m[3 * p + 1], k.m[3 * p + 2], Uf);
+                    c = __builtin_amdgcn_cosf(tf);
+                    sn = __builtin_amdgcn_sinf(tf);
+                } else {
+                    sincos_turns_f32(mode_phase(mr.mx, mr.my, mr.mz, U), c, sn);
+                }
                 // Im(e^{-i theta} rho) * coef = c * A - s * B
                 w = (double)fmaf(c, mr.Af, -(sn * mr.Bf));
                 // Re(e^{-i theta} rho) * coef = c * B + s * A
                 if (FLUX) re = (double)fmaf(c, mr.Bf, sn * mr.Af);
             } else {
                 double c, sn;
-                sincos1024(t, tab, c, sn);
+                sincos1024(mode_phase(mr.mx, mr.my, mr.mz, U), tab, c, sn);
                 w = fma(c, mr.A, -(sn * mr.B));
                 if (FLUX) re = fma(c, mr.B, sn * mr.A);
             }
@@ -1882,10 +1951,10 @@ __global__ __launch_bounds__(kBlock) void k_kforce(RB_ARGS, const KDev* __restri
         for (; p + 2 <= k.n_modes; p += 2) {
             const ModeRec m0 = k.modes[p];
             const ModeRec m1 = k.modes[p + 1];
-            one(m0, FLUX ? k.mode_g[p] : 0.0);
-            one(m1, FLUX ? k.mode_g[p + 1] : 0.0);
+            one(m0, p, FLUX ? k.mode_g[p] : 0.0);
+            one(m1, p + 1, FLUX ? k.mode_g[p + 1] : 0.0);
         }
-        if (p < k.n_modes) one(k.modes[p], FLUX ? k.mode_g[p] : 0.0);
+        if (p < k.n_modes) one(k.modes[p], p, FLUX ? k.mode_g[p] : 0.0);
         const int ti = s.type[i];
         const double qk = -s.coulomb_k * s.spc->q[ti];
         if (!FUSED) {
@@ -2381,7 +2450,7 @@ void launch_lists(const Plan& P, bool gate, hipStream_t st)
     const int K = P.stored ? P.n_chunks : 1;
     const size_t sm_sel = sizeof(uint32_t) * (size_t)((P.cap_cand + 31) / 32) * 64;
     for (int k = 0; k < K; ++k) {
-        const Shape& cs = P.stored ? P.cell_chunk[k] : P.cells;
+        const Shape& cs = P.stored ? P.cell_chunk[k] : P.list_cells;
 #define RB_LISTS(C)                                                                                    \
     do {                                                                                               \
         if (P.species_cut)                                                                             \
@@ -2466,16 +2535,23 @@ void launch_rho(const Plan& P, bool mixed, hipStream_t st)
 {
     if (P.rho.blocks <= 0) return;
     const int nb = P.rho.blocks;
+    const bool iph = mixed && P.iph;
+    // fixed-point positions for this evaluation (read by the force kernel too)
+    if (iph && P.atoms.blocks > 0) k_fixpos<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms));
     if (P.tune.rho_mpl == 2) {
-        if (mixed)
-            k_rho<true, 2><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+        if (iph)
+            k_rho<true, 2, true><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+        else if (mixed)
+            k_rho<true, 2, false><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
         else
-            k_rho<false, 2><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+            k_rho<false, 2, false><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
     } else {
-        if (mixed)
-            k_rho<true, 1><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+        if (iph)
+            k_rho<true, 1, true><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+        else if (mixed)
+            k_rho<true, 1, false><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
         else
-            k_rho<false, 1><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
+            k_rho<false, 1, false><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);
     }
 }
 
@@ -2494,10 +2570,12 @@ void launch_kforce(const Plan& P, bool mixed, hipStream_t st)
     const int nb = P.kf_atoms.blocks;
     const int bs = P.tune.kf_block;
     if (nb <= 0) return;
-    if (mixed)
-        k_kforce<true, false, false, 0><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+    if (mixed && P.iph)
+        k_kforce<true, false, false, 0, true><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+    else if (mixed)
+        k_kforce<true, false, false, 0, false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
     else
-        k_kforce<false, false, false, 0><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
+        k_kforce<false, false, false, 0, false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);
 }
 
 void launch_kforce_fused(const Plan& P, bool mixed, bool kick, int ke, hipStream_t st)
@@ -2505,7 +2583,13 @@ void launch_kforce_fused(const Plan& P, bool mixed, bool kick, int ke, hipStream
     const int nb = P.kf_atoms.blocks;
     const int bs = P.tune.kf_block;
     if (nb <= 0) return;
-#define RB_KF(M, K, E) k_kforce<M, true, K, E><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd)
+#define RB_KF(M, K, E)                                                                  \
+    do {                                                                                \
+        if (M && P.iph)                                                                 \
+            k_kforce<M, true, K, E, M><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);      \
+        else                                                                            \
+            k_kforce<M, true, K, E, false><<<nb, bs, 0, st>>>(RB_MAP(kf_atoms), P.kd);  \
+    } while (0)
 #define RB_KF_KE(M, K)        \
     do {                      \
         if (ke == 2)          \

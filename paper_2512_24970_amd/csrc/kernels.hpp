@@ -59,6 +59,10 @@ struct DevSys {
     // chunk of cells at a time (n_chunks chunks, cand_rows rows).  Otherwise
     // n_chunks = 1 and cand_idx holds a row per atom.
     int shell_stored;
+    uint4* ufix;           // [n] positions as 32-bit fractions of the box and the type (integer phase)
+    // workgroups per list cell in the list build: a cell with many atoms (a
+    // small box that is one list cell per axis) is split over several
+    int list_parts;
     int n_chunks;
     int cand_rows;
     uint32_t replica;
@@ -173,6 +177,7 @@ struct Plan {
     Shape pair_atoms;  // tune.pair_block-atom blocks (pair kernel)
     Shape kf_atoms;    // tune.kf_block-atom blocks (k-space force kernel)
     Shape cells;    // one block per cell
+    Shape list_cells;  // list_parts blocks per cell (list build)
     Shape cell_chunk[kMaxListChunks];  // the cells of each build chunk (memory form)
     Shape rows64;   // 64-row blocks over each system's candidate rows (batch draw)
     Shape atom1;    // one block per atom (per-atom list kernel)
@@ -182,6 +187,7 @@ struct Plan {
     int list_mode = 0;  // < kListPerAtom: per-cell list kernel staging kListCaps[mode] atoms; else per-atom kernel
     bool stored = false;  // memory form: batch drawn at the build
     bool langevin = false;  // some system runs the Langevin thermostat
+    bool iph = false;       // mixed form: k-space phases in 32-bit fixed point
     bool species_cut = false;  // species-dependent core radii
     int n_chunks = 1;     // build chunks (1 unless stored)
     int cap_core = 0, cap_cand = 0;

@@ -20,6 +20,7 @@ MAX_SOG = 512
 FP64 = 0
 MIXED = 1
 FLAG_SHELL_STORED = 1  # shell batch drawn at the list build and kept (memory form)
+FLAG_INT_PHASE = 2     # mixed form: k-space phases in 32-bit fixed point
 THERMOSTATS = {"berendsen": 0, "nose_hoover": 1, "langevin": 2}
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_OOM", -5: "E_LIST_STALE",
@@ -171,7 +172,8 @@ def make_params(sysp: dict, precision: int = FP64, n_atoms: int | None = None) -
     p.precision = int(precision)
     p.seed = int(sysp["seed"])
     p.replica = int(sysp.get("replica", 0))
-    p.flags = FLAG_SHELL_STORED if sysp.get("shell_stored", False) else 0
+    p.flags = (FLAG_SHELL_STORED if sysp.get("shell_stored", False) else 0) | \
+        (FLAG_INT_PHASE if sysp.get("int_phase", False) else 0)
     p.coulomb_k = float(sysp["coulomb_k"])
     p.t_target = float(sysp.get("t_target", 0.0))
     p.tau_t = float(sysp.get("tau_t", 0.0))
