@@ -509,6 +509,8 @@ def main() -> int:
                     help="timed steps of the 5e6-ion leg (0: skip)")
     ap.add_argument("--shell-stored", type=int, default=0,
                     help="1: the main legs use the memory form of the list (shell batch drawn at the build)")
+    ap.add_argument("--int-phase-main", type=int, default=0,
+                    help="1: the main legs use the fixed-point k-space phase (mixed form only)")
     ap.add_argument("--stored", type=int, default=1,
                     help="1: also time the memory form of the list (shell batch drawn at the build) "
                          "on the 1e6-ion workload and, with --large-steps, on the 5e6-ion melt")
@@ -542,7 +544,9 @@ def main() -> int:
     cfg = W.config(args.workload)
     if args.shell_stored:
         cfg = dict(cfg, sys=dict(cfg["sys"], shell_stored=True))
-    wl_key = args.workload + ("_stored" if args.shell_stored else "")
+    if args.int_phase_main:
+        cfg = dict(cfg, sys=dict(cfg["sys"], int_phase=True))
+    wl_key = args.workload + ("_stored" if args.shell_stored else "") + ("_intphase" if args.int_phase_main else "")
     n = len(cfg["types"])
     _log(f"[bench] workload {args.workload}: N={n} inputs in {time.perf_counter() - t:.1f} s")
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]

@@ -192,6 +192,33 @@ def test_nacl32768_fp64_thousand_steps():
     assert np.isfinite(f.cpu().numpy()).all()
 
 
+def test_nacl32768_fp64_thousand_steps_plain_nve():
+    """The 32768-ion FP64 run as the workload states it: 1000 plain
+    velocity-Verlet steps of 1 fs (no thermostat), lists rebuilt every 10
+    steps.  The random batch estimators' force noise does work every step,
+    so the total energy is not conserved (Section 2.3 pairs random batch
+    methods in NVE with a weakly coupled bath for that reason); the run must
+    stay finite and rebuild on schedule, and the energy it gains shows as
+    heat: kinetic and potential energy both end above where they started."""
+    _say("case: nacl_32768 fp64 1000 plain nve steps")
+    cfg = W.config("nacl_32768")
+    ctx, _ = gpu_system(cfg, R.FP64)
+    n = len(cfg["types"])
+    e_first = None
+    for block in range(10):
+        e = ctx.rbsog_step(100)
+        T = 2 * e["kinetic"] / ((3 * n - 3) * W.KB)
+        if e_first is None:
+            e_first = e
+        _say(f"  after {100 * (block + 1)} steps: T {T:.1f} K, E {e['u_total'] + e['kinetic']:.2f} eV, "
+             f"builds {e['n_builds']}")
+        assert math.isfinite(e["u_total"]) and math.isfinite(e["kinetic"])
+    assert e["n_builds"] >= 100
+    assert e["kinetic"] > e_first["kinetic"] and e["u_total"] > e_first["u_total"]
+    _, _, f, _ = ctx.rbsog_get_state()
+    assert np.isfinite(f.cpu().numpy()).all()
+
+
 def test_forces_mixed_nacl32768():
     _say("case: forces mixed nacl_32768")
     cfg = W.config("nacl_32768")
