@@ -151,6 +151,8 @@ def run_gpu(cfg, precision: str, steps: int, warmup: int, tuning: str = "auto", 
     # per step; the paper runs NVT, here a Berendsen thermostat with tau = dt
     sysp = dict(cfg["sys"], t_target=cfg["T"], tau_t=cfg["sys"]["dt"] if tau is None else tau,
                 thermostat=thermostat)
+    if precision != "mixed":
+        sysp.pop("int_phase", None)  # an option of the mixed form
     p = R.make_params(sysp, prec, n_atoms=len(cfg["types"]))
     ctx.rbsog_set_system(p, torch.as_tensor(cfg["types"], device=dev), torch.as_tensor(cfg["pos"], device=dev),
                          torch.as_tensor(cfg["vel"], device=dev))
