@@ -587,15 +587,23 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
 // the (up to) 27 neighbouring list cells are staged in LDS and sorted there
 // by cell of the ordering grid (half the side, 6 x 6 x 6 of them around the
 // block's cell), stably, so the staged array is in canonical candidate order.
-// Each ordering cell of the block (2 x 2 x 2) then needs only the 5 x 5 x 5
-// ordering cells around it, which are a few dozen runs of the staged array;
-// a wavefront takes up to kListA atoms of one such cell and sweeps its runs,
-// one candidate per lane, testing every candidate against all its atoms and
-// compacting hits with ballots straight into the lists.
+// A wavefront takes up to kListA atoms of one of the block's ordering cells
+// (a unit) and makes two passes over the staged array.  The first keeps the
+// staged atoms inside a sphere around the unit: centred on the unit's
+// bounding box, of radius the largest list radius plus the distance to the
+// unit's farthest atom, so by the triangle inequality every list neighbour
+// of every atom of the unit is kept (a margin covers rounding).  The kept
+// positions go, in staged order, into a small queue of the wavefront in LDS.
+// Each time the queue holds 64 entries the second pass takes them, one per
+// lane, tests them against every atom of the unit with the exact FP64
+// distance of the lists, and compacts hits with ballots straight into the
+// lists.  The filter only decides which candidates get the exact test, so
+// the lists are the same bits as a sweep over every staged atom; about half
+// the candidates of the unit's 5 x 5 x 5 window of ordering cells survive it.
 constexpr int kListBlock = 512;
 constexpr int kRegion = 216;  // ordering cells staged per block, at most 6 x 6 x 6
-constexpr int kMaxRuns = 64;  // runs of window cells per ordering cell (<= 50)
-constexpr int kListA = 4;     // atoms per sweep
+constexpr int kListA = 4;     // atoms per unit
+constexpr int kQueue = 128;   // queue entries per wavefront (a power of two >= 128)
 
 __device__ inline int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -609,6 +617,15 @@ __device__ inline int mbcnt64(uint64_t m, int base = 0)
 __device__ inline int chunk_first_atom(const DevSys& s, int chunk)
 {
     return s.cell_start[(int)(((long long)chunk * s.ncell) / s.n_chunks)];
+}
+
+// A wave-uniform double, kept in scalar registers.
+__device__ inline double uniform_f64(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // PC: species-dependent core radii; staged indices then carry the species in
@@ -641,18 +658,14 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     __shared__ int cstart[kRegion];     // first staged position of each region cell
     __shared__ int rcell[kRegion];      // region cell of each rank (ascending global index)
     __shared__ int rstart[kRegion];     // first staged position of each rank
-    __shared__ int run_beg[8][kMaxRuns];
-    __shared__ int run_pre[8][kMaxRuns + 1];
-    __shared__ int n_runs[8];
+    __shared__ int16_t queue[kListBlock / 64][kQueue];
     __shared__ int total_sm;
-    __shared__ int bad;
     // block lb is part `part` of list cell c: the parts share the staging and
     // take every list_parts-th group of work units
     const int c = lb / s.list_parts;
     const int part = lb - c * s.list_parts;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int cx0 = c % s.nc[0];
     const int cy0 = (c / s.nc[0]) % s.nc[1];
     const int cz0 = c / (s.nc[0] * s.nc[1]);
@@ -663,7 +676,6 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     const int R0 = sx ? 6 : 1, R1 = sy ? 6 : 1, R2 = sz ? 6 : 1;
     const int R = R0 * R1 * R2;
     const int gx0 = sx ? 2 * cx0 - 2 : 0, gy0 = sy ? 2 * cy0 - 2 : 0, gz0 = sz ? 2 * cz0 - 2 : 0;
-    if (threadIdx.x == 0) bad = 0;
     // each region cell is a contiguous range of the sorted atoms: its list
     // cell's range, cut at the sub-cell bounds the cell sort recorded
     for (int q = threadIdx.x; q < R; q += blockDim.x) {
@@ -750,88 +762,23 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         const int fx = f % F0, fy = (f / F0) % F1, fz = f / (F0 * F1);
         return ((sz ? 2 + fz : 0) * R1 + (sy ? 2 + fy : 0)) * R0 + (sx ? 2 + fx : 0);
     };
-    // runs of the window (+-2 cells per split axis) of ordering cell `wave`,
-    // in rank order; consecutive ranks in the window form one run
-    if (wave < F) {
-        const int f = wave;
-        const int q0 = own_cell(f);
-        const int ox = q0 % R0, oy = (q0 / R0) % R1, oz = q0 / (R0 * R1);
-        uint64_t m[4];
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            const int r = ch * 64 + lane;
-            bool sel = false;
-            if (r < R) {
-                const int q = rcell[r];
-                const int lx = q % R0, ly = (q / R0) % R1, lz = q / (R0 * R1);
-                sel = abs(lx - ox) <= 2 && abs(ly - oy) <= 2 && abs(lz - oz) <= 2;
-            }
-            m[ch] = __ballot(sel);
-        }
-        int nb = 0;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            const uint64_t prev = (m[ch] << 1) | (ch > 0 ? (m[ch - 1] >> 63) : 0ull);
-            const uint64_t bm = m[ch] & ~prev;
-            const int r = ch * 64 + lane;
-            if ((bm >> lane) & 1ull) {
-                const int k = nb + __popcll(bm & below);
-                if (k < kMaxRuns) run_beg[f][k] = cstart[rcell[r]];
-            }
-            nb += __popcll(bm);
-        }
-        // run ends: the first sorted position after the last window rank of the run
-        int ne = 0;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            const uint64_t next = (m[ch] >> 1) | (ch < 3 ? (m[ch + 1] << 63) : 0ull);
-            const uint64_t em = m[ch] & ~next;
-            const int r = ch * 64 + lane;
-            if ((em >> lane) & 1ull) {
-                const int k = ne + __popcll(em & below);
-                const int q = rcell[r];
-                if (k < kMaxRuns) run_pre[f][k + 1] = cstart[q] + lcnt[q];  // run end for now
-            }
-            ne += __popcll(em);
-        }
-        if (nb > kMaxRuns && lane == 0) bad = 1;
-        // lengths -> prefix (one chunk: nb <= 64)
-        const int k = lane;
-        const int len = k < min(nb, kMaxRuns) ? run_pre[f][k + 1] - run_beg[f][k] : 0;
-        int x = len;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (k < min(nb, kMaxRuns)) run_pre[f][k + 1] = x;
-        if (lane == 0) {
-            run_pre[f][0] = 0;
-            n_runs[f] = min(nb, kMaxRuns);
-        }
-    }
-    __syncthreads();
-    if (bad) {
-        if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 4);
-        return;
-    }
     // With at least 5 list cells along every axis and no stencil cell across
     // the box edge, every |d| < 2 L/n_c <= 0.4 L, so rint(d/L) = 0 and the
     // minimum image leaves d unchanged: skipping it gives the same bits.
     const bool interior = s.nc[0] >= 5 && s.nc[1] >= 5 && s.nc[2] >= 5 && cx0 > 0 && cx0 < s.nc[0] - 1 &&
                           cy0 > 0 && cy0 < s.nc[1] - 1 && cz0 > 0 && cz0 < s.nc[2] - 1;
+    // largest list radius: the candidate bound, or a longer core radius
+    double rl2 = fmax(s.hi2_list, s.rc2_list);
+    if (PC)
+        for (int t = 0; t < s.n_species * s.n_species; ++t) rl2 = fmax(rl2, thr[t].x);
+    const double r_list = sqrt(rl2);
     // work units: (ordering cell f, group of kListA of its atoms), dealt to
     // the wavefronts in turn
     int n_units = 0;
     for (int f = 0; f < F; ++f) n_units += (lcnt[own_cell(f)] + kListA - 1) / kListA;
     const int cmax = s.cap_core - 1, kmax = s.cap_cand - 1;
-    // One unit: its atoms against the ordering cell's window, 64 window
-    // entries at a time.  An empty lane (past the window) and a missing atom
-    // of the unit sit at infinity, so every distance test fails for them
-    // (inf or NaN compare false); the atom itself is excluded by its staged
-    // index.  Hit masks come straight from the compares; a lane's slot is
-    // the row count plus its rank among the hits below it.
-    auto sweep = [&](auto interior_tag, int f, int a0, int na) {
+    int16_t* qw = queue[wave];
+    auto sweep = [&](auto interior_tag, int a0, int na) {
         constexpr bool INTERIOR = decltype(interior_tag)::value;
         double xu[kListA], yu[kListA], zu[kListA];
         int tu[kListA], ncore[kListA], ncand[kListA];
@@ -839,13 +786,18 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         int32_t* ccol[kListA];
         const int v0 = __builtin_amdgcn_readfirstlane(val[a0]);
         const int i0 = PC ? v0 & kIdxMask : v0;
+        double blo[3] = {px[a0], py[a0], pz[a0]};
+        double bhi[3] = {blo[0], blo[1], blo[2]};
 #pragma unroll
         for (int u = 0; u < kListA; ++u) {
             const bool here = u < na;
             const int a = here ? a0 + u : a0;
-            xu[u] = here ? px[a] : __builtin_inf();
-            yu[u] = py[a];
-            zu[u] = pz[a];
+            xu[u] = uniform_f64(here ? px[a] : __builtin_inf());
+            yu[u] = uniform_f64(py[a]);
+            zu[u] = uniform_f64(pz[a]);
+            blo[0] = fmin(blo[0], px[a]), bhi[0] = fmax(bhi[0], px[a]);
+            blo[1] = fmin(blo[1], yu[u]), bhi[1] = fmax(bhi[1], yu[u]);
+            blo[2] = fmin(blo[2], zu[u]), bhi[2] = fmax(bhi[2], zu[u]);
             const int va = __builtin_amdgcn_readfirstlane(val[a]);
             tu[u] = (PC && here) ? va >> kIdxBits : 0;
             // a missing atom sweeps into the rows of the unit's first atom,
@@ -856,18 +808,24 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             ncore[u] = 0;
             ncand[u] = 0;
         }
-        const int* rb = run_beg[f];
-        const int* rp = run_pre[f];
-        const int W = rp[n_runs[f]];  // window size
-        int k = 0;                    // run cursor of this lane
-        for (int t0 = 0; t0 < W; t0 += 64) {
-            const int t = t0 + lane;
-            const bool in = t < W;
-            int idx = 0;
-            if (in) {
-                while (rp[k + 1] <= t) ++k;
-                idx = rb[k] + (t - rp[k]);
+        // filter sphere of the unit (the atoms sit inside one ordering cell,
+        // so the box is at most half a list cell per axis)
+        const double cx = uniform_f64(0.5 * (blo[0] + bhi[0])), cy = uniform_f64(0.5 * (blo[1] + bhi[1])),
+                     cz = uniform_f64(0.5 * (blo[2] + bhi[2]));
+        double ru2 = 0.0;
+#pragma unroll
+        for (int u = 0; u < kListA; ++u) {
+            if (u < na) {
+                const double ex = xu[u] - cx, ey = yu[u] - cy, ez = zu[u] - cz;
+                ru2 = fmax(ru2, ex * ex + ey * ey + ez * ez);
             }
+        }
+        const double rf = r_list + sqrt(ru2) + 1e-6 * (r_list + 1.0);
+        const double rf2 = uniform_f64(rf * rf);
+        // exact tests of queue entries [qh, qh + cnt) against the unit
+        auto test_chunk = [&](int qh, int cnt) {
+            const bool in = lane < cnt;
+            const int idx = in ? (int)qw[(qh + lane) & (kQueue - 1)] : 0;
             const int vj = val[idx];
             const int j = PC ? vj & kIdxMask : vj;
             const int tj = PC ? vj >> kIdxBits : 0;
@@ -908,7 +866,36 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
                 ncore[u] += __popcll(mc);
                 ncand[u] += __popcll(mk);
             }
+        };
+        // first pass: keep the staged atoms inside the sphere, in staged
+        // order; the queue never holds more than 127 entries (at most 63 left
+        // over plus 64 new), so no entry is overwritten before it is tested
+        int qn = 0, qh = 0;
+        for (int t0 = 0; t0 < total; t0 += 64) {
+            const int t = t0 + lane;
+            bool keep = false;
+            if (t < total) {
+                double dx = cx - px[t], dy = cy - py[t], dz = cz - pz[t];
+                if (!INTERIOR) {
+                    dx = min_image(dx, s.L[0], s.invL[0]);
+                    dy = min_image(dy, s.L[1], s.invL[1]);
+                    dz = min_image(dz, s.L[2], s.invL[2]);
+                }
+                keep = (dx * dx + dy * dy) + dz * dz < rf2;
+            }
+            const uint64_t mq = __builtin_amdgcn_ballot_w64(keep);
+            if (keep) qw[(qn + mbcnt64(mq)) & (kQueue - 1)] = (int16_t)t;
+            qn += __popcll(mq);
+            // a wavefront's LDS accesses complete in order; the barrier keeps
+            // the compiler from moving the queue reads above the writes
+            __builtin_amdgcn_wave_barrier();
+            if (qn - qh >= 64) {
+                test_chunk(qh, 64);
+                qh += 64;
+                __builtin_amdgcn_wave_barrier();
+            }
         }
+        if (qn > qh) test_chunk(qh, qn - qh);
 #pragma unroll
         for (int u = 0; u < kListA; ++u) {
             if (lane == 0 && u < na) {
@@ -938,9 +925,9 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         const int a0 = cstart[q0] + g * kListA;
         const int na = min(kListA, cstart[q0] + lcnt[q0] - a0);
         if (interior)
-            sweep(std::true_type{}, f, a0, na);
+            sweep(std::true_type{}, a0, na);
         else
-            sweep(std::false_type{}, f, a0, na);
+            sweep(std::false_type{}, a0, na);
     }
 }
 
