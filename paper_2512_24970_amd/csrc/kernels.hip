@@ -602,7 +602,7 @@ __global__ __launch_bounds__(64) void k_lists(RB_ARGS, int gate)
 // the candidates of the unit's 5 x 5 x 5 window of ordering cells survive it.
 constexpr int kListBlock = 512;
 constexpr int kRegion = 216;  // ordering cells staged per block, at most 6 x 6 x 6
-constexpr int kListA = 4;     // atoms per unit
+constexpr int kListA = 8;     // atoms per unit
 constexpr int kQueue = 128;   // queue entries per wavefront (a power of two >= 128)
 
 __device__ inline int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
