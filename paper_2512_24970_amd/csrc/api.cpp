@@ -757,7 +757,7 @@ void autotune(rbsog_ctx* c, int reps)
     // steps from one saved device state (atoms, list counts, lists and
     // scalars), which is put back afterwards: tuning leaves the trajectory
     // bit for bit as it was.  Alternating rounds, best of three.
-    DBuf* state[] = {&c->atoms, &c->counts, &c->lists_core, &c->lists_cand, &c->lists_bat, &c->scalars};
+    DBuf* state[] = {&c->atoms, &c->ufix, &c->counts, &c->lists_core, &c->lists_cand, &c->lists_bat, &c->scalars};
     constexpr int kState = sizeof(state) / sizeof(state[0]);
     std::unique_ptr<DBuf[]> saved(new DBuf[kState]);
     auto copy_state = [&](bool save) {
@@ -857,6 +857,14 @@ void init_devsys(const rbsog_params& p, int n, DevSys& s)
     s.hi2_list = hi * hi;
     s.rc2 = p.r_core * p.r_core;
     s.rs2 = p.r_shell * p.r_shell;
+    {
+        // A coordinate of a fixed-point record is within d = L 2^-32 below
+        // the true one, so a difference is within d of the FP64 minimum
+        // image and r^2 within 2 sqrt(3) r d + 3 d^2; at the cutoffs (r <=
+        // r_shell) that is below the guard, kept at four times the bound.
+        const double d = std::max(p.box[0], std::max(p.box[1], p.box[2])) * std::ldexp(1.0, -32);
+        s.fix_guard = 4.0 * (2.0 * std::sqrt(3.0) * p.r_shell * d + 3.0 * d * d) + 1e-12 * s.rs2;
+    }
     s.half_skin2 = 0.25 * p.skin * p.skin;
     // A list entry was within r_shell + skin at the build and both atoms
     // have moved at most skin/2 since, so it is now within M = r_shell +
@@ -1030,10 +1038,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
     c->flux_part.alloc(sizeof(double) * kFluxPart * std::max<size_t>(1, n_waves));
     c->at_ew.alloc(sizeof(double4) * 2 * N);
-    if (c->plan.iph)
-        c->ufix.alloc(sizeof(uint4) * N);
-    else
-        c->ufix.release();
+    c->ufix.alloc(sizeof(uint4) * N);
     c->scalars.alloc(sizeof(DeviceScalars) * R);
     HIP_OK(hipMemsetAsync(c->scalars.p, 0, sizeof(DeviceScalars) * R, c->stream));
     {
@@ -1079,7 +1084,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             s.kin_part = c->kin_part.as<double>() + wav;
             s.flux_part = c->flux_part.as<double>() + wav * kFluxPart;
             s.at_ew = c->at_ew.as<double4>() + 2 * o;
-            s.ufix = c->plan.iph ? c->ufix.as<uint4>() + o : nullptr;
+            s.ufix = c->ufix.as<uint4>() + o;
             wav += blocks_for(s.n, 64);
             s.sc = c->scalars.as<DeviceScalars>() + r;
         }

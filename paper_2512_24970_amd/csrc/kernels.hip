@@ -152,6 +152,21 @@ __device__ inline int fine_cell(const DevSys& s, const double4& P)
     return (fz * s.nf[1] + fy) * s.nf[0] + fx;
 }
 
+// Fixed-point record of a wrapped position: floor(x/L 2^32) per axis (a
+// fraction of the box, 2^32 wrapping to 0: the same point) and the type.
+// The 32-bit difference of two records, read as signed, is the minimum
+// image of their displacement in units of L 2^-32.
+__device__ inline uint32_t frac32(double f)
+{
+    // f in [0, 1]: floor(f 2^32), with 2^32 wrapping to 0 (the same turn)
+    return (uint32_t)(uint64_t)(f * 4294967296.0);
+}
+
+__device__ inline uint4 fix_record(const DevSys& s, double x, double y, double z, double type)
+{
+    return make_uint4(frac32(x * s.invL[0]), frac32(y * s.invL[1]), frac32(z * s.invL[2]), (uint32_t)type);
+}
+
 // One flag write per wavefront holding a non-finite value (every lane of the
 // wavefront calls it).
 __device__ inline void flag_nonfinite(bool bad, DeviceScalars* sc)
@@ -442,6 +457,7 @@ __global__ void k_gather(RB_ARGS, int gate)
     const int o = s.order[t];
     const double4 P = s.tp[o];
     s.p[t] = P;
+    s.ufix[t] = fix_record(s, P.x, P.y, P.z, P.w);
     s.xr[t] = P.x;
     s.yr[t] = P.y;
     s.zr[t] = P.z;
@@ -1142,9 +1158,10 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
     // inside every face (inner_lo <= x <= inner_hi) has no list neighbour
     // across the box edge: each stored difference already is the minimum
     // image (|d| < 0.4 L, so rint(d / L) = 0) and the wrap is skipped, with
-    // the same bits.
+    // the same bits (FP64 form; the mixed form gathers fixed-point records,
+    // whose differences wrap by themselves).
     bool inner = true;
-    if (i < s.n) {
+    if (!MIXED && i < s.n) {
         const double4 Pi = s.p[i];
         inner = Pi.x >= s.inner_lo[0] && Pi.x <= s.inner_hi[0] && Pi.y >= s.inner_lo[1] && Pi.y <= s.inner_hi[1] &&
                 Pi.z >= s.inner_lo[2] && Pi.z <= s.inner_hi[2];
@@ -1157,6 +1174,9 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
         const double4 Pi = s.p[i];
         const double xi = Pi.x, yi = Pi.y, zi = Pi.z;
         const int ti = s.type[i];
+        const uint4 Ui = MIXED ? s.ufix[i] : make_uint4(0u, 0u, 0u, 0u);
+        // fixed-point units per axis (L 2^-32, exact)
+        const double ux = s.L[0] * 0x1p-32, uy = s.L[1] * 0x1p-32, uz = s.L[2] * 0x1p-32;
         // pair force scalar for r2 of species pair (ti, tj)
         auto pair_f = [&](int tj, double r2, double& u) -> double {
             const int t = ti * S + tj;
@@ -1168,25 +1188,49 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
             }
             return pair_scalar_f64<J, ENERGY>(pc[t], g, r2, u);
         };
-        // Neighbours are fetched kU at a time (indices, then positions and
-        // types) before any arithmetic, so the gathers overlap; the sums still
-        // run in list order.  Core-list lines are read once: non-temporal
-        // loads keep them from evicting the positions that neighbours re-read
-        // (a candidate row is re-read by its own lane, so it stays cached).
-        constexpr int kU = KU;
-        if (!shell) {
-            // core sum, eq. (24)
-            const int nc = min(s.core_cnt[i], s.cap_core - 1);
-            const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
-            for (int k0 = 0; k0 < nc; k0 += kU) {
-                int jj[kU];
-                double X[kU], Y[kU], Z[kU];
-                int T[kU];
+        // Neighbours jj[0..kU) (entries k0.. of a list of cnt; padding past
+        // cnt) are fetched before any arithmetic, so the gathers overlap; the
+        // sums still run in list order.  SH: the shell test r_core^2 <= r^2 <
+        // r_shell^2, else the core test r^2 < r_core^2, each decided on the
+        // FP64 minimum image.  The mixed form reads a neighbour's 16-byte
+        // fixed-point record (one load instead of two for the FP64 one): the
+        // record differences give r^2 within fix_guard of the FP64 value, and
+        // the rare pair that close to a cutoff is decided (and evaluated)
+        // from the FP64 positions, so the pair set is the FP64 one.
+        auto visit = [&](auto shell_tag, const int* jj, int k0, int cnt, double& Ax, double& Ay, double& Az,
+                         double& Au) {
+            constexpr bool SH = decltype(shell_tag)::value;
+            if (MIXED) {
+                uint4 Q[KU];
 #pragma unroll
-                for (int u = 0; u < kU; ++u)
-                    jj[u] = (k0 + u < nc) ? __builtin_nontemporal_load(ctile + (size_t)(k0 + u) * 64) : i;
+                for (int u = 0; u < KU; ++u) Q[u] = s.ufix[jj[u]];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
+                for (int u = 0; u < KU; ++u) {
+                    if (k0 + u >= cnt) break;
+                    double dx = (double)(int32_t)(Ui.x - Q[u].x) * ux;
+                    double dy = (double)(int32_t)(Ui.y - Q[u].y) * uy;
+                    double dz = (double)(int32_t)(Ui.z - Q[u].z) * uz;
+                    double r2 = (dx * dx + dy * dy) + dz * dz;
+                    const int tj = (int)Q[u].w;
+                    const double rc2 = s.species_cut ? rc2s[ti * S + tj] : s.rc2;
+                    if (fabs(r2 - rc2) <= s.fix_guard || (SH && fabs(r2 - s.rs2) <= s.fix_guard)) {
+                        const double4 Q64 = s.p[jj[u]];
+                        dx = min_image(xi - Q64.x, s.L[0], s.invL[0]);
+                        dy = min_image(yi - Q64.y, s.L[1], s.invL[1]);
+                        dz = min_image(zi - Q64.z, s.L[2], s.invL[2]);
+                        r2 = (dx * dx + dy * dy) + dz * dz;
+                    }
+                    if (SH ? (r2 >= rc2 && r2 < s.rs2) : (r2 < rc2)) {
+                        double uu = 0.0;
+                        const double f = pair_f(tj, r2, uu);
+                        add_pair<ENERGY>(f, uu, dx, dy, dz, Ax, Ay, Az, Au, Wv);
+                    }
+                }
+            } else {
+                double X[KU], Y[KU], Z[KU];
+                int T[KU];
+#pragma unroll
+                for (int u = 0; u < KU; ++u) {
                     const double4 Q = s.p[jj[u]];
                     X[u] = Q.x;
                     Y[u] = Q.y;
@@ -1194,18 +1238,35 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     T[u] = (int)Q.w;
                 }
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    if (k0 + u >= nc) break;
+                for (int u = 0; u < KU; ++u) {
+                    if (k0 + u >= cnt) break;
                     const double dx = mi(xi - X[u], 0);
                     const double dy = mi(yi - Y[u], 1);
                     const double dz = mi(zi - Z[u], 2);
                     const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2)) {
+                    const double rc2 = s.species_cut ? rc2s[ti * S + T[u]] : s.rc2;
+                    if (SH ? (r2 >= rc2 && r2 < s.rs2) : (r2 < rc2)) {
                         double uu = 0.0;
                         const double f = pair_f(T[u], r2, uu);
-                        add_pair<ENERGY>(f, uu, dx, dy, dz, Fx, Fy, Fz, Uc, Wv);
+                        add_pair<ENERGY>(f, uu, dx, dy, dz, Ax, Ay, Az, Au, Wv);
                     }
                 }
+            }
+        };
+        // Core-list lines are read once: non-temporal loads keep them from
+        // evicting the positions that neighbours re-read (a candidate row is
+        // re-read by its own lane, so it stays cached).
+        constexpr int kU = KU;
+        if (!shell) {
+            // core sum, eq. (24)
+            const int nc = min(s.core_cnt[i], s.cap_core - 1);
+            const int32_t* ctile = s.core_idx + (size_t)(i >> 6) * s.cap_core * 64 + (i & 63);
+            for (int k0 = 0; k0 < nc; k0 += kU) {
+                int jj[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    jj[u] = (k0 + u < nc) ? __builtin_nontemporal_load(ctile + (size_t)(k0 + u) * 64) : i;
+                visit(std::false_type{}, jj, k0, nc, Fx, Fy, Fz, Uc);
             }
         } else if (s.shell_stored) {
             // shell batch of eq. (25) drawn at the list build: a tile row per
@@ -1217,32 +1278,10 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
             const int32_t* btile = s.bat_idx + (size_t)(i >> 6) * s.p_r * 64 + (i & 63);
             for (int k0 = 0; k0 < cnt; k0 += kU) {
                 int jj[kU];
-                double X[kU], Y[kU], Z[kU];
-                int T[kU];
 #pragma unroll
                 for (int u = 0; u < kU; ++u)
                     jj[u] = (k0 + u < cnt) ? __builtin_nontemporal_load(btile + (size_t)(k0 + u) * 64) : i;
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const double4 Q = s.p[jj[u]];
-                    X[u] = Q.x;
-                    Y[u] = Q.y;
-                    Z[u] = Q.z;
-                    T[u] = (int)Q.w;
-                }
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    if (k0 + u >= cnt) break;
-                    const double dx = mi(xi - X[u], 0);
-                    const double dy = mi(yi - Y[u], 1);
-                    const double dz = mi(zi - Z[u], 2);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 >= (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2) && r2 < s.rs2) {
-                        double uu = 0.0;
-                        const double f = pair_f(T[u], r2, uu);
-                        add_pair<ENERGY>(f, uu, dx, dy, dz, Sx, Sy, Sz, Su, Wv);
-                    }
-                }
+                visit(std::true_type{}, jj, k0, cnt, Sx, Sy, Sz, Su);
             }
         } else {
             // shell batch, eq. (25)
@@ -1263,8 +1302,6 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
             uint32_t m_cur = take_all ? 0u : fm.m[0];
             for (int k0 = 0; k0 < cnt; k0 += kU) {
                 int jj[kU];
-                double X[kU], Y[kU], Z[kU];
-                int T[kU];
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     int e = 0;
@@ -1279,32 +1316,12 @@ __global__ __launch_bounds__(2 * kBlock) void k_pair(RB_ARGS, SogCoef g, SogCoef
                     }
                     jj[u] = (k0 + u < cnt) ? crow[e] : i;
                 }
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const double4 Q = s.p[jj[u]];
-                    X[u] = Q.x;
-                    Y[u] = Q.y;
-                    Z[u] = Q.z;
-                    T[u] = (int)Q.w;
-                }
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    if (k0 + u >= cnt) break;
-                    const double dx = mi(xi - X[u], 0);
-                    const double dy = mi(yi - Y[u], 1);
-                    const double dz = mi(zi - Z[u], 2);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 >= (s.species_cut ? rc2s[ti * S + T[u]] : s.rc2) && r2 < s.rs2) {
-                        double uu = 0.0;
-                        const double f = pair_f(T[u], r2, uu);
-                        add_pair<ENERGY>(f, uu, dx, dy, dz, Sx, Sy, Sz, Su, Wv);
-                    }
-                }
+                visit(std::true_type{}, jj, k0, cnt, Sx, Sy, Sz, Su);
             }
         }
     }
     };
-    if (wave_inner)
+    if (MIXED || wave_inner)
         body(std::true_type{});
     else
         body(std::false_type{});
@@ -1585,28 +1602,12 @@ __device__ inline void sincos_turns_f32(double t, float& c, float& s)
 // The mixed form sums the four FP32 products q cos, q sin of an iteration in
 // FP32 and adds that to the FP64 accumulators.
 // Fixed-point phase (IPH, mixed form): positions as 32-bit fractions of the
-// box u (k_fixpos), the phase m . u wraps exactly modulo 2^32 (one turn), and
+// box u (the fixed-point records), the phase m . u wraps exactly modulo 2^32 (one turn), and
 // its signed value times 2^-32 is the FP32 turn fed to the hardware sin/cos.
 __device__ inline float turns_fix(int mx, int my, int mz, const uint4& U)
 {
     const uint32_t ph = (uint32_t)mx * U.x + (uint32_t)my * U.y + (uint32_t)mz * U.z;
     return (float)(int32_t)ph * 2.3283064365386963e-10f;
-}
-
-__device__ inline uint32_t frac32(double f)
-{
-    // f in [0, 1]: floor(f 2^32), with 2^32 wrapping to 0 (the same turn)
-    return (uint32_t)(uint64_t)(f * 4294967296.0);
-}
-
-__global__ void k_fixpos(RB_ARGS)
-{
-    RB_SYS(blockIdx.x)
-    const int i = lb * blockDim.x + threadIdx.x;
-    if (i >= s.n) return;
-    const double4 P = s.p[i];
-    s.ufix[i] = make_uint4(frac32(P.x * s.invL[0]), frac32(P.y * s.invL[1]), frac32(P.z * s.invL[2]),
-                           (uint32_t)s.type[i]);
 }
 
 template <bool MIXED, int MPL, bool IPH>
@@ -2170,6 +2171,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(RB_ARGS, int scheduled)
         const double y = wrap_coord(py, s.L[1], s.invL[1]);
         const double z = wrap_coord(pz, s.L[2], s.invL[2]);
         s.p[i] = make_double4(x, y, z, P.w);
+        s.ufix[i] = fix_record(s, x, y, z, P.w);
         bad = !finite3(x, y, z);
         const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
         const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
@@ -2367,7 +2369,9 @@ __global__ void k_set_pos(RB_ARGS, const double* pos)
         const double x = wrap_coord(pos[3 * u], s.L[0], s.invL[0]);
         const double y = wrap_coord(pos[3 * u + 1], s.L[1], s.invL[1]);
         const double z = wrap_coord(pos[3 * u + 2], s.L[2], s.invL[2]);
-        s.p[i] = make_double4(x, y, z, s.p[i].w);
+        const double w = s.p[i].w;
+        s.p[i] = make_double4(x, y, z, w);
+        s.ufix[i] = fix_record(s, x, y, z, w);
         const double dx = min_image(x - s.xr[i], s.L[0], s.invL[0]);
         const double dy = min_image(y - s.yr[i], s.L[1], s.invL[1]);
         const double dz = min_image(z - s.zr[i], s.L[2], s.invL[2]);
@@ -2523,8 +2527,6 @@ void launch_rho(const Plan& P, bool mixed, hipStream_t st)
     if (P.rho.blocks <= 0) return;
     const int nb = P.rho.blocks;
     const bool iph = mixed && P.iph;
-    // fixed-point positions for this evaluation (read by the force kernel too)
-    if (iph && P.atoms.blocks > 0) k_fixpos<<<P.atoms.blocks, kBlock, 0, st>>>(RB_MAP(atoms));
     if (P.tune.rho_mpl == 2) {
         if (iph)
             k_rho<true, 2, true><<<nb, kBlock, 0, st>>>(RB_MAP(rho), P.kd);

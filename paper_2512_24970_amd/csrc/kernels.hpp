@@ -39,6 +39,9 @@ struct DevSys {
     double two_pi_L[3];
     double rc2_list, lo2_list, hi2_list;  // (r_core+skin)^2, (r_core-skin)^2, (r_shell+skin)^2
     double rc2, rs2;                      // r_core^2, r_shell^2
+    // bound on |r^2 from the fixed-point records - r^2 of the FP64 minimum
+    // image| (A^2): pairs closer than this to a cutoff are decided in FP64
+    double fix_guard;
     int species_cut;       // core radii differ between species pairs (PairCoef rc2, rc2_list, lo2_list)
     double half_skin2;
     // atoms with inner_lo <= x <= inner_hi on every axis have no list
@@ -59,7 +62,10 @@ struct DevSys {
     // chunk of cells at a time (n_chunks chunks, cand_rows rows).  Otherwise
     // n_chunks = 1 and cand_idx holds a row per atom.
     int shell_stored;
-    uint4* ufix;           // [n] positions as 32-bit fractions of the box and the type (integer phase)
+    // [n] positions as 32-bit fractions of the box (floor(x/L 2^32)) and the
+    // type, rewritten wherever p is: the 16-byte neighbour records of the
+    // mixed pair kernel and the integer k-space phase
+    uint4* ufix;
     // workgroups per list cell in the list build: a cell with many atoms (a
     // small box that is one list cell per axis) is split over several
     int list_parts;
