@@ -104,6 +104,7 @@ struct rbsog_ctx {
     // memory form of the list: build chunks asked for, and the headroom of the
     // candidate scratch over a chunk's expected atom count
     int list_chunks = 8;
+    std::vector<int> list_mode_r;    // staging class of each system (kListPerAtom: per-atom kernel)
     double row_slack = 1.25;
     DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, vir_part, kin_part, export_tmp, snap, sogk, neartab;
     DBuf flux_part, at_ew, ufix;
@@ -323,6 +324,10 @@ Plan one(const rbsog_ctx* c, int r)
     P.modes1.blocks = s.n > 0 ? k.n_modes : 0;
     P.rows64.blocks = (s.n > 0 && s.shell_stored) ? blocks_for(s.cand_rows, 64) : 0;
     P.list_mode = c->plan.list_mode;
+    if (P.list_mode < kListPerAtom && r < (int)c->list_mode_r.size()) {
+        P.list_mode = c->list_mode_r[r];
+        if (P.list_mode < kListPerAtom) P.list_by_cap[P.list_mode] = P.list_cells;
+    }
     P.stored = c->plan.stored;
     P.n_chunks = c->plan.n_chunks;
     P.cap_core = c->plan.cap_core;
@@ -346,15 +351,18 @@ void plan_launches(rbsog_ctx* c)
     P.kd = c->d_kd.as<KDev>();
     P.sc = c->scalars.as<DeviceScalars>();
     P.R = c->R;
-    constexpr int kShapes = 10;
-    Shape* dst[kShapes] = {&P.atoms, &P.pair_atoms, &P.kf_atoms, &P.cells, &P.atom1,
-                           &P.modes64, &P.rho, &P.modes1, &P.rows64, &P.list_cells};
+    constexpr int kShapes = 10 + kListPerAtom;
+    Shape* dst[kShapes] = {&P.atoms, &P.pair_atoms, &P.kf_atoms, &P.cells, &P.atom1, &P.modes64, &P.rho,
+                           &P.modes1, &P.rows64, &P.list_cells, &P.list_by_cap[0], &P.list_by_cap[1],
+                           &P.list_by_cap[2]};
+    static_assert(kListPerAtom == 3, "one staging-class shape per capacity");
     std::vector<std::vector<int2>> m(kShapes + kMaxListChunks);
     const bool maps = c->R > 1;
     for (int r = 0; r < c->R; ++r) {
         const Plan o = one(c, r);
-        const Shape* sh[kShapes] = {&o.atoms, &o.pair_atoms, &o.kf_atoms, &o.cells, &o.atom1,
-                                    &o.modes64, &o.rho, &o.modes1, &o.rows64, &o.list_cells};
+        const Shape* sh[kShapes] = {&o.atoms, &o.pair_atoms, &o.kf_atoms, &o.cells, &o.atom1, &o.modes64, &o.rho,
+                                    &o.modes1, &o.rows64, &o.list_cells, &o.list_by_cap[0], &o.list_by_cap[1],
+                                    &o.list_by_cap[2]};
         for (int q = 0; q < kShapes; ++q) {
             if (maps)
                 for (int b = 0; b < sh[q]->blocks; ++b) m[q].push_back(make_int2(r, b));
@@ -520,7 +528,16 @@ void grow_after_overflow(rbsog_ctx* c, int o)
         cap_cand = std::max(cap_cand, round_up(mk + mk / 4 + 8, 32));
         require(cap_cand <= 4096 && cap_core <= 4096, RBSOG_E_CAPACITY, "neighbour list capacity above 4096");
     }
-    if (o & 4) c->plan.list_mode = std::min(kListPerAtom, c->plan.list_mode + 1);
+    if (o & 4) {
+        // the systems whose stencil did not fit move to the next capacity
+        const auto h = read_scalars(c);
+        for (int r = 0; r < c->R; ++r)
+            if (h[r].overflow & 4) c->list_mode_r[r] = std::min(kListPerAtom, c->list_mode_r[r] + 1);
+        // the memory form and the per-atom kernel take the largest for all
+        int m = 0;
+        for (int v : c->list_mode_r) m = std::max(m, v);
+        c->plan.list_mode = m;
+    }
     if (o & 8) c->row_slack *= 2.0;
     plan_lists(c, cap_core, cap_cand);
     plan_launches(c);
@@ -1130,6 +1147,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     // list capacities from the densest system; the list kernel from the
     // largest stencil
     int cap_core = 32, cap_cand = 32, list_mode = 0, n_max = 0;
+    c->list_mode_r.assign(R, 0);
     for (int r = 0; r < R; ++r) {
         const rbsog_params& p = prm[r];
         const DevSys& s = c->hs[r];
@@ -1165,6 +1183,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
         for (int q = kListPerAtom - 1; q >= 0; --q)
             if (need <= kListCaps[q]) mode = q;
         list_mode = std::max(list_mode, mode);
+        c->list_mode_r[r] = mode;
     }
     cap_core = std::min(cap_core, std::max(32, round_up(n_max, 32)));
     cap_cand = std::min(cap_cand, std::max(32, round_up(n_max, 32)));

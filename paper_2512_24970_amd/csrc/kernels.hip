@@ -2449,7 +2449,27 @@ void launch_lists(const Plan& P, bool gate, hipStream_t st)
         else                                                                                           \
             k_lists_cell<kListCaps[C], false><<<cs.blocks, kListBlock, 0, st>>>(P.sys, cs.map, g, k); \
     } while (0)
-        if (P.list_mode < kListPerAtom) {
+        if (P.list_mode < kListPerAtom && !P.stored) {
+            // one launch per staging capacity in use (a batch can mix them)
+            for (int q = 0; q < kListPerAtom; ++q) {
+                const Shape& cq = P.list_by_cap[q];
+                if (cq.blocks <= 0) continue;
+#define RB_LISTS_Q(C)                                                                                  \
+    do {                                                                                               \
+        if (P.species_cut)                                                                             \
+            k_lists_cell<kListCaps[C], true><<<cq.blocks, kListBlock, 0, st>>>(P.sys, cq.map, g, k);  \
+        else                                                                                           \
+            k_lists_cell<kListCaps[C], false><<<cq.blocks, kListBlock, 0, st>>>(P.sys, cq.map, g, k); \
+    } while (0)
+                if (q == 0)
+                    RB_LISTS_Q(0);
+                else if (q == 1)
+                    RB_LISTS_Q(1);
+                else
+                    RB_LISTS_Q(2);
+#undef RB_LISTS_Q
+            }
+        } else if (P.list_mode < kListPerAtom) {
             if (cs.blocks > 0) {
                 if (P.list_mode == 0)
                     RB_LISTS(0);

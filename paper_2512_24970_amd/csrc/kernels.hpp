@@ -184,6 +184,10 @@ struct Plan {
     Shape kf_atoms;    // tune.kf_block-atom blocks (k-space force kernel)
     Shape cells;    // one block per cell
     Shape list_cells;  // list_parts blocks per cell (list build)
+    // the same cells grouped by the staging capacity kListCaps[q] of their
+    // system (a batch mixes small boxes, whose stencil is most of the box,
+    // with large ones); used unless the build is chunked or per atom
+    Shape list_by_cap[kListPerAtom];
     Shape cell_chunk[kMaxListChunks];  // the cells of each build chunk (memory form)
     Shape rows64;   // 64-row blocks over each system's candidate rows (batch draw)
     Shape atom1;    // one block per atom (per-atom list kernel)
