@@ -46,9 +46,12 @@ PEAK_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # VALU issue: one wave64 instruction per SIMD every 4 cycles, i.e. 256 x 4 x
 # 16 lane-instructions per cycle at 2.4 GHz; an FP32 transcendental
-# (v_exp, v_rsq, v_sin, v_cos) takes four of those slots.
+# (v_exp, v_rsq, v_sin, v_cos) takes two of those slots: on this GPU a
+# throughput probe (independent chains, all SIMDs busy) issues v_sin_f32 at
+# 9.0 and v_exp_f32 at 8.3 cycles per wavefront instruction against 4.9 for
+# v_fma_f64.
 PEAK_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
-TRANS_SLOTS = 4
+TRANS_SLOTS = 2
 
 # Work models, FMA = 2 flops, a transcendental = 1 flop (and 4 issue slots).
 # k-space kernels, per (atom, mode):
@@ -59,9 +62,11 @@ TRANS_SLOTS = 4
 #   mixed force:  phase 5, sum of w m_a (3 FMA)                                FP64 11
 #                 c A - s B (FMA + mul), sin + cos                             FP32 5
 # pair kernel, per distance test (every core-list entry and every batch
-# entry): three differences and r^2 (8), the minimum image (9) in the
-# wavefronts that touch the box edge (a quarter at the 10^6-ion size), so
-# 10.25 FP64; per evaluated pair: FP64 form 181 for the pair function (two
+# entry): FP64 form three differences and r^2 (8), the minimum image (9) in
+# the wavefronts that touch the box edge (a quarter at the 10^6-ion size), so
+# 10.25 FP64; mixed form the three scaled differences of 32-bit fixed-point
+# records (integer subtractions, then 3 FP64 products) and r^2, 8 FP64;
+# per evaluated pair: FP64 form 181 for the pair function (two
 # software exponentials, the squaring chain of the narrow Gaussians, the
 # 13-term polynomial of the wide ones, BMH terms) plus 6 to accumulate F;
 # mixed form 40 FP32 for the table-driven pair function as compiled (rsqrt
@@ -74,7 +79,7 @@ KSPACE_MODEL = {
 }  # (FP64 flops, FP32 flops, FP32 transcendentals) per (atom, mode)
 PAIR_MODEL = {
     "fp64": {"fp64_test": 10.25, "fp64_pair": 187.0, "fp32_pair": 0.0, "trans_pair": 0.0},
-    "mixed": {"fp64_test": 10.25, "fp64_pair": 6.0, "fp32_pair": 40.0, "trans_pair": 3.0},
+    "mixed": {"fp64_test": 8.0, "fp64_pair": 6.0, "fp32_pair": 40.0, "trans_pair": 3.0},
 }
 
 
@@ -307,9 +312,11 @@ def kernel_work(precision: str, phase: str, n: int, sysp: dict) -> dict:
         f64 = n * (c["tests"] * m["fp64_test"] + c["pairs"] * m["fp64_pair"])
         f32 = n * c["pairs"] * m["fp32_pair"]
         tr = n * c["pairs"] * m["trans_pair"]
-        # position record 32 B, list counts 8 B, core-list entries, one
-        # candidate index per batch entry, short-range force 24 B
-        hbm = n * (32 + 8 + 4 * c["core_list"] + 4 * c["batch"] + 24)
+        # own position record (FP64 32 B; the mixed form's fixed-point record
+        # 16 B), list counts 8 B, core-list entries, one candidate index per
+        # batch entry, short-range force 24 B
+        rec = 16 if precision == "mixed" else 32
+        hbm = n * (rec + 8 + 4 * c["core_list"] + 4 * c["batch"] + 24)
     else:
         am = float(n) * float(sysp["p_f"])
         a, b, t = KSPACE_MODEL[(precision, phase)]
@@ -358,7 +365,7 @@ def kernel_roofline(precision: str, phase: str, ms: float, launches: int, n: int
     cnt = _profile_json(workload, "counters")
     if cnt and key in cnt.get("per_launch", {}):
         c = cnt["per_launch"][key]
-        # VALU issue: lane-instructions, a transcendental taking four slots
+        # VALU issue: lane-instructions, a transcendental taking two slots
         slots = c["valu_lane_instr"] + (TRANS_SLOTS - 1) * c["trans_lane_instr"]
         out["counted"] = {"fp64_flops_per_launch": c["fp64_flops"], "fp32_flops_per_launch": c["fp32_flops"],
                           "valu_lane_instr_per_launch": c["valu_lane_instr"],
