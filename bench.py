@@ -374,6 +374,13 @@ def kernel_roofline(precision: str, phase: str, ms: float, launches: int, n: int
                           "flops_frac": round((c["fp64_flops"] + c["fp32_flops"]) / avg / 1e12
                                               / PEAK_VALU_TFLOPS, 4),
                           "model_over_counted_flops": round(flops / max(c["fp64_flops"] + c["fp32_flops"], 1), 3)}
+        if "td_busy" in c:
+            # the vector-memory path: L1 accesses (one per lane and cache
+            # line of a load) and how busy the texture address and data
+            # units were while the kernel ran alone
+            out["counted"].update({"l1_accesses_per_launch": c["l1_accesses"],
+                                   "l1_accesses_per_atom": round(c["l1_accesses"] / n, 2),
+                                   "ta_busy_frac": c["ta_busy"], "td_busy_frac": c["td_busy"]})
     tr = _profile_json(workload, "traffic")
     if tr and key in tr.get("bytes_per_launch", {}):
         b = tr["bytes_per_launch"][key]
