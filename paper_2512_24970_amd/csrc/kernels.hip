@@ -676,6 +676,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     __shared__ int rstart[kRegion];     // first staged position of each rank
     __shared__ int16_t queue[kListBlock / 64][kQueue];
     __shared__ int total_sm;
+    __shared__ uint8_t srank[CAP];      // rank of each staged position
     // block lb is part `part` of list cell c: the parts share the staging and
     // take every list_parts-th group of work units
     const int c = lb / s.list_parts;
@@ -752,18 +753,23 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 4);
         return;
     }
-    // stage, in rank order: staged position d belongs to the last rank whose
-    // first position is <= d (that rank holds atoms)
+    // The rank of each staged position (a rank's atoms are consecutive
+    // positions from its rstart) and each rank's atom-index offset, which
+    // takes gbeg's place (indexed by rank from here on; one thread per rank,
+    // R <= blockDim.x); then stage in rank order.
+    static_assert(kRegion <= kListBlock, "one thread per rank");
+    int off = 0;
+    if ((int)threadIdx.x < R) {
+        const int r = threadIdx.x, q = rcell[r];
+        const int b = rstart[r], e = b + lcnt[q];
+        off = gbeg[q] - b;
+        for (int d = b; d < e; ++d) srank[d] = (uint8_t)r;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < R) gbeg[threadIdx.x] = off;
+    __syncthreads();
     for (int d = threadIdx.x; d < total; d += blockDim.x) {
-        int lo = 0, hi = R - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (rstart[mid] <= d)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const int j = gbeg[rcell[lo]] + (d - rstart[lo]);
+        const int j = d + gbeg[srank[d]];
         const double4 P = s.p[j];
         px[d] = P.x;
         py[d] = P.y;
