@@ -379,6 +379,9 @@ __global__ void k_scatter(RB_ARGS, int gate)
 // Within each list cell, order atoms by (ordering sub-cell, id): the order is
 // deterministic and each of the eight sub-cells is a contiguous range, whose
 // first positions go to sub_beg.  Keys: sub-cell << 28 | id (ids < 2^28).
+// A cell of up to 64 atoms (nearly every cell of a large box) is sorted by
+// the block's first wavefront in registers, a bitonic network across its
+// lanes; a larger one (a small box is one cell) by the whole block over LDS.
 __global__ __launch_bounds__(kBlock) void k_cell_sort(RB_ARGS, int gate)
 {
     RB_SYS(blockIdx.x)
@@ -386,6 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(RB_ARGS, int gate)
     __shared__ int32_t key[kCellCap];
     __shared__ int32_t val[kCellCap];
     const int c = lb;
+    const int lane = threadIdx.x & 63;
     const int beg = s.cell_start[c];
     const int cnt = s.cell_start[c + 1] - beg;
     int32_t* sb = s.sub_beg + (size_t)c * 8;
@@ -397,19 +401,45 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(RB_ARGS, int gate)
         if (threadIdx.x == 0) atomicOr(&s.sc->overflow, 2);
         return;
     }
+    auto key_of = [&](int t) {
+        const double4 Q = s.tp[beg + t];
+        const int fx = cell_coord(Q.x, s.fine_scale[0], s.nf[0]);
+        const int fy = cell_coord(Q.y, s.fine_scale[1], s.nf[1]);
+        const int fz = cell_coord(Q.z, s.fine_scale[2], s.nf[2]);
+        const int sub = ((fz & 1) * 2 + (fy & 1)) * 2 + (fx & 1);
+        return (sub << 28) | s.tid[beg + t];
+    };
+    if (cnt <= 64) {
+        if (threadIdx.x >= 64) return;
+        // lane pairs (l, l ^ j) compare-exchange: the lower lane of a pair
+        // keeps the smaller key in ascending blocks (l & size == 0) and the
+        // larger in descending ones; padding keys are INT_MAX
+        int k = lane < cnt ? key_of(lane) : INT_MAX;
+        int v = lane < cnt ? beg + lane : -1;
+        for (int size = 2; size <= 64; size <<= 1) {
+            for (int j = size >> 1; j > 0; j >>= 1) {
+                const int ko = __shfl_xor(k, j, 64);
+                const int vo = __shfl_xor(v, j, 64);
+                const bool keep_min = ((lane & size) == 0) == ((lane & j) == 0);
+                if (keep_min ? ko < k : ko > k) {
+                    k = ko;
+                    v = vo;
+                }
+            }
+        }
+        if (lane < cnt) s.order[beg + lane] = v;
+        // first sorted position whose sub-cell is >= q: the keys below q << 28
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(lane < cnt && k < (q << 28));
+            if (lane == q) sb[q] = __popcll(m);
+        }
+        return;
+    }
     int P = 1;
     while (P < cnt) P <<= 1;
     for (int t = threadIdx.x; t < P; t += blockDim.x) {
-        int k = INT_MAX;
-        if (t < cnt) {
-            const double4 Q = s.tp[beg + t];
-            const int fx = cell_coord(Q.x, s.fine_scale[0], s.nf[0]);
-            const int fy = cell_coord(Q.y, s.fine_scale[1], s.nf[1]);
-            const int fz = cell_coord(Q.z, s.fine_scale[2], s.nf[2]);
-            const int sub = ((fz & 1) * 2 + (fy & 1)) * 2 + (fx & 1);
-            k = (sub << 28) | s.tid[beg + t];
-        }
-        key[t] = k;
+        key[t] = t < cnt ? key_of(t) : INT_MAX;
         val[t] = t < cnt ? beg + t : -1;
     }
     __syncthreads();
