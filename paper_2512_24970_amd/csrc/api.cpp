@@ -753,7 +753,8 @@ void autotune(rbsog_ctx* c, int reps)
     launch_rho_finalize(c->plan, st);
     launch_pair(c->plan, c->coef, c->mixed, false, st);
     launch_finalize(c->plan, false, st);
-    // the k-space force kernel alone: its workgroup size
+    // a first pick of the k-space force workgroup size, the kernel alone
+    // (refined on whole steps below)
     double tb = 1e300;
     for (int bs : {64, 128, 256}) {
         Tuning t = best;
@@ -804,9 +805,9 @@ void autotune(rbsog_ctx* c, int reps)
                     t.kf_aux = aux;
                     cands.push_back(Cand{t, 1e300});
                 }
-    try {
+    auto search = [&](std::vector<Cand>& cs) {
         for (int round = 0; round < 3; ++round)
-            for (Cand& cd : cands) {
+            for (Cand& cd : cs) {
                 try_shape(cd.t);
                 copy_state(false);
                 // time_ms runs the steps once untimed first (which also
@@ -815,6 +816,25 @@ void autotune(rbsog_ctx* c, int reps)
                     for (int k = 0; k < n_steps; ++k) launch_step(c, false, false);
                 }));
             }
+        double t_best = 1e300;
+        for (const Cand& cd : cs)
+            if (cd.ms < t_best) {
+                t_best = cd.ms;
+                best = cd.t;
+            }
+    };
+    try {
+        search(cands);
+        // then the k-space force workgroup again, on whole steps with the
+        // shapes just chosen (alone it ranks sizes that run beside the pair
+        // kernel differently)
+        std::vector<Cand> kf;
+        for (int bs : {64, 128, 256}) {
+            Tuning t = best;
+            t.kf_block = bs;
+            kf.push_back(Cand{t, 1e300});
+        }
+        search(kf);
     } catch (...) {
         // put the saved state back before reporting the failure
         try {
@@ -826,12 +846,6 @@ void autotune(rbsog_ctx* c, int reps)
         c->profiling = was_profiling;
         throw;
     }
-    double t_best = 1e300;
-    for (const Cand& cd : cands)
-        if (cd.ms < t_best) {
-            t_best = cd.ms;
-            best = cd.t;
-        }
     try_shape(best);
     copy_state(false);
     HIP_OK(hipStreamSynchronize(st));
