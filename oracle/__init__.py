@@ -97,6 +97,8 @@ def lib():
             "orc_list_counts": (C.c_int, [C.c_void_p, i32p, i32p]),
             "orc_list_atom": (C.c_int, [C.c_void_p, C.c_int32, i32p, i32p]),
             "orc_shell_ranks": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint64, i32p]),
+            "orc_scan_lists_atom": (C.c_int, [C.c_void_p, C.c_int32, i32p, i32p, i32p, i32p]),
+            "orc_shell_ranks_count": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, i32p]),
             "orc_pair_force": (C.c_double, [P(Params), C.c_int32, C.c_int32, dp, dp]),
             "orc_forces": (C.c_int, [C.c_void_p, C.c_uint64, dp, P(Energy)]),
             "orc_forces_short": (C.c_int, [C.c_void_p, C.c_uint64, dp, dp, dp, dp]),
@@ -292,6 +294,28 @@ class System:
         _, nk = self.list_counts()
         r = np.zeros(max(nk[i], 1), dtype=np.int32)
         k = lib().orc_shell_ranks(self._h, i, ev, _ptr(r, C.c_int32))
+        return r[:k]
+
+    def scan_lists_of(self, i: int):
+        """Core and candidate lists of atom i by a scan over every atom (no
+        full build): the same lists as lists_of, at any size."""
+        nc = np.zeros(1, dtype=np.int32)
+        nk = np.zeros(1, dtype=np.int32)
+        null = C.POINTER(C.c_int32)()
+        if lib().orc_scan_lists_atom(self._h, i, null, null, _ptr(nc, C.c_int32), _ptr(nk, C.c_int32)) != 0:
+            raise ValueError("bad atom index")
+        core = np.zeros(max(int(nc[0]), 1), dtype=np.int32)
+        cand = np.zeros(max(int(nk[0]), 1), dtype=np.int32)
+        lib().orc_scan_lists_atom(self._h, i, _ptr(core, C.c_int32), _ptr(cand, C.c_int32), _ptr(nc, C.c_int32),
+                                  _ptr(nk, C.c_int32))
+        return core[: nc[0]], cand[: nk[0]]
+
+    def shell_ranks_count(self, i: int, n: int, ev: int) -> np.ndarray:
+        """Shell ranks of atom i for a candidate count n (no lists needed)."""
+        r = np.zeros(max(n, 1), dtype=np.int32)
+        k = lib().orc_shell_ranks_count(self._h, i, n, ev, _ptr(r, C.c_int32))
+        if k < 0:
+            raise ValueError("bad atom index or count")
         return r[:k]
 
     def forces(self, ev: int):

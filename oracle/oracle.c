@@ -743,6 +743,24 @@ static void shell_stream(const orc_ctx* c, uint64_t eval, uint32_t* ctr1, uint32
     }
 }
 
+int orc_scan_lists_atom(const orc_ctx* c, int32_t i, int32_t* core, int32_t* cand, int32_t* n_core, int32_t* n_cand)
+{
+    if (i < 0 || i >= c->n) return -1;
+    int nc, nk;
+    scan_atom(c, i, core, &nc, cand, &nk, core == NULL || cand == NULL);
+    *n_core = nc;
+    *n_cand = nk;
+    return 0;
+}
+
+int orc_shell_ranks_count(const orc_ctx* c, int32_t i, int32_t n, uint64_t eval, int32_t* ranks)
+{
+    if (i < 0 || i >= c->n || n < 0) return -1;
+    uint32_t ctr1, tag;
+    shell_stream(c, eval, &ctr1, &tag);
+    return shell_ranks(&c->p, (uint32_t)i, n, ctr1, tag, ranks);
+}
+
 int orc_shell_ranks(const orc_ctx* c, int32_t i, uint64_t eval, int32_t* ranks)
 {
     if (!c->cand_off || i < 0 || i >= c->n) return -1;

@@ -144,6 +144,14 @@ int orc_list_atom(const orc_ctx* c, int32_t i, int32_t* core, int32_t* cand);
  * With shell_stored the batch is the one drawn for the last list build and
  * `eval` is not used. */
 int orc_shell_ranks(const orc_ctx* c, int32_t i, uint64_t eval, int32_t* ranks);
+/* The lists of atom i alone, by the same scan over every other atom (no full
+ * build, so usable at 10^6 atoms and more): with core or cand NULL only the
+ * counts; otherwise core and cand must hold them.  -1 for a bad index. */
+int orc_scan_lists_atom(const orc_ctx* c, int32_t i, int32_t* core, int32_t* cand, int32_t* n_core,
+                        int32_t* n_cand);
+/* The shell ranks of atom i for evaluation `eval` given its candidate count
+ * n (no lists needed); as orc_shell_ranks otherwise. */
+int orc_shell_ranks_count(const orc_ctx* c, int32_t i, int32_t n, uint64_t eval, int32_t* ranks);
 /* List builds since the system was created (the first build is number 0). */
 int64_t orc_n_builds(const orc_ctx* c);
 /* Force on i from j (d = r_i - r_j, minimum image) of eq. (15) with k_e;

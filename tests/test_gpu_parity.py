@@ -361,6 +361,37 @@ def test_full_size_sampled_atoms(name, precision, tol):
     assert np.abs(f_tot.sum(0)).max() < 1e-6 * np.abs(f_tot).max() * len(f_tot) ** 0.5
 
 
+@pytest.mark.parametrize("name", ["licl_nacl_1m", "nacl_5m"])
+def test_full_size_sampled_lists_and_shell_batch(name):
+    """Sampled indices bit-exact at full size, in the benchmark's
+    configuration (FP32-mixed): for 40 random ions, the core list, the
+    candidate row in its canonical order and the shell batch of an
+    evaluation (ids at the drawn ranks) equal the oracle's, which finds
+    each ion's lists by a scan over all ions."""
+    _say(f"case: full size lists and shell batch {name}")
+    cfg = W.config(name)
+    n = len(cfg["types"])
+    ctx, sysp = gpu_system(cfg, R.MIXED)
+    osys = oracle_system(cfg, sysp)
+    ev = 4
+    ctx.rbsog_compute_forces(ev, want_energy=False)
+    ncg, nkg = ctx.rbsog_get_list_counts()
+    nk_s, ids = ctx.rbsog_get_shell_samples()
+    assert np.array_equal(nk_s, nkg)
+    P = ids.shape[1]
+    for i in np.random.default_rng(11).choice(n, 40, replace=False):
+        i = int(i)
+        co, ko = osys.scan_lists_of(i)
+        assert (ncg[i], nkg[i]) == (len(co), len(ko)), i
+        cg, kg = ctx.rbsog_get_lists_of(i, int(ncg[i]), int(nkg[i]))
+        assert np.array_equal(cg, np.sort(co)) and np.array_equal(kg, ko), i
+        want = np.sort(ko[osys.shell_ranks_count(i, len(ko), ev)])
+        cnt = min(len(ko), P)
+        assert np.array_equal(ids[i, :cnt], want), i
+        assert (ids[i, cnt:] == -1).all()
+    ctx.close()
+
+
 def test_velocity_verlet_with_thermostat_matches_oracle(nacl512):
     """Berendsen rescaling (tau = dt) at the start of every step, on both sides."""
     _say("case: vv 12 steps thermostat nacl_512")

@@ -459,6 +459,26 @@ def test_rbl_shell_force_in_oracle_uses_the_batch():
     assert np.allclose(f[i], want, rtol=1e-12, atol=1e-13)
 
 
+def test_scanned_lists_and_ranks_equal_the_built_ones():
+    """The per-atom scan (used where a full O(N^2) build is too slow) gives
+    each atom the same core list and the same candidate row, in the same
+    canonical order, as the full build, and the ranks drawn from a given
+    candidate count are the batch's ranks; a 16000-ion four-species melt,
+    six list cells per axis, so the ordering grid has many cells."""
+    n = 16000
+    cfg = W.config("licl_nacl_1m", n=n, box=329.0 * (n / 1e6) ** (1 / 3))
+    s = O.System(cfg["sys"], cfg["types"], cfg["pos"])
+    for i in np.random.default_rng(4).choice(n, 30, replace=False):
+        i = int(i)
+        core, cand = s.lists_of(i)
+        core_s, cand_s = s.scan_lists_of(i)
+        assert np.array_equal(core, core_s) and np.array_equal(cand, cand_s)
+        for ev in (0, 9):
+            assert np.array_equal(s.shell_ranks(i, ev), s.shell_ranks_count(i, len(cand), ev))
+    with pytest.raises(ValueError):
+        s.scan_lists_of(n)
+
+
 def test_stored_batch_fixed_between_builds():
     """Memory form of the list (Section 2.4: O(core + P_R) entries per atom):
     the shell batch is drawn at the list build and kept, so the evaluation
