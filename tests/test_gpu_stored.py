@@ -226,6 +226,29 @@ def test_stored_batch_of_systems_equals_singles():
         off += n
 
 
+def test_stored_full_size_sampled_batches():
+    """The 10^6-ion four-species workload at full size in the stored form (8
+    build chunks): the batch drawn at build 0 for 40 random ions, as ids in
+    ascending rank order, equals the oracle's candidates (found by a scan
+    over all ions) at its ranks of build 0, and the candidate counts agree."""
+    _say("case: stored full size batches licl_nacl_1m")
+    cfg = W.config("licl_nacl_1m")
+    n = len(cfg["types"])
+    ctx, sysp = gpu_system(cfg, R.MIXED)
+    osys = oracle_system(cfg, sysp)
+    nk_g, ids_g = ctx.rbsog_get_shell_batch()
+    P = ids_g.shape[1]
+    for i in np.random.default_rng(13).choice(n, 40, replace=False):
+        i = int(i)
+        _, ko = osys.scan_lists_of(i)
+        assert nk_g[i] == len(ko), i
+        want = ko[osys.shell_ranks_count(i, len(ko), 0)]
+        cnt = min(len(ko), P)
+        assert np.array_equal(ids_g[i, :cnt], want), i
+        assert (ids_g[i, cnt:] == -1).all()
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision,tol", [(R.MIXED, TOL32), (R.FP64, TOL64)])
 def test_stored_full_size_sampled_atoms(precision, tol):
     """The 10^6-ion four-species workload at full size in the stored form
