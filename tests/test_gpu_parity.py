@@ -392,6 +392,33 @@ def test_full_size_sampled_lists_and_shell_batch(name):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision,bar", [(R.FP64, 2e-4), (R.MIXED, 2e-4)])
+def test_nve_energy_flat_without_randomness(nacl512, precision, bar):
+    """Randomness switched off (every shell candidate, the full k-sum):
+    plain velocity Verlet on the GPU keeps the total energy flat over 100
+    steps at dt = 1 fs (drift bounded by the unshifted cut of the BMH terms
+    at r_shell, as in the oracle's own pin), and the FP64 form's energies
+    follow the oracle's trajectory."""
+    _say(f"case: nve without randomness nacl_512 precision {precision}")
+    ctx, sysp = gpu_system(nacl512, precision, p_r=0, p_f=0)
+    _, e0 = ctx.rbsog_compute_forces(0)
+    E0 = e0["u_total"] + e0["kinetic"]
+    osys = oracle_system(nacl512, sysp) if precision == R.FP64 else None
+    if osys is not None:
+        osys.forces(0)
+    Es = []
+    for _ in range(5):
+        e = ctx.rbsog_step(20)
+        Es.append(e["u_total"] + e["kinetic"])
+        if osys is not None:
+            eo = osys.vv_steps(20)
+            assert e["u_total"] + e["kinetic"] == pytest.approx(eo["u_total"] + eo["kinetic"], rel=1e-9)
+    drift = max(abs(x - E0) for x in Es)
+    _say(f"  drift / kinetic {drift / e0['kinetic']:.2e} over 100 steps")
+    assert drift / e0["kinetic"] < bar
+    ctx.close()
+
+
 def test_velocity_verlet_with_thermostat_matches_oracle(nacl512):
     """Berendsen rescaling (tau = dt) at the start of every step, on both sides."""
     _say("case: vv 12 steps thermostat nacl_512")
