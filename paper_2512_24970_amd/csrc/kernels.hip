@@ -679,8 +679,13 @@ __device__ inline double uniform_f64(double v)
 constexpr int kIdxBits = 28;
 constexpr int kIdxMask = (1 << kIdxBits) - 1;
 
+// Waves per SIMD that the LDS of a block staging CAP atoms leaves room for
+// (3 blocks of 8 waves per CU up to about 53 KB each, else 2, else 1): the
+// register budget is capped to match, so registers never cost a block.
+constexpr int kListWaves(int cap) { return cap <= 1600 ? 6 : (cap <= 2048 ? 4 : 2); }
+
 template <int CAP, bool PC>
-__global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, int chunk)
+__global__ __launch_bounds__(kListBlock) __attribute__((amdgpu_waves_per_eu(kListWaves(CAP)))) void k_lists_cell(RB_ARGS, int gate, int chunk)
 {
     RB_SYS(xcd_block(blockIdx.x, gridDim.x))
     RB_GATE
@@ -706,7 +711,8 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     __shared__ int rstart[kRegion];     // first staged position of each rank
     __shared__ int16_t queue[kListBlock / 64][kQueue];
     __shared__ int total_sm;
-    __shared__ uint8_t srank[CAP];      // rank of each staged position
+    __shared__ uint8_t srank[CAP];      // rank of each staged position, then its image code
+    __shared__ uint8_t rcode[kRegion];  // image code of each rank (2 bits per axis)
     // block lb is part `part` of list cell c: the parts share the staging and
     // take every list_parts-th group of work units
     const int c = lb / s.list_parts;
@@ -752,6 +758,16 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         const int rank = (axis_rank(lz, gz0, s.nf[2], R2) * R1 + axis_rank(ly, gy0, s.nf[1], R1)) * R0 +
                          axis_rank(lx, gx0, s.nf[0], R0);
         rcell[rank] = q;
+        // Periodic image of the cell as seen from the block: per split axis
+        // k = -1 where the cell wraps from below the box (its atoms sit near
+        // L, the block's near 0), +1 where it wraps from above, else 0, in
+        // two bits (two's complement).
+        auto image = [](int l, int g0, int n) {
+            const int g = g0 + l;
+            return (g < 0 ? 3 : (g >= n ? 1 : 0));
+        };
+        rcode[rank] = (uint8_t)((sx ? image(lx, gx0, s.nf[0]) : 0) | ((sy ? image(ly, gy0, s.nf[1]) : 0) << 2) |
+                                ((sz ? image(lz, gz0, s.nf[2]) : 0) << 4));
     }
     __syncthreads();
     // first staged position of each region cell: exclusive scan over ranks
@@ -799,12 +815,14 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     if ((int)threadIdx.x < R) gbeg[threadIdx.x] = off;
     __syncthreads();
     for (int d = threadIdx.x; d < total; d += blockDim.x) {
-        const int j = d + gbeg[srank[d]];
+        const int r = srank[d];
+        const int j = d + gbeg[r];
         const double4 P = s.p[j];
         px[d] = P.x;
         py[d] = P.y;
         pz[d] = P.z;
         val[d] = PC ? (j | ((int)P.w << kIdxBits)) : j;
+        srank[d] = rcode[r];
     }
     __syncthreads();
     // ordering cells of the block: 2 per split axis
@@ -830,14 +848,35 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
     for (int f = 0; f < F; ++f) n_units += (lcnt[own_cell(f)] + kListA - 1) / kListA;
     const int cmax = s.cap_core - 1, kmax = s.cap_cand - 1;
     int16_t* qw = queue[wave];
-    auto sweep = [&](auto interior_tag, int a0, int na) {
-        constexpr bool INTERIOR = decltype(interior_tag)::value;
+    // Distances in the sweep, by block: kInterior, the plain difference;
+    // kShift (every axis split, so each staged cell is one periodic image of
+    // the block's neighbourhood), the difference minus L k with k the
+    // staged cell's image code; kMinImage, the minimum image of each
+    // difference.  All three give the bits of the minimum image for every
+    // pair that can be in a list: a pair's image along a split axis differs
+    // from the minimum image only where the two are at least L/2 apart along
+    // that axis, beyond the list radius (at most a list cell, a third of L),
+    // and with equal k the operations are the same: d - L k.
+    enum { kInterior, kShift, kMinImage };
+    auto sweep = [&](auto mode_tag, int a0, int na) {
+        constexpr int MODE = decltype(mode_tag)::value;
         double xu[kListA], yu[kListA], zu[kListA];
-        int tu[kListA], ncore[kListA], ncand[kListA];
-        int32_t* crow[kListA];
-        int32_t* ccol[kListA];
+        // per atom of the unit: core count in the low 16 bits, candidate
+        // count in the high 16 (each at most the staged total <= CAP)
+        static_assert(CAP < 65536, "counts fit 16 bits");
+        int tu[kListA];
+        uint32_t cnt2[kListA];
         const int v0 = __builtin_amdgcn_readfirstlane(val[a0]);
         const int i0 = PC ? v0 & kIdxMask : v0;
+        // A unit's atoms are consecutive sorted atoms i0, i0 + 1, ... (one
+        // ordering cell is one contiguous range): their candidate rows follow
+        // each other from crow0, their core columns follow each other from
+        // ccol0 up to the end of its 64-atom tile, and the next tile starts
+        // cap_core * 64 entries on.
+        int32_t* const crow0 = s.cand_idx + (size_t)(i0 - row0) * s.cap_cand;
+        int32_t* const ccol0 = s.core_idx + (size_t)(i0 >> 6) * s.cap_core * 64 + (i0 & 63);
+        const int tile_wrap = 64 - (i0 & 63);
+        const int tile_skip = s.cap_core * 64 - 64;
         double blo[3] = {px[a0], py[a0], pz[a0]};
         double bhi[3] = {blo[0], blo[1], blo[2]};
 #pragma unroll
@@ -850,15 +889,8 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             blo[0] = fmin(blo[0], px[a]), bhi[0] = fmax(bhi[0], px[a]);
             blo[1] = fmin(blo[1], yu[u]), bhi[1] = fmax(bhi[1], yu[u]);
             blo[2] = fmin(blo[2], zu[u]), bhi[2] = fmax(bhi[2], zu[u]);
-            const int va = __builtin_amdgcn_readfirstlane(val[a]);
-            tu[u] = (PC && here) ? va >> kIdxBits : 0;
-            // a missing atom sweeps into the rows of the unit's first atom,
-            // where its (no-hit) stores land on the unused last entry
-            const int ii = here ? (PC ? va & kIdxMask : va) : i0;
-            crow[u] = s.cand_idx + (size_t)(ii - row0) * s.cap_cand;
-            ccol[u] = s.core_idx + (size_t)(ii >> 6) * s.cap_core * 64 + (ii & 63);
-            ncore[u] = 0;
-            ncand[u] = 0;
+            if (PC) tu[u] = here ? __builtin_amdgcn_readfirstlane(val[a]) >> kIdxBits : 0;
+            cnt2[u] = 0;
         }
         // filter sphere of the unit (the atoms sit inside one ordering cell,
         // so the box is at most half a list cell per axis)
@@ -876,6 +908,15 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
         const double rf2 = uniform_f64(rf * rf);
         // exact tests of queue entries [qh, qh + cnt) against the unit
         auto test_chunk = [&](int qh, int cnt) {
+            // Wave-uniform values passed through an empty asm statement once
+            // per chunk, so that the compiler derives the per-atom offsets and
+            // conditions from them here (cheap scalar work) instead of holding
+            // eight copies in scalar registers across the sweep, which spills.
+            int tw = tile_wrap, ts = tile_skip, ck = s.cap_cand, nu = na, cm = cmax - 1, km = kmax - 1;
+            const double4* pu_g = s.p + i0;
+            asm volatile("" : "+s"(tw), "+s"(ts), "+s"(ck), "+s"(pu_g), "+s"(nu), "+s"(cm), "+s"(km));
+            using cdouble = const __attribute__((address_space(4))) double;
+            cdouble* pu = (cdouble*)pu_g;
             const bool in = lane < cnt;
             const int idx = in ? (int)qw[(qh + lane) & (kQueue - 1)] : 0;
             const int vj = val[idx];
@@ -883,10 +924,30 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             const int tj = PC ? vj >> kIdxBits : 0;
             const double pxj = in ? px[idx] : __builtin_inf();
             const double pyj = py[idx], pzj = pz[idx];
+            // staged position relative to the unit's first atom: lane is atom
+            // u of the unit itself where rel == u
+            const int rel = idx - a0;
+            // L k per axis from the staged atom's image code (exact products)
+            double lkx = 0.0, lky = 0.0, lkz = 0.0;
+            if (MODE == kShift) {
+                const uint32_t code = srank[idx];
+                lkx = s.L[0] * (double)((int)(code << 30) >> 30);
+                lky = s.L[1] * (double)((int)(code << 28) >> 30);
+                lkz = s.L[2] * (double)((int)(code << 26) >> 30);
+            }
 #pragma unroll
             for (int u = 0; u < kListA; ++u) {
-                double dx = xu[u] - pxj, dy = yu[u] - pyj, dz = zu[u] - pzj;
-                if (!INTERIOR) {
+                if (u >= nu) break;  // wave-uniform
+                // The unit atom's position, read again per chunk through the
+                // scalar cache (constant address space: this kernel does not
+                // write the positions); the same doubles as the staged copy.
+                double dx = pu[4 * u] - pxj, dy = pu[4 * u + 1] - pyj, dz = pu[4 * u + 2] - pzj;
+                if (MODE == kShift) {
+                    dx = dx - lkx;
+                    dy = dy - lky;
+                    dz = dz - lkz;
+                }
+                if (MODE == kMinImage) {
                     dx = min_image(dx, s.L[0], s.invL[0]);
                     dy = min_image(dy, s.L[1], s.invL[1]);
                     dz = min_image(dz, s.L[2], s.invL[2]);
@@ -900,7 +961,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
                 }
                 // masks of single compares (each is the compare's own lane
                 // mask), combined on the scalar unit
-                const bool other = idx != a0 + u;
+                const bool other = rel != u;
                 const bool in_core = r2 < rcl, above = r2 >= lol, below = r2 < s.hi2_list;
                 const uint64_t m_other = __builtin_amdgcn_ballot_w64(other);
                 const uint64_t mc = __builtin_amdgcn_ballot_w64(in_core) & m_other;
@@ -911,12 +972,14 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
                 // hits past the capacity all land on the row's last usable
                 // entry: the counts report the overflow and the host builds
                 // again with longer rows.
-                const int rc_ = min(mbcnt64(mc, ncore[u]), cmax - 1);
-                const int rk_ = min(mbcnt64(mk, ncand[u]), kmax - 1);
-                if (is_core) *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ccol[u]) + ((uint32_t)rc_ << 8)) = j;
-                if (is_cand) *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(crow[u]) + ((uint32_t)rk_ << 2)) = j;
-                ncore[u] += __popcll(mc);
-                ncand[u] += __popcll(mk);
+                const int rc_ = min(mbcnt64(mc, (int)(cnt2[u] & 0xFFFFu)), cm);
+                const int rk_ = min(mbcnt64(mk, (int)(cnt2[u] >> 16)), km);
+                // byte offsets of atom i0 + u's core column and candidate row
+                const uint32_t coff = (uint32_t)(u < tw ? u : u + ts) << 2;
+                const uint32_t koff = (uint32_t)(u * ck) << 2;
+                if (is_core) *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ccol0) + (((uint32_t)rc_ << 8) + coff)) = j;
+                if (is_cand) *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(crow0) + (((uint32_t)rk_ << 2) + koff)) = j;
+                cnt2[u] += (uint32_t)__popcll(mc) + ((uint32_t)__popcll(mk) << 16);
             }
         };
         // first pass: keep the staged atoms inside the sphere, in staged
@@ -928,7 +991,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             bool keep = false;
             if (t < total) {
                 double dx = cx - px[t], dy = cy - py[t], dz = cz - pz[t];
-                if (!INTERIOR) {
+                if (MODE != kInterior) {
                     dx = min_image(dx, s.L[0], s.invL[0]);
                     dy = min_image(dy, s.L[1], s.invL[1]);
                     dz = min_image(dz, s.L[2], s.invL[2]);
@@ -953,14 +1016,15 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             if (lane == 0 && u < na) {
                 const int va = val[a0 + u];
                 const int i = PC ? va & kIdxMask : va;
-                s.core_cnt[i] = ncore[u];
-                s.cand_cnt[i] = ncand[u];
+                const int ncore = (int)(cnt2[u] & 0xFFFFu), ncand = (int)(cnt2[u] >> 16);
+                s.core_cnt[i] = ncore;
+                s.cand_cnt[i] = ncand;
                 // same-address atomics serialise: only overflowing atoms
                 // report; the last entry of a row is not usable here
-                if (ncore[u] >= s.cap_core || ncand[u] >= s.cap_cand) {
+                if (ncore >= s.cap_core || ncand >= s.cap_cand) {
                     atomicOr(&s.sc->overflow, 1);
-                    atomicMax(&s.sc->max_core, ncore[u] + 1);
-                    atomicMax(&s.sc->max_cand, ncand[u] + 1);
+                    atomicMax(&s.sc->max_core, ncore + 1);
+                    atomicMax(&s.sc->max_cand, ncand + 1);
                 }
             }
         }
@@ -974,12 +1038,14 @@ __global__ __launch_bounds__(kListBlock) void k_lists_cell(RB_ARGS, int gate, in
             g -= nu;
         }
         const int q0 = own_cell(f);
-        const int a0 = cstart[q0] + g * kListA;
-        const int na = min(kListA, cstart[q0] + lcnt[q0] - a0);
+        const int a0 = __builtin_amdgcn_readfirstlane(cstart[q0] + g * kListA);
+        const int na = __builtin_amdgcn_readfirstlane(min(kListA, cstart[q0] + lcnt[q0] - a0));
         if (interior)
-            sweep(std::true_type{}, a0, na);
+            sweep(std::integral_constant<int, kInterior>{}, a0, na);
+        else if (sx && sy && sz)
+            sweep(std::integral_constant<int, kShift>{}, a0, na);
         else
-            sweep(std::false_type{}, a0, na);
+            sweep(std::integral_constant<int, kMinImage>{}, a0, na);
     }
 }
 
