@@ -106,7 +106,7 @@ struct rbsog_ctx {
     int list_chunks = 8;
     std::vector<int> list_mode_r;    // staging class of each system (kListPerAtom: per-atom kernel)
     double row_slack = 1.25;
-    DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, vir_part, kin_part, export_tmp, snap, sogk, neartab;
+    DBuf ktab, kcdf, kmodes, krho_part, krho, pair_part, vir_part, fin_part, kin_part, export_tmp, snap, sogk, neartab;
     DBuf flux_part, at_ew, ufix;
     // mean-square displacement: [n_user][3] last positions, then [n_user][3]
     // unwrapped displacements; which systems have a marked origin
@@ -1066,6 +1066,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->pair_part.alloc(sizeof(double) * kPairPart * std::max<size_t>(1, n_waves));
     c->vir_part.alloc(sizeof(double) * kVirPart * std::max<size_t>(1, n_waves));
     HIP_OK(hipMemsetAsync(c->vir_part.p, 0, c->vir_part.bytes, c->stream));
+    c->fin_part.alloc(sizeof(double) * kFin * kFinBlocks * std::max(R, 1));
     c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
     c->flux_part.alloc(sizeof(double) * kFluxPart * std::max<size_t>(1, n_waves));
     c->at_ew.alloc(sizeof(double4) * 2 * N);
@@ -1112,6 +1113,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
             cells += 10 * (size_t)s.ncell + 1;
             s.pair_part = c->pair_part.as<double>() + wav * kPairPart;
             s.vir_part = c->vir_part.as<double>() + wav * kVirPart;
+            s.fin_part = c->fin_part.as<double>() + (size_t)r * kFinBlocks * kFin;
             s.kin_part = c->kin_part.as<double>() + wav;
             s.flux_part = c->flux_part.as<double>() + wav * kFluxPart;
             s.at_ew = c->at_ew.as<double4>() + 2 * o;

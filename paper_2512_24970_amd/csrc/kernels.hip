@@ -62,6 +62,7 @@ __device__ inline DevSys global_view(DevSys s)
     s.cand_cnt = glob(s.cand_cnt), s.cand_idx = glob(s.cand_idx), s.bat_idx = glob(s.bat_idx);
     s.pair = glob(s.pair), s.sc = glob(s.sc), s.spc = glob(s.spc);
     s.pair_part = glob(s.pair_part), s.kin_part = glob(s.kin_part), s.vir_part = glob(s.vir_part);
+    s.fin_part = glob(s.fin_part);
     s.ufix = glob(s.ufix);
     return s;
 }
@@ -1893,57 +1894,83 @@ __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __rest
     }
 }
 
-// Momentum correction (eq. 26) and energy sums; one 1024-thread block per
-// system.
-__global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sys, const KDev* __restrict__ kd,
-                                                   int energy)
+// Momentum correction (eq. 26) and energy sums, first pass: block b of each
+// system sums slice b of the wavefront partials and of the modes, and writes
+// the kFin sums to fin_part[b].
+__global__ __launch_bounds__(256) void k_finalize_part(const DevSys* __restrict__ sys, const KDev* __restrict__ kd,
+                                                       int energy)
 {
-    const DevSys s = global_view(sys[blockIdx.x]);
-    const KDev k = global_view(kd[blockIdx.x]);
+    const int r = blockIdx.x / kFinBlocks, b = blockIdx.x - r * kFinBlocks;
+    const DevSys s = global_view(sys[r]);
+    const KDev k = global_view(kd[r]);
     const double* part = s.pair_part;
     const int nb = (s.n + 63) / 64;  // wavefront partials
-    __shared__ double red[16];
+    const int w0 = (int)((long long)nb * b / kFinBlocks), w1 = (int)((long long)nb * (b + 1) / kFinBlocks);
+    __shared__ double red[4];
     double v[kPairPart + kVirPart];
     for (int c = 0; c < kPairPart + kVirPart; ++c) v[c] = 0.0;
 #pragma unroll 4
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-        for (int c = 0; c < kPairPart; ++c) v[c] += part[(size_t)b * kPairPart + c];
+    for (int w = w0 + (int)threadIdx.x; w < w1; w += blockDim.x)
+        for (int c = 0; c < kPairPart; ++c) v[c] += part[(size_t)w * kPairPart + c];
     if (energy) {
 #pragma unroll 4
-        for (int b = threadIdx.x; b < nb; b += blockDim.x)
-            for (int c = 0; c < kVirPart; ++c) v[kPairPart + c] += s.vir_part[(size_t)b * kVirPart + c];
+        for (int w = w0 + (int)threadIdx.x; w < w1; w += blockDim.x)
+            for (int c = 0; c < kVirPart; ++c) v[kPairPart + c] += s.vir_part[(size_t)w * kVirPart + c];
     }
     const int nc = energy ? kPairPart + kVirPart : kPairPart;
     double ue = 0.0;
     double wk[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int nm = s.n > 0 ? k.n_modes : 0;  // an empty system sums no modes
-    for (int p = threadIdx.x; p < nm; p += blockDim.x) {
-        const ModeRec r = k.modes[p];
-        ue += r.e;
+    const int m0 = (int)((long long)nm * b / kFinBlocks), m1 = (int)((long long)nm * (b + 1) / kFinBlocks);
+    for (int p = m0 + (int)threadIdx.x; p < m1; p += blockDim.x) {
+        const ModeRec mr = k.modes[p];
+        ue += mr.e;
         if (energy) {
             // strain derivative of the mode's energy: e (delta_ab - g k_a k_b)
             // g of the mode, kept for the per-atom shares of the fused pass
-            const double kx = s.two_pi_L[0] * r.mx, ky = s.two_pi_L[1] * r.my, kz = s.two_pi_L[2] * r.mz;
+            const double kx = s.two_pi_L[0] * mr.mx, ky = s.two_pi_L[1] * mr.my, kz = s.two_pi_L[2] * mr.mz;
             const double g = mode_g(k, (kx * kx + ky * ky) + kz * kz);
             k.mode_g[p] = g;
-            const double eg = r.e * g;
-            wk[0] += r.e - eg * kx * kx;
-            wk[1] += r.e - eg * ky * ky;
-            wk[2] += r.e - eg * kz * kz;
+            const double eg = mr.e * g;
+            wk[0] += mr.e - eg * kx * kx;
+            wk[1] += mr.e - eg * ky * ky;
+            wk[2] += mr.e - eg * kz * kz;
             wk[3] -= eg * kx * ky;
             wk[4] -= eg * kx * kz;
             wk[5] -= eg * ky * kz;
         }
     }
-    // fixed trip count (nc is uniform): constant indices keep tot in registers
-    double tot[kPairPart + kVirPart];
+    // nc and energy are uniform, so every thread takes part in each block_sum
+    double* out = s.fin_part + (size_t)b * kFin;
 #pragma unroll
-    for (int c = 0; c < kPairPart + kVirPart; ++c) tot[c] = c < nc ? block_sum(v[c], red) : 0.0;
+    for (int c = 0; c < kPairPart + kVirPart; ++c) {
+        const double t = c < nc ? block_sum(v[c], red) : 0.0;
+        if (threadIdx.x == 0) out[c] = t;
+    }
     const double ut = block_sum(ue, red);
-    double wt[6];
-    if (energy)
-        for (int c = 0; c < 6; ++c) wt[c] = block_sum(wk[c], red);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) out[kPairPart + kVirPart] = ut;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const double t = energy ? block_sum(wk[c], red) : 0.0;
+        if (threadIdx.x == 0) out[kPairPart + kVirPart + 1 + c] = t;
+    }
+}
+
+// Second pass: one wavefront per system; lane q adds quantity q of the
+// kFinBlocks block sums in block order, and the evaluation's scalars are
+// written from them.
+__global__ __launch_bounds__(64) void k_finalize(const DevSys* __restrict__ sys, int energy)
+{
+    const DevSys s = global_view(sys[blockIdx.x]);
+    const int q = threadIdx.x;
+    double t = 0.0;
+    if (q < kFin)
+        for (int b = 0; b < kFinBlocks; ++b) t += s.fin_part[(size_t)b * kFin + q];
+    auto get = [&](int c) { return __shfl(t, c, 64); };
+    double tot[kFin];
+#pragma unroll
+    for (int c = 0; c < kFin; ++c) tot[c] = get(c);
+    if (q == 0) {
         DeviceScalars* sc = s.sc;
         const double inv_n = s.n > 0 ? 1.0 / (double)s.n : 0.0;
         sc->p_corr[0] = tot[0] * inv_n;
@@ -1951,9 +1978,11 @@ __global__ __launch_bounds__(1024) void k_finalize(const DevSys* __restrict__ sy
         sc->p_corr[2] = tot[2] * inv_n;
         sc->u_core = tot[3];
         sc->u_shell = tot[4];
+        const double ut = tot[kPairPart + kVirPart];
         sc->u_kspace = 0.5 * s.coulomb_k * ut;
         if (energy)
-            for (int c = 0; c < 6; ++c) sc->virial[c] = tot[kPairPart + c] + 0.5 * s.coulomb_k * wt[c];
+            for (int c = 0; c < 6; ++c)
+                sc->virial[c] = tot[kPairPart + c] + 0.5 * s.coulomb_k * tot[kPairPart + kVirPart + 1 + c];
     }
 }
 
@@ -2673,7 +2702,9 @@ void launch_rho_finalize(const Plan& P, hipStream_t st)
 
 void launch_finalize(const Plan& P, bool energy, hipStream_t st)
 {
-    if (P.R > 0) k_finalize<<<P.R, 1024, 0, st>>>(P.sys, P.kd, energy ? 1 : 0);
+    if (P.R <= 0) return;
+    k_finalize_part<<<P.R * kFinBlocks, 256, 0, st>>>(P.sys, P.kd, energy ? 1 : 0);
+    k_finalize<<<P.R, 64, 0, st>>>(P.sys, energy ? 1 : 0);
 }
 
 void launch_kforce(const Plan& P, bool mixed, hipStream_t st)

@@ -100,6 +100,7 @@ struct DevSys {
     DeviceScalars* sc;
     double* pair_part;     // [ceil(n/64)][kPairPart] wavefront partials of the pair kernel
     double* vir_part;      // [ceil(n/64)][kVirPart] wavefront virial partials (evaluations with energies)
+    double* fin_part;      // [kFinBlocks][kFin] per-block sums of the evaluation's force-sum reduction
     double* kin_part;      // [ceil(n/64)] kinetic-energy wavefront partials
     double* flux_part;     // [ceil(n/64)][kFluxPart] kinetic tensor and heat-flux partials
     double4* at_ew;        // [n][2] per-atom short-range energy and virial shares of the
@@ -136,6 +137,11 @@ struct KDev {
 // u_shell; and, in evaluations with energies, the virial W (6) in vir_part.
 constexpr int kPairPart = 5;
 constexpr int kVirPart = 6;
+// The reduction of those partials and of the modes' energies runs in two
+// passes: kFinBlocks blocks per system, each over a fixed slice, then one
+// wavefront per system adding their kFin sums in block order.
+constexpr int kFinBlocks = 32;
+constexpr int kFin = kPairPart + kVirPart + 1 + 6;  // pair sums, virial, mode energy, mode virial
 // Per-wavefront partials of the closing pass of an evaluation with energies:
 // sum m v_a v_b (6), sum (m v^2 / 2) v (3), sum (e_i v + W_i v) (3).
 constexpr int kFluxPart = 12;
