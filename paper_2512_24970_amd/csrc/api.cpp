@@ -351,6 +351,8 @@ void plan_launches(rbsog_ctx* c)
     P.kd = c->d_kd.as<KDev>();
     P.sc = c->scalars.as<DeviceScalars>();
     P.R = c->R;
+    P.fin_grid = 1;
+    for (const auto& s : c->hs) P.fin_grid = std::max(P.fin_grid, fin_blocks(s.n));
     constexpr int kShapes = 10 + kListPerAtom;
     Shape* dst[kShapes] = {&P.atoms, &P.pair_atoms, &P.kf_atoms, &P.cells, &P.atom1, &P.modes64, &P.rho,
                            &P.modes1, &P.rows64, &P.list_cells, &P.list_by_cap[0], &P.list_by_cap[1],
@@ -1067,6 +1069,7 @@ void set_batch_impl(rbsog_ctx* c, int R, const rbsog_params* params, const int32
     c->vir_part.alloc(sizeof(double) * kVirPart * std::max<size_t>(1, n_waves));
     HIP_OK(hipMemsetAsync(c->vir_part.p, 0, c->vir_part.bytes, c->stream));
     c->fin_part.alloc(sizeof(double) * kFin * kFinBlocks * std::max(R, 1));
+    HIP_OK(hipMemsetAsync(c->fin_part.p, 0, c->fin_part.bytes, c->stream));
     c->kin_part.alloc(sizeof(double) * std::max<size_t>(1, n_waves));
     c->flux_part.alloc(sizeof(double) * kFluxPart * std::max<size_t>(1, n_waves));
     c->at_ew.alloc(sizeof(double4) * 2 * N);

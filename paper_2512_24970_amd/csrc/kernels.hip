@@ -1898,14 +1898,16 @@ __global__ __launch_bounds__(64) void k_rho_finalize(RB_ARGS, const KDev* __rest
 // system sums slice b of the wavefront partials and of the modes, and writes
 // the kFin sums to fin_part[b].
 __global__ __launch_bounds__(256) void k_finalize_part(const DevSys* __restrict__ sys, const KDev* __restrict__ kd,
-                                                       int energy)
+                                                       int energy, int grid)
 {
-    const int r = blockIdx.x / kFinBlocks, b = blockIdx.x - r * kFinBlocks;
+    const int r = blockIdx.x / grid, b = blockIdx.x - r * grid;
     const DevSys s = global_view(sys[r]);
+    const int nf = fin_blocks(s.n);
+    if (b >= nf) return;  // a smaller system of a batch
     const KDev k = global_view(kd[r]);
     const double* part = s.pair_part;
     const int nb = (s.n + 63) / 64;  // wavefront partials
-    const int w0 = (int)((long long)nb * b / kFinBlocks), w1 = (int)((long long)nb * (b + 1) / kFinBlocks);
+    const int w0 = nb * b / nf, w1 = nb * (b + 1) / nf;  // nb * 32 fits 32 bits
     __shared__ double red[4];
     double v[kPairPart + kVirPart];
     for (int c = 0; c < kPairPart + kVirPart; ++c) v[c] = 0.0;
@@ -1921,7 +1923,7 @@ __global__ __launch_bounds__(256) void k_finalize_part(const DevSys* __restrict_
     double ue = 0.0;
     double wk[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int nm = s.n > 0 ? k.n_modes : 0;  // an empty system sums no modes
-    const int m0 = (int)((long long)nm * b / kFinBlocks), m1 = (int)((long long)nm * (b + 1) / kFinBlocks);
+    const int m0 = nm * b / nf, m1 = nm * (b + 1) / nf;
     for (int p = m0 + (int)threadIdx.x; p < m1; p += blockDim.x) {
         const ModeRec mr = k.modes[p];
         ue += mr.e;
@@ -1957,15 +1959,22 @@ __global__ __launch_bounds__(256) void k_finalize_part(const DevSys* __restrict_
 }
 
 // Second pass: one wavefront per system; lane q adds quantity q of the
-// kFinBlocks block sums in block order, and the evaluation's scalars are
-// written from them.
+// system's fin_blocks(n) block sums in block order, and the evaluation's
+// scalars are written from them.
 __global__ __launch_bounds__(64) void k_finalize(const DevSys* __restrict__ sys, int energy)
 {
     const DevSys s = global_view(sys[blockIdx.x]);
     const int q = threadIdx.x;
     double t = 0.0;
-    if (q < kFin)
-        for (int b = 0; b < kFinBlocks; ++b) t += s.fin_part[(size_t)b * kFin + q];
+    const int nf = fin_blocks(s.n);
+    // every row is read (all loads in flight together); rows past nf add 0
+    if (q < kFin) {
+#pragma unroll
+        for (int b = 0; b < kFinBlocks; ++b) {
+            const double x = s.fin_part[(size_t)b * kFin + q];
+            t += b < nf ? x : 0.0;
+        }
+    }
     auto get = [&](int c) { return __shfl(t, c, 64); };
     double tot[kFin];
 #pragma unroll
@@ -2703,7 +2712,7 @@ void launch_rho_finalize(const Plan& P, hipStream_t st)
 void launch_finalize(const Plan& P, bool energy, hipStream_t st)
 {
     if (P.R <= 0) return;
-    k_finalize_part<<<P.R * kFinBlocks, 256, 0, st>>>(P.sys, P.kd, energy ? 1 : 0);
+    k_finalize_part<<<P.R * P.fin_grid, 256, 0, st>>>(P.sys, P.kd, energy ? 1 : 0, P.fin_grid);
     k_finalize<<<P.R, 64, 0, st>>>(P.sys, energy ? 1 : 0);
 }
 

@@ -138,10 +138,18 @@ struct KDev {
 constexpr int kPairPart = 5;
 constexpr int kVirPart = 6;
 // The reduction of those partials and of the modes' energies runs in two
-// passes: kFinBlocks blocks per system, each over a fixed slice, then one
-// wavefront per system adding their kFin sums in block order.
+// passes: fin_blocks(n) blocks per system (one per 256 wavefront partials,
+// at most kFinBlocks), each over a fixed slice, then one wavefront per
+// system adding their kFin sums in block order.  The slicing depends on the
+// system's own size only, so a system sums in the same order alone and in a
+// batch.
 constexpr int kFinBlocks = 32;
 constexpr int kFin = kPairPart + kVirPart + 1 + 6;  // pair sums, virial, mode energy, mode virial
+constexpr int fin_blocks(int n)
+{
+    const int b = ((n + 63) / 64 + 255) / 256;
+    return b < 1 ? 1 : (b > kFinBlocks ? kFinBlocks : b);
+}
 // Per-wavefront partials of the closing pass of an evaluation with energies:
 // sum m v_a v_b (6), sum (m v^2 / 2) v (3), sum (e_i v + W_i v) (3).
 constexpr int kFluxPart = 12;
@@ -206,6 +214,7 @@ struct Plan {
     bool iph = false;       // mixed form: k-space phases in 32-bit fixed point
     bool species_cut = false;  // species-dependent core radii
     int n_chunks = 1;     // build chunks (1 unless stored)
+    int fin_grid = 1;     // largest fin_blocks over the systems (blocks per system of the first pass)
     int cap_core = 0, cap_cand = 0;
     NearTab near;
     Tuning tune;
